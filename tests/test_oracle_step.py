@@ -1,0 +1,306 @@
+"""Pins of the oracle's 3D CTU+CT step (Sect. 5.2) on periodic patches.
+
+P5 reduction to an independent 1D update, P6 conservation, P7 div b, P9
+decomposition invariance, P10 uniform fixed point, P11 ghost-width cone,
+P12 dt by hand, P13/P8 convergence to closed-form solutions, P14 restart.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import default_params, line_fluxes
+from paper_1701_07452_amd import inputs as I
+from tests._helpers import l1_norm, oracle_gather, oracle_sim
+
+GAM = 5.0 / 3.0
+
+
+def _frame(q, cm):
+    return np.stack([q[0], q[1 + cm[0]], q[1 + cm[1]], q[1 + cm[2]], q[4 + cm[0]], q[4 + cm[1]], q[4 + cm[2]], q[7]], -1)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_P5_reduction_to_1d(axis):
+    """Brio-Wu data varying along one axis: the 3D step equals a plain 1D
+    conservative update with the line fluxes, bitwise, for every axis."""
+    N, g = 32, 5
+    shape = [8, 8, 8]
+    shape[2 - axis] = N
+    shape = tuple(shape)
+    q0, b0 = I.shock_tube_x((8, 8, N), gamma=2.0)
+    cm = [(0 + axis) % 3, (1 + axis) % 3, (2 + axis) % 3]
+    lineq, lineb = q0[:, 0, 0, :], b0[:, 0, 0, :]
+
+    def place(v):
+        s = [1, 1, 1]
+        s[2 - axis] = N
+        return np.broadcast_to(v.reshape(s), shape)
+
+    q = np.zeros((8,) + shape)
+    b = np.zeros((3,) + shape)
+    q[0], q[7] = place(lineq[0]), place(lineq[7])
+    for c in range(3):
+        q[1 + cm[c]] = place(lineq[1 + c])
+        q[4 + cm[c]] = place(lineq[4 + c])
+        b[cm[c]] = place(lineb[c])
+    dx = (1.0 / N,) * 3
+    G = I.uniform_grid((shape[2], shape[1], shape[0]), (shape[2], shape[1], shape[0]))
+    sim = oracle_sim(G, q, b, dx=dx, gamma=2.0)
+    P = sim.params
+
+    def line(a):
+        sl = [0, 0, 0]
+        sl[2 - axis] = slice(None)
+        return a[(slice(None),) + tuple(sl)]
+
+    fr = _frame(line(q), cm)
+    bpar = line(b)[cm[0]]
+    for _ in range(6):
+        sim.fill_ghosts()
+        dt = sim.compute_dt()
+        sim.advance(dt)
+        qq = np.concatenate([fr[-g:], fr, fr[:g]])
+        bf = np.concatenate([bpar[-g:], bpar, bpar[:g]])
+        F = line_fluxes(P, qq, bf, dt / dx[0])
+        fr = fr - dt / dx[0] * (F[g + 1:g + N + 1] - F[g:g + N])
+    qn, bn = sim.get_state(0)
+    assert np.array_equal(_frame(line(qn), cm), fr)
+    # and the state stays planar
+    ref = line(qn)
+    s = [1, 1, 1]
+    s[2 - axis] = N
+    assert np.array_equal(qn, np.broadcast_to(ref.reshape((8,) + tuple(s)), qn.shape))
+
+
+def _random_run(nsteps, N=16, npb=1, seed=1, **kw):
+    q, b = I.random_smooth((N, N, N), seed)
+    G = I.uniform_grid(N, N // npb)
+    sim = oracle_sim(G, q, b, dx=(1.0 / N,) * 3, **kw)
+    tot0, dn0, dr0, _ = sim.diagnostics()
+    for _ in range(nsteps):
+        sim.fill_ghosts()
+        sim.advance(sim.compute_dt())
+    return sim, G, tot0, dn0
+
+
+def test_P6_P7_conservation_and_divb():
+    sim, G, tot0, dn0 = _random_run(20, N=16, npb=2)
+    tot, dn, dr, nfl = sim.diagnostics()
+    assert nfl == 0
+    assert dn0 < 1e-13
+    # rho, m, E and the face-averaged B are conserved to roundoff (periodic box)
+    scale = np.maximum(np.abs(tot0), 1e-3)
+    assert np.all(np.abs(tot - tot0) / scale < 1e-13), (tot - tot0) / scale
+    assert dn < 1e-13, dn
+
+
+def test_P9_decomposition_invariance():
+    """1 patch of 24^3 == 27 patches of 8^3 (g=5 <= 8) == uneven 8/16 tiling, bitwise."""
+    q, b = I.random_smooth((24, 24, 24), 4)
+    dx = (1.0 / 24,) * 3
+    grids = [I.uniform_grid(24, 24), I.uniform_grid(24, 8), I.patch_grid([8, 16], [16, 8], [8, 8, 8])]
+    outs = []
+    for G in grids:
+        sim = oracle_sim(G, q, b, dx=dx)
+        for _ in range(3):
+            sim.fill_ghosts()
+            sim.advance(sim.compute_dt())
+        outs.append(oracle_gather(G, sim))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0])
+        assert np.array_equal(o[1], outs[0][1])
+
+
+def test_P10_uniform_fixed_point():
+    N = 16
+    q = I.conserved(np.full((N, N, N), 1.3), [np.full((N, N, N), v) for v in (0.3, -0.2, 0.5)],
+                    I.uniform_faces((N, N, N), (0.4, 0.9, -0.6)), 0.7)
+    b = I.uniform_faces((N, N, N), (0.4, 0.9, -0.6))
+    G = I.uniform_grid(N, N)
+    sim = oracle_sim(G, q, b, dx=(1.0 / N,) * 3)
+    for _ in range(3):
+        sim.fill_ghosts()
+        sim.advance(sim.compute_dt())
+    qn, bn = sim.get_state(0)
+    assert np.array_equal(bn, b)
+    assert np.allclose(qn, q, rtol=1e-15, atol=0)
+
+
+def test_P11_ghost_width_cone():
+    """Poison stored layers deeper than w with NaN after the fill: the interior
+    result is unchanged for w >= 4 and differs (NaN) for w = 3."""
+    N = 12
+    q, b = I.random_smooth((N, N, N), 9)
+    G = I.uniform_grid(N, N)
+    dx = (1.0 / N,) * 3
+    ref = oracle_sim(G, q, b, dx=dx)
+    ref.fill_ghosts()
+    dt = ref.compute_dt()
+    qs, bs = ref.get_stored(0)
+    ref.advance(dt)
+    qr, br = ref.get_state(0)
+    g = 5
+    results = {}
+    for w in (3, 4):
+        sim = oracle_sim(G, q, b, dx=dx)
+        qp, bp = qs.copy(), bs.copy()
+        Ns = N + 2 * g
+        idx = np.arange(Ns)
+        bad = (idx < g - w) | (idx >= g + N + w)
+        mask = bad[:, None, None] | bad[None, :, None] | bad[None, None, :]
+        qp[:, mask] = np.nan
+        bp[:, mask] = np.nan
+        sim.set_stored(0, qp, bp)
+        sim.advance(dt)
+        qn, bn = sim.get_state(0)
+        results[w] = np.array_equal(qn, qr) and np.array_equal(bn, br)
+    assert results[4] and not results[3]
+
+
+def test_P12_dt_by_hand():
+    N = 8
+    rho, v, B, p = 1.3, (0.3, -0.2, 0.5), (0.4, 0.9, -0.6), 0.7
+    b = I.uniform_faces((N, N, N), B)
+    q = I.conserved(np.full((N, N, N), rho), [np.full((N, N, N), x) for x in v], b, p)
+    dx = (0.1, 0.2, 0.15)
+    G = I.uniform_grid(N, N)
+    sim = oracle_sim(G, q, b, dx=dx)
+    dt = sim.compute_dt()
+    a2 = GAM * p / rho
+    B2 = sum(x * x for x in B)
+    want = []
+    for d in range(3):
+        disc = math.sqrt((a2 + B2 / rho) ** 2 - 4 * a2 * B[d] ** 2 / rho)
+        cf = math.sqrt(0.5 * (a2 + B2 / rho + disc))
+        want.append(dx[d] / (abs(v[d]) + cf))
+    assert abs(dt - 0.4 * min(want)) <= 1e-14 * dt
+
+
+def test_P14_restart_bitwise():
+    q, b = I.random_smooth((16, 16, 16), 2)
+    G = I.uniform_grid(16, 8)
+    dx = (1.0 / 16,) * 3
+    a = oracle_sim(G, q, b, dx=dx)
+    a.run_steps(6)
+    qa, ba = oracle_gather(G, a)
+    c = oracle_sim(G, q, b, dx=dx)
+    c.run_steps(3)
+    mid = oracle_gather(G, c)
+    d = oracle_sim(G, *mid, dx=dx)
+    d.run_steps(3)
+    qd, bd = oracle_gather(G, d)
+    assert np.array_equal(qa, qd) and np.array_equal(ba, bd)
+
+
+def _wave_error(N, npb, frac=0.5):
+    q, b, wv = I.fast_wave_diagonal(N)
+    G = I.uniform_grid(N, N // npb)
+    sim = oracle_sim(G, q, b, dx=(1.0 / N,) * 3)
+    t, T = 0.0, wv.period * frac
+    while t < T * (1 - 1e-12):
+        sim.fill_ghosts()
+        dt = min(sim.compute_dt(), T - t)
+        sim.advance(dt)
+        t += dt
+    qn, _ = oracle_gather(G, sim)
+    return l1_norm(qn - wv.exact((N, N, N), (1.0 / N,) * 3, t))
+
+
+@pytest.mark.slow
+def test_P8_linear_fast_wave_second_order():
+    """Closed-form fast wave along the diagonal (C1 setup): the L1 error norm
+    falls with slope -> 2 (TVD clipping at extrema makes coarse grids lower)."""
+    e16, e32, e64 = _wave_error(16, 1), _wave_error(32, 2), _wave_error(64, 2)
+    s1, s2 = math.log2(e16 / e32), math.log2(e32 / e64)
+    assert e64 < e32 < e16
+    assert s2 > 1.7, (s1, s2)
+    assert s2 > s1
+
+
+def _line_wave_error(N, wave, beta=1.0):
+    from paper_1701_07452_amd.inputs import _primitive_matrix
+    A = _primitive_matrix(1.0, 0.0, 1.0, math.sqrt(2), 0.5, 0.6, GAM)
+    w, V = np.linalg.eig(A)
+    w, V = w.real, V.real
+    o = np.argsort(w)
+    k = {"fast": o[6], "slow": o[4], "alfven": o[5]}[wave]
+    vec = V[:, k] / (V[0, k] if wave != "alfven" else np.linalg.norm(V[2:4, k]))
+    c = w[k]
+    amp, g = 1e-6, 5
+    x = (np.arange(N) + 0.5) / N
+
+    def st(t):
+        cc = amp * np.cos(2 * math.pi * (x - c * t))
+        rho = 1 + vec[0] * cc
+        v = np.stack([vec[1 + a] * cc for a in range(3)])
+        Bt = np.stack([math.sqrt(2) + vec[4] * cc, 0.5 + vec[5] * cc])
+        p = 0.6 + vec[6] * cc
+        q = np.zeros((N, 8))
+        q[:, 0] = rho
+        q[:, 1:4] = (rho * v).T
+        q[:, 4] = 1.0
+        q[:, 5:7] = Bt.T
+        q[:, 7] = p / (GAM - 1) + 0.5 * rho * (v ** 2).sum(0) + 0.5 * (1 + (Bt ** 2).sum(0))
+        return q
+
+    P = default_params(dx=(1.0 / N,) * 3, limiter_beta=beta)
+    q, T, t, dx = st(0), 1.0 / abs(c), 0.0, 1.0 / N
+    while t < T * (1 - 1e-13):
+        dt = min(0.4 * dx / 2.0, T - t)
+        qq = np.concatenate([q[-g:], q, q[:g]])
+        F = line_fluxes(P, qq, np.ones(N + 2 * g), dt / dx)
+        q = q - dt / dx * (F[g + 1:g + N + 1] - F[g:g + N])
+        t += dt
+    return l1_norm((q - st(t)).T)
+
+
+@pytest.mark.parametrize("wave", ["fast", "slow", "alfven"])
+def test_P8_1d_waves_second_order(wave):
+    """1D MHD waves of the Sect. 6.1 background after one period: slope -> 2."""
+    e = [_line_wave_error(N, wave) for N in (64, 128, 256)]
+    s = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert s[1] > 1.8 and e[2] < e[1] < e[0], s
+
+
+@pytest.mark.slow
+def test_P13_circularly_polarised_alfven():
+    """Exact nonlinear CP Alfven wave oblique to the grid (Sect. 6.9 setup): L1
+    error after one period converges at second order."""
+    errs = []
+    for N, npb in ((8, 1), (16, 1), (32, 2)):
+        q, b, exact, dx = I.cp_alfven(N)
+        G = I.uniform_grid((2 * N, N, N), (2 * N // npb, N // npb, N // npb))
+        sim = oracle_sim(G, q, b, dx=dx)
+        t = 0.0
+        while t < 1.0 - 1e-12:
+            sim.fill_ghosts()
+            dt = min(sim.compute_dt(), 1.0 - t)
+            sim.advance(dt)
+            t += dt
+        qn, _ = oracle_gather(G, sim)
+        errs.append(l1_norm(qn - exact(t)))
+    s = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert s[1] > 1.8 and s[0] > 1.5, s
+
+
+def test_P16_field_loop():
+    """Weak field loop advected with v_z != 0: magnetic energy decays
+    monotonically (a downwind corner-EMF choice makes it grow without bound),
+    B_z stays at truncation level (the div-B source keeps the loop planar),
+    and div b stays at roundoff."""
+    N = 32
+    dx = (2.0 / N, 1.0 / N, 1.0 / N)
+    q, b = I.field_loop((N, N, N), dx, v=(2.0, 1.0, 1.0))
+    G = I.uniform_grid(N, 16)
+    sim = oracle_sim(G, q, b, dx=dx)
+    me = [0.5 * (q[4:7] ** 2).sum()]
+    for _ in range(4):
+        sim.run_steps(10)
+        qn, bn = oracle_gather(G, sim)
+        me.append(0.5 * (qn[4:7] ** 2).sum())
+    assert all(me[i + 1] < me[i] for i in range(4)), me
+    assert me[-1] / me[0] > 0.3
+    assert np.abs(qn[6]).max() < 0.05 * np.abs(q[4:6]).max()
+    _, dn, _, _ = sim.diagnostics()
+    assert dn < 1e-12
