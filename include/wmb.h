@@ -1,0 +1,162 @@
+/*
+ * wmb.h -- C ABI of the MI355X (gfx950) library that advances batches of
+ * ghosted Cartesian patches of 3D ideal MHD by the MHDTVD CTU+CT scheme of
+ * Mendygral et al. 2017 (WOMBAT), Sect. 5.2 ("MHD in Three Dimensions",
+ * Steps 1-11) with the MHDTVD flux of Appendix A.
+ *
+ * The verbs follow the paper's statement of the problem (Sect. 2.1, 4.1): a
+ * periodic world grid cut into patches with their own boundary zones; ghost
+ * zones filled between patches; a global CFL reduction for dt (Sect. 4.1.1);
+ * a solver that updates the patch arrays; state read back.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: WMB_OK (0) or a negative WMB_E* code.  Nothing aborts or
+ *     throws across this boundary.  wmb_last_error() gives a message for the
+ *     last failure on a context.
+ *   - Ownership: the caller owns the device pool (one allocation of at least
+ *     wmb_pool_bytes() bytes, e.g. a torch uint8 tensor) and the HIP stream;
+ *     both must outlive the context, which never frees them.  The library owns
+ *     the context, its small device tables (descriptors, work lists, dt and
+ *     reduction scratch) and its captured graphs; wmb_destroy frees them.
+ *   - Host arrays belong to the caller.  wmb_set_state / wmb_get_state /
+ *     wmb_compute_dt(out != NULL) / wmb_diagnostics are synchronous on the
+ *     stream; wmb_fill_ghosts, wmb_advance and wmb_run_steps only enqueue.
+ *   - One context is used by one host thread at a time.
+ *   - Layout of host state arrays (double, C order): q is 8 x nz x ny x nx in
+ *     the paper's component order (rho, rho vx, rho vy, rho vz, Bx, By, Bz, E)
+ *     (Sect. 5, 1D conservative form); b is 3 x nz x ny x nx, where b[a] at
+ *     zone (i,j,k) is the face-centred field component a on the zone's LEFT
+ *     face along a (x_{i-1/2} for a = x, and so on).  Units carry no 4 pi.
+ *   - Device layout (inside the pool): per patch, structure of arrays over
+ *     the ghosted box (n+2g)^3, x fastest, FP32 or FP64 by precision.
+ */
+#ifndef WMB_H
+#define WMB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WMB_OK 0
+#define WMB_EINVAL (-1) /* bad argument or inconsistent patch table */
+#define WMB_ENOMEM (-2) /* host or library-owned device allocation failed */
+#define WMB_EHIP (-3)   /* a HIP runtime call failed (message in last_error) */
+#define WMB_ESTATE (-4) /* non-finite input, rho <= 0 or P <= 0 */
+#define WMB_ECFL (-5)   /* dt above the CFL limit */
+#define WMB_ESIZE (-6)  /* pool smaller than wmb_pool_bytes */
+#define WMB_EORDER (-7) /* call out of sequence (e.g. advance before init) */
+
+#define WMB_FP64 0 /* all stages in double */
+#define WMB_FP32 1 /* sweeps and CT in float; dt, floors, diagnostics in double */
+
+typedef struct wmb_params {
+    double gamma;        /* adiabatic index (Sect. 5) */
+    double cfl;          /* Courant number of the dt reduction */
+    double eps[7];       /* entropy-fix epsilon_k of Q_k (Appendix A), 0 <= eps < 0.5,
+                            waves in ascending order v-cf, v-ca, v-cs, v, v+cs, v+ca, v+cf */
+    double limiter_beta; /* Sweby limiter parameter in [1, 2] (Appendix A) */
+    double rho_floor;    /* density floor (Appendix A, last paragraph) */
+    double p_floor;      /* pressure floor */
+    double dx[3];        /* zone widths along x, y, z */
+    double degen_tol;    /* degeneracy threshold of the eigenvectors (e.g. 1e-12) */
+    int32_t ghost;       /* ghost width g, >= 4 (the paper uses 5, Sect. 5.1) */
+    int32_t precision;   /* WMB_FP64 or WMB_FP32 */
+} wmb_params;
+
+typedef struct wmb_patch_desc {
+    int32_t n[3];      /* interior zones along x, y, z (each >= ghost) */
+    int32_t nbr[27];   /* patch id at offset (dz,dy,dx) in {-1,0,1}^3, index
+                          9(dz+1) + 3(dy+1) + (dx+1); the caller resolves
+                          periodic wrap; nbr[13] is the patch itself.  Face
+                          neighbours must share the face extent. */
+    int64_t origin[3]; /* global zone offset (diagnostics only) */
+} wmb_patch_desc;
+
+typedef struct wmb_ctx wmb_ctx;
+
+/* Create a context.  Validates p (gamma > 1, cfl in (0,1], ghost >= 4,
+   dx > 0, precision known).  *out receives the context. */
+int wmb_create(const wmb_params *p, wmb_ctx **out);
+
+/* Device bytes the caller must provide for npatch patches: two state copies
+   (11 words per stored zone each) plus the step's intermediates. */
+int wmb_pool_bytes(const wmb_params *p, int32_t npatch, const wmb_patch_desc *d, uint64_t *bytes);
+
+/* Bind the patches to the caller's device pool and stream (hipStream_t, NULL
+   = default stream).  Checks the neighbour table (face extents agree, the
+   neighbour of my neighbour is me) and builds the launch plans.  The pool's
+   contents are undefined until wmb_set_state has been called for every
+   patch.  WMB_ESIZE if pool_bytes < wmb_pool_bytes. */
+int wmb_init_patches(wmb_ctx *c, int32_t npatch, const wmb_patch_desc *d, void *dev_pool,
+                     uint64_t pool_bytes, void *hip_stream);
+
+/* Upload one patch's interior state (host arrays, layout above).  Rounds to
+   FP32 in FP32 mode.  WMB_ESTATE if any value is non-finite, rho <= 0, or the
+   pressure (from E with the zone-centred field) is <= 0. */
+int wmb_set_state(wmb_ctx *c, int32_t patch, const double *q, const double *b);
+
+/* Read one patch's interior state (and its own left faces) back to host
+   double arrays, same layout as wmb_set_state. */
+int wmb_get_state(wmb_ctx *c, int32_t patch, double *q, double *b);
+
+/* Read the whole ghosted box of one patch: q is 8 x Nz x Ny x Nx, b is
+   3 x Nz x Ny x Nx with N = n + 2 ghost (test hook for the ghost exchange). */
+int wmb_get_stored(wmb_ctx *c, int32_t patch, double *q, double *b);
+
+/* Enqueue the ghost exchange (Sect. 4.1, local patch copies): every ghost
+   zone and ghost face of every patch becomes a copy of the neighbour's
+   interior value covering it; a patch's right-boundary face is the
+   neighbour's own left face.  Bitwise copies. */
+int wmb_fill_ghosts(wmb_ctx *c);
+
+/* CFL reduction in FP64 over all interior zones:
+   dt = cfl * min_{zones, d} dx_d / (|v_d| + c_f,d), with c_f,d the fast speed
+   (Sect. 5) taking B_d as the longitudinal field.  The result stays in device
+   memory for wmb_advance(c, 0) / wmb_run_steps; if dt_out != NULL it is also
+   copied to the host (synchronising the stream). */
+int wmb_compute_dt(wmb_ctx *c, double *dt_out);
+
+/* One CTU+CT step (Sect. 5.2, Steps 1-11) of every patch.  Ghosts must be
+   current.  dt > 0: use this dt (the call checks it against the CFL limit of
+   the current state and returns WMB_ECFL if it is larger by more than 1e-12
+   relative; this check synchronises).  dt <= 0: use the device-resident dt of
+   the last wmb_compute_dt.  Floors (rho_floor, p_floor) are applied in FP64
+   and counted. */
+int wmb_advance(wmb_ctx *c, double dt);
+
+/* nsteps x (fill ghosts, compute dt, advance) with dt kept on the device,
+   replayed from a captured HIP graph (captured on the first call).  Enqueue
+   only; this is the timed call. */
+int wmb_run_steps(wmb_ctx *c, int32_t nsteps);
+
+/* FP64 diagnostics over all interiors: totals[8] = sum over zones of q times
+   the zone volume; max_divb_raw = max |div b| with div b = sum_d (b_d(+) -
+   b_d(-)) / dx_d; max_divb_norm = max_divb_raw * min(dx) / B_rms; n_floored =
+   floor activations since wmb_init_patches.  Any output pointer may be NULL. */
+int wmb_diagnostics(wmb_ctx *c, double totals[8], double *max_divb_norm, double *max_divb_raw,
+                    int64_t *n_floored);
+
+/* Test hook: copy an intermediate of the last step of one patch over the
+   ghosted box, widened to double, in this layout: stage 1 Step-1 fluxes
+   (3 x 8 x vol, lab component order, B_par row 0), 3 b^{n+1/2} (3 x vol),
+   5 Step-6/7 fluxes (3 x 8 x vol), 6 Step-9 edge EMFs (3 x vol).  Values
+   outside the ranges the step needs are unspecified.  Other stages (the
+   Step-3 edges are overwritten by Step 9) give WMB_EINVAL.  Synchronous. */
+int wmb_debug_stage(wmb_ctx *c, int32_t patch, int32_t stage, double *out);
+
+/* Free the context, its tables and graphs (not the pool, not the stream). */
+int wmb_destroy(wmb_ctx *c);
+
+/* Static message for an error code. */
+const char *wmb_strerror(int code);
+
+/* Message of the last failure on this context ("" if none). */
+const char *wmb_last_error(const wmb_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WMB_H */

@@ -1,0 +1,73 @@
+// wmb_internal.h -- device-side layout shared by the runtime and the kernels
+// of the patch MHD library (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace wmb {
+
+// Scheme parameters as the kernels see them.
+struct DevParams {
+    double gamma;
+    double cfl;
+    double eps[7];
+    double limiter_beta;
+    double rho_floor;
+    double p_floor;
+    double dx[3];
+    double degen_tol;
+    int ghost;
+    int pad_;
+};
+
+// One patch inside the device pool: structure of arrays over the ghosted box
+// N = n + 2g, x fastest.  Every field array holds `vol` elements starting at
+// base + field * vol (elements of the working precision).
+struct PatchDev {
+    int n[3];
+    int N[3];
+    long long base;
+    long long vol;
+};
+
+// Field slots of a patch, in units of vol.
+enum : int {
+    F_ST0 = 0,   // state copy 0: q (8) then b (3)
+    F_ST1 = 11,  // state copy 1
+    F_FL1 = 22,  // Step-1 fluxes, 3 directions x 7 rows
+    F_FL2 = 43,  // Step-6/7 fluxes, 3 directions x 7 rows
+    F_ED = 64,   // edge EMFs (3), reused by Steps 3 and 9
+    F_BH = 67,   // b^{n+1/2} (3)
+    F_ER = 70,   // zone-centred reference EMF (3), reused by Steps 2 and 8
+    F_TOTAL = 73
+};
+// Row order of a flux array of direction d: rho, mx, my, mz, E, B_{d+1}, B_{d+2}
+// (the B_d row of the 1D flux is identically zero and is not stored).
+
+struct WorkItem {
+    int patch;
+    int a;  // box kernels: block index in the patch; sweeps: first fast-transverse coord
+    int b;  // sweeps: slow-transverse coord
+    int c;  // sweeps: last fast-transverse coord (inclusive)
+};
+
+struct FillRegion {
+    int dst, src;
+    int d0[3];  // first stored index of the destination box (x, y, z)
+    int s0[3];  // first stored index of the source box in the neighbour
+    int ext[3];
+};
+
+// Box kernels: interior-relative inclusive ranges [lo, n + hi] per axis.
+struct Box {
+    int lo, hi;
+};
+
+// Per-component ranges of the edge-EMF kernel: along the edge's own axis
+// [lo_c, n + hi_c], along the two others [lo_o, n + hi_o].
+struct EdgeRanges {
+    int lo_c, hi_c, lo_o, hi_o;
+};
+
+}  // namespace wmb

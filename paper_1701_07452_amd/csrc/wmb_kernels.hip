@@ -1,0 +1,866 @@
+// wmb_kernels.hip -- gfx950 kernels of one CTU+CT MHDTVD step over a batch of
+// ghosted patches (Mendygral et al. 2017, Sect. 5.2 Steps 1-11, Appendix A).
+//
+// Every kernel is templated on the working precision R (float or double).
+// The CFL reduction, floors and diagnostics are FP64 whatever R is.
+//
+// Kernel map (one step):
+//   fill_ghosts      bitwise copy of the 26 neighbour regions, 11 fields
+//   dt_reduce        FP64 max signal speed, wave reduction + atomicMax
+//   dt_finalize      dt = cfl / smax, kept in device memory
+//   emf_ref<q^n>     Step 2   zone-centred E^r = -v x B
+//   sweep<d,1>       Step 1   MHDTVD fluxes from q^n, B_par = b^n   (hot)
+//   edge_emf         Step 3   upwinded edge EMFs
+//   ct_half          Step 4   b^{n+1/2} = b^n - dt/2 curl E
+//   sweep<d,2>       Steps 5-7  transverse predictor + source, then MHDTVD
+//                              fluxes with B_par = b^{n+1/2}        (hot)
+//   emf_half         Step 8   E^r from the unsplit half update and face-averaged b^{n+1/2}
+//   edge_emf         Step 9
+//   final_update     Steps 10-11  q^{n+1}, b^{n+1}, zone field, FP64 floors
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "wmb_internal.h"
+
+namespace wmb {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ R sgn1(R x) { return x >= R(0) ? R(1) : R(-1); }
+
+// coefficient of numerical viscosity Q_k(chi) (Appendix A)
+template <typename R>
+__device__ __forceinline__ R qvisc(R chi, R eps) {
+    R ac = fabs(chi);
+    if (ac < R(2) * eps) return chi * chi / (R(4) * eps) + eps;
+    return ac;
+}
+
+// g_i = SIGN(gp) * SWEBY(gp, gm) (Appendix A), Sweby family with parameter beta
+template <typename R>
+__device__ __forceinline__ R sweby(R gp, R gm, R beta) {
+    R s = sgn1(gp);
+    R t1 = fmin(beta * fabs(gp), s * gm);
+    R t2 = fmin(fabs(gp), beta * s * gm);
+    return s * fmax(R(0), fmax(t1, t2));
+}
+
+__device__ __forceinline__ double minmod2(double a, double b) {
+    if (a > 0.0 && b > 0.0) return fmin(a, b);
+    if (a < 0.0 && b < 0.0) return fmax(a, b);
+    return 0.0;
+}
+
+__device__ __forceinline__ long long sidx(const PatchDev& P, int i, int j, int k) {
+    return ((long long)k * P.N[1] + j) * P.N[0] + i;
+}
+
+__device__ __forceinline__ long long stride_of(const PatchDev& P, int a) {
+    return a == 0 ? 1LL : (a == 1 ? (long long)P.N[0] : (long long)P.N[0] * P.N[1]);
+}
+
+// FP64 floors on one zone (density raised with momentum kept, then pressure
+// raised by adding thermal energy).  Returns true if a floor fired.
+template <typename R>
+__device__ __forceinline__ bool apply_floor(R u[8], const DevParams& p) {
+    bool hit = false;
+    double rho = (double)u[0];
+    if (rho < p.rho_floor) {
+        rho = p.rho_floor;
+        u[0] = (R)rho;
+        hit = true;
+    }
+    double m2 = (double)u[1] * u[1] + (double)u[2] * u[2] + (double)u[3] * u[3];
+    double b2 = (double)u[4] * u[4] + (double)u[5] * u[5] + (double)u[6] * u[6];
+    double pr = (p.gamma - 1.0) * ((double)u[7] - 0.5 * m2 / rho - 0.5 * b2);
+    if (pr < p.p_floor) {
+        u[7] = (R)((double)u[7] + (p.p_floor - pr) / (p.gamma - 1.0));
+        hit = true;
+    }
+    return hit;
+}
+
+// ---------------------------------------------------------------------------
+// ghost exchange
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(256) fill_ghosts_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
+                                                          const FillRegion* __restrict__ regs, int cur) {
+    const FillRegion rg = regs[blockIdx.x];
+    const PatchDev D = patches[rg.dst];
+    const PatchDev S = patches[rg.src];
+    const int ex = rg.ext[0], ey = rg.ext[1], ez = rg.ext[2];
+    const int total = ex * ey * ez;
+    R* dbase = pool + D.base + (long long)(cur ? F_ST1 : F_ST0) * D.vol;
+    const R* sbase = pool + S.base + (long long)(cur ? F_ST1 : F_ST0) * S.vol;
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        int i = t % ex, r = t / ex;
+        int j = r % ey, k = r / ey;
+        long long di = sidx(D, rg.d0[0] + i, rg.d0[1] + j, rg.d0[2] + k);
+        long long si = sidx(S, rg.s0[0] + i, rg.s0[1] + j, rg.s0[2] + k);
+#pragma unroll
+        for (int c = 0; c < 11; c++) dbase[(long long)c * D.vol + di] = sbase[(long long)c * S.vol + si];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// box-kernel indexing: block (patch, blk) covers 256 consecutive linear
+// indices of the patch's box [lo, n+hi]^3 (x fastest)
+// ---------------------------------------------------------------------------
+
+struct BoxPos {
+    int i, j, k;  // interior-relative
+    bool valid;
+};
+
+__device__ __forceinline__ BoxPos box_pos(const PatchDev& P, int blk, Box bx) {
+    int ex = P.n[0] + bx.hi - bx.lo + 1;
+    int ey = P.n[1] + bx.hi - bx.lo + 1;
+    int ez = P.n[2] + bx.hi - bx.lo + 1;
+    int t = blk * blockDim.x + threadIdx.x;
+    BoxPos r;
+    r.valid = t < ex * ey * ez;
+    r.i = t % ex + bx.lo;
+    int u = t / ex;
+    r.j = u % ey + bx.lo;
+    r.k = u / ey + bx.lo;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// CFL reduction (FP64)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double fast_speed(double rho, double p, double gam, double b2, double bd) {
+    double a2 = gam * p / rho;
+    double ca2 = bd * bd / rho;
+    double bp2 = (b2 - bd * bd) / rho;
+    double dpr = a2 - ca2 - bp2;
+    double d = sqrt(dpr * dpr + 4.0 * a2 * bp2);
+    return sqrt(0.5 * (a2 + ca2 + bp2 + d));
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) dt_reduce_kernel(const R* __restrict__ pool, const PatchDev* __restrict__ patches,
+                                                        const WorkItem* __restrict__ work, DevParams prm, int cur,
+                                                        unsigned long long* __restrict__ smax_bits) {
+    __shared__ double red[4];
+    const WorkItem w = work[blockIdx.x];
+    const PatchDev P = patches[w.patch];
+    BoxPos bp = box_pos(P, w.a, Box{0, -1});
+    double s = 0.0;
+    if (bp.valid) {
+        const int g = prm.ghost;
+        long long x = sidx(P, bp.i + g, bp.j + g, bp.k + g);
+        const R* q = pool + P.base + (long long)(cur ? F_ST1 : F_ST0) * P.vol;
+        double rho = (double)q[x];
+        double v[3] = {(double)q[P.vol + x] / rho, (double)q[2 * P.vol + x] / rho, (double)q[3 * P.vol + x] / rho};
+        double B[3] = {(double)q[4 * P.vol + x], (double)q[5 * P.vol + x], (double)q[6 * P.vol + x]};
+        double b2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+        double pr = (prm.gamma - 1.0) * ((double)q[7 * P.vol + x] - 0.5 * rho * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - 0.5 * b2);
+        if (pr < prm.p_floor) pr = prm.p_floor;
+        for (int d = 0; d < 3; d++) {
+            double sd = (fabs(v[d]) + fast_speed(rho, pr, prm.gamma, b2, B[d])) / prm.dx[d];
+            s = fmax(s, sd);
+        }
+    }
+    s = wave_max(s);
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int t = 1; t < (int)(blockDim.x >> 6); t++) m = fmax(m, red[t]);
+        // positive doubles order like their bit patterns
+        atomicMax(smax_bits, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+__global__ void dt_finalize_kernel(unsigned long long* smax_bits, double* dt, double cfl) {
+    double smax = __longlong_as_double((long long)*smax_bits);
+    dt[0] = cfl / smax;
+    *smax_bits = 0ULL;
+}
+
+// ---------------------------------------------------------------------------
+// Step 2: zone-centred reference EMF E^r = -v x B from q^n
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(256) emf_ref_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
+                                                      const WorkItem* __restrict__ work, DevParams prm, int cur, Box bx) {
+    const WorkItem w = work[blockIdx.x];
+    const PatchDev P = patches[w.patch];
+    BoxPos bp = box_pos(P, w.a, bx);
+    if (!bp.valid) return;
+    const int g = prm.ghost;
+    long long x = sidx(P, bp.i + g, bp.j + g, bp.k + g);
+    const R* q = pool + P.base + (long long)(cur ? F_ST1 : F_ST0) * P.vol;
+    R* er = pool + P.base + (long long)F_ER * P.vol;
+    R rho = q[x];
+    R vx = q[P.vol + x] / rho, vy = q[2 * P.vol + x] / rho, vz = q[3 * P.vol + x] / rho;
+    R Bx = q[4 * P.vol + x], By = q[5 * P.vol + x], Bz = q[6 * P.vol + x];
+    er[x] = vz * By - vy * Bz;
+    er[P.vol + x] = vx * Bz - vz * Bx;
+    er[2 * P.vol + x] = vy * Bx - vx * By;
+}
+
+// ---------------------------------------------------------------------------
+// Step 8: E^r from the unsplit half update of q^n with the Step-6/7 fluxes
+// (velocity) and the face average of b^{n+1/2} (zone field)
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(256) emf_half_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
+                                                       const WorkItem* __restrict__ work, DevParams prm, int cur,
+                                                       const double* __restrict__ dtp, Box bx) {
+    const WorkItem w = work[blockIdx.x];
+    const PatchDev P = patches[w.patch];
+    BoxPos bp = box_pos(P, w.a, bx);
+    if (!bp.valid) return;
+    const int g = prm.ghost;
+    const R hdt = R(0.5 * dtp[0]);
+    long long x = sidx(P, bp.i + g, bp.j + g, bp.k + g);
+    const long long V = P.vol;
+    const R* q = pool + P.base + (long long)(cur ? F_ST1 : F_ST0) * V;
+    const R* fl = pool + P.base + (long long)F_FL2 * V;
+    const R* bh = pool + P.base + (long long)F_BH * V;
+    R* er = pool + P.base + (long long)F_ER * V;
+    R u[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        R div = R(0);
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const R* f = fl + (long long)(7 * d + c) * V;
+            long long s = stride_of(P, d);
+            div += (f[x + s] - f[x]) / R(prm.dx[d]);
+        }
+        u[c] = q[(long long)c * V + x] - hdt * div;
+    }
+    R B[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) B[d] = R(0.5) * (bh[(long long)d * V + x] + bh[(long long)d * V + x + stride_of(P, d)]);
+    R vx = u[1] / u[0], vy = u[2] / u[0], vz = u[3] / u[0];
+    er[x] = vz * B[1] - vy * B[2];
+    er[V + x] = vx * B[2] - vz * B[0];
+    er[2 * V + x] = vy * B[0] - vx * B[1];
+}
+
+// ---------------------------------------------------------------------------
+// Steps 3 and 9: upwinded edge EMFs from face fluxes and E^r.  For the edge of
+// component c at the lower corner of the (a, b) = (c+1, c+2) plane, each of
+// the four adjacent face values (-flux_a[B_b] on a-faces, +flux_b[B_a] on
+// b-faces) is extrapolated half a zone to the edge with the face-to-centre
+// difference on the upwind side (by the sign of the mass flux across the
+// face carrying it; the average of both sides when it is exactly zero); the
+// edge value is the mean of the four.
+// range[c] gives, per component, (lo along c, hi along c, lo other, hi other).
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ R upwind_pick(R f, R dl, R dr) {
+    return f > R(0) ? dl : (f < R(0) ? dr : R(0.5) * (dl + dr));
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) edge_emf_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
+                                                       const WorkItem* __restrict__ work, DevParams prm, int fslot,
+                                                       Box bx, EdgeRanges rg) {
+    const WorkItem w = work[blockIdx.x];
+    const PatchDev P = patches[w.patch];
+    BoxPos bp = box_pos(P, w.a, bx);
+    if (!bp.valid) return;
+    const int g = prm.ghost;
+    const long long V = P.vol;
+    const long long x = sidx(P, bp.i + g, bp.j + g, bp.k + g);
+    const R* fl = pool + P.base + (long long)fslot * V;
+    const R* er = pool + P.base + (long long)F_ER * V;
+    R* ed = pool + P.base + (long long)F_ED * V;
+    const int z[3] = {bp.i, bp.j, bp.k};
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const int a = (c + 1) % 3, b = (c + 2) % 3;
+        bool in = z[c] >= rg.lo_c && z[c] <= P.n[c] + rg.hi_c && z[a] >= rg.lo_o && z[a] <= P.n[a] + rg.hi_o &&
+                  z[b] >= rg.lo_o && z[b] <= P.n[b] + rg.hi_o;
+        if (!in) continue;
+        const long long sa = stride_of(P, a), sb = stride_of(P, b);
+        const R* fa = fl + (long long)(7 * a) * V;  // flux_a rows
+        const R* fb = fl + (long long)(7 * b) * V;
+        const R* E0 = er + (long long)c * V;
+        // flux_a row 5 is B_{a+1} = B_b; flux_b row 6 is B_{b+2} = B_a
+        R Ea_0 = -fa[5 * V + x], Ea_b = -fa[5 * V + x - sb];
+        R Eb_0 = fb[6 * V + x], Eb_a = fb[6 * V + x - sa];
+        R e0 = E0[x], ea = E0[x - sa], eb = E0[x - sb], eab = E0[x - sa - sb];
+        R d1 = upwind_pick(fa[x], ea - Eb_a, e0 - Eb_0);
+        R d2 = upwind_pick(fa[x - sb], Eb_a - eab, Eb_0 - eb);
+        R d3 = upwind_pick(fb[x], eb - Ea_b, e0 - Ea_0);
+        R d4 = upwind_pick(fb[x - sa], Ea_b - eab, Ea_0 - ea);
+        ed[(long long)c * V + x] = R(0.25) * ((Ea_0 - d1) + (Ea_b + d2) + (Eb_0 - d3) + (Eb_a + d4));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Step 4: b^{n+1/2} = b^n - (dt/2) curl E (Stokes form on each face); face b_d
+// computed where z_d in [-2, n+2] and the transverse coords in [-1, n]
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(256) ct_half_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
+                                                      const WorkItem* __restrict__ work, DevParams prm, int cur,
+                                                      const double* __restrict__ dtp, Box bx) {
+    const WorkItem w = work[blockIdx.x];
+    const PatchDev P = patches[w.patch];
+    BoxPos bp = box_pos(P, w.a, bx);
+    if (!bp.valid) return;
+    const int g = prm.ghost;
+    const long long V = P.vol;
+    const long long x = sidx(P, bp.i + g, bp.j + g, bp.k + g);
+    const R* b = pool + P.base + (long long)((cur ? F_ST1 : F_ST0) + 8) * V;
+    const R* ed = pool + P.base + (long long)F_ED * V;
+    R* bh = pool + P.base + (long long)F_BH * V;
+    const R tau = R(0.5 * dtp[0]);
+    const int z[3] = {bp.i, bp.j, bp.k};
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
+        bool in = z[a1] >= -1 && z[a1] <= P.n[a1] && z[a2] >= -1 && z[a2] <= P.n[a2];
+        if (!in) continue;
+        const R* E2 = ed + (long long)a2 * V;
+        const R* E1 = ed + (long long)a1 * V;
+        R curl = (E2[x + stride_of(P, a1)] - E2[x]) / R(prm.dx[a1]) - (E1[x + stride_of(P, a2)] - E1[x]) / R(prm.dx[a2]);
+        bh[(long long)d * V + x] = b[(long long)d * V + x] - tau * curl;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Steps 10-11: conservative update, CT with the Step-9 EMFs, zone field from
+// the face average, FP64 floors.  Writes the other state copy.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(256) final_update_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
+                                                           const WorkItem* __restrict__ work, DevParams prm, int cur,
+                                                           const double* __restrict__ dtp,
+                                                           unsigned long long* __restrict__ nfloor) {
+    const WorkItem w = work[blockIdx.x];
+    const PatchDev P = patches[w.patch];
+    BoxPos bp = box_pos(P, w.a, Box{0, -1});
+    if (!bp.valid) return;
+    const int g = prm.ghost;
+    const long long V = P.vol;
+    const long long x = sidx(P, bp.i + g, bp.j + g, bp.k + g);
+    const R* q = pool + P.base + (long long)(cur ? F_ST1 : F_ST0) * V;
+    const R* b = q + 8 * V;
+    R* qn = pool + P.base + (long long)(cur ? F_ST0 : F_ST1) * V;
+    R* bn = qn + 8 * V;
+    const R* fl = pool + P.base + (long long)F_FL2 * V;
+    const R* ed = pool + P.base + (long long)F_ED * V;
+    const R dt = R(dtp[0]);
+    const int z[3] = {bp.i, bp.j, bp.k};
+    R u[8];
+    // Step 10 on rho, m, E (flux rows 0..4 map to components 0,1,2,3,7)
+#pragma unroll
+    for (int r = 0; r < 5; r++) {
+        const int c = r < 4 ? r : 7;
+        R div = R(0);
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const R* f = fl + (long long)(7 * d + r) * V;
+            div += (f[x + stride_of(P, d)] - f[x]) / R(prm.dx[d]);
+        }
+        u[c] = q[(long long)c * V + x] - dt * div;
+    }
+    // Step 11: CT on the two faces of the zone along each axis
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
+        const long long s1 = stride_of(P, a1), s2 = stride_of(P, a2), sd = stride_of(P, d);
+        const R* E2 = ed + (long long)a2 * V;
+        const R* E1 = ed + (long long)a1 * V;
+        R bl = b[(long long)d * V + x] -
+               dt * ((E2[x + s1] - E2[x]) / R(prm.dx[a1]) - (E1[x + s2] - E1[x]) / R(prm.dx[a2]));
+        const long long xr = x + sd;
+        R br = b[(long long)d * V + xr] -
+               dt * ((E2[xr + s1] - E2[xr]) / R(prm.dx[a1]) - (E1[xr + s2] - E1[xr]) / R(prm.dx[a2]));
+        bn[(long long)d * V + x] = bl;
+        if (z[d] == P.n[d] - 1) bn[(long long)d * V + xr] = br;  // shared right face
+        u[4 + d] = R(0.5) * (bl + br);
+    }
+    if (apply_floor(u, prm)) atomicAdd(nfloor, 1ULL);
+#pragma unroll
+    for (int c = 0; c < 8; c++) qn[(long long)c * V + x] = u[c];
+}
+
+// ---------------------------------------------------------------------------
+// MHDTVD directional sweep (Appendix A; Step 1 when STAGE == 1, Steps 5-7
+// when STAGE == 2).  A block holds W pencils of P zones along D; every thread
+// owns one zone of one pencil and, after a barrier, the face on its left.
+//
+//   phase A  zone state -> primitives (rho, v_par, v_t1, v_t2, B_t1, B_t2, P) in LDS
+//            (STAGE 2 first builds the predictor state q^{n+1/2}_D from q^n,
+//             the transverse Step-1 fluxes and the div-B source, with FP64 floors)
+//   phase B  face s (zones s-1, s): Roe average, eigen-speeds, characteristic
+//            jumps alpha_k, nu_k, g-tilde_k -> LDS
+//   phase C  faces 2 .. P-2: limiter g of both zones, gamma_k, beta_k, the
+//            correction sum_k beta_k R_k, modified flux (7 rows) -> HBM
+//
+// The characteristic algebra is done in the primitive-like variables
+// (rho, v, B_t, P) in which the Roe matrix is the textbook primitive matrix:
+// alpha_k = L_k . (d rho, d v, d B_t, dP + X d rho) and the correction
+// sum_k beta_k R_k is assembled there and mapped to conserved variables once.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+struct FaceEig {
+    R rho, sq, vx, vy, vz, b1, b2, X;
+    R a2, a, cf, cs, alf, als, by, bz, s;
+};
+
+template <typename R, int D, int STAGE>
+__global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
+                                                     const WorkItem* __restrict__ work, DevParams prm, int cur,
+                                                     const double* __restrict__ dtp, int P, int W, int zlo) {
+    extern __shared__ unsigned char smem_raw[];
+    R* sh = reinterpret_cast<R*>(smem_raw);
+    const int nthr = P * W;
+    R* shp = sh;              // 7 x nthr primitives
+    R* shg = sh + 7 * nthr;   // 7 x nthr g-tilde
+
+    constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
+    constexpr int FA = (D == 0) ? 1 : 0;                 // fast transverse axis
+    constexpr int SA = (D == 0) ? 2 : (D == 1 ? 2 : 1);  // slow transverse axis
+
+    const WorkItem wi = work[blockIdx.x];
+    const PatchDev Pt = patches[wi.patch];
+    const int tid = threadIdx.x;
+    int s, w;
+    if (D == 0) {
+        s = tid % P;
+        w = tid / P;
+    } else {
+        w = tid % W;
+        s = tid / W;
+    }
+    const int sstep = (D == 0) ? 1 : W;  // LDS distance between neighbours along the pencil
+    const int fast = wi.a + w;
+    const bool live = (tid < nthr) && (fast <= wi.c);
+    const int g = prm.ghost;
+    int zc[3];
+    zc[D] = zlo + s;
+    zc[FA] = fast;
+    zc[SA] = wi.b;
+    const long long V = Pt.vol;
+    const long long x = live ? sidx(Pt, zc[0] + g, zc[1] + g, zc[2] + g) : 0;
+    const R gam = R(prm.gamma);
+    const R gm1 = gam - R(1);
+    const double dt = dtp[0];
+    const R lam = R(dt / prm.dx[D]);
+    const R* q = pool + Pt.base + (long long)(cur ? F_ST1 : F_ST0) * V;
+
+    // ---------------- phase A: zone primitives ----------------
+    if (live) {
+        R u[8];
+#pragma unroll
+        for (int c = 0; c < 8; c++) u[c] = q[(long long)c * V + x];
+        if (STAGE == 2) {
+            const R hdt = R(0.5 * dt);
+            const R* fl = pool + Pt.base + (long long)F_FL1 * V;
+            const R* f1 = fl + (long long)(7 * A1) * V;
+            const R* f2 = fl + (long long)(7 * A2) * V;
+            const long long s1 = stride_of(Pt, A1), s2 = stride_of(Pt, A2), sd = stride_of(Pt, D);
+            const R i1 = R(1.0 / prm.dx[A1]), i2 = R(1.0 / prm.dx[A2]);
+            // rho, m, E (rows 0..4 -> components 0,1,2,3,7)
+#pragma unroll
+            for (int r = 0; r < 5; r++) {
+                const int c = r < 4 ? r : 7;
+                R div = (f1[(long long)r * V + x + s1] - f1[(long long)r * V + x]) * i1 +
+                        (f2[(long long)r * V + x + s2] - f2[(long long)r * V + x]) * i2;
+                u[c] -= hdt * div;
+            }
+            // B_D: flux_A1 row 6 (B_{A1+2}) and flux_A2 row 5 (B_{A2+1})
+            {
+                R div = (f1[6 * V + x + s1] - f1[6 * V + x]) * i1 + (f2[5 * V + x + s2] - f2[5 * V + x]) * i2;
+                u[4 + D] -= hdt * div;
+            }
+            // B_A1 only from flux_A2 row 6; B_A2 only from flux_A1 row 5
+            u[4 + A1] -= hdt * ((f2[6 * V + x + s2] - f2[6 * V + x]) * i2);
+            u[4 + A2] -= hdt * ((f1[5 * V + x + s1] - f1[5 * V + x]) * i1);
+            // div-B source (Gardiner & Stone 2008 form): momentum B dB_D/dx_D,
+            // B_t v_t minmod(dB_D/dx_D, -dB_t'/dx_t'), energy B_t . S[B_t]
+            const R* b = q + 8 * V;
+            R dB[3];
+            const long long st[3] = {1, (long long)Pt.N[0], (long long)Pt.N[0] * Pt.N[1]};
+#pragma unroll
+            for (int a = 0; a < 3; a++) dB[a] = (b[(long long)a * V + x + st[a]] - b[(long long)a * V + x]) / R(prm.dx[a]);
+            (void)sd;
+            R rho0 = q[x];
+            R v1 = q[(long long)(1 + A1) * V + x] / rho0, v2 = q[(long long)(1 + A2) * V + x] / rho0;
+            R B1 = q[(long long)(4 + A1) * V + x], B2 = q[(long long)(4 + A2) * V + x];
+            R sB1 = v1 * R(minmod2((double)dB[D], -(double)dB[A2]));
+            R sB2 = v2 * R(minmod2((double)dB[D], -(double)dB[A1]));
+#pragma unroll
+            for (int c = 0; c < 3; c++) u[1 + c] += hdt * q[(long long)(4 + c) * V + x] * dB[D];
+            u[4 + A1] += hdt * sB1;
+            u[4 + A2] += hdt * sB2;
+            u[7] += hdt * (B1 * sB1 + B2 * sB2);
+            apply_floor(u, prm);
+        }
+        R rho = u[0];
+        R ir = R(1) / rho;
+        R vpar = u[1 + D] * ir, vt1 = u[1 + A1] * ir, vt2 = u[1 + A2] * ir;
+        R b2 = u[4] * u[4] + u[5] * u[5] + u[6] * u[6];
+        R pr = gm1 * (u[7] - R(0.5) * rho * (vpar * vpar + vt1 * vt1 + vt2 * vt2) - R(0.5) * b2);
+        if (pr < R(prm.p_floor)) pr = R(prm.p_floor);
+        shp[0 * nthr + tid] = rho;
+        shp[1 * nthr + tid] = vpar;
+        shp[2 * nthr + tid] = vt1;
+        shp[3 * nthr + tid] = vt2;
+        shp[4 * nthr + tid] = u[4 + A1];
+        shp[5 * nthr + tid] = u[4 + A2];
+        shp[6 * nthr + tid] = pr;
+    }
+    __syncthreads();
+
+    // ---------------- phase B: face s between zones s-1 and s ----------------
+    FaceEig<R> e;
+    R alpha[7], nu[7];
+    R bf = R(0);
+    const bool face = live && s >= 1;
+    if (face) {
+        const R* bsrc = (STAGE == 1) ? (q + (long long)(8 + D) * V) : (pool + Pt.base + (long long)(F_BH + D) * V);
+        bf = bsrc[x];
+        const int tl = tid - sstep;
+        R rl = shp[tl], vxl = shp[nthr + tl], vyl = shp[2 * nthr + tl], vzl = shp[3 * nthr + tl];
+        R b1l = shp[4 * nthr + tl], b2l = shp[5 * nthr + tl], pl = shp[6 * nthr + tl];
+        R rr = shp[tid], vxr = shp[nthr + tid], vyr = shp[2 * nthr + tid], vzr = shp[3 * nthr + tid];
+        R b1r = shp[4 * nthr + tid], b2r = shp[5 * nthr + tid], prr = shp[6 * nthr + tid];
+
+        const R gg = gam / gm1;
+        R bf2 = bf * bf;
+        R hl = (gg * pl + R(0.5) * rl * (vxl * vxl + vyl * vyl + vzl * vzl) + bf2 + b1l * b1l + b2l * b2l) / rl;
+        R hr = (gg * prr + R(0.5) * rr * (vxr * vxr + vyr * vyr + vzr * vzr) + bf2 + b1r * b1r + b2r * b2r) / rr;
+        R sl = sqrt(rl), sr = sqrt(rr);
+        R isum = R(1) / (sl + sr);
+        e.rho = sl * sr;
+        e.vx = (sl * vxl + sr * vxr) * isum;
+        e.vy = (sl * vyl + sr * vyr) * isum;
+        e.vz = (sl * vzl + sr * vzr) * isum;
+        R h = (sl * hl + sr * hr) * isum;
+        e.b1 = (sr * b1l + sl * b1r) * isum;
+        e.b2 = (sr * b2l + sl * b2r) * isum;
+        R db1 = b1r - b1l, db2 = b2r - b2l;
+        e.X = (db1 * db1 + db2 * db2) * R(0.5) * isum * isum;
+        R v2 = e.vx * e.vx + e.vy * e.vy + e.vz * e.vz;
+        R bt2 = e.b1 * e.b1 + e.b2 * e.b2;
+        R irho = R(1) / e.rho;
+        R a2 = gm1 * (h - R(0.5) * v2 - (bf2 + bt2) * irho) - (gam - R(2)) * e.X;
+        R a2min = gam * R(prm.p_floor) * irho;
+        if (a2 < a2min) a2 = a2min;
+        R ca2 = bf2 * irho, bp2 = bt2 * irho;
+        R dpr = a2 - ca2 - bp2;
+        R dd = sqrt(dpr * dpr + R(4) * a2 * bp2);
+        R cf2 = R(0.5) * (a2 + ca2 + bp2 + dd);
+        R cs2 = a2 * ca2 / cf2;
+        const R tol = R(prm.degen_tol);
+        if (dd <= tol * (a2 + ca2 + bp2)) {
+            e.alf = R(1);
+            e.als = R(0);
+        } else {
+            R af2, as2;
+            if (dpr >= R(0)) {
+                af2 = R(0.5) * (dd + dpr);
+                as2 = a2 * bp2 / af2;
+            } else {
+                as2 = R(0.5) * (dd - dpr);
+                af2 = a2 * bp2 / as2;
+            }
+            e.alf = sqrt(af2 / dd);
+            e.als = sqrt(as2 / dd);
+        }
+        if (bt2 <= tol * tol * (bf2 + bt2)) {
+            e.by = R(0.70710678118654752440);
+            e.bz = R(0.70710678118654752440);
+        } else {
+            R ib = R(1) / sqrt(bt2);
+            e.by = e.b1 * ib;
+            e.bz = e.b2 * ib;
+        }
+        e.s = bf >= R(0) ? R(1) : R(-1);
+        e.sq = sqrt(e.rho);
+        e.a2 = a2;
+        e.a = sqrt(a2);
+        e.cf = sqrt(cf2);
+        e.cs = sqrt(cs2);
+        R ca = sqrt(ca2);
+
+        // characteristic jumps: alpha_k = L_k . (d rho, d v, d B_t, dP + X d rho)
+        R drho = rr - rl;
+        R dvx = vxr - vxl, dvy = vyr - vyl, dvz = vzr - vzl;
+        R dp = (prr - pl) + e.X * drho;
+        R dvpar = e.by * dvy + e.bz * dvz, dvper = -e.bz * dvy + e.by * dvz;
+        R dbpar = e.by * db1 + e.bz * db2, dbper = -e.bz * db1 + e.by * db2;
+        R i2a2 = R(0.5) / a2;
+        R ipa = R(1) / (R(2) * e.sq * e.a);
+        R pterm = dp * irho * i2a2;
+        R Ef = e.alf * pterm + e.als * dbpar * ipa;
+        R Of = (e.alf * e.cf * dvx - e.als * e.cs * e.s * dvpar) * i2a2;
+        R Es = e.als * pterm - e.alf * dbpar * ipa;
+        R Os = (e.als * e.cs * dvx + e.alf * e.cf * e.s * dvpar) * i2a2;
+        R Ea = R(0.5) * dvper;
+        R Oa = -e.s * dbper / (R(2) * e.sq);
+        alpha[0] = Ef - Of;
+        alpha[6] = Ef + Of;
+        alpha[2] = Es - Os;
+        alpha[4] = Es + Os;
+        alpha[1] = Ea - Oa;
+        alpha[5] = Ea + Oa;
+        alpha[3] = drho - dp / a2;
+        R ev[7] = {e.vx - e.cf, e.vx - ca, e.vx - e.cs, e.vx, e.vx + e.cs, e.vx + ca, e.vx + e.cf};
+#pragma unroll
+        for (int k = 0; k < 7; k++) {
+            nu[k] = lam * ev[k];
+            R gt = R(0.5) * (qvisc(nu[k], R(prm.eps[k])) - nu[k] * nu[k]) * alpha[k];
+            shg[k * nthr + tid] = gt;
+        }
+    }
+    __syncthreads();
+
+    // ---------------- phase C: modified flux at faces 2 .. P-2 ----------------
+    if (face && s >= 2 && s <= P - 2) {
+        const R beta_l = R(prm.limiter_beta);
+        R bet[7];
+#pragma unroll
+        for (int k = 0; k < 7; k++) {
+            R gm = shg[k * nthr + tid - sstep];
+            R g0 = shg[k * nthr + tid];
+            R gp = shg[k * nthr + tid + sstep];
+            R gL = sweby(g0, gm, beta_l);  // zone s-1: faces s-1 (left), s (right)
+            R gR = sweby(gp, g0, beta_l);  // zone s: faces s, s+1
+            R gk = (alpha[k] != R(0)) ? (gR - gL) / alpha[k] : R(0);
+            bet[k] = qvisc(nu[k] + gk, R(prm.eps[k])) * alpha[k] - (gL + gR);
+        }
+        // correction sum_k beta_k R_k in (rho, v, B_t, P), then mapped to conserved
+        R bfp = bet[6] + bet[0], bfm = bet[6] - bet[0];
+        R bsp = bet[4] + bet[2], bsm = bet[4] - bet[2];
+        R bap = bet[5] + bet[1], bam = bet[5] - bet[1];
+        R wrho = e.rho * (e.alf * bfp + e.als * bsp) + bet[3];
+        R wvx = e.alf * e.cf * bfm + e.als * e.cs * bsm;
+        R wvpar = e.s * (-e.als * e.cs * bfm + e.alf * e.cf * bsm);
+        R wvy = wvpar * e.by - bap * e.bz;
+        R wvz = wvpar * e.bz + bap * e.by;
+        R wbpar = e.sq * e.a * (e.als * bfp - e.alf * bsp);
+        R wb1 = wbpar * e.by + e.s * e.sq * bam * e.bz;
+        R wb2 = wbpar * e.bz - e.s * e.sq * bam * e.by;
+        R wp = e.rho * e.a2 * (e.alf * bfp + e.als * bsp);
+        R v2 = e.vx * e.vx + e.vy * e.vy + e.vz * e.vz;
+        R c0 = wrho;
+        R c1 = e.vx * wrho + e.rho * wvx;
+        R c2 = e.vy * wrho + e.rho * wvy;
+        R c3 = e.vz * wrho + e.rho * wvz;
+        R c7 = (R(0.5) * v2 + (gam - R(2)) * e.X / gm1) * wrho + e.rho * (e.vx * wvx + e.vy * wvy + e.vz * wvz) +
+               e.b1 * wb1 + e.b2 * wb2 + wp / gm1;
+        // physical fluxes of the two rebuilt face states
+        R F[2][7];
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            const int t = side ? tid : tid - sstep;
+            R r = shp[t], vx = shp[nthr + t], vy = shp[2 * nthr + t], vz = shp[3 * nthr + t];
+            R b1 = shp[4 * nthr + t], b2 = shp[5 * nthr + t], pr = shp[6 * nthr + t];
+            R bb = bf * bf + b1 * b1 + b2 * b2;
+            R pt = pr + R(0.5) * bb;
+            R ept = gam / gm1 * pr + R(0.5) * r * (vx * vx + vy * vy + vz * vz) + bb;  // E + P*
+            R mx = r * vx;
+            F[side][0] = mx;
+            F[side][1] = mx * vx + pt - bf * bf;
+            F[side][2] = mx * vy - bf * b1;
+            F[side][3] = mx * vz - bf * b2;
+            F[side][4] = ept * vx - bf * (bf * vx + b1 * vy + b2 * vz);
+            F[side][5] = b1 * vx - bf * vy;
+            F[side][6] = b2 * vx - bf * vz;
+        }
+        const R il = R(0.5) / lam;
+        R out[7];
+        out[0] = R(0.5) * (F[0][0] + F[1][0]) - il * c0;
+        out[1] = R(0.5) * (F[0][1] + F[1][1]) - il * c1;
+        out[2] = R(0.5) * (F[0][2] + F[1][2]) - il * c2;
+        out[3] = R(0.5) * (F[0][3] + F[1][3]) - il * c3;
+        out[4] = R(0.5) * (F[0][4] + F[1][4]) - il * c7;
+        out[5] = R(0.5) * (F[0][5] + F[1][5]) - il * wb1;
+        out[6] = R(0.5) * (F[0][6] + F[1][6]) - il * wb2;
+        R* fo = pool + Pt.base + (long long)((STAGE == 1 ? F_FL1 : F_FL2) + 7 * D) * V;
+        // frame -> lab rows: m_par -> m_D, m_t1 -> m_A1, m_t2 -> m_A2
+        fo[x] = out[0];
+        fo[(long long)(1 + D) * V + x] = out[1];
+        fo[(long long)(1 + A1) * V + x] = out[2];
+        fo[(long long)(1 + A2) * V + x] = out[3];
+        fo[4 * V + x] = out[4];
+        fo[5 * V + x] = out[5];
+        fo[6 * V + x] = out[6];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 diagnostics: per-block partial sums of q * dV (8), |B|^2 and the block
+// max of |div b|; reduced on the host in a fixed order
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(256) diag_kernel(const R* __restrict__ pool, const PatchDev* __restrict__ patches,
+                                                   const WorkItem* __restrict__ work, DevParams prm, int cur,
+                                                   double* __restrict__ partial) {
+    __shared__ double red[10][256];
+    const WorkItem w = work[blockIdx.x];
+    const PatchDev P = patches[w.patch];
+    BoxPos bp = box_pos(P, w.a, Box{0, -1});
+    double v[10];
+#pragma unroll
+    for (int c = 0; c < 10; c++) v[c] = 0.0;
+    if (bp.valid) {
+        const int g = prm.ghost;
+        const long long V = P.vol;
+        long long x = sidx(P, bp.i + g, bp.j + g, bp.k + g);
+        const R* q = pool + P.base + (long long)(cur ? F_ST1 : F_ST0) * V;
+        const R* b = q + 8 * V;
+        double dV = prm.dx[0] * prm.dx[1] * prm.dx[2];
+        for (int c = 0; c < 8; c++) v[c] = (double)q[(long long)c * V + x] * dV;
+        v[8] = (double)q[4 * V + x] * q[4 * V + x] + (double)q[5 * V + x] * q[5 * V + x] + (double)q[6 * V + x] * q[6 * V + x];
+        double div = 0.0;
+        for (int d = 0; d < 3; d++) div += ((double)b[(long long)d * V + x + stride_of(P, d)] - (double)b[(long long)d * V + x]) / prm.dx[d];
+        v[9] = fabs(div);
+    }
+    for (int c = 0; c < 10; c++) red[c][threadIdx.x] = v[c];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            for (int c = 0; c < 9; c++) red[c][threadIdx.x] += red[c][threadIdx.x + h];
+            red[9][threadIdx.x] = fmax(red[9][threadIdx.x], red[9][threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 10) partial[(long long)blockIdx.x * 10 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// ---------------------------------------------------------------------------
+// host-side launch wrappers
+// ---------------------------------------------------------------------------
+
+template <typename R>
+hipError_t launch_fill(void* pool, const PatchDev* pt, const FillRegion* regs, int nreg, int cur, hipStream_t st) {
+    if (nreg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_ghosts_kernel<R>, dim3(nreg), dim3(256), 0, st, (R*)pool, pt, regs, cur);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_dt(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, int cur,
+                     unsigned long long* smax, double* dt, hipStream_t st) {
+    if (nblk > 0) hipLaunchKernelGGL(dt_reduce_kernel<R>, dim3(nblk), dim3(256), 0, st, (const R*)pool, pt, wk, prm, cur, smax);
+    hipLaunchKernelGGL(dt_finalize_kernel, dim3(1), dim3(1), 0, st, smax, dt, prm.cfl);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_emf_ref(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, int cur, Box bx,
+                          hipStream_t st) {
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(emf_ref_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, prm, cur, bx);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_emf_half(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, int cur,
+                           const double* dt, Box bx, hipStream_t st) {
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(emf_half_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, prm, cur, dt, bx);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_edge(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, int fslot, Box bx,
+                       EdgeRanges rg, hipStream_t st) {
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(edge_emf_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, prm, fslot, bx, rg);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_ct_half(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, int cur,
+                          const double* dt, Box bx, hipStream_t st) {
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ct_half_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, prm, cur, dt, bx);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_final(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, int cur,
+                        const double* dt, unsigned long long* nfl, hipStream_t st) {
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(final_update_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, prm, cur, dt, nfl);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_sweep(int d, int stage, void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm,
+                        int cur, const double* dt, int P, int W, int zlo, hipStream_t st) {
+    if (nblk <= 0) return hipSuccess;
+    size_t shmem = sizeof(R) * 14 * (size_t)P * W;
+    dim3 blk(P * W);
+#define WMB_SW(DD, SS)                                                                                            \
+    hipLaunchKernelGGL((sweep_kernel<R, DD, SS>), dim3(nblk), blk, shmem, st, (R*)pool, pt, wk, prm, cur, dt, P, W, \
+                       zlo)
+    if (stage == 1) {
+        if (d == 0) WMB_SW(0, 1);
+        else if (d == 1) WMB_SW(1, 1);
+        else WMB_SW(2, 1);
+    } else {
+        if (d == 0) WMB_SW(0, 2);
+        else if (d == 1) WMB_SW(1, 2);
+        else WMB_SW(2, 2);
+    }
+#undef WMB_SW
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_diag(const void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, int cur,
+                       double* partial, hipStream_t st) {
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(diag_kernel<R>, dim3(nblk), dim3(256), 0, st, (const R*)pool, pt, wk, prm, cur, partial);
+    return hipGetLastError();
+}
+
+// explicit instantiations
+#define WMB_INST(R)                                                                                                      \
+    template hipError_t launch_fill<R>(void*, const PatchDev*, const FillRegion*, int, int, hipStream_t);               \
+    template hipError_t launch_dt<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,                \
+                                     unsigned long long*, double*, hipStream_t);                                         \
+    template hipError_t launch_emf_ref<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, Box,      \
+                                          hipStream_t);                                                                  \
+    template hipError_t launch_emf_half<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,          \
+                                           const double*, Box, hipStream_t);                                             \
+    template hipError_t launch_edge<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, Box,         \
+                                       EdgeRanges, hipStream_t);                                                         \
+    template hipError_t launch_ct_half<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,           \
+                                          const double*, Box, hipStream_t);                                              \
+    template hipError_t launch_final<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,             \
+                                        const double*, unsigned long long*, hipStream_t);                                \
+    template hipError_t launch_sweep<R>(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,   \
+                                        const double*, int, int, int, hipStream_t);                                      \
+    template hipError_t launch_diag<R>(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,        \
+                                       double*, hipStream_t);
+WMB_INST(float)
+WMB_INST(double)
+#undef WMB_INST
+
+}  // namespace wmb

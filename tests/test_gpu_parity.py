@@ -1,0 +1,347 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Bars: ghost exchange bitwise; FP64 path within 1e-11 of the oracle's scale
+after several steps (FMA contraction and the algebraically equivalent
+characteristic projection are the only differences); FP32 path within the
+spec tolerance (relative L1 <= 1e-5 on rho and E after 10 steps,
+normalised div b <= 1e-6); graph replay, determinism and restart bitwise.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1701_07452_amd import inputs as I
+from tests._helpers import oracle_gather, oracle_sim
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wmb():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1701_07452_amd import build
+    from paper_1701_07452_amd import wmb as W
+
+    if build.is_stale():
+        raise RuntimeError("libwmb.so is older than its sources: run __graft_entry__.build() first")
+    W.load_library()
+    return W
+
+
+def gpu_sim(W, G, q, b, prec, **kw):
+    print("gpu_sim: %d patches, prec=%s" % (G.npatch, "fp32" if prec else "fp64"), flush=True)
+    return W.sim_from_grid(G, q, b, precision=prec, **kw)
+
+
+def as_f32(a):
+    return a.astype(np.float32).astype(np.float64)
+
+
+def rel_max(a, ref):
+    return float(np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+CASES = {
+    "uniform8": lambda: (I.uniform_grid(16, 8), I.random_smooth((16, 16, 16), 11)),
+    "uneven": lambda: (I.patch_grid([8, 12], [8, 16], [10]), I.random_smooth((10, 24, 20), 12)),
+    "single": lambda: (I.uniform_grid((12, 10, 9), (12, 10, 9)), I.random_smooth((9, 10, 12), 13)),
+}
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("case", ["uniform8", "uneven"])
+def test_ghost_fill_bitwise(wmb, prec, case):
+    G, (q, b) = CASES[case]()
+    N = G.shape
+    dx = (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
+    if prec == 1:
+        q, b = as_f32(q), as_f32(b)
+    sim = gpu_sim(wmb, G, q, b, prec, dx=dx)
+    orc = oracle_sim(G, q, b, dx=dx)
+    sim.fill_ghosts()
+    orc.fill_ghosts()
+    for ip in range(G.npatch):
+        qg, bg = sim.get_stored(ip)
+        qo, bo = orc.get_stored(ip)
+        assert np.array_equal(qg, qo) and np.array_equal(bg, bo), ip
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_dt_parity(wmb, prec):
+    G, (q, b) = CASES["uneven"]()
+    dx = (0.05, 0.04, 0.03)
+    if prec == 1:
+        q, b = as_f32(q), as_f32(b)
+    sim = gpu_sim(wmb, G, q, b, prec, dx=dx)
+    orc = oracle_sim(G, q, b, dx=dx)
+    d1, d2 = sim.compute_dt(), orc.compute_dt()
+    assert abs(d1 - d2) <= 1e-13 * d2, (d1, d2)
+    sim.close()
+
+
+def _interior_ranges(n, lo, hi, g):
+    return slice(g + lo, g + n + hi + 1)
+
+
+@pytest.mark.parametrize("case", ["uniform8", "single"])
+def test_stage_parity_fp64(wmb, case):
+    """Step-1 fluxes, b^{n+1/2}, Step-6/7 fluxes and Step-9 edges of one step,
+    on exactly the ranges the step needs."""
+    G, (q, b) = CASES[case]()
+    N = G.shape
+    dx = (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
+    sim = gpu_sim(wmb, G, q, b, 0, dx=dx)
+    orc = oracle_sim(G, q, b, dx=dx)
+    orc.keep_stages(True)
+    sim.fill_ghosts()
+    dt = sim.compute_dt()
+    sim.advance(0.0)
+    orc.fill_ghosts()
+    orc.advance(dt)
+    g = 5
+    for ip in range(min(G.npatch, 3)):
+        n = G.descs[ip][0]  # (nx, ny, nz)
+        nz_, ny_, nx_ = n[2], n[1], n[0]
+        for stage, (flo, fhi, tlo, thi) in [(1, (-2, 2, -3, 2)), (5, (-1, 1, -1, 0))]:
+            fg, fo = sim.debug_stage(ip, stage), orc.stage(ip, stage)
+            for d in range(3):
+                sl = [None, None, None]  # array axes (z, y, x) <- lab axes (2,1,0)
+                for a in range(3):
+                    lo, hi = (flo, fhi) if a == d else (tlo, thi)
+                    sl[2 - a] = slice(g + lo, g + n[a] + hi + 1)
+                A, B = fg[d][(slice(None),) + tuple(sl)], fo[d][(slice(None),) + tuple(sl)]
+                for c in range(8):
+                    if c == 4 + d:
+                        continue
+                    assert rel_max(A[c], B[c]) < 1e-12, (stage, d, c, rel_max(A[c], B[c]))
+        # b^{n+1/2}: along d [-2, n+2], transverse [-1, n]
+        bh_g, bh_o = sim.debug_stage(ip, 3), orc.stage(ip, 3)
+        for d in range(3):
+            sl = [None] * 3
+            for a in range(3):
+                lo, hi = (-2, 2) if a == d else (-1, 0)
+                sl[2 - a] = slice(g + lo, g + n[a] + hi + 1)
+            assert rel_max(bh_g[d][tuple(sl)], bh_o[d][tuple(sl)]) < 1e-12
+        # Step-9 edges: along c [0, n-1], others [0, n]
+        eg, eo = sim.debug_stage(ip, 6), orc.stage(ip, 6)
+        for c in range(3):
+            sl = [None] * 3
+            for a in range(3):
+                lo, hi = (0, -1) if a == c else (0, 0)
+                sl[2 - a] = slice(g + lo, g + n[a] + hi + 1)
+            A, B = eg[c][tuple(sl)], eo[c][tuple(sl)]
+            assert np.abs(A - B).max() <= 1e-12 * max(np.abs(B).max(), 1e-3)
+    sim.close()
+
+
+@pytest.mark.parametrize("case", ["uniform8", "uneven", "single"])
+def test_steps_fp64(wmb, case):
+    G, (q, b) = CASES[case]()
+    N = G.shape
+    dx = (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
+    sim = gpu_sim(wmb, G, q, b, 0, dx=dx)
+    orc = oracle_sim(G, q, b, dx=dx)
+    for _ in range(8):
+        sim.fill_ghosts()
+        dt = sim.compute_dt()
+        sim.advance(0.0)
+        orc.fill_ghosts()
+        assert abs(orc.compute_dt() - dt) <= 1e-12 * dt
+        orc.advance(dt)
+    qg, bg = I.gather(G, [sim.get_state(i) for i in range(G.npatch)])
+    qo, bo = oracle_gather(G, orc)
+    for c in range(8):
+        assert rel_max(qg[c], qo[c]) < 1e-11, (c, rel_max(qg[c], qo[c]))
+    for c in range(3):
+        assert rel_max(bg[c], bo[c]) < 1e-11
+    sim.close()
+
+
+def _rel_l1(a, ref):
+    return float(np.abs(a - ref).sum() / np.abs(ref).sum())
+
+
+@pytest.mark.parametrize("setup", ["fastwave", "turb"])
+def test_steps_fp32_tolerance(wmb, setup):
+    """FP32 sweeps/CT with FP64 dt and floors against the FP64 oracle after 10
+    steps: relative L1 <= 1e-5 on rho and E, normalised div b <= 1e-6."""
+    if setup == "fastwave":
+        N = 32
+        q, b, _ = I.fast_wave_diagonal(N, amp=1e-3)
+        G = I.uniform_grid(N, 16)
+    else:
+        N = 32
+        q, b = I.turbulence(N, seed=7)
+        G = I.uniform_grid(N, 16)
+    dx = (1.0 / N,) * 3
+    q32, b32 = as_f32(q), as_f32(b)
+    sim = gpu_sim(wmb, G, q32, b32, 1, dx=dx)
+    orc = oracle_sim(G, q32, b32, dx=dx)
+    for _ in range(10):
+        sim.fill_ghosts()
+        dt = sim.compute_dt()
+        sim.advance(0.0)
+        orc.fill_ghosts()
+        orc.advance(dt)
+    qg, bg = I.gather(G, [sim.get_state(i) for i in range(G.npatch)])
+    qo, bo = oracle_gather(G, orc)
+    e_rho, e_e = _rel_l1(qg[0], qo[0]), _rel_l1(qg[7], qo[7])
+    _, dn, dr, nfl = sim.diagnostics()
+    print("fp32 %s: relL1 rho %.2e E %.2e divb_norm %.2e raw %.2e" % (setup, e_rho, e_e, dn, dr))
+    assert e_rho <= 1e-5 and e_e <= 1e-5
+    assert dn <= 1e-6
+    assert nfl == 0
+    sim.close()
+
+
+def test_run_steps_graph_equals_eager_and_determinism(wmb):
+    G, (q, b) = CASES["uneven"]()
+    N = G.shape
+    dx = (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
+    outs = []
+    for mode in ("graph", "eager", "graph"):
+        sim = gpu_sim(wmb, G, q, b, 1, dx=dx)
+        if mode == "graph":
+            sim.run_steps(3)
+            sim.run_steps(2)
+        else:
+            for _ in range(5):
+                sim.fill_ghosts()
+                sim.compute_dt(fetch=False)
+                sim.advance(0.0)
+        outs.append(I.gather(G, [sim.get_state(i) for i in range(G.npatch)]))
+        sim.close()
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
+def test_restart_bitwise(wmb):
+    G, (q, b) = CASES["uniform8"]()
+    dx = (1.0 / 16,) * 3
+    a = gpu_sim(wmb, G, q, b, 1, dx=dx)
+    a.run_steps(6)
+    qa, ba = I.gather(G, [a.get_state(i) for i in range(G.npatch)])
+    c = gpu_sim(wmb, G, q, b, 1, dx=dx)
+    c.run_steps(3)
+    mid = I.gather(G, [c.get_state(i) for i in range(G.npatch)])
+    d = gpu_sim(wmb, G, *mid, 1, dx=dx)
+    d.run_steps(3)
+    qd, bd = I.gather(G, [d.get_state(i) for i in range(G.npatch)])
+    assert np.array_equal(qa, qd) and np.array_equal(ba, bd)
+    for s in (a, c, d):
+        s.close()
+
+
+def test_device_conservation_fp64(wmb):
+    G, (q, b) = CASES["uniform8"]()
+    dx = (1.0 / 16,) * 3
+    sim = gpu_sim(wmb, G, q, b, 0, dx=dx)
+    sim.fill_ghosts()
+    tot0, dn0, _, _ = sim.diagnostics()
+    sim.run_steps(20)
+    tot, dn, _, nfl = sim.diagnostics()
+    scale = np.maximum(np.abs(tot0), 1e-3)
+    assert np.all(np.abs(tot - tot0) / scale < 1e-13)
+    assert dn < 1e-12 and nfl == 0
+    sim.close()
+
+
+def test_error_codes(wmb):
+    W = wmb
+    G, (q, b) = CASES["uniform8"]()
+    dx = (1.0 / 16,) * 3
+    sim = gpu_sim(W, G, q, b, 1, dx=dx)
+    bad = q[:, :8, :8, :8].copy()
+    bad[0, 0, 0, 0] = -1.0
+    with pytest.raises(W.WmbError) as e:
+        sim.set_state(0, bad, b[:, :8, :8, :8])
+    assert e.value.code == W.WMB_ESTATE
+    bad = q[:, :8, :8, :8].copy()
+    bad[7, 1, 1, 1] = np.nan
+    with pytest.raises(W.WmbError) as e:
+        sim.set_state(0, bad, b[:, :8, :8, :8])
+    assert e.value.code == W.WMB_ESTATE
+    sim.fill_ghosts()
+    dt = sim.compute_dt()
+    with pytest.raises(W.WmbError) as e:
+        sim.advance(dt * 1.01)
+    assert e.value.code == W.WMB_ECFL
+    sim.advance(dt * 0.5)  # below the limit is fine
+    sim.close()
+    # inconsistent neighbour table
+    descs = [(n, list(nbr)) for n, nbr in G.descs]
+    descs[0][1][14] = 0  # +x neighbour of patch 0 made itself: table no longer symmetric
+    with pytest.raises(W.WmbError) as e:
+        W.Sim(W.make_params(dx=dx), descs)
+    assert e.value.code == W.WMB_EINVAL
+    # pool too small
+    import torch
+
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(W.WmbError) as e:
+        W.Sim(W.make_params(dx=dx), G.descs, pool=small)
+    assert e.value.code == W.WMB_ESIZE
+
+
+def _sampled_full_size(W, G, q, b, prec, samples, tol_max, tol_l1, nsteps_before=1, dx=None):
+    """Full-size batch in the benchmark's launch configuration (graph replay);
+    sampled patches are recomputed one by one by the oracle from the GPU's
+    ghost-filled stored box and the GPU's dt."""
+    N = G.shape
+    dx = dx or (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
+    sim = gpu_sim(W, G, q, b, prec, dx=dx)
+    sim.run_steps(nsteps_before)
+    sim.fill_ghosts()
+    stored = {ip: sim.get_stored(ip) for ip in samples}
+    dt = sim.compute_dt()
+    sim.run_steps(1)  # fill + dt + step, as timed
+    from oracle import OracleSim, default_params
+
+    worst = 0.0
+    for ip in samples:
+        n, _ = G.descs[ip]
+        orc = OracleSim(default_params(dx=dx), [(n, [0] * 27)])
+        orc.set_stored(0, *stored[ip])
+        orc.advance(dt)
+        qo, bo = orc.get_state(0)
+        qg, bg = sim.get_state(ip)
+        for c in range(8):
+            m = rel_max(qg[c], qo[c])
+            worst = max(worst, m)
+            assert m <= tol_max, (ip, c, m)
+        assert _rel_l1(qg[0], qo[0]) <= tol_l1 and _rel_l1(qg[7], qo[7]) <= tol_l1
+        for c in range(3):
+            assert rel_max(bg[c], bo[c]) <= tol_max
+        orc.close()
+    sim.close()
+    return worst
+
+
+def test_full_size_turbulence_256_fp32_sampled(wmb):
+    """256^3 as 512 patches of 32^3 (the benchmark workload), FP32."""
+    q, b = I.turbulence(256)
+    G = I.uniform_grid(256, 32)
+    w = _sampled_full_size(wmb, G, q, b, 1, [0, 137, 511], 2e-5, 1e-6)
+    print("256^3 fp32 sampled worst rel max %.2e" % w)
+
+
+def test_full_size_turbulence_256_fp64_sampled(wmb):
+    q, b = I.turbulence(256)
+    G = I.uniform_grid(256, 32)
+    w = _sampled_full_size(wmb, G, q, b, 0, [5, 300], 1e-12, 1e-13)
+    print("256^3 fp64 sampled worst rel max %.2e" % w)
+
+
+def test_full_size_uneven_400_fp32_sampled(wmb):
+    """Uneven batch: 400 patches with edges from {16,24,32,48,64}, FP32."""
+    G = I.uneven_grid()
+    Nz, Ny, Nx = G.shape
+    q, b = I.turbulence(None, seed=170107454, shape=G.shape, box=(Nx / 256, Ny / 256, Nz / 256))
+    sizes = [np.prod(n) for n, _ in G.descs]
+    samples = [int(np.argmax(sizes)), int(np.argmin(sizes)), 123]
+    w = _sampled_full_size(wmb, G, q, b, 1, samples, 2e-5, 1e-6, dx=(1 / 256,) * 3)
+    print("uneven fp32 sampled worst rel max %.2e" % w)
