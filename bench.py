@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Benchmark: zone-updates/s of the patch MHD update on one MI355X.
+
+Workload: 3D periodic 256^3 box as 512 patches of 32^3 (ghost width 4, the
+stencil minimum), rho = 1, P = 1, B = (0.1, 0, 0), seeded Gaussian random
+velocity with a k^-5/3 spectrum at rms Mach 1, gamma = 5/3, CFL 0.4.
+One step = ghost exchange + FP64 CFL reduction + the full CTU+CT MHDTVD
+update (Steps 1-11) of all patches, replayed from a captured HIP graph, with
+the state resident in HBM.  The headline value is the FP32 batch (FP32 sweeps
+and CT, FP64 dt and floors); the FP64 batch is reported beside it.
+
+Prints ONE JSON line.  --gpus > 1 is not supported (one GPU per process; the
+multi-GPU design is documented, not built).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "zone-updates/sec on 1 MI355X (FP32 batched vs FP64 plain) + % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# algorithmic bytes per launch of each kernel class (unique words each launch
+# must read or write at least once, times the word size)
+# ---------------------------------------------------------------------------
+
+def alg_bytes(kclass, n, g, es, npatch):
+    """n: interior edge, g: ghost width, es: bytes per word (uniform patches)."""
+    def box(lo, hi):
+        return (n + hi - lo + 1) ** 3
+
+    if kclass == "fill":
+        per = 22 * ((n + 2 * g) ** 3 - n ** 3)          # 11 words read + 11 written per ghost zone
+    elif kclass == "dt":
+        per = 8 * n ** 3
+    elif kclass == "emf_ref":
+        per = 10 * box(-3, 2)                            # rho, m, B in; 3 out
+    elif kclass.startswith("sweep1"):
+        T, P = n + 6, n + 8
+        per = 9 * P * T * T + 7 * (P - 3) * T * T        # q + b_par in; 7 flux rows out
+    elif kclass.startswith("sweep2"):
+        T, P = n + 2, n + 6
+        per = (8 + 2 * 7 + 3 + 1) * P * T * T + 7 * (P - 3) * T * T  # q, 2 transverse fluxes, b, b^{n+1/2}; flux out
+    elif kclass in ("edge1", "edge2"):
+        lo, hi = (-2, 2) if kclass == "edge1" else (0, 0)
+        per = (9 + 3 + 3) * box(lo, hi)                  # 3 flux rows x 3 dirs + E^r in; 3 edges out
+    elif kclass == "ct_half":
+        per = 9 * box(-2, 2)
+    elif kclass == "emf_half":
+        per = (4 + 12 + 3 + 3) * box(-1, 0)
+    elif kclass == "final":
+        per = (8 + 15 + 3 + 3 + 11) * n ** 3
+    else:
+        raise KeyError(kclass)
+    return per * es * npatch
+
+
+def cpu_baseline(q, b, G, dx, ghost, budget_s=12.0):
+    """The FP64 oracle as it stands, timed on this host's cores on a bounded
+    sample: a 2x2xk block of the workload's 32^3 patches (periodic sample box),
+    one warm-up step then timed steps until about budget_s seconds."""
+    import numpy as np
+
+    from oracle import OracleSim, default_params
+    from paper_1701_07452_amd import inputs as I
+
+    nblk = int(os.environ.get("WMB_CPU_SAMPLE_PATCHES", "16"))
+    kz = max(1, nblk // 4)
+    sub = I.uniform_grid((64, 64, 32 * kz), 32)
+    qs = np.ascontiguousarray(q[:, :32 * kz, :64, :64])
+    bs = np.ascontiguousarray(b[:, :32 * kz, :64, :64])
+    orc = OracleSim(default_params(dx=dx, ghost=ghost), sub.descs)
+    for ip, (qp, bp) in enumerate(I.split(sub, qs, bs)):
+        orc.set_state(ip, qp, bp)
+    orc.run_steps(1)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        orc.run_steps(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or steps >= 50:
+            break
+    zones = sub.zones()
+    return {
+        "value": zones * steps / el,
+        "unit": "zone-updates/s",
+        "cores": orc.num_threads(),
+        "kind": "oracle",
+        "sample": "%d patches of 32^3 (%d zones) cut from the workload, periodic sample box, FP64, %d steps in %.1f s"
+                  % (sub.npatch, zones, steps, el),
+    }
+
+
+def run_precision(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps):
+    import torch
+
+    from paper_1701_07452_amd import inputs as I
+
+    stream = torch.cuda.Stream()
+    sim = W.Sim(W.make_params(dx=dx, precision=prec, ghost=ghost), G.descs, origins=G.origin, stream=stream)
+    for ip, (qp, bp) in enumerate(I.split(G, q, b)):
+        sim.set_state(ip, qp, bp)
+    sim.run_steps(max(warmup, 1))
+    stream.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sim.run_steps(steps)
+    ev1.record(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    # per-kernel durations: the same launches, HIP events after every kernel class
+    kern = None
+    for _ in range(prof_steps):
+        k = sim.profile_step()
+        kern = {c: kern[c] + k[c] for c in k} if kern else k
+    if kern:
+        kern = {c: v / prof_steps for c, v in kern.items()}
+    tot, dn, dr, nfl = sim.diagnostics()
+    sim.close()
+    return ms, wall, kern, {"max_divb_norm": dn, "max_divb_raw": dr, "floors": nfl}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--ghost", type=int, default=4)
+    ap.add_argument("--prof-steps", type=int, default=3)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(the multi-GPU sharding is a documented design, not built)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1701_07452_amd import inputs as I
+    from paper_1701_07452_amd import wmb as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    W.load_library()
+
+    N, n, g = 256, 32, args.ghost
+    dx = (1.0 / N,) * 3
+    log("bench: building the 256^3 turbulence state")
+    q, b = I.turbulence(N)
+    G = I.uniform_grid(N, n)
+    zones = G.zones()
+
+    log("bench: FP32 batch, %d warm-up + %d timed steps" % (args.warmup, args.steps))
+    ms32, wall32, kern32, diag32 = run_precision(W, G, q, b, dx, W.WMB_FP32, g, args.steps, args.warmup, args.prof_steps)
+    value = zones * args.steps / (ms32 / 1e3)
+    log("bench: FP32 %.3f ms/step, %.3e zone-updates/s" % (ms32 / args.steps, value))
+    fp64 = None
+    if not args.no_fp64:
+        log("bench: FP64 batch")
+        ms64, wall64, kern64, diag64 = run_precision(W, G, q, b, dx, W.WMB_FP64, g, args.steps, args.warmup,
+                                                     args.prof_steps)
+        fp64 = {"value": zones * args.steps / (ms64 / 1e3), "ms_per_step": ms64 / args.steps,
+                "kernels_ms": kern64, **diag64}
+        log("bench: FP64 %.3f ms/step" % (ms64 / args.steps))
+
+    # roofline of the dominant kernel class (FP32 batch)
+    dom = max(kern32, key=kern32.get)
+    per_launch = alg_bytes(dom, n, g, 4, G.npatch)
+    achieved = per_launch / (kern32[dom] * 1e-3) / 1e9
+    step_bytes = sum(alg_bytes(k, n, g, 4, G.npatch) for k in kern32)
+    roof = {
+        "kernel": dom,
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "alg_bytes_per_launch": per_launch,
+        "avg_launch_ms": kern32[dom],
+        "step_alg_bytes": step_bytes,
+        "step_alg_frac": round(step_bytes / (ms32 / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+    }
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: CPU baseline (oracle)")
+        cpu = cpu_baseline(q, b, G, dx, g)
+        log("bench: CPU %.3e zone-updates/s on %d threads" % (cpu["value"], cpu["cores"]))
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "zone-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "turbulence 256^3 as 512 patches of 32^3, ghost 4, FP32 sweeps+CT, FP64 dt/floors, 20-step run",
+            "zones": zones, "patches": G.npatch, "patch_edge": n, "ghost": g, "gamma": 5.0 / 3.0, "cfl": 0.4,
+            "rms_mach": 1.0, "B0": [0.1, 0.0, 0.0], "seed": 170107452,
+        },
+        "wall_s_timed": wall32,
+        "kernels_ms": kern32,
+        "fp32_diag": diag32,
+        "fp64": fp64,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -146,6 +146,17 @@ int wmb_diagnostics(wmb_ctx *c, double totals[8], double *max_divb_norm, double 
    Step-3 edges are overwritten by Step 9) give WMB_EINVAL.  Synchronous. */
 int wmb_debug_stage(wmb_ctx *c, int32_t patch, int32_t stage, double *out);
 
+/* Benchmark hook: enqueue one (fill ghosts, compute dt, advance) with the
+   same launches the captured graph replays, with a HIP event recorded on the
+   context's stream after each kernel class, wait for it, and store the
+   duration in milliseconds of each class in ms[0 .. WMB_NCLASS-1], in this
+   order: fill, dt (reduce + finalize), reference EMF (Step 2), sweep x, y, z
+   (Step 1), edge EMFs (Step 3), CT half (Step 4), sweep x, y, z (Steps 5-7),
+   half-step EMF (Step 8), edge EMFs (Step 9), final update (Steps 10-11).
+   Advances the state by one step.  Synchronous. */
+#define WMB_NCLASS 14
+int wmb_profile_step(wmb_ctx *c, double *ms, int32_t nclass);
+
 /* Free the context, its tables and graphs (not the pool, not the stream). */
 int wmb_destroy(wmb_ctx *c);
 

@@ -74,6 +74,8 @@ struct wmb_ctx {
     hipGraph_t graph[2] = {nullptr, nullptr};
     std::string err;
     std::vector<void*> owned;  // library-owned device allocations
+    hipEvent_t* marks = nullptr;  // when set, an event is recorded after every kernel class
+    int nmark = 0;
 };
 
 namespace {
@@ -170,10 +172,15 @@ int check_table(int32_t np, const wmb_patch_desc* d, int g, std::string& why) {
     return WMB_OK;
 }
 
+void mark(wmb_ctx* c) {
+    if (c->marks) hipEventRecord(c->marks[c->nmark++], c->stream);
+}
+
 template <typename R>
 int run_fill(wmb_ctx* c) {
     hipError_t e = launch_fill<R>(c->pool, c->d_patch, c->d_fill, c->nfill, c->cur, c->stream);
     if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("fill_ghosts: ") + hipGetErrorString(e));
+    mark(c);
     return WMB_OK;
 }
 
@@ -181,6 +188,7 @@ template <typename R>
 int run_dt(wmb_ctx* c) {
     hipError_t e = launch_dt<R>(c->pool, c->d_patch, c->wl_int.d, c->wl_int.n, c->dp, c->cur, c->d_smax, c->d_dt, c->stream);
     if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("dt_reduce: ") + hipGetErrorString(e));
+    mark(c);
     return WMB_OK;
 }
 
@@ -192,28 +200,38 @@ int run_step(wmb_ctx* c) {
     if (e != hipSuccess) return fail(c, WMB_EHIP, std::string(what) + ": " + hipGetErrorString(e))
     e = launch_emf_ref<R>(c->pool, c->d_patch, c->wl_er1.d, c->wl_er1.n, c->dp, cur, BOX_ER1, c->stream);
     STEPCK("emf_ref");
-    for (int d = 0; d < 3; d++)
+    mark(c);
+    for (int d = 0; d < 3; d++) {
         for (auto& G : c->sweeps[d][0]) {
             e = launch_sweep<R>(d, 1, c->pool, c->d_patch, G.wl.d, G.wl.n, c->dp, cur, c->d_dt, G.P, G.W, G.zlo, c->stream);
             STEPCK("sweep1");
         }
+        mark(c);
+    }
     e = launch_edge<R>(c->pool, c->d_patch, c->wl_edge1.d, c->wl_edge1.n, c->dp, F_FL1, BOX_EDGE1, EdgeRanges{-1, 0, -2, 2},
                        c->stream);
     STEPCK("edge_emf1");
+    mark(c);
     e = launch_ct_half<R>(c->pool, c->d_patch, c->wl_cth.d, c->wl_cth.n, c->dp, cur, c->d_dt, BOX_CTH, c->stream);
     STEPCK("ct_half");
-    for (int d = 0; d < 3; d++)
+    mark(c);
+    for (int d = 0; d < 3; d++) {
         for (auto& G : c->sweeps[d][1]) {
             e = launch_sweep<R>(d, 2, c->pool, c->d_patch, G.wl.d, G.wl.n, c->dp, cur, c->d_dt, G.P, G.W, G.zlo, c->stream);
             STEPCK("sweep2");
         }
+        mark(c);
+    }
     e = launch_emf_half<R>(c->pool, c->d_patch, c->wl_er2.d, c->wl_er2.n, c->dp, cur, c->d_dt, BOX_ER2, c->stream);
     STEPCK("emf_half");
+    mark(c);
     e = launch_edge<R>(c->pool, c->d_patch, c->wl_edge2.d, c->wl_edge2.n, c->dp, F_FL2, BOX_EDGE2, EdgeRanges{0, -1, 0, 0},
                        c->stream);
     STEPCK("edge_emf2");
+    mark(c);
     e = launch_final<R>(c->pool, c->d_patch, c->wl_int.d, c->wl_int.n, c->dp, cur, c->d_dt, c->d_nfloor, c->stream);
     STEPCK("final_update");
+    mark(c);
 #undef STEPCK
     c->cur ^= 1;
     return WMB_OK;
@@ -670,6 +688,32 @@ int wmb_debug_stage(wmb_ctx* c, int32_t patch, int32_t stage, double* out) {
     if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
     if (patch < 0 || patch >= c->npatch) return fail(c, WMB_EINVAL, "bad patch");
     return c->esize == 4 ? debug_stage_t<float>(c, patch, stage, out) : debug_stage_t<double>(c, patch, stage, out);
+}
+
+int wmb_profile_step(wmb_ctx* c, double* ms, int32_t nclass) {
+    if (!c || !ms) return WMB_EINVAL;
+    if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
+    if (nclass < WMB_NCLASS) return fail(c, WMB_EINVAL, "ms must hold WMB_NCLASS entries");
+    hipEvent_t ev[WMB_NCLASS + 1];
+    for (int i = 0; i <= WMB_NCLASS; i++) CKH(hipEventCreate(&ev[i]));
+    CKH(hipEventRecord(ev[0], c->stream));
+    c->marks = ev + 1;
+    c->nmark = 0;
+    int rc = dispatch_fill(c);
+    if (!rc) rc = dispatch_dt(c);
+    if (!rc) rc = dispatch_step(c);
+    c->marks = nullptr;
+    if (!rc && c->nmark != WMB_NCLASS) rc = fail(c, WMB_EHIP, "profile: unexpected kernel count");
+    if (!rc) {
+        CKH(hipEventSynchronize(ev[WMB_NCLASS]));
+        for (int i = 0; i < WMB_NCLASS; i++) {
+            float t = 0.f;
+            CKH(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+            ms[i] = t;
+        }
+    }
+    for (int i = 0; i <= WMB_NCLASS; i++) hipEventDestroy(ev[i]);
+    return rc;
 }
 
 int wmb_destroy(wmb_ctx* c) {

@@ -21,8 +21,10 @@ WMB_FP64, WMB_FP32 = 0, 1
 EXPORTS = [
     "wmb_create", "wmb_pool_bytes", "wmb_init_patches", "wmb_set_state", "wmb_get_state", "wmb_get_stored",
     "wmb_fill_ghosts", "wmb_compute_dt", "wmb_advance", "wmb_run_steps", "wmb_diagnostics", "wmb_debug_stage",
-    "wmb_destroy", "wmb_strerror", "wmb_last_error",
+    "wmb_profile_step", "wmb_destroy", "wmb_strerror", "wmb_last_error",
 ]
+KERNEL_CLASSES = ["fill", "dt", "emf_ref", "sweep1_x", "sweep1_y", "sweep1_z", "edge1", "ct_half",
+                  "sweep2_x", "sweep2_y", "sweep2_z", "emf_half", "edge2", "final"]
 
 
 class WmbError(RuntimeError):
@@ -93,6 +95,7 @@ def load_library():
     lib.wmb_run_steps.argtypes = [vp, C.c_int32]
     lib.wmb_diagnostics.argtypes = [vp, dp, dp, dp, C.POINTER(C.c_int64)]
     lib.wmb_debug_stage.argtypes = [vp, C.c_int32, C.c_int32, dp]
+    lib.wmb_profile_step.argtypes = [vp, dp, C.c_int32]
     lib.wmb_destroy.argtypes = [vp]
     lib.wmb_strerror.argtypes = [C.c_int]
     lib.wmb_strerror.restype = C.c_char_p
@@ -229,6 +232,12 @@ class Sim:
         out = np.zeros((nw,) + sh)
         self._check(self.lib.wmb_debug_stage(self.h, ip, stage, _dp(out)))
         return out.reshape((3, 8) + sh) if nw == 24 else out
+
+    def profile_step(self):
+        """Per-kernel-class durations (ms) of one eager step; advances the state."""
+        out = np.zeros(len(KERNEL_CLASSES))
+        self._check(self.lib.wmb_profile_step(self.h, _dp(out), len(KERNEL_CLASSES)))
+        return dict(zip(KERNEL_CLASSES, out.tolist()))
 
     def synchronize(self):
         self.stream.synchronize()
