@@ -146,15 +146,27 @@ int wmb_diagnostics(wmb_ctx *c, double totals[8], double *max_divb_norm, double 
    Step-3 edges are overwritten by Step 9) give WMB_EINVAL.  Synchronous. */
 int wmb_debug_stage(wmb_ctx *c, int32_t patch, int32_t stage, double *out);
 
+/* Search the block shape of the directional sweeps (pencils per block) for
+   every group of patches with the same edge along the sweep axis, timing
+   each candidate `reps` times on the device, and keep the fastest.  The
+   choice never changes results (the arithmetic of a face does not depend on
+   it).  The interior state is unchanged; ghosts are refreshed and the step
+   intermediates overwritten.  Invalidates the captured graphs.  If chosen !=
+   NULL it receives quadruples (stage, axis, edge, pencils per block), up to
+   nchosen ints, 0-terminated when shorter.  Synchronous. */
+int wmb_autotune(wmb_ctx *c, int32_t reps, int32_t *chosen, int32_t nchosen);
+
 /* Benchmark hook: enqueue one (fill ghosts, compute dt, advance) with the
    same launches the captured graph replays, with a HIP event recorded on the
    context's stream after each kernel class, wait for it, and store the
    duration in milliseconds of each class in ms[0 .. WMB_NCLASS-1], in this
-   order: fill, dt (reduce + finalize), reference EMF (Step 2), sweep x, y, z
-   (Step 1), edge EMFs (Step 3), CT half (Step 4), sweep x, y, z (Steps 5-7),
-   half-step EMF (Step 8), edge EMFs (Step 9), final update (Steps 10-11).
-   Advances the state by one step.  Synchronous. */
-#define WMB_NCLASS 14
+   order: fill (3 passes), dt (finalize of the reduction that the previous
+   final update folded in), sweep x, y, z (Step 1, the x sweep also forming
+   the Step-2 reference EMF), edge EMFs (Step 3), CT half (Step 4), sweep x,
+   y, z (Steps 5-7), half-step EMF (Step 8), edge EMFs (Step 9), final update
+   (Steps 10-11 and the signal-speed maximum of the new state).  Advances the
+   state by one step.  Synchronous. */
+#define WMB_NCLASS 13
 int wmb_profile_step(wmb_ctx *c, double *ms, int32_t nclass);
 
 /* Free the context, its tables and graphs (not the pool, not the stream). */

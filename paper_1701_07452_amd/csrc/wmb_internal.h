@@ -21,12 +21,34 @@ struct DevParams {
     int pad_;
 };
 
+// Per-step constants derived from dt, written on the device by the dt
+// finalize kernel (or by the explicit-dt setter), read by every step kernel.
+struct StepConst {
+    double dt, hdt;
+    double lam[3];  // dt / dx_d
+    double il[3];   // dx_d / (2 dt)
+    float fdt, fhdt;
+    float flam[3];
+    float fil[3];
+};
+
+// Scheme constants in the working precision, derived on the host once.
+template <typename R>
+struct Coef {
+    R gam, gm1, gm2, ggm, igm1;  // gamma, gamma-1, gamma-2, gamma/(gamma-1), 1/(gamma-1)
+    R beta_l, p_floor, rho_floor, tol, tol2;
+    R idx[3];                    // 1 / dx_d
+    R eps[7], q4e[7];            // epsilon_k and 1/(4 epsilon_k) (0 where epsilon_k = 0)
+};
+
 // One patch inside the device pool: structure of arrays over the ghosted box
 // N = n + 2g, x fastest.  Every field array holds `vol` elements starting at
 // base + field * vol (elements of the working precision).
 struct PatchDev {
     int n[3];
     int N[3];
+    int nb[6];  // face neighbours: -x, +x, -y, +y, -z, +z
+    int pad_;
     long long base;
     long long vol;
 };
@@ -50,13 +72,6 @@ struct WorkItem {
     int a;  // box kernels: block index in the patch; sweeps: first fast-transverse coord
     int b;  // sweeps: slow-transverse coord
     int c;  // sweeps: last fast-transverse coord (inclusive)
-};
-
-struct FillRegion {
-    int dst, src;
-    int d0[3];  // first stored index of the destination box (x, y, z)
-    int s0[3];  // first stored index of the source box in the neighbour
-    int ext[3];
 };
 
 // Box kernels: interior-relative inclusive ranges [lo, n + hi] per axis.

@@ -5,18 +5,22 @@
 // The CFL reduction, floors and diagnostics are FP64 whatever R is.
 //
 // Kernel map (one step):
-//   fill_ghosts      bitwise copy of the 26 neighbour regions, 11 fields
-//   dt_reduce        FP64 max signal speed, wave reduction + atomicMax
-//   dt_finalize      dt = cfl / smax, kept in device memory
-//   emf_ref<q^n>     Step 2   zone-centred E^r = -v x B
-//   sweep<d,1>       Step 1   MHDTVD fluxes from q^n, B_par = b^n   (hot)
-//   edge_emf         Step 3   upwinded edge EMFs
-//   ct_half          Step 4   b^{n+1/2} = b^n - dt/2 curl E
-//   sweep<d,2>       Steps 5-7  transverse predictor + source, then MHDTVD
+//   fill_pass<x,y,z>  ghost exchange in three dependent passes: x-ghosts of
+//                     interior rows, then whole y-ghost rows, then whole
+//                     z-ghost planes (each ghost value written once, rows and
+//                     planes copied contiguously)
+//   dt_reduce         FP64 max signal speed (only when no fused value exists)
+//   dt_finalize       dt = cfl / smax, kept in device memory
+//   sweep<d,1>        Step 1   MHDTVD fluxes from q^n, B_par = b^n    (hot);
+//                              the x sweep also writes E^r (Step 2)
+//   edge_emf          Step 3   upwinded edge EMFs
+//   ct_half           Step 4   b^{n+1/2} = b^n - dt/2 curl E
+//   sweep<d,2>        Steps 5-7  transverse predictor + source, then MHDTVD
 //                              fluxes with B_par = b^{n+1/2}        (hot)
-//   emf_half         Step 8   E^r from the unsplit half update and face-averaged b^{n+1/2}
-//   edge_emf         Step 9
-//   final_update     Steps 10-11  q^{n+1}, b^{n+1}, zone field, FP64 floors
+//   emf_half          Step 8   E^r from the unsplit half update and face-averaged b^{n+1/2}
+//   edge_emf          Step 9
+//   final_update      Steps 10-11  q^{n+1}, b^{n+1}, zone field, FP64 floors,
+//                              and the FP64 signal-speed max of q^{n+1} for the next dt
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -29,14 +33,25 @@ namespace wmb {
 // small helpers
 // ---------------------------------------------------------------------------
 
+// Reciprocal and square root: hardware v_rcp_f32 / v_sqrt_f32 (about 1 ulp)
+// in the FP32 path, correctly rounded operations in the FP64 path.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+// smallest |alpha| divided by in the limiter's gamma (FP32: keeps the hardware
+// reciprocal away from denormals; FP64: exact zero test)
+__device__ __forceinline__ float alpha_min(float) { return 1e-30f; }
+__device__ __forceinline__ double alpha_min(double) { return 0.0; }
+
 template <typename R>
 __device__ __forceinline__ R sgn1(R x) { return x >= R(0) ? R(1) : R(-1); }
 
-// coefficient of numerical viscosity Q_k(chi) (Appendix A)
+// coefficient of numerical viscosity Q_k(chi) (Appendix A); q4e = 1/(4 eps)
 template <typename R>
-__device__ __forceinline__ R qvisc(R chi, R eps) {
+__device__ __forceinline__ R qvisc(R chi, R eps, R q4e) {
     R ac = fabs(chi);
-    if (ac < R(2) * eps) return chi * chi / (R(4) * eps) + eps;
+    if (ac < R(2) * eps) return chi * chi * q4e + eps;
     return ac;
 }
 
@@ -49,11 +64,22 @@ __device__ __forceinline__ R sweby(R gp, R gm, R beta) {
     return s * fmax(R(0), fmax(t1, t2));
 }
 
-__device__ __forceinline__ double minmod2(double a, double b) {
-    if (a > 0.0 && b > 0.0) return fmin(a, b);
-    if (a < 0.0 && b < 0.0) return fmax(a, b);
-    return 0.0;
+template <typename R>
+__device__ __forceinline__ R minmod2(R a, R b) {
+    if (a > R(0) && b > R(0)) return fmin(a, b);
+    if (a < R(0) && b < R(0)) return fmax(a, b);
+    return R(0);
 }
+
+// per-step constants in the working precision
+__device__ __forceinline__ float sc_dt(const StepConst& s, float) { return s.fdt; }
+__device__ __forceinline__ double sc_dt(const StepConst& s, double) { return s.dt; }
+__device__ __forceinline__ float sc_hdt(const StepConst& s, float) { return s.fhdt; }
+__device__ __forceinline__ double sc_hdt(const StepConst& s, double) { return s.hdt; }
+__device__ __forceinline__ float sc_lam(const StepConst& s, int d, float) { return s.flam[d]; }
+__device__ __forceinline__ double sc_lam(const StepConst& s, int d, double) { return s.lam[d]; }
+__device__ __forceinline__ float sc_il(const StepConst& s, int d, float) { return s.fil[d]; }
+__device__ __forceinline__ double sc_il(const StepConst& s, int d, double) { return s.il[d]; }
 
 __device__ __forceinline__ long long sidx(const PatchDev& P, int i, int j, int k) {
     return ((long long)k * P.N[1] + j) * P.N[0] + i;
@@ -66,7 +92,7 @@ __device__ __forceinline__ long long stride_of(const PatchDev& P, int a) {
 // FP64 floors on one zone (density raised with momentum kept, then pressure
 // raised by adding thermal energy).  Returns true if a floor fired.
 template <typename R>
-__device__ __forceinline__ bool apply_floor(R u[8], const DevParams& p) {
+__device__ __forceinline__ bool apply_floor64(R u[8], const DevParams& p) {
     bool hit = false;
     double rho = (double)u[0];
     if (rho < p.rho_floor) {
@@ -84,65 +110,141 @@ __device__ __forceinline__ bool apply_floor(R u[8], const DevParams& p) {
     return hit;
 }
 
-// ---------------------------------------------------------------------------
-// ghost exchange
-// ---------------------------------------------------------------------------
-
-template <typename R>
-__global__ void __launch_bounds__(256) fill_ghosts_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
-                                                          const FillRegion* __restrict__ regs, int cur) {
-    const FillRegion rg = regs[blockIdx.x];
-    const PatchDev D = patches[rg.dst];
-    const PatchDev S = patches[rg.src];
-    const int ex = rg.ext[0], ey = rg.ext[1], ez = rg.ext[2];
-    const int total = ex * ey * ez;
-    R* dbase = pool + D.base + (long long)(cur ? F_ST1 : F_ST0) * D.vol;
-    const R* sbase = pool + S.base + (long long)(cur ? F_ST1 : F_ST0) * S.vol;
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        int i = t % ex, r = t / ex;
-        int j = r % ey, k = r / ey;
-        long long di = sidx(D, rg.d0[0] + i, rg.d0[1] + j, rg.d0[2] + k);
-        long long si = sidx(S, rg.s0[0] + i, rg.s0[1] + j, rg.s0[2] + k);
-#pragma unroll
-        for (int c = 0; c < 11; c++) dbase[(long long)c * D.vol + di] = sbase[(long long)c * S.vol + si];
+// The FP64 decision is the reference; in FP32 a zone whose FP32 pressure is
+// above the floor by more than a bound on its FP32 rounding error (and whose
+// density is above twice the floor) cannot be floored in FP64 either, so the
+// FP64 evaluation is skipped for it.
+__device__ __forceinline__ bool apply_floor(double u[8], const DevParams& p, const Coef<double>&) {
+    return apply_floor64(u, p);
+}
+__device__ __forceinline__ bool apply_floor(float u[8], const DevParams& p, const Coef<float>& cf) {
+    if (u[0] > 2.0f * cf.rho_floor) {
+        float ir = frcp(u[0]);
+        float ke = 0.5f * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * ir;
+        float me = 0.5f * (u[4] * u[4] + u[5] * u[5] + u[6] * u[6]);
+        float pr = cf.gm1 * (u[7] - ke - me);
+        float err = 1e-6f * cf.gm1 * (fabsf(u[7]) + ke + me);
+        if (pr - err > cf.p_floor) return false;
     }
+    return apply_floor64(u, p);
 }
 
 // ---------------------------------------------------------------------------
-// box-kernel indexing: block (patch, blk) covers 256 consecutive linear
-// indices of the patch's box [lo, n+hi]^3 (x fastest)
+// box-kernel indexing: block (patch, blk) covers blockDim consecutive linear
+// indices of an (ex, ey, ez) box, x fastest
 // ---------------------------------------------------------------------------
 
 struct BoxPos {
-    int i, j, k;  // interior-relative
+    int i, j, k;
     bool valid;
 };
 
-__device__ __forceinline__ BoxPos box_pos(const PatchDev& P, int blk, Box bx) {
-    int ex = P.n[0] + bx.hi - bx.lo + 1;
-    int ey = P.n[1] + bx.hi - bx.lo + 1;
-    int ez = P.n[2] + bx.hi - bx.lo + 1;
+__device__ __forceinline__ BoxPos lin_pos(int blk, int ex, int ey, int ez) {
     int t = blk * blockDim.x + threadIdx.x;
     BoxPos r;
     r.valid = t < ex * ey * ez;
-    r.i = t % ex + bx.lo;
+    r.i = t % ex;
     int u = t / ex;
-    r.j = u % ey + bx.lo;
-    r.k = u / ey + bx.lo;
+    r.j = u % ey;
+    r.k = u / ey;
+    return r;
+}
+
+// interior-relative position in the box [lo, n+hi]^3
+__device__ __forceinline__ BoxPos box_pos(const PatchDev& P, int blk, Box bx) {
+    BoxPos r = lin_pos(blk, P.n[0] + bx.hi - bx.lo + 1, P.n[1] + bx.hi - bx.lo + 1, P.n[2] + bx.hi - bx.lo + 1);
+    r.i += bx.lo;
+    r.j += bx.lo;
+    r.k += bx.lo;
     return r;
 }
 
 // ---------------------------------------------------------------------------
-// CFL reduction (FP64)
+// ghost exchange, pass AX (0: x-ghosts of interior rows; 1: whole y-ghost rows
+// of interior z-planes; 2: whole z-ghost planes).  Each pass copies from the
+// face neighbour's interior (and, for passes 1-2, the ghosts the previous
+// passes filled there), so edge and corner ghosts arrive through the chain
+// x -> y -> z.  Bitwise copies of all 11 fields.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double fast_speed(double rho, double p, double gam, double b2, double bd) {
-    double a2 = gam * p / rho;
-    double ca2 = bd * bd / rho;
-    double bp2 = (b2 - bd * bd) / rho;
-    double dpr = a2 - ca2 - bp2;
-    double d = sqrt(dpr * dpr + 4.0 * a2 * bp2);
-    return sqrt(0.5 * (a2 + ca2 + bp2 + d));
+template <typename R, int AX>
+__global__ void __launch_bounds__(256) fill_pass_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
+                                                        const WorkItem* __restrict__ work, int g, int cur) {
+    const WorkItem w = work[blockIdx.x];
+    if (w.patch < 0) return;  // padding item (whole block)
+    const PatchDev D = patches[w.patch];
+    int ex, ey, ez;
+    if (AX == 0) {
+        ex = 2 * g;
+        ey = D.n[1];
+        ez = D.n[2];
+    } else if (AX == 1) {
+        ex = D.N[0];
+        ey = 2 * g;
+        ez = D.n[2];
+    } else {
+        ex = D.N[0];
+        ey = D.N[1];
+        ez = 2 * g;
+    }
+    BoxPos p = lin_pos(w.a, ex, ey, ez);
+    if (!p.valid) return;
+    int d[3], s[3];
+    int side;
+    if (AX == 0) {
+        side = p.i >= g;
+        d[0] = side ? D.n[0] + p.i : p.i;  // p.i in [g, 2g) -> g + n + (p.i - g)
+        d[1] = p.j + g;
+        d[2] = p.k + g;
+    } else if (AX == 1) {
+        side = p.j >= g;
+        d[0] = p.i;
+        d[1] = side ? D.n[1] + p.j : p.j;
+        d[2] = p.k + g;
+    } else {
+        side = p.k >= g;
+        d[0] = p.i;
+        d[1] = p.j;
+        d[2] = side ? D.n[2] + p.k : p.k;
+    }
+    const PatchDev S = patches[D.nb[2 * AX + side]];
+    s[0] = d[0];
+    s[1] = d[1];
+    s[2] = d[2];
+    // left ghost r = d - g < 0 comes from the neighbour's r + n_src; right ghost
+    // r >= n_dst from the neighbour's r - n_dst
+    s[AX] = side ? d[AX] - D.n[AX] : d[AX] + S.n[AX];
+    const long long di = sidx(D, d[0], d[1], d[2]);
+    const long long si = sidx(S, s[0], s[1], s[2]);
+    R* dbase = pool + D.base + (long long)(cur ? F_ST1 : F_ST0) * D.vol;
+    const R* sbase = pool + S.base + (long long)(cur ? F_ST1 : F_ST0) * S.vol;
+#pragma unroll
+    for (int c = 0; c < 11; c++) dbase[(long long)c * D.vol + di] = sbase[(long long)c * S.vol + si];
+}
+
+// ---------------------------------------------------------------------------
+// CFL signal speed (FP64): max_d (|v_d| + c_f,d) / dx_d, c_f,d the fast speed
+// (Sect. 5) with B_d as the longitudinal field
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double signal_speed(const double u[8], const DevParams& p) {
+    double ir = 1.0 / u[0];
+    double v[3] = {u[1] * ir, u[2] * ir, u[3] * ir};
+    double b2 = u[4] * u[4] + u[5] * u[5] + u[6] * u[6];
+    double pr = (p.gamma - 1.0) * (u[7] - 0.5 * u[0] * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - 0.5 * b2);
+    if (pr < p.p_floor) pr = p.p_floor;
+    double a2 = p.gamma * pr * ir;
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        double ca2 = u[4 + d] * u[4 + d] * ir;
+        double bp2 = (b2 - u[4 + d] * u[4 + d]) * ir;
+        double dpr = a2 - ca2 - bp2;
+        double dd = sqrt(dpr * dpr + 4.0 * a2 * bp2);
+        double cf = sqrt(0.5 * (a2 + ca2 + bp2 + dd));
+        s = fmax(s, (fabs(v[d]) + cf) / p.dx[d]);
+    }
+    return s;
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -150,30 +252,9 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-template <typename R>
-__global__ void __launch_bounds__(256) dt_reduce_kernel(const R* __restrict__ pool, const PatchDev* __restrict__ patches,
-                                                        const WorkItem* __restrict__ work, DevParams prm, int cur,
-                                                        unsigned long long* __restrict__ smax_bits) {
+// block max (every thread of a 256-thread block must call) + atomicMax
+__device__ __forceinline__ void block_max_atomic(double s, unsigned long long* smax_bits) {
     __shared__ double red[4];
-    const WorkItem w = work[blockIdx.x];
-    const PatchDev P = patches[w.patch];
-    BoxPos bp = box_pos(P, w.a, Box{0, -1});
-    double s = 0.0;
-    if (bp.valid) {
-        const int g = prm.ghost;
-        long long x = sidx(P, bp.i + g, bp.j + g, bp.k + g);
-        const R* q = pool + P.base + (long long)(cur ? F_ST1 : F_ST0) * P.vol;
-        double rho = (double)q[x];
-        double v[3] = {(double)q[P.vol + x] / rho, (double)q[2 * P.vol + x] / rho, (double)q[3 * P.vol + x] / rho};
-        double B[3] = {(double)q[4 * P.vol + x], (double)q[5 * P.vol + x], (double)q[6 * P.vol + x]};
-        double b2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
-        double pr = (prm.gamma - 1.0) * ((double)q[7 * P.vol + x] - 0.5 * rho * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - 0.5 * b2);
-        if (pr < prm.p_floor) pr = prm.p_floor;
-        for (int d = 0; d < 3; d++) {
-            double sd = (fabs(v[d]) + fast_speed(rho, pr, prm.gamma, b2, B[d])) / prm.dx[d];
-            s = fmax(s, sd);
-        }
-    }
     s = wave_max(s);
     int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) red[wid] = s;
@@ -186,34 +267,49 @@ __global__ void __launch_bounds__(256) dt_reduce_kernel(const R* __restrict__ po
     }
 }
 
-__global__ void dt_finalize_kernel(unsigned long long* smax_bits, double* dt, double cfl) {
+template <typename R>
+__global__ void __launch_bounds__(256) dt_reduce_kernel(const R* __restrict__ pool, const PatchDev* __restrict__ patches,
+                                                        const WorkItem* __restrict__ work, DevParams prm, int cur,
+                                                        unsigned long long* __restrict__ smax_bits) {
+    const WorkItem w = work[blockIdx.x];
+    if (w.patch < 0) return;  // padding item (whole block)
+    const PatchDev P = patches[w.patch];
+    BoxPos bp = box_pos(P, w.a, Box{0, -1});
+    double s = 0.0;
+    if (bp.valid) {
+        const int g = prm.ghost;
+        long long x = sidx(P, bp.i + g, bp.j + g, bp.k + g);
+        const R* q = pool + P.base + (long long)(cur ? F_ST1 : F_ST0) * P.vol;
+        double u[8];
+#pragma unroll
+        for (int c = 0; c < 8; c++) u[c] = (double)q[(long long)c * P.vol + x];
+        s = signal_speed(u, prm);
+    }
+    block_max_atomic(s, smax_bits);
+}
+
+__device__ __forceinline__ void write_step_const(StepConst* sc, double dt, const DevParams& p) {
+    sc->dt = dt;
+    sc->hdt = 0.5 * dt;
+    sc->fdt = (float)dt;
+    sc->fhdt = (float)(0.5 * dt);
+    for (int d = 0; d < 3; d++) {
+        sc->lam[d] = dt / p.dx[d];
+        sc->il[d] = 0.5 * p.dx[d] / dt;
+        sc->flam[d] = (float)sc->lam[d];
+        sc->fil[d] = (float)sc->il[d];
+    }
+}
+
+__global__ void dt_finalize_kernel(unsigned long long* smax_bits, StepConst* sc, DevParams p) {
     double smax = __longlong_as_double((long long)*smax_bits);
-    dt[0] = cfl / smax;
+    write_step_const(sc, p.cfl / smax, p);
     *smax_bits = 0ULL;
 }
 
-// ---------------------------------------------------------------------------
-// Step 2: zone-centred reference EMF E^r = -v x B from q^n
-// ---------------------------------------------------------------------------
+__global__ void set_dt_kernel(StepConst* sc, double dt, DevParams p) { write_step_const(sc, dt, p); }
 
-template <typename R>
-__global__ void __launch_bounds__(256) emf_ref_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
-                                                      const WorkItem* __restrict__ work, DevParams prm, int cur, Box bx) {
-    const WorkItem w = work[blockIdx.x];
-    const PatchDev P = patches[w.patch];
-    BoxPos bp = box_pos(P, w.a, bx);
-    if (!bp.valid) return;
-    const int g = prm.ghost;
-    long long x = sidx(P, bp.i + g, bp.j + g, bp.k + g);
-    const R* q = pool + P.base + (long long)(cur ? F_ST1 : F_ST0) * P.vol;
-    R* er = pool + P.base + (long long)F_ER * P.vol;
-    R rho = q[x];
-    R vx = q[P.vol + x] / rho, vy = q[2 * P.vol + x] / rho, vz = q[3 * P.vol + x] / rho;
-    R Bx = q[4 * P.vol + x], By = q[5 * P.vol + x], Bz = q[6 * P.vol + x];
-    er[x] = vz * By - vy * Bz;
-    er[P.vol + x] = vx * Bz - vz * Bx;
-    er[2 * P.vol + x] = vy * Bx - vx * By;
-}
+__global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ULL; }
 
 // ---------------------------------------------------------------------------
 // Step 8: E^r from the unsplit half update of q^n with the Step-6/7 fluxes
@@ -222,36 +318,39 @@ __global__ void __launch_bounds__(256) emf_ref_kernel(R* __restrict__ pool, cons
 
 template <typename R>
 __global__ void __launch_bounds__(256) emf_half_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
-                                                       const WorkItem* __restrict__ work, DevParams prm, int cur,
-                                                       const double* __restrict__ dtp, Box bx) {
+                                                       const WorkItem* __restrict__ work, Coef<R> cf, int ghost, int cur,
+                                                       const StepConst* __restrict__ sc, Box bx) {
     const WorkItem w = work[blockIdx.x];
+    if (w.patch < 0) return;  // padding item (whole block)
     const PatchDev P = patches[w.patch];
     BoxPos bp = box_pos(P, w.a, bx);
     if (!bp.valid) return;
-    const int g = prm.ghost;
-    const R hdt = R(0.5 * dtp[0]);
-    long long x = sidx(P, bp.i + g, bp.j + g, bp.k + g);
-    const long long V = P.vol;
-    const R* q = pool + P.base + (long long)(cur ? F_ST1 : F_ST0) * V;
-    const R* fl = pool + P.base + (long long)F_FL2 * V;
-    const R* bh = pool + P.base + (long long)F_BH * V;
-    R* er = pool + P.base + (long long)F_ER * V;
+    const int g = ghost;
+    const R hdt = sc_hdt(*sc, R(0));
+    const int V = (int)P.vol;
+    const int x = (int)sidx(P, bp.i + g, bp.j + g, bp.k + g);
+    const int st[3] = {1, P.N[0], P.N[0] * P.N[1]};
+    R* __restrict__ pp = pool + P.base;
+    const R* q = pp + (cur ? F_ST1 : F_ST0) * V;
+    const R* fl = pp + F_FL2 * V;
+    const R* bh = pp + F_BH * V;
+    R* er = pp + F_ER * V;
     R u[4];
 #pragma unroll
     for (int c = 0; c < 4; c++) {
         R div = R(0);
 #pragma unroll
         for (int d = 0; d < 3; d++) {
-            const R* f = fl + (long long)(7 * d + c) * V;
-            long long s = stride_of(P, d);
-            div += (f[x + s] - f[x]) / R(prm.dx[d]);
+            const R* f = fl + (7 * d + c) * V;
+            div += (f[x + st[d]] - f[x]) * cf.idx[d];
         }
-        u[c] = q[(long long)c * V + x] - hdt * div;
+        u[c] = q[c * V + x] - hdt * div;
     }
     R B[3];
 #pragma unroll
-    for (int d = 0; d < 3; d++) B[d] = R(0.5) * (bh[(long long)d * V + x] + bh[(long long)d * V + x + stride_of(P, d)]);
-    R vx = u[1] / u[0], vy = u[2] / u[0], vz = u[3] / u[0];
+    for (int d = 0; d < 3; d++) B[d] = R(0.5) * (bh[d * V + x] + bh[d * V + x + st[d]]);
+    R ir = frcp(u[0]);
+    R vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
     er[x] = vz * B[1] - vy * B[2];
     er[V + x] = vx * B[2] - vz * B[0];
     er[2 * V + x] = vy * B[0] - vx * B[1];
@@ -265,7 +364,6 @@ __global__ void __launch_bounds__(256) emf_half_kernel(R* __restrict__ pool, con
 // difference on the upwind side (by the sign of the mass flux across the
 // face carrying it; the average of both sides when it is exactly zero); the
 // edge value is the mean of the four.
-// range[c] gives, per component, (lo along c, hi along c, lo other, hi other).
 // ---------------------------------------------------------------------------
 
 template <typename R>
@@ -275,18 +373,21 @@ __device__ __forceinline__ R upwind_pick(R f, R dl, R dr) {
 
 template <typename R>
 __global__ void __launch_bounds__(256) edge_emf_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
-                                                       const WorkItem* __restrict__ work, DevParams prm, int fslot,
-                                                       Box bx, EdgeRanges rg) {
+                                                       const WorkItem* __restrict__ work, int ghost, int fslot, Box bx,
+                                                       EdgeRanges rg) {
     const WorkItem w = work[blockIdx.x];
+    if (w.patch < 0) return;  // padding item (whole block)
     const PatchDev P = patches[w.patch];
     BoxPos bp = box_pos(P, w.a, bx);
     if (!bp.valid) return;
-    const int g = prm.ghost;
-    const long long V = P.vol;
-    const long long x = sidx(P, bp.i + g, bp.j + g, bp.k + g);
-    const R* fl = pool + P.base + (long long)fslot * V;
-    const R* er = pool + P.base + (long long)F_ER * V;
-    R* ed = pool + P.base + (long long)F_ED * V;
+    const int g = ghost;
+    const int V = (int)P.vol;
+    const int x = (int)sidx(P, bp.i + g, bp.j + g, bp.k + g);
+    const int st[3] = {1, P.N[0], P.N[0] * P.N[1]};
+    R* __restrict__ pp = pool + P.base;
+    const R* fl = pp + fslot * V;
+    const R* er = pp + F_ER * V;
+    R* ed = pp + F_ED * V;
     const int z[3] = {bp.i, bp.j, bp.k};
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -294,10 +395,10 @@ __global__ void __launch_bounds__(256) edge_emf_kernel(R* __restrict__ pool, con
         bool in = z[c] >= rg.lo_c && z[c] <= P.n[c] + rg.hi_c && z[a] >= rg.lo_o && z[a] <= P.n[a] + rg.hi_o &&
                   z[b] >= rg.lo_o && z[b] <= P.n[b] + rg.hi_o;
         if (!in) continue;
-        const long long sa = stride_of(P, a), sb = stride_of(P, b);
-        const R* fa = fl + (long long)(7 * a) * V;  // flux_a rows
-        const R* fb = fl + (long long)(7 * b) * V;
-        const R* E0 = er + (long long)c * V;
+        const int sa = st[a], sb = st[b];
+        const R* fa = fl + (7 * a) * V;  // flux_a rows
+        const R* fb = fl + (7 * b) * V;
+        const R* E0 = er + c * V;
         // flux_a row 5 is B_{a+1} = B_b; flux_b row 6 is B_{b+2} = B_a
         R Ea_0 = -fa[5 * V + x], Ea_b = -fa[5 * V + x - sb];
         R Eb_0 = fb[6 * V + x], Eb_a = fb[6 * V + x - sa];
@@ -306,7 +407,7 @@ __global__ void __launch_bounds__(256) edge_emf_kernel(R* __restrict__ pool, con
         R d2 = upwind_pick(fa[x - sb], Eb_a - eab, Eb_0 - eb);
         R d3 = upwind_pick(fb[x], eb - Ea_b, e0 - Ea_0);
         R d4 = upwind_pick(fb[x - sa], Ea_b - eab, Ea_0 - ea);
-        ed[(long long)c * V + x] = R(0.25) * ((Ea_0 - d1) + (Ea_b + d2) + (Eb_0 - d3) + (Eb_a + d4));
+        ed[c * V + x] = R(0.25) * ((Ea_0 - d1) + (Ea_b + d2) + (Eb_0 - d3) + (Eb_a + d4));
     }
 }
 
@@ -317,99 +418,116 @@ __global__ void __launch_bounds__(256) edge_emf_kernel(R* __restrict__ pool, con
 
 template <typename R>
 __global__ void __launch_bounds__(256) ct_half_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
-                                                      const WorkItem* __restrict__ work, DevParams prm, int cur,
-                                                      const double* __restrict__ dtp, Box bx) {
+                                                      const WorkItem* __restrict__ work, Coef<R> cf, int ghost, int cur,
+                                                      const StepConst* __restrict__ sc, Box bx) {
     const WorkItem w = work[blockIdx.x];
+    if (w.patch < 0) return;  // padding item (whole block)
     const PatchDev P = patches[w.patch];
     BoxPos bp = box_pos(P, w.a, bx);
     if (!bp.valid) return;
-    const int g = prm.ghost;
-    const long long V = P.vol;
-    const long long x = sidx(P, bp.i + g, bp.j + g, bp.k + g);
-    const R* b = pool + P.base + (long long)((cur ? F_ST1 : F_ST0) + 8) * V;
-    const R* ed = pool + P.base + (long long)F_ED * V;
-    R* bh = pool + P.base + (long long)F_BH * V;
-    const R tau = R(0.5 * dtp[0]);
+    const int g = ghost;
+    const int V = (int)P.vol;
+    const int x = (int)sidx(P, bp.i + g, bp.j + g, bp.k + g);
+    const int st[3] = {1, P.N[0], P.N[0] * P.N[1]};
+    R* __restrict__ pp = pool + P.base;
+    const R* b = pp + ((cur ? F_ST1 : F_ST0) + 8) * V;
+    const R* ed = pp + F_ED * V;
+    R* bh = pp + F_BH * V;
+    const R tau = sc_hdt(*sc, R(0));
     const int z[3] = {bp.i, bp.j, bp.k};
 #pragma unroll
     for (int d = 0; d < 3; d++) {
         const int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
         bool in = z[a1] >= -1 && z[a1] <= P.n[a1] && z[a2] >= -1 && z[a2] <= P.n[a2];
         if (!in) continue;
-        const R* E2 = ed + (long long)a2 * V;
-        const R* E1 = ed + (long long)a1 * V;
-        R curl = (E2[x + stride_of(P, a1)] - E2[x]) / R(prm.dx[a1]) - (E1[x + stride_of(P, a2)] - E1[x]) / R(prm.dx[a2]);
-        bh[(long long)d * V + x] = b[(long long)d * V + x] - tau * curl;
+        const R* E2 = ed + a2 * V;
+        const R* E1 = ed + a1 * V;
+        R curl = (E2[x + st[a1]] - E2[x]) * cf.idx[a1] - (E1[x + st[a2]] - E1[x]) * cf.idx[a2];
+        bh[d * V + x] = b[d * V + x] - tau * curl;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Steps 10-11: conservative update, CT with the Step-9 EMFs, zone field from
-// the face average, FP64 floors.  Writes the other state copy.
+// the face average, FP64 floors.  Writes the other state copy, and folds the
+// FP64 signal speed of the new state into smax (the next step's dt).
 // ---------------------------------------------------------------------------
 
 template <typename R>
 __global__ void __launch_bounds__(256) final_update_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
-                                                           const WorkItem* __restrict__ work, DevParams prm, int cur,
-                                                           const double* __restrict__ dtp,
-                                                           unsigned long long* __restrict__ nfloor) {
+                                                           const WorkItem* __restrict__ work, DevParams prm, Coef<R> cf,
+                                                           int cur, const StepConst* __restrict__ sc,
+                                                           unsigned long long* __restrict__ nfloor,
+                                                           unsigned long long* __restrict__ smax_bits) {
     const WorkItem w = work[blockIdx.x];
+    if (w.patch < 0) return;  // padding item (whole block)
     const PatchDev P = patches[w.patch];
     BoxPos bp = box_pos(P, w.a, Box{0, -1});
-    if (!bp.valid) return;
-    const int g = prm.ghost;
-    const long long V = P.vol;
-    const long long x = sidx(P, bp.i + g, bp.j + g, bp.k + g);
-    const R* q = pool + P.base + (long long)(cur ? F_ST1 : F_ST0) * V;
-    const R* b = q + 8 * V;
-    R* qn = pool + P.base + (long long)(cur ? F_ST0 : F_ST1) * V;
-    R* bn = qn + 8 * V;
-    const R* fl = pool + P.base + (long long)F_FL2 * V;
-    const R* ed = pool + P.base + (long long)F_ED * V;
-    const R dt = R(dtp[0]);
-    const int z[3] = {bp.i, bp.j, bp.k};
-    R u[8];
-    // Step 10 on rho, m, E (flux rows 0..4 map to components 0,1,2,3,7)
+    double sp = 0.0;
+    if (bp.valid) {
+        const int g = prm.ghost;
+        const int V = (int)P.vol;
+        const int x = (int)sidx(P, bp.i + g, bp.j + g, bp.k + g);
+        const int st[3] = {1, P.N[0], P.N[0] * P.N[1]};
+        R* __restrict__ pp = pool + P.base;
+        const R* q = pp + (cur ? F_ST1 : F_ST0) * V;
+        const R* b = q + 8 * V;
+        R* qn = pp + (cur ? F_ST0 : F_ST1) * V;
+        R* bn = qn + 8 * V;
+        const R* fl = pp + F_FL2 * V;
+        const R* ed = pp + F_ED * V;
+        const R dt = sc_dt(*sc, R(0));
+        const int z[3] = {bp.i, bp.j, bp.k};
+        R u[8];
+        // Step 10 on rho, m, E (flux rows 0..4 map to components 0,1,2,3,7)
 #pragma unroll
-    for (int r = 0; r < 5; r++) {
-        const int c = r < 4 ? r : 7;
-        R div = R(0);
+        for (int r = 0; r < 5; r++) {
+            const int c = r < 4 ? r : 7;
+            R div = R(0);
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                const R* f = fl + (7 * d + r) * V;
+                div += (f[x + st[d]] - f[x]) * cf.idx[d];
+            }
+            u[c] = q[c * V + x] - dt * div;
+        }
+        // Step 11: CT on the two faces of the zone along each axis
 #pragma unroll
         for (int d = 0; d < 3; d++) {
-            const R* f = fl + (long long)(7 * d + r) * V;
-            div += (f[x + stride_of(P, d)] - f[x]) / R(prm.dx[d]);
+            const int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
+            const int s1 = st[a1], s2 = st[a2], sd = st[d];
+            const R* E2 = ed + a2 * V;
+            const R* E1 = ed + a1 * V;
+            R bl = b[d * V + x] - dt * ((E2[x + s1] - E2[x]) * cf.idx[a1] - (E1[x + s2] - E1[x]) * cf.idx[a2]);
+            const int xr = x + sd;
+            R br = b[d * V + xr] - dt * ((E2[xr + s1] - E2[xr]) * cf.idx[a1] - (E1[xr + s2] - E1[xr]) * cf.idx[a2]);
+            bn[d * V + x] = bl;
+            if (z[d] == P.n[d] - 1) bn[d * V + xr] = br;  // shared right face
+            u[4 + d] = R(0.5) * (bl + br);
         }
-        u[c] = q[(long long)c * V + x] - dt * div;
-    }
-    // Step 11: CT on the two faces of the zone along each axis
+        if (apply_floor(u, prm, cf)) atomicAdd(nfloor, 1ULL);
 #pragma unroll
-    for (int d = 0; d < 3; d++) {
-        const int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
-        const long long s1 = stride_of(P, a1), s2 = stride_of(P, a2), sd = stride_of(P, d);
-        const R* E2 = ed + (long long)a2 * V;
-        const R* E1 = ed + (long long)a1 * V;
-        R bl = b[(long long)d * V + x] -
-               dt * ((E2[x + s1] - E2[x]) / R(prm.dx[a1]) - (E1[x + s2] - E1[x]) / R(prm.dx[a2]));
-        const long long xr = x + sd;
-        R br = b[(long long)d * V + xr] -
-               dt * ((E2[xr + s1] - E2[xr]) / R(prm.dx[a1]) - (E1[xr + s2] - E1[xr]) / R(prm.dx[a2]));
-        bn[(long long)d * V + x] = bl;
-        if (z[d] == P.n[d] - 1) bn[(long long)d * V + xr] = br;  // shared right face
-        u[4 + d] = R(0.5) * (bl + br);
-    }
-    if (apply_floor(u, prm)) atomicAdd(nfloor, 1ULL);
+        for (int c = 0; c < 8; c++) qn[c * V + x] = u[c];
+        double ud[8];
 #pragma unroll
-    for (int c = 0; c < 8; c++) qn[(long long)c * V + x] = u[c];
+        for (int c = 0; c < 8; c++) ud[c] = (double)u[c];
+        sp = signal_speed(ud, prm);
+    }
+    block_max_atomic(sp, smax_bits);
 }
 
 // ---------------------------------------------------------------------------
 // MHDTVD directional sweep (Appendix A; Step 1 when STAGE == 1, Steps 5-7
 // when STAGE == 2).  A block holds W pencils of P zones along D; every thread
 // owns one zone of one pencil and, after a barrier, the face on its left.
+// The pencils of a patch are numbered fast-transverse-first and a block takes
+// W consecutive ones, so no lanes idle on partial tiles.
 //
-//   phase A  zone state -> primitives (rho, v_par, v_t1, v_t2, B_t1, B_t2, P) in LDS
+//   phase A  zone state -> primitives (rho, v_par, v_t1, v_t2, B_t1, B_t2, P)
+//            and the zone's physical flux terms in LDS
 //            (STAGE 2 first builds the predictor state q^{n+1/2}_D from q^n,
-//             the transverse Step-1 fluxes and the div-B source, with FP64 floors)
+//             the transverse Step-1 fluxes and the div-B source, with FP64
+//             floors; STAGE 1 along x also writes the Step-2 reference EMF)
 //   phase B  face s (zones s-1, s): Roe average, eigen-speeds, characteristic
 //            jumps alpha_k, nu_k, g-tilde_k -> LDS
 //   phase C  faces 2 .. P-2: limiter g of both zones, gamma_k, beta_k, the
@@ -429,8 +547,9 @@ struct FaceEig {
 
 template <typename R, int D, int STAGE>
 __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
-                                                     const WorkItem* __restrict__ work, DevParams prm, int cur,
-                                                     const double* __restrict__ dtp, int P, int W, int zlo) {
+                                                     const WorkItem* __restrict__ work, DevParams prm, Coef<R> cf,
+                                                     int cur, const StepConst* __restrict__ sc, int P, int W, int zlo,
+                                                     int tlo, int thi) {
     extern __shared__ unsigned char smem_raw[];
     R* sh = reinterpret_cast<R*>(smem_raw);
     const int nthr = P * W;
@@ -442,6 +561,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
     constexpr int SA = (D == 0) ? 2 : (D == 1 ? 2 : 1);  // slow transverse axis
 
     const WorkItem wi = work[blockIdx.x];
+    if (wi.patch < 0) return;  // padding item (whole block, before any barrier)
     const PatchDev Pt = patches[wi.patch];
     const int tid = threadIdx.x;
     int s, w;
@@ -453,39 +573,48 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
         s = tid / W;
     }
     const int sstep = (D == 0) ? 1 : W;  // LDS distance between neighbours along the pencil
-    const int fast = wi.a + w;
-    const bool live = (tid < nthr) && (fast <= wi.c);
+    const int pen = wi.a + w;            // pencil number in the patch
+    const bool live = (tid < nthr) && (pen <= wi.c);
+    const int tf = Pt.n[FA] + thi - tlo + 1;
     const int g = prm.ghost;
     int zc[3];
     zc[D] = zlo + s;
-    zc[FA] = fast;
-    zc[SA] = wi.b;
-    const long long V = Pt.vol;
-    const long long x = live ? sidx(Pt, zc[0] + g, zc[1] + g, zc[2] + g) : 0;
-    const R gam = R(prm.gamma);
-    const R gm1 = gam - R(1);
-    const double dt = dtp[0];
-    const R lam = R(dt / prm.dx[D]);
-    const R* q = pool + Pt.base + (long long)(cur ? F_ST1 : F_ST0) * V;
+    zc[FA] = tlo + pen % tf;
+    zc[SA] = tlo + pen / tf;
+    const int V = (int)Pt.vol;
+    const int st[3] = {1, Pt.N[0], Pt.N[0] * Pt.N[1]};
+    const int x = live ? (zc[0] + g) + st[1] * (zc[1] + g) + st[2] * (zc[2] + g) : 0;
+    const R lam = sc_lam(*sc, D, R(0));
+    R* __restrict__ pp = pool + Pt.base;
+    const R* q = pp + (cur ? F_ST1 : F_ST0) * V;
 
     // ---------------- phase A: zone primitives ----------------
     if (live) {
         R u[8];
 #pragma unroll
-        for (int c = 0; c < 8; c++) u[c] = q[(long long)c * V + x];
+        for (int c = 0; c < 8; c++) u[c] = q[c * V + x];
+        if (STAGE == 1 && D == 0) {
+            // Step 2: reference EMF E^r = -v x B from q^n on [-3, n+2]^3
+            if (zc[0] >= -3 && zc[0] <= Pt.n[0] + 2) {
+                R* er = pp + F_ER * V;
+                R ir = frcp(u[0]);
+                R vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
+                er[x] = vz * u[5] - vy * u[6];
+                er[V + x] = vx * u[6] - vz * u[4];
+                er[2 * V + x] = vy * u[4] - vx * u[5];
+            }
+        }
         if (STAGE == 2) {
-            const R hdt = R(0.5 * dt);
-            const R* fl = pool + Pt.base + (long long)F_FL1 * V;
-            const R* f1 = fl + (long long)(7 * A1) * V;
-            const R* f2 = fl + (long long)(7 * A2) * V;
-            const long long s1 = stride_of(Pt, A1), s2 = stride_of(Pt, A2), sd = stride_of(Pt, D);
-            const R i1 = R(1.0 / prm.dx[A1]), i2 = R(1.0 / prm.dx[A2]);
+            const R hdt = sc_hdt(*sc, R(0));
+            const R* f1 = pp + (F_FL1 + 7 * A1) * V;
+            const R* f2 = pp + (F_FL1 + 7 * A2) * V;
+            const int s1 = st[A1], s2 = st[A2];
+            const R i1 = cf.idx[A1], i2 = cf.idx[A2];
             // rho, m, E (rows 0..4 -> components 0,1,2,3,7)
 #pragma unroll
             for (int r = 0; r < 5; r++) {
                 const int c = r < 4 ? r : 7;
-                R div = (f1[(long long)r * V + x + s1] - f1[(long long)r * V + x]) * i1 +
-                        (f2[(long long)r * V + x + s2] - f2[(long long)r * V + x]) * i2;
+                R div = (f1[r * V + x + s1] - f1[r * V + x]) * i1 + (f2[r * V + x + s2] - f2[r * V + x]) * i2;
                 u[c] -= hdt * div;
             }
             // B_D: flux_A1 row 6 (B_{A1+2}) and flux_A2 row 5 (B_{A2+1})
@@ -500,28 +629,26 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
             // B_t v_t minmod(dB_D/dx_D, -dB_t'/dx_t'), energy B_t . S[B_t]
             const R* b = q + 8 * V;
             R dB[3];
-            const long long st[3] = {1, (long long)Pt.N[0], (long long)Pt.N[0] * Pt.N[1]};
 #pragma unroll
-            for (int a = 0; a < 3; a++) dB[a] = (b[(long long)a * V + x + st[a]] - b[(long long)a * V + x]) / R(prm.dx[a]);
-            (void)sd;
-            R rho0 = q[x];
-            R v1 = q[(long long)(1 + A1) * V + x] / rho0, v2 = q[(long long)(1 + A2) * V + x] / rho0;
-            R B1 = q[(long long)(4 + A1) * V + x], B2 = q[(long long)(4 + A2) * V + x];
-            R sB1 = v1 * R(minmod2((double)dB[D], -(double)dB[A2]));
-            R sB2 = v2 * R(minmod2((double)dB[D], -(double)dB[A1]));
+            for (int a = 0; a < 3; a++) dB[a] = (b[a * V + x + st[a]] - b[a * V + x]) * cf.idx[a];
+            R ir0 = frcp(q[x]);
+            R v1 = q[(1 + A1) * V + x] * ir0, v2 = q[(1 + A2) * V + x] * ir0;
+            R B1 = q[(4 + A1) * V + x], B2 = q[(4 + A2) * V + x];
+            R sB1 = v1 * minmod2(dB[D], -dB[A2]);
+            R sB2 = v2 * minmod2(dB[D], -dB[A1]);
 #pragma unroll
-            for (int c = 0; c < 3; c++) u[1 + c] += hdt * q[(long long)(4 + c) * V + x] * dB[D];
+            for (int c = 0; c < 3; c++) u[1 + c] += hdt * q[(4 + c) * V + x] * dB[D];
             u[4 + A1] += hdt * sB1;
             u[4 + A2] += hdt * sB2;
             u[7] += hdt * (B1 * sB1 + B2 * sB2);
-            apply_floor(u, prm);
+            apply_floor(u, prm, cf);
         }
         R rho = u[0];
-        R ir = R(1) / rho;
+        R ir = frcp(rho);
         R vpar = u[1 + D] * ir, vt1 = u[1 + A1] * ir, vt2 = u[1 + A2] * ir;
         R b2 = u[4] * u[4] + u[5] * u[5] + u[6] * u[6];
-        R pr = gm1 * (u[7] - R(0.5) * rho * (vpar * vpar + vt1 * vt1 + vt2 * vt2) - R(0.5) * b2);
-        if (pr < R(prm.p_floor)) pr = R(prm.p_floor);
+        R pr = cf.gm1 * (u[7] - R(0.5) * rho * (vpar * vpar + vt1 * vt1 + vt2 * vt2) - R(0.5) * b2);
+        if (pr < cf.p_floor) pr = cf.p_floor;
         shp[0 * nthr + tid] = rho;
         shp[1 * nthr + tid] = vpar;
         shp[2 * nthr + tid] = vt1;
@@ -538,7 +665,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
     R bf = R(0);
     const bool face = live && s >= 1;
     if (face) {
-        const R* bsrc = (STAGE == 1) ? (q + (long long)(8 + D) * V) : (pool + Pt.base + (long long)(F_BH + D) * V);
+        const R* bsrc = (STAGE == 1) ? (q + (8 + D) * V) : (pp + (F_BH + D) * V);
         bf = bsrc[x];
         const int tl = tid - sstep;
         R rl = shp[tl], vxl = shp[nthr + tl], vyl = shp[2 * nthr + tl], vzl = shp[3 * nthr + tl];
@@ -546,12 +673,11 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
         R rr = shp[tid], vxr = shp[nthr + tid], vyr = shp[2 * nthr + tid], vzr = shp[3 * nthr + tid];
         R b1r = shp[4 * nthr + tid], b2r = shp[5 * nthr + tid], prr = shp[6 * nthr + tid];
 
-        const R gg = gam / gm1;
         R bf2 = bf * bf;
-        R hl = (gg * pl + R(0.5) * rl * (vxl * vxl + vyl * vyl + vzl * vzl) + bf2 + b1l * b1l + b2l * b2l) / rl;
-        R hr = (gg * prr + R(0.5) * rr * (vxr * vxr + vyr * vyr + vzr * vzr) + bf2 + b1r * b1r + b2r * b2r) / rr;
-        R sl = sqrt(rl), sr = sqrt(rr);
-        R isum = R(1) / (sl + sr);
+        R hl = (cf.ggm * pl + R(0.5) * rl * (vxl * vxl + vyl * vyl + vzl * vzl) + bf2 + b1l * b1l + b2l * b2l) * frcp(rl);
+        R hr = (cf.ggm * prr + R(0.5) * rr * (vxr * vxr + vyr * vyr + vzr * vzr) + bf2 + b1r * b1r + b2r * b2r) * frcp(rr);
+        R sl = fsqrt(rl), sr = fsqrt(rr);
+        R isum = frcp(sl + sr);
         e.rho = sl * sr;
         e.vx = (sl * vxl + sr * vxr) * isum;
         e.vy = (sl * vyl + sr * vyr) * isum;
@@ -563,46 +689,46 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
         e.X = (db1 * db1 + db2 * db2) * R(0.5) * isum * isum;
         R v2 = e.vx * e.vx + e.vy * e.vy + e.vz * e.vz;
         R bt2 = e.b1 * e.b1 + e.b2 * e.b2;
-        R irho = R(1) / e.rho;
-        R a2 = gm1 * (h - R(0.5) * v2 - (bf2 + bt2) * irho) - (gam - R(2)) * e.X;
-        R a2min = gam * R(prm.p_floor) * irho;
+        R irho = frcp(e.rho);
+        R a2 = cf.gm1 * (h - R(0.5) * v2 - (bf2 + bt2) * irho) - cf.gm2 * e.X;
+        R a2min = cf.gam * cf.p_floor * irho;
         if (a2 < a2min) a2 = a2min;
         R ca2 = bf2 * irho, bp2 = bt2 * irho;
         R dpr = a2 - ca2 - bp2;
-        R dd = sqrt(dpr * dpr + R(4) * a2 * bp2);
+        R dd = fsqrt(dpr * dpr + R(4) * a2 * bp2);
         R cf2 = R(0.5) * (a2 + ca2 + bp2 + dd);
-        R cs2 = a2 * ca2 / cf2;
-        const R tol = R(prm.degen_tol);
-        if (dd <= tol * (a2 + ca2 + bp2)) {
+        R cs2 = a2 * ca2 * frcp(cf2);
+        if (dd <= cf.tol * (a2 + ca2 + bp2)) {
             e.alf = R(1);
             e.als = R(0);
         } else {
             R af2, as2;
             if (dpr >= R(0)) {
                 af2 = R(0.5) * (dd + dpr);
-                as2 = a2 * bp2 / af2;
+                as2 = a2 * bp2 * frcp(af2);
             } else {
                 as2 = R(0.5) * (dd - dpr);
-                af2 = a2 * bp2 / as2;
+                af2 = a2 * bp2 * frcp(as2);
             }
-            e.alf = sqrt(af2 / dd);
-            e.als = sqrt(as2 / dd);
+            R idd = frcp(dd);
+            e.alf = fsqrt(af2 * idd);
+            e.als = fsqrt(as2 * idd);
         }
-        if (bt2 <= tol * tol * (bf2 + bt2)) {
+        if (bt2 <= cf.tol2 * (bf2 + bt2)) {
             e.by = R(0.70710678118654752440);
             e.bz = R(0.70710678118654752440);
         } else {
-            R ib = R(1) / sqrt(bt2);
+            R ib = frcp(fsqrt(bt2));
             e.by = e.b1 * ib;
             e.bz = e.b2 * ib;
         }
         e.s = bf >= R(0) ? R(1) : R(-1);
-        e.sq = sqrt(e.rho);
+        e.sq = fsqrt(e.rho);
         e.a2 = a2;
-        e.a = sqrt(a2);
-        e.cf = sqrt(cf2);
-        e.cs = sqrt(cs2);
-        R ca = sqrt(ca2);
+        e.a = fsqrt(a2);
+        e.cf = fsqrt(cf2);
+        e.cs = fsqrt(cs2);
+        R ca = fsqrt(ca2);
 
         // characteristic jumps: alpha_k = L_k . (d rho, d v, d B_t, dP + X d rho)
         R drho = rr - rl;
@@ -610,27 +736,29 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
         R dp = (prr - pl) + e.X * drho;
         R dvpar = e.by * dvy + e.bz * dvz, dvper = -e.bz * dvy + e.by * dvz;
         R dbpar = e.by * db1 + e.bz * db2, dbper = -e.bz * db1 + e.by * db2;
-        R i2a2 = R(0.5) / a2;
-        R ipa = R(1) / (R(2) * e.sq * e.a);
+        R ia2 = frcp(a2);
+        R i2a2 = R(0.5) * ia2;
+        R isq = frcp(e.sq);
+        R ipa = R(0.5) * isq * frcp(e.a);
         R pterm = dp * irho * i2a2;
         R Ef = e.alf * pterm + e.als * dbpar * ipa;
         R Of = (e.alf * e.cf * dvx - e.als * e.cs * e.s * dvpar) * i2a2;
         R Es = e.als * pterm - e.alf * dbpar * ipa;
         R Os = (e.als * e.cs * dvx + e.alf * e.cf * e.s * dvpar) * i2a2;
         R Ea = R(0.5) * dvper;
-        R Oa = -e.s * dbper / (R(2) * e.sq);
+        R Oa = -R(0.5) * e.s * dbper * isq;
         alpha[0] = Ef - Of;
         alpha[6] = Ef + Of;
         alpha[2] = Es - Os;
         alpha[4] = Es + Os;
         alpha[1] = Ea - Oa;
         alpha[5] = Ea + Oa;
-        alpha[3] = drho - dp / a2;
+        alpha[3] = drho - dp * ia2;
         R ev[7] = {e.vx - e.cf, e.vx - ca, e.vx - e.cs, e.vx, e.vx + e.cs, e.vx + ca, e.vx + e.cf};
 #pragma unroll
         for (int k = 0; k < 7; k++) {
             nu[k] = lam * ev[k];
-            R gt = R(0.5) * (qvisc(nu[k], R(prm.eps[k])) - nu[k] * nu[k]) * alpha[k];
+            R gt = R(0.5) * (qvisc(nu[k], cf.eps[k], cf.q4e[k]) - nu[k] * nu[k]) * alpha[k];
             shg[k * nthr + tid] = gt;
         }
     }
@@ -638,17 +766,16 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
 
     // ---------------- phase C: modified flux at faces 2 .. P-2 ----------------
     if (face && s >= 2 && s <= P - 2) {
-        const R beta_l = R(prm.limiter_beta);
         R bet[7];
 #pragma unroll
         for (int k = 0; k < 7; k++) {
             R gm = shg[k * nthr + tid - sstep];
             R g0 = shg[k * nthr + tid];
             R gp = shg[k * nthr + tid + sstep];
-            R gL = sweby(g0, gm, beta_l);  // zone s-1: faces s-1 (left), s (right)
-            R gR = sweby(gp, g0, beta_l);  // zone s: faces s, s+1
-            R gk = (alpha[k] != R(0)) ? (gR - gL) / alpha[k] : R(0);
-            bet[k] = qvisc(nu[k] + gk, R(prm.eps[k])) * alpha[k] - (gL + gR);
+            R gL = sweby(g0, gm, cf.beta_l);  // zone s-1: faces s-1 (left), s (right)
+            R gR = sweby(gp, g0, cf.beta_l);  // zone s: faces s, s+1
+            R gk = (fabs(alpha[k]) > alpha_min(alpha[k])) ? (gR - gL) * frcp(alpha[k]) : R(0);
+            bet[k] = qvisc(nu[k] + gk, cf.eps[k], cf.q4e[k]) * alpha[k] - (gL + gR);
         }
         // correction sum_k beta_k R_k in (rho, v, B_t, P), then mapped to conserved
         R bfp = bet[6] + bet[0], bfm = bet[6] - bet[0];
@@ -668,8 +795,8 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
         R c1 = e.vx * wrho + e.rho * wvx;
         R c2 = e.vy * wrho + e.rho * wvy;
         R c3 = e.vz * wrho + e.rho * wvz;
-        R c7 = (R(0.5) * v2 + (gam - R(2)) * e.X / gm1) * wrho + e.rho * (e.vx * wvx + e.vy * wvy + e.vz * wvz) +
-               e.b1 * wb1 + e.b2 * wb2 + wp / gm1;
+        R c7 = (R(0.5) * v2 + cf.gm2 * e.X * cf.igm1) * wrho + e.rho * (e.vx * wvx + e.vy * wvy + e.vz * wvz) +
+               e.b1 * wb1 + e.b2 * wb2 + wp * cf.igm1;
         // physical fluxes of the two rebuilt face states
         R F[2][7];
 #pragma unroll
@@ -679,7 +806,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
             R b1 = shp[4 * nthr + t], b2 = shp[5 * nthr + t], pr = shp[6 * nthr + t];
             R bb = bf * bf + b1 * b1 + b2 * b2;
             R pt = pr + R(0.5) * bb;
-            R ept = gam / gm1 * pr + R(0.5) * r * (vx * vx + vy * vy + vz * vz) + bb;  // E + P*
+            R ept = cf.ggm * pr + R(0.5) * r * (vx * vx + vy * vy + vz * vz) + bb;  // E + P*
             R mx = r * vx;
             F[side][0] = mx;
             F[side][1] = mx * vx + pt - bf * bf;
@@ -689,7 +816,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
             F[side][5] = b1 * vx - bf * vy;
             F[side][6] = b2 * vx - bf * vz;
         }
-        const R il = R(0.5) / lam;
+        const R il = sc_il(*sc, D, R(0));  // 1 / (2 lambda)
         R out[7];
         out[0] = R(0.5) * (F[0][0] + F[1][0]) - il * c0;
         out[1] = R(0.5) * (F[0][1] + F[1][1]) - il * c1;
@@ -698,12 +825,12 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
         out[4] = R(0.5) * (F[0][4] + F[1][4]) - il * c7;
         out[5] = R(0.5) * (F[0][5] + F[1][5]) - il * wb1;
         out[6] = R(0.5) * (F[0][6] + F[1][6]) - il * wb2;
-        R* fo = pool + Pt.base + (long long)((STAGE == 1 ? F_FL1 : F_FL2) + 7 * D) * V;
+        R* fo = pp + ((STAGE == 1 ? F_FL1 : F_FL2) + 7 * D) * V;
         // frame -> lab rows: m_par -> m_D, m_t1 -> m_A1, m_t2 -> m_A2
         fo[x] = out[0];
-        fo[(long long)(1 + D) * V + x] = out[1];
-        fo[(long long)(1 + A1) * V + x] = out[2];
-        fo[(long long)(1 + A2) * V + x] = out[3];
+        fo[(1 + D) * V + x] = out[1];
+        fo[(1 + A1) * V + x] = out[2];
+        fo[(1 + A2) * V + x] = out[3];
         fo[4 * V + x] = out[4];
         fo[5 * V + x] = out[5];
         fo[6 * V + x] = out[6];
@@ -756,69 +883,74 @@ __global__ void __launch_bounds__(256) diag_kernel(const R* __restrict__ pool, c
 // ---------------------------------------------------------------------------
 
 template <typename R>
-hipError_t launch_fill(void* pool, const PatchDev* pt, const FillRegion* regs, int nreg, int cur, hipStream_t st) {
-    if (nreg <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fill_ghosts_kernel<R>, dim3(nreg), dim3(256), 0, st, (R*)pool, pt, regs, cur);
+hipError_t launch_fill(void* pool, const PatchDev* pt, const WorkItem* const wl[3], const int nw[3], int g, int cur,
+                       hipStream_t st) {
+    if (nw[0] > 0) hipLaunchKernelGGL((fill_pass_kernel<R, 0>), dim3(nw[0]), dim3(256), 0, st, (R*)pool, pt, wl[0], g, cur);
+    if (nw[1] > 0) hipLaunchKernelGGL((fill_pass_kernel<R, 1>), dim3(nw[1]), dim3(256), 0, st, (R*)pool, pt, wl[1], g, cur);
+    if (nw[2] > 0) hipLaunchKernelGGL((fill_pass_kernel<R, 2>), dim3(nw[2]), dim3(256), 0, st, (R*)pool, pt, wl[2], g, cur);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_dt(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, int cur,
-                     unsigned long long* smax, double* dt, hipStream_t st) {
+hipError_t launch_dt_reduce(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, int cur,
+                            unsigned long long* smax, hipStream_t st) {
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, st, smax);
     if (nblk > 0) hipLaunchKernelGGL(dt_reduce_kernel<R>, dim3(nblk), dim3(256), 0, st, (const R*)pool, pt, wk, prm, cur, smax);
-    hipLaunchKernelGGL(dt_finalize_kernel, dim3(1), dim3(1), 0, st, smax, dt, prm.cfl);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt_finalize(unsigned long long* smax, StepConst* sc, const DevParams& prm, hipStream_t st) {
+    hipLaunchKernelGGL(dt_finalize_kernel, dim3(1), dim3(1), 0, st, smax, sc, prm);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_dt(StepConst* sc, double dt, const DevParams& prm, hipStream_t st) {
+    hipLaunchKernelGGL(set_dt_kernel, dim3(1), dim3(1), 0, st, sc, dt, prm);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_emf_ref(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, int cur, Box bx,
-                          hipStream_t st) {
+hipError_t launch_emf_half(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const Coef<R>& cf, int g, int cur,
+                           const StepConst* sc, Box bx, hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(emf_ref_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, prm, cur, bx);
+    hipLaunchKernelGGL(emf_half_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, cf, g, cur, sc, bx);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_emf_half(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, int cur,
-                           const double* dt, Box bx, hipStream_t st) {
+hipError_t launch_edge(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, int g, int fslot, Box bx, EdgeRanges rg,
+                       hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(emf_half_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, prm, cur, dt, bx);
+    hipLaunchKernelGGL(edge_emf_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, g, fslot, bx, rg);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_edge(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, int fslot, Box bx,
-                       EdgeRanges rg, hipStream_t st) {
+hipError_t launch_ct_half(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const Coef<R>& cf, int g, int cur,
+                          const StepConst* sc, Box bx, hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(edge_emf_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, prm, fslot, bx, rg);
+    hipLaunchKernelGGL(ct_half_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, cf, g, cur, sc, bx);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_ct_half(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, int cur,
-                          const double* dt, Box bx, hipStream_t st) {
+hipError_t launch_final(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, const Coef<R>& cf,
+                        int cur, const StepConst* sc, unsigned long long* nfl, unsigned long long* smax, hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(ct_half_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, prm, cur, dt, bx);
-    return hipGetLastError();
-}
-
-template <typename R>
-hipError_t launch_final(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, int cur,
-                        const double* dt, unsigned long long* nfl, hipStream_t st) {
-    if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(final_update_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, prm, cur, dt, nfl);
+    hipLaunchKernelGGL(final_update_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, prm, cf, cur, sc, nfl, smax);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_sweep(int d, int stage, void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm,
-                        int cur, const double* dt, int P, int W, int zlo, hipStream_t st) {
+                        const Coef<R>& cf, int cur, const StepConst* sc, int P, int W, int zlo, int tlo, int thi,
+                        hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
     size_t shmem = sizeof(R) * 14 * (size_t)P * W;
     dim3 blk(P * W);
-#define WMB_SW(DD, SS)                                                                                            \
-    hipLaunchKernelGGL((sweep_kernel<R, DD, SS>), dim3(nblk), blk, shmem, st, (R*)pool, pt, wk, prm, cur, dt, P, W, \
-                       zlo)
+#define WMB_SW(DD, SS)                                                                                               \
+    hipLaunchKernelGGL((sweep_kernel<R, DD, SS>), dim3(nblk), blk, shmem, st, (R*)pool, pt, wk, prm, cf, cur, sc, P, W, \
+                       zlo, tlo, thi)
     if (stage == 1) {
         if (d == 0) WMB_SW(0, 1);
         else if (d == 1) WMB_SW(1, 1);
@@ -842,21 +974,20 @@ hipError_t launch_diag(const void* pool, const PatchDev* pt, const WorkItem* wk,
 
 // explicit instantiations
 #define WMB_INST(R)                                                                                                      \
-    template hipError_t launch_fill<R>(void*, const PatchDev*, const FillRegion*, int, int, hipStream_t);               \
-    template hipError_t launch_dt<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,                \
-                                     unsigned long long*, double*, hipStream_t);                                         \
-    template hipError_t launch_emf_ref<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, Box,      \
-                                          hipStream_t);                                                                  \
-    template hipError_t launch_emf_half<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,          \
-                                           const double*, Box, hipStream_t);                                             \
-    template hipError_t launch_edge<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, Box,         \
-                                       EdgeRanges, hipStream_t);                                                         \
-    template hipError_t launch_ct_half<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,           \
-                                          const double*, Box, hipStream_t);                                              \
-    template hipError_t launch_final<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,             \
-                                        const double*, unsigned long long*, hipStream_t);                                \
-    template hipError_t launch_sweep<R>(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,   \
-                                        const double*, int, int, int, hipStream_t);                                      \
+    template hipError_t launch_fill<R>(void*, const PatchDev*, const WorkItem* const[3], const int[3], int, int,       \
+                                       hipStream_t);                                                                     \
+    template hipError_t launch_dt_reduce<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,         \
+                                            unsigned long long*, hipStream_t);                                           \
+    template hipError_t launch_emf_half<R>(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int,       \
+                                           const StepConst*, Box, hipStream_t);                                          \
+    template hipError_t launch_edge<R>(void*, const PatchDev*, const WorkItem*, int, int, int, Box, EdgeRanges,         \
+                                       hipStream_t);                                                                     \
+    template hipError_t launch_ct_half<R>(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int,        \
+                                          const StepConst*, Box, hipStream_t);                                           \
+    template hipError_t launch_final<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&,  \
+                                        int, const StepConst*, unsigned long long*, unsigned long long*, hipStream_t);   \
+    template hipError_t launch_sweep<R>(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&,        \
+                                        const Coef<R>&, int, const StepConst*, int, int, int, int, int, hipStream_t);    \
     template hipError_t launch_diag<R>(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,        \
                                        double*, hipStream_t);
 WMB_INST(float)

@@ -13,14 +13,15 @@
 #include "wmb_internal.h"
 
 namespace wmb {
-template <typename R> hipError_t launch_fill(void*, const PatchDev*, const FillRegion*, int, int, hipStream_t);
-template <typename R> hipError_t launch_dt(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, unsigned long long*, double*, hipStream_t);
-template <typename R> hipError_t launch_emf_ref(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, Box, hipStream_t);
-template <typename R> hipError_t launch_emf_half(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, const double*, Box, hipStream_t);
-template <typename R> hipError_t launch_edge(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, Box, EdgeRanges, hipStream_t);
-template <typename R> hipError_t launch_ct_half(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, const double*, Box, hipStream_t);
-template <typename R> hipError_t launch_final(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, const double*, unsigned long long*, hipStream_t);
-template <typename R> hipError_t launch_sweep(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, const double*, int, int, int, hipStream_t);
+template <typename R> hipError_t launch_fill(void*, const PatchDev*, const WorkItem* const[3], const int[3], int, int, hipStream_t);
+template <typename R> hipError_t launch_dt_reduce(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, unsigned long long*, hipStream_t);
+hipError_t launch_dt_finalize(unsigned long long*, StepConst*, const DevParams&, hipStream_t);
+hipError_t launch_set_dt(StepConst*, double, const DevParams&, hipStream_t);
+template <typename R> hipError_t launch_emf_half(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int, const StepConst*, Box, hipStream_t);
+template <typename R> hipError_t launch_edge(void*, const PatchDev*, const WorkItem*, int, int, int, Box, EdgeRanges, hipStream_t);
+template <typename R> hipError_t launch_ct_half(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int, const StepConst*, Box, hipStream_t);
+template <typename R> hipError_t launch_final(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, unsigned long long*, unsigned long long*, hipStream_t);
+template <typename R> hipError_t launch_sweep(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, int, int, int, int, int, hipStream_t);
 template <typename R> hipError_t launch_diag(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, double*, hipStream_t);
 }  // namespace wmb
 
@@ -34,13 +35,15 @@ struct DevList {
 };
 
 struct SweepGroup {
-    int P, W, zlo;
+    int P, W, zlo, tlo, thi, n;
     DevList wl;
 };
 
+// What the device signal-speed maximum (smax) holds relative to the current state.
+enum SmaxState { SMAX_ZERO = 0, SMAX_CLEAN = 1, SMAX_DIRTY = 2 };
+
 // Box of each box kernel, interior-relative [lo, n + hi]
 const Box BOX_INTERIOR{0, -1};
-const Box BOX_ER1{-3, 2};
 const Box BOX_EDGE1{-2, 2};
 const Box BOX_CTH{-2, 2};
 const Box BOX_ER2{-1, 0};
@@ -62,12 +65,14 @@ struct wmb_ctx {
     bool own_stream = false;
     int cur = 0;
     PatchDev* d_patch = nullptr;
-    FillRegion* d_fill = nullptr;
-    int nfill = 0;
-    DevList wl_int, wl_er1, wl_edge1, wl_cth, wl_er2, wl_edge2;
+    DevList wl_fill[3];
+    DevList wl_int, wl_diag, wl_edge1, wl_cth, wl_er2, wl_edge2;
+    int smax_state = SMAX_ZERO;
     std::vector<SweepGroup> sweeps[3][2];
     unsigned long long* d_smax = nullptr;
-    double* d_dt = nullptr;
+    StepConst* d_sc = nullptr;
+    Coef<float> cf32{};
+    Coef<double> cf64{};
     unsigned long long* d_nfloor = nullptr;
     double* d_partial = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -79,6 +84,29 @@ struct wmb_ctx {
 };
 
 namespace {
+
+template <typename R> const Coef<R>& coef(const wmb_ctx* c);
+template <> const Coef<float>& coef<float>(const wmb_ctx* c) { return c->cf32; }
+template <> const Coef<double>& coef<double>(const wmb_ctx* c) { return c->cf64; }
+
+template <typename R>
+void make_coef(const wmb_params& p, Coef<R>& cf) {
+    cf.gam = (R)p.gamma;
+    cf.gm1 = (R)(p.gamma - 1.0);
+    cf.gm2 = (R)(p.gamma - 2.0);
+    cf.ggm = (R)(p.gamma / (p.gamma - 1.0));
+    cf.igm1 = (R)(1.0 / (p.gamma - 1.0));
+    cf.beta_l = (R)p.limiter_beta;
+    cf.p_floor = (R)p.p_floor;
+    cf.rho_floor = (R)p.rho_floor;
+    cf.tol = (R)p.degen_tol;
+    cf.tol2 = (R)(p.degen_tol * p.degen_tol);
+    for (int a = 0; a < 3; a++) cf.idx[a] = (R)(1.0 / p.dx[a]);
+    for (int k = 0; k < 7; k++) {
+        cf.eps[k] = (R)p.eps[k];
+        cf.q4e[k] = p.eps[k] > 0.0 ? (R)(0.25 / p.eps[k]) : (R)0;
+    }
+}
 
 int fail(wmb_ctx* c, int code, const std::string& msg) {
     if (c) c->err = msg;
@@ -101,6 +129,24 @@ int dev_alloc(wmb_ctx* c, T** ptr, size_t count) {
     c->owned.push_back(p);
     *ptr = static_cast<T*>(p);
     return WMB_OK;
+}
+
+// Workgroups are dispatched to the 8 XCDs round-robin by workgroup id, and
+// each XCD has its own L2.  Reorder a work list so that all blocks of a patch
+// run on the same XCD (patch p -> XCD p mod 8) in their original order: block
+// id 8 j + x takes the j-th item of XCD x's queue.  Queues are padded with
+// empty items (patch = -1) that exit at once.
+constexpr int NXCD = 8;
+std::vector<WorkItem> xcd_order(const std::vector<WorkItem>& items) {
+    std::vector<std::vector<WorkItem>> q(NXCD);
+    for (const WorkItem& w : items) q[w.patch % NXCD].push_back(w);
+    size_t len = 0;
+    for (auto& v : q) len = v.size() > len ? v.size() : len;
+    std::vector<WorkItem> out;
+    out.reserve(len * NXCD);
+    for (size_t j = 0; j < len; j++)
+        for (int x = 0; x < NXCD; x++) out.push_back(j < q[x].size() ? q[x][j] : WorkItem{-1, 0, 0, 0});
+    return out;
 }
 
 template <typename T>
@@ -167,6 +213,16 @@ int check_table(int32_t np, const wmb_patch_desc* d, int g, std::string& why) {
                 why = "patch " + std::to_string(i) + ": neighbour table not symmetric";
                 return WMB_EINVAL;
             }
+            // edge and corner neighbours are reached through face neighbours
+            // (z, then y, then x): the ghost exchange copies along that chain
+            int r = i;
+            if (off[2]) r = d[r].nbr[9 * (off[2] + 1) + 4];
+            if (off[1]) r = d[r].nbr[9 + 3 * (off[1] + 1) + 1];
+            if (off[0]) r = d[r].nbr[12 + off[0] + 1];
+            if (r != q) {
+                why = "patch " + std::to_string(i) + ": edge/corner neighbour inconsistent with the face neighbours";
+                return WMB_EINVAL;
+            }
         }
     }
     return WMB_OK;
@@ -178,16 +234,28 @@ void mark(wmb_ctx* c) {
 
 template <typename R>
 int run_fill(wmb_ctx* c) {
-    hipError_t e = launch_fill<R>(c->pool, c->d_patch, c->d_fill, c->nfill, c->cur, c->stream);
+    const WorkItem* wl[3] = {c->wl_fill[0].d, c->wl_fill[1].d, c->wl_fill[2].d};
+    const int nw[3] = {c->wl_fill[0].n, c->wl_fill[1].n, c->wl_fill[2].n};
+    hipError_t e = launch_fill<R>(c->pool, c->d_patch, wl, nw, c->p.ghost, c->cur, c->stream);
     if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("fill_ghosts: ") + hipGetErrorString(e));
     mark(c);
     return WMB_OK;
 }
 
+// make smax the signal-speed maximum of the current state (explicit reduction)
 template <typename R>
-int run_dt(wmb_ctx* c) {
-    hipError_t e = launch_dt<R>(c->pool, c->d_patch, c->wl_int.d, c->wl_int.n, c->dp, c->cur, c->d_smax, c->d_dt, c->stream);
+int run_reduce(wmb_ctx* c) {
+    hipError_t e = launch_dt_reduce<R>(c->pool, c->d_patch, c->wl_int.d, c->wl_int.n, c->dp, c->cur, c->d_smax, c->stream);
     if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("dt_reduce: ") + hipGetErrorString(e));
+    c->smax_state = SMAX_CLEAN;
+    return WMB_OK;
+}
+
+// dt = cfl / smax (smax then reset to zero)
+int run_finalize(wmb_ctx* c) {
+    hipError_t e = launch_dt_finalize(c->d_smax, c->d_sc, c->dp, c->stream);
+    if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("dt_finalize: ") + hipGetErrorString(e));
+    c->smax_state = SMAX_ZERO;
     mark(c);
     return WMB_OK;
 }
@@ -198,50 +266,61 @@ int run_step(wmb_ctx* c) {
     const int cur = c->cur;
 #define STEPCK(what)                                                                        \
     if (e != hipSuccess) return fail(c, WMB_EHIP, std::string(what) + ": " + hipGetErrorString(e))
-    e = launch_emf_ref<R>(c->pool, c->d_patch, c->wl_er1.d, c->wl_er1.n, c->dp, cur, BOX_ER1, c->stream);
-    STEPCK("emf_ref");
-    mark(c);
     for (int d = 0; d < 3; d++) {
         for (auto& G : c->sweeps[d][0]) {
-            e = launch_sweep<R>(d, 1, c->pool, c->d_patch, G.wl.d, G.wl.n, c->dp, cur, c->d_dt, G.P, G.W, G.zlo, c->stream);
+            e = launch_sweep<R>(d, 1, c->pool, c->d_patch, G.wl.d, G.wl.n, c->dp, coef<R>(c), cur, c->d_sc, G.P, G.W,
+                                G.zlo, G.tlo, G.thi, c->stream);
             STEPCK("sweep1");
         }
         mark(c);
     }
-    e = launch_edge<R>(c->pool, c->d_patch, c->wl_edge1.d, c->wl_edge1.n, c->dp, F_FL1, BOX_EDGE1, EdgeRanges{-1, 0, -2, 2},
-                       c->stream);
+    e = launch_edge<R>(c->pool, c->d_patch, c->wl_edge1.d, c->wl_edge1.n, c->p.ghost, F_FL1, BOX_EDGE1,
+                       EdgeRanges{-1, 0, -2, 2}, c->stream);
     STEPCK("edge_emf1");
     mark(c);
-    e = launch_ct_half<R>(c->pool, c->d_patch, c->wl_cth.d, c->wl_cth.n, c->dp, cur, c->d_dt, BOX_CTH, c->stream);
+    e = launch_ct_half<R>(c->pool, c->d_patch, c->wl_cth.d, c->wl_cth.n, coef<R>(c), c->p.ghost, cur, c->d_sc, BOX_CTH,
+                          c->stream);
     STEPCK("ct_half");
     mark(c);
     for (int d = 0; d < 3; d++) {
         for (auto& G : c->sweeps[d][1]) {
-            e = launch_sweep<R>(d, 2, c->pool, c->d_patch, G.wl.d, G.wl.n, c->dp, cur, c->d_dt, G.P, G.W, G.zlo, c->stream);
+            e = launch_sweep<R>(d, 2, c->pool, c->d_patch, G.wl.d, G.wl.n, c->dp, coef<R>(c), cur, c->d_sc, G.P, G.W,
+                                G.zlo, G.tlo, G.thi, c->stream);
             STEPCK("sweep2");
         }
         mark(c);
     }
-    e = launch_emf_half<R>(c->pool, c->d_patch, c->wl_er2.d, c->wl_er2.n, c->dp, cur, c->d_dt, BOX_ER2, c->stream);
+    e = launch_emf_half<R>(c->pool, c->d_patch, c->wl_er2.d, c->wl_er2.n, coef<R>(c), c->p.ghost, cur, c->d_sc, BOX_ER2,
+                           c->stream);
     STEPCK("emf_half");
     mark(c);
-    e = launch_edge<R>(c->pool, c->d_patch, c->wl_edge2.d, c->wl_edge2.n, c->dp, F_FL2, BOX_EDGE2, EdgeRanges{0, -1, 0, 0},
-                       c->stream);
+    e = launch_edge<R>(c->pool, c->d_patch, c->wl_edge2.d, c->wl_edge2.n, c->p.ghost, F_FL2, BOX_EDGE2,
+                       EdgeRanges{0, -1, 0, 0}, c->stream);
     STEPCK("edge_emf2");
     mark(c);
-    e = launch_final<R>(c->pool, c->d_patch, c->wl_int.d, c->wl_int.n, c->dp, cur, c->d_dt, c->d_nfloor, c->stream);
+    e = launch_final<R>(c->pool, c->d_patch, c->wl_int.d, c->wl_int.n, c->dp, coef<R>(c), cur, c->d_sc, c->d_nfloor,
+                        c->d_smax, c->stream);
     STEPCK("final_update");
     mark(c);
 #undef STEPCK
     c->cur ^= 1;
+    // the final update folds the new state's signal speeds into smax
+    c->smax_state = (c->smax_state == SMAX_ZERO) ? SMAX_CLEAN : SMAX_DIRTY;
     return WMB_OK;
 }
 
 int dispatch_fill(wmb_ctx* c) { return c->esize == 4 ? run_fill<float>(c) : run_fill<double>(c); }
-int dispatch_dt(wmb_ctx* c) { return c->esize == 4 ? run_dt<float>(c) : run_dt<double>(c); }
+int ensure_smax(wmb_ctx* c) {
+    if (c->smax_state == SMAX_CLEAN) return WMB_OK;
+    return c->esize == 4 ? run_reduce<float>(c) : run_reduce<double>(c);
+}
+int dispatch_dt(wmb_ctx* c) {
+    int rc = ensure_smax(c);
+    return rc ? rc : run_finalize(c);
+}
 int dispatch_step(wmb_ctx* c) { return c->esize == 4 ? run_step<float>(c) : run_step<double>(c); }
 
-int build_box_list(wmb_ctx* c, Box bx, DevList& out) {
+int build_box_list(wmb_ctx* c, Box bx, DevList& out, bool xcd = true) {
     std::vector<WorkItem> items;
     for (int p = 0; p < c->npatch; p++) {
         long long e = 1;
@@ -249,8 +328,30 @@ int build_box_list(wmb_ctx* c, Box bx, DevList& out) {
         int nb = (int)((e + 255) / 256);
         for (int b = 0; b < nb; b++) items.push_back(WorkItem{p, b, 0, 0});
     }
+    if (xcd) items = xcd_order(items);
     out.n = (int)items.size();
     return upload(c, &out.d, items);
+}
+
+int build_fill_lists(wmb_ctx* c) {
+    const int g = c->p.ghost;
+    for (int ax = 0; ax < 3; ax++) {
+        std::vector<WorkItem> items;
+        for (int p = 0; p < c->npatch; p++) {
+            const int* n = c->desc[p].n;
+            long long e;
+            if (ax == 0) e = 2LL * g * n[1] * n[2];
+            else if (ax == 1) e = 2LL * g * (n[0] + 2 * g) * n[2];
+            else e = 2LL * g * (n[0] + 2 * g) * (n[1] + 2 * g);
+            int nb = (int)((e + 255) / 256);
+            for (int b = 0; b < nb; b++) items.push_back(WorkItem{p, b, 0, 0});
+        }
+        items = xcd_order(items);
+        c->wl_fill[ax].n = (int)items.size();
+        int rc = upload(c, &c->wl_fill[ax].d, items);
+        if (rc) return rc;
+    }
+    return WMB_OK;
 }
 
 int choose_W(int d, int P, size_t es) {
@@ -263,10 +364,23 @@ int choose_W(int d, int P, size_t es) {
     return W;
 }
 
+// pencils of every patch whose edge along d is n, W consecutive pencils a block
+std::vector<WorkItem> sweep_items(const wmb_ctx* c, int d, int n, int tlo, int thi, int W) {
+    const int FA = (d == 0) ? 1 : 0;
+    const int SA = (d == 0) ? 2 : (d == 1 ? 2 : 1);
+    std::vector<WorkItem> items;
+    for (int p = 0; p < c->npatch; p++) {
+        if (c->desc[p].n[d] != n) continue;
+        int tf = c->desc[p].n[FA] + thi - tlo + 1, ts = c->desc[p].n[SA] + thi - tlo + 1;
+        int npen = tf * ts;
+        for (int p0 = 0; p0 < npen; p0 += W)
+            items.push_back(WorkItem{p, p0, 0, (p0 + W - 1 < npen - 1) ? p0 + W - 1 : npen - 1});
+    }
+    return xcd_order(items);
+}
+
 int build_sweeps(wmb_ctx* c) {
     for (int d = 0; d < 3; d++) {
-        const int FA = (d == 0) ? 1 : 0;
-        const int SA = (d == 0) ? 2 : (d == 1 ? 2 : 1);
         for (int stage = 0; stage < 2; stage++) {
             const int zlo = stage == 0 ? -4 : -3;
             const int extra = stage == 0 ? 8 : 6;
@@ -283,15 +397,11 @@ int build_sweeps(wmb_ctx* c) {
                 SweepGroup G;
                 G.P = n + extra;
                 G.zlo = zlo;
+                G.tlo = tlo;
+                G.thi = thi;
+                G.n = n;
                 G.W = choose_W(d, G.P, c->esize);
-                std::vector<WorkItem> items;
-                for (int p = 0; p < c->npatch; p++) {
-                    if (c->desc[p].n[d] != n) continue;
-                    int fhi = c->desc[p].n[FA] + thi, shi = c->desc[p].n[SA] + thi;
-                    for (int sl = tlo; sl <= shi; sl++)
-                        for (int f0 = tlo; f0 <= fhi; f0 += G.W)
-                            items.push_back(WorkItem{p, f0, sl, (f0 + G.W - 1 < fhi) ? f0 + G.W - 1 : fhi});
-                }
+                std::vector<WorkItem> items = sweep_items(c, d, n, tlo, thi, G.W);
                 G.wl.n = (int)items.size();
                 int rc = upload(c, &G.wl.d, items);
                 if (rc) return rc;
@@ -300,41 +410,6 @@ int build_sweeps(wmb_ctx* c) {
         }
     }
     return WMB_OK;
-}
-
-int build_fill(wmb_ctx* c) {
-    const int g = c->p.ghost;
-    std::vector<FillRegion> regs;
-    for (int i = 0; i < c->npatch; i++) {
-        const wmb_patch_desc& D = c->desc[i];
-        for (int t = 0; t < 27; t++) {
-            if (t == 13) continue;
-            int off[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
-            int q = D.nbr[t];
-            const wmb_patch_desc& S = c->desc[q];
-            FillRegion r;
-            r.dst = i;
-            r.src = q;
-            for (int a = 0; a < 3; a++) {
-                if (off[a] < 0) {
-                    r.d0[a] = 0;
-                    r.s0[a] = S.n[a];
-                    r.ext[a] = g;
-                } else if (off[a] > 0) {
-                    r.d0[a] = g + D.n[a];
-                    r.s0[a] = g;
-                    r.ext[a] = g;
-                } else {
-                    r.d0[a] = g;
-                    r.s0[a] = g;
-                    r.ext[a] = D.n[a];
-                }
-            }
-            regs.push_back(r);
-        }
-    }
-    c->nfill = (int)regs.size();
-    return upload(c, &c->d_fill, regs);
 }
 
 void free_graphs(wmb_ctx* c) {
@@ -346,17 +421,22 @@ void free_graphs(wmb_ctx* c) {
     }
 }
 
+// One graph per state copy: fill ghosts, dt = cfl / smax, step (whose final
+// update refills smax for the next replay).  Replays require smax to hold the
+// current state's maximum at their start.
 int capture_graphs(wmb_ctx* c) {
+    const int saved_state = c->smax_state;
     for (int k = 0; k < 2; k++) {
         const int cur0 = c->cur;
         CKH(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
         int rc = dispatch_fill(c);
-        if (!rc) rc = dispatch_dt(c);
+        if (!rc) rc = run_finalize(c);
         if (!rc) rc = dispatch_step(c);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->stream, &g);
         if (rc) {
             if (g) hipGraphDestroy(g);
+            c->smax_state = saved_state;
             return rc;
         }
         if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
@@ -364,6 +444,7 @@ int capture_graphs(wmb_ctx* c) {
         CKH(hipGraphInstantiate(&c->gexec[cur0], g, nullptr, nullptr, 0));
         // dispatch_step flipped cur; the second capture covers the other copy
     }
+    c->smax_state = saved_state;  // nothing ran during capture
     return WMB_OK;
 }
 
@@ -411,6 +492,7 @@ int set_state_t(wmb_ctx* c, int ip, const double* q, const double* b) {
     }
     std::vector<R> buf((size_t)P.vol, (R)NAN);
     R* base = (R*)c->pool + P.base + (long long)(c->cur ? F_ST1 : F_ST0) * P.vol;
+    if (c->smax_state != SMAX_ZERO) c->smax_state = SMAX_DIRTY;
     for (int f = 0; f < 11; f++) {
         const double* src = f < 8 ? q + f * n3 : b + (f - 8) * n3;
         to_device_layout<R>(src, buf.data(), P, g, n3);
@@ -478,15 +560,15 @@ int debug_stage_t(wmb_ctx* c, int ip, int stage, double* out) {
 
 template <typename R>
 int diagnostics_t(wmb_ctx* c, double totals[8], double* dn, double* dr, int64_t* nfl) {
-    hipError_t e = launch_diag<R>(c->pool, c->d_patch, c->wl_int.d, c->wl_int.n, c->dp, c->cur, c->d_partial, c->stream);
+    hipError_t e = launch_diag<R>(c->pool, c->d_patch, c->wl_diag.d, c->wl_diag.n, c->dp, c->cur, c->d_partial, c->stream);
     if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("diag: ") + hipGetErrorString(e));
-    std::vector<double> part((size_t)c->wl_int.n * 10);
+    std::vector<double> part((size_t)c->wl_diag.n * 10);
     CKH(hipMemcpyAsync(part.data(), c->d_partial, sizeof(double) * part.size(), hipMemcpyDeviceToHost, c->stream));
     unsigned long long nf = 0;
     CKH(hipMemcpyAsync(&nf, c->d_nfloor, sizeof(nf), hipMemcpyDeviceToHost, c->stream));
     CKH(hipStreamSynchronize(c->stream));
     double sum[9] = {0}, comp[9] = {0}, mx = 0.0;
-    for (int b = 0; b < c->wl_int.n; b++) {
+    for (int b = 0; b < c->wl_diag.n; b++) {
         for (int k = 0; k < 9; k++) {
             double y = part[(size_t)b * 10 + k] - comp[k];
             double t = sum[k] + y;
@@ -505,6 +587,91 @@ int diagnostics_t(wmb_ctx* c, double totals[8], double* dn, double* dr, int64_t*
     if (dr) *dr = mx;
     if (dn) *dn = mx * dmin / brms;
     if (nfl) *nfl = (int64_t)nf;
+    return WMB_OK;
+}
+
+// Sweep block shape search.  The pencil count per block W changes only the
+// grouping of pencils into blocks, never the arithmetic of a face, so results
+// are bitwise independent of the choice.  Timed on the current state: ghosts
+// are refreshed and dt formed, then every candidate of each sweep group is
+// launched (writing only step intermediates); the fastest W is kept.
+template <typename R>
+int autotune_t(wmb_ctx* c, int reps) {
+    int rc = dispatch_fill(c);
+    if (!rc) rc = ensure_smax(c);
+    if (!rc) rc = run_finalize(c);
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    CKH(hipEventCreate(&e0));
+    CKH(hipEventCreate(&e1));
+    const size_t es = sizeof(R);
+    for (int stage = 0; stage < 2; stage++) {
+        if (stage == 1) {
+            // intermediates the corrector sweeps read: Step-1 fluxes, edges, b^{n+1/2}
+            hipError_t e = hipSuccess;
+            for (int d = 0; d < 3 && e == hipSuccess; d++)
+                for (auto& G : c->sweeps[d][0])
+                    e = launch_sweep<R>(d, 1, c->pool, c->d_patch, G.wl.d, G.wl.n, c->dp, coef<R>(c), c->cur, c->d_sc, G.P,
+                                        G.W, G.zlo, G.tlo, G.thi, c->stream);
+            if (e == hipSuccess)
+                e = launch_edge<R>(c->pool, c->d_patch, c->wl_edge1.d, c->wl_edge1.n, c->p.ghost, F_FL1, BOX_EDGE1,
+                                   EdgeRanges{-1, 0, -2, 2}, c->stream);
+            if (e == hipSuccess)
+                e = launch_ct_half<R>(c->pool, c->d_patch, c->wl_cth.d, c->wl_cth.n, coef<R>(c), c->p.ghost, c->cur,
+                                      c->d_sc, BOX_CTH, c->stream);
+            if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+        }
+        for (int d = 0; d < 3; d++) {
+            for (auto& G : c->sweeps[d][stage]) {
+                std::vector<int> cand;
+                const int opts_x[] = {1, 2, 3, 4, 6, 8, 12, 16, 24};
+                const int opts_t[] = {2, 4, 8, 16, 32};
+                if (d == 0)
+                    for (int W : opts_x) cand.push_back(W);
+                else
+                    for (int W : opts_t) cand.push_back(W);
+                float best = 1e30f;
+                int bestW = G.W;
+                for (int W : cand) {
+                    if ((size_t)G.P * W > 1024 || es * 14 * (size_t)G.P * W > 64 * 1024 || G.P * W < 64) continue;
+                    std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, W);
+                    WorkItem* dl = nullptr;
+                    CKH(hipMalloc(&dl, sizeof(WorkItem) * items.size()));
+                    CKH(hipMemcpy(dl, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
+                    float tot = 0.f;
+                    hipError_t e = hipSuccess;
+                    for (int r = 0; r <= reps && e == hipSuccess; r++) {
+                        CKH(hipEventRecord(e0, c->stream));
+                        e = launch_sweep<R>(d, stage + 1, c->pool, c->d_patch, dl, (int)items.size(), c->dp, coef<R>(c),
+                                            c->cur, c->d_sc, G.P, W, G.zlo, G.tlo, G.thi, c->stream);
+                        CKH(hipEventRecord(e1, c->stream));
+                        CKH(hipEventSynchronize(e1));
+                        float t = 0.f;
+                        CKH(hipEventElapsedTime(&t, e0, e1));
+                        if (r > 0) tot += t;  // first launch is a warm-up
+                    }
+                    hipFree(dl);
+                    if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+                    if (tot < best) {
+                        best = tot;
+                        bestW = W;
+                    }
+                }
+                if (bestW != G.W) {
+                    std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, bestW);
+                    WorkItem* dl = nullptr;
+                    int rc2 = upload(c, &dl, items);
+                    if (rc2) return rc2;
+                    G.W = bestW;
+                    G.wl.d = dl;
+                    G.wl.n = (int)items.size();
+                }
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    free_graphs(c);  // launch plans changed
     return WMB_OK;
 }
 
@@ -528,6 +695,8 @@ int wmb_create(const wmb_params* p, wmb_ctx** out) {
     c->dp.gamma = p->gamma;
     c->dp.cfl = p->cfl;
     for (int k = 0; k < 7; k++) c->dp.eps[k] = p->eps[k];
+    make_coef(*p, c->cf32);
+    make_coef(*p, c->cf64);
     c->dp.limiter_beta = p->limiter_beta;
     c->dp.rho_floor = p->rho_floor;
     c->dp.p_floor = p->p_floor;
@@ -578,27 +747,31 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
         }
         P.vol = vol_of(d[i], g);
         P.base = (long long)(off / c->esize);
+        const int faces[6] = {12, 14, 10, 16, 4, 22};
+        for (int t = 0; t < 6; t++) P.nb[t] = d[i].nbr[faces[t]];
+        P.pad_ = 0;
         off += region_bytes(d[i], g, c->esize);
     }
     int rc;
     if ((rc = upload(c, &c->d_patch, c->hpatch))) return rc;
-    if ((rc = build_fill(c))) return rc;
+    if ((rc = build_fill_lists(c))) return rc;
     if ((rc = build_box_list(c, BOX_INTERIOR, c->wl_int))) return rc;
-    if ((rc = build_box_list(c, BOX_ER1, c->wl_er1))) return rc;
+    if ((rc = build_box_list(c, BOX_INTERIOR, c->wl_diag, false))) return rc;
     if ((rc = build_box_list(c, BOX_EDGE1, c->wl_edge1))) return rc;
     if ((rc = build_box_list(c, BOX_CTH, c->wl_cth))) return rc;
     if ((rc = build_box_list(c, BOX_ER2, c->wl_er2))) return rc;
     if ((rc = build_box_list(c, BOX_EDGE2, c->wl_edge2))) return rc;
     if ((rc = build_sweeps(c))) return rc;
     if ((rc = dev_alloc(c, &c->d_smax, 1))) return rc;
-    if ((rc = dev_alloc(c, &c->d_dt, 1))) return rc;
+    if ((rc = dev_alloc(c, &c->d_sc, 1))) return rc;
     if ((rc = dev_alloc(c, &c->d_nfloor, 1))) return rc;
-    if ((rc = dev_alloc(c, &c->d_partial, (size_t)c->wl_int.n * 10))) return rc;
+    if ((rc = dev_alloc(c, &c->d_partial, (size_t)c->wl_diag.n * 10))) return rc;
     CKH(hipMemsetAsync(c->d_smax, 0, sizeof(unsigned long long), c->stream));
-    CKH(hipMemsetAsync(c->d_dt, 0, sizeof(double), c->stream));
+    CKH(hipMemsetAsync(c->d_sc, 0, sizeof(StepConst), c->stream));
     CKH(hipMemsetAsync(c->d_nfloor, 0, sizeof(unsigned long long), c->stream));
     CKH(hipStreamSynchronize(c->stream));
     c->cur = 0;
+    c->smax_state = SMAX_ZERO;
     c->inited = true;
     return WMB_OK;
 }
@@ -636,7 +809,7 @@ int wmb_compute_dt(wmb_ctx* c, double* dt_out) {
     int rc = dispatch_dt(c);
     if (rc) return rc;
     if (dt_out) {
-        CKH(hipMemcpyAsync(dt_out, c->d_dt, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        CKH(hipMemcpyAsync(dt_out, &c->d_sc->dt, sizeof(double), hipMemcpyDeviceToHost, c->stream));
         CKH(hipStreamSynchronize(c->stream));
     }
     return WMB_OK;
@@ -651,8 +824,7 @@ int wmb_advance(wmb_ctx* c, double dt) {
         int rc = wmb_compute_dt(c, &lim);
         if (rc) return rc;
         if (dt > lim * (1.0 + 1e-12)) return fail(c, WMB_ECFL, "dt above the CFL limit " + std::to_string(lim));
-        CKH(hipMemcpyAsync(c->d_dt, &dt, sizeof(double), hipMemcpyHostToDevice, c->stream));
-        CKH(hipStreamSynchronize(c->stream));
+        CKH(launch_set_dt(c->d_sc, dt, c->dp, c->stream));
     }
     return dispatch_step(c);
 }
@@ -669,10 +841,13 @@ int wmb_run_steps(wmb_ctx* c, int32_t nsteps) {
             return rc;
         }
     }
+    int rc = ensure_smax(c);
+    if (rc) return rc;
     for (int s = 0; s < nsteps; s++) {
         CKH(hipGraphLaunch(c->gexec[c->cur], c->stream));
         c->cur ^= 1;
     }
+    c->smax_state = SMAX_CLEAN;
     return WMB_OK;
 }
 
@@ -690,17 +865,41 @@ int wmb_debug_stage(wmb_ctx* c, int32_t patch, int32_t stage, double* out) {
     return c->esize == 4 ? debug_stage_t<float>(c, patch, stage, out) : debug_stage_t<double>(c, patch, stage, out);
 }
 
+int wmb_autotune(wmb_ctx* c, int32_t reps, int32_t* chosen, int32_t nchosen) {
+    if (!c) return WMB_EINVAL;
+    if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
+    if (reps < 1) reps = 1;
+    int rc = c->esize == 4 ? autotune_t<float>(c, reps) : autotune_t<double>(c, reps);
+    if (rc) return rc;
+    if (chosen) {
+        int k = 0;
+        for (int stage = 0; stage < 2; stage++)
+            for (int d = 0; d < 3; d++)
+                for (auto& G : c->sweeps[d][stage]) {
+                    if (k + 4 > nchosen) return WMB_OK;
+                    chosen[k++] = stage + 1;
+                    chosen[k++] = d;
+                    chosen[k++] = G.n;
+                    chosen[k++] = G.W;
+                }
+        if (k < nchosen) chosen[k] = 0;
+    }
+    return WMB_OK;
+}
+
 int wmb_profile_step(wmb_ctx* c, double* ms, int32_t nclass) {
     if (!c || !ms) return WMB_EINVAL;
     if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
     if (nclass < WMB_NCLASS) return fail(c, WMB_EINVAL, "ms must hold WMB_NCLASS entries");
+    int rc = ensure_smax(c);
+    if (rc) return rc;
     hipEvent_t ev[WMB_NCLASS + 1];
     for (int i = 0; i <= WMB_NCLASS; i++) CKH(hipEventCreate(&ev[i]));
     CKH(hipEventRecord(ev[0], c->stream));
     c->marks = ev + 1;
     c->nmark = 0;
-    int rc = dispatch_fill(c);
-    if (!rc) rc = dispatch_dt(c);
+    rc = dispatch_fill(c);
+    if (!rc) rc = run_finalize(c);
     if (!rc) rc = dispatch_step(c);
     c->marks = nullptr;
     if (!rc && c->nmark != WMB_NCLASS) rc = fail(c, WMB_EHIP, "profile: unexpected kernel count");

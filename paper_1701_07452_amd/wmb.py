@@ -21,9 +21,9 @@ WMB_FP64, WMB_FP32 = 0, 1
 EXPORTS = [
     "wmb_create", "wmb_pool_bytes", "wmb_init_patches", "wmb_set_state", "wmb_get_state", "wmb_get_stored",
     "wmb_fill_ghosts", "wmb_compute_dt", "wmb_advance", "wmb_run_steps", "wmb_diagnostics", "wmb_debug_stage",
-    "wmb_profile_step", "wmb_destroy", "wmb_strerror", "wmb_last_error",
+    "wmb_autotune", "wmb_profile_step", "wmb_destroy", "wmb_strerror", "wmb_last_error",
 ]
-KERNEL_CLASSES = ["fill", "dt", "emf_ref", "sweep1_x", "sweep1_y", "sweep1_z", "edge1", "ct_half",
+KERNEL_CLASSES = ["fill", "dt", "sweep1_x", "sweep1_y", "sweep1_z", "edge1", "ct_half",
                   "sweep2_x", "sweep2_y", "sweep2_z", "emf_half", "edge2", "final"]
 
 
@@ -96,6 +96,7 @@ def load_library():
     lib.wmb_diagnostics.argtypes = [vp, dp, dp, dp, C.POINTER(C.c_int64)]
     lib.wmb_debug_stage.argtypes = [vp, C.c_int32, C.c_int32, dp]
     lib.wmb_profile_step.argtypes = [vp, dp, C.c_int32]
+    lib.wmb_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.c_int32]
     lib.wmb_destroy.argtypes = [vp]
     lib.wmb_strerror.argtypes = [C.c_int]
     lib.wmb_strerror.restype = C.c_char_p
@@ -232,6 +233,16 @@ class Sim:
         out = np.zeros((nw,) + sh)
         self._check(self.lib.wmb_debug_stage(self.h, ip, stage, _dp(out)))
         return out.reshape((3, 8) + sh) if nw == 24 else out
+
+    def autotune(self, reps=3):
+        """Pick the sweep block shapes by timing; returns {(stage, axis, edge): pencils per block}."""
+        buf = (C.c_int32 * 256)()
+        self._check(self.lib.wmb_autotune(self.h, int(reps), buf, 256))
+        out, k = {}, 0
+        while k + 4 <= 256 and buf[k] != 0:
+            out[(buf[k], buf[k + 1], buf[k + 2])] = buf[k + 3]
+            k += 4
+        return out
 
     def profile_step(self):
         """Per-kernel-class durations (ms) of one eager step; advances the state."""

@@ -345,3 +345,22 @@ def test_full_size_uneven_400_fp32_sampled(wmb):
     samples = [int(np.argmax(sizes)), int(np.argmin(sizes)), 123]
     w = _sampled_full_size(wmb, G, q, b, 1, samples, 2e-5, 1e-6, dx=(1 / 256,) * 3)
     print("uneven fp32 sampled worst rel max %.2e" % w)
+
+
+def test_autotune_does_not_change_results(wmb):
+    """The sweep block shape is a scheduling choice only: results bitwise equal."""
+    G, (q, b) = CASES["uneven"]()
+    N = G.shape
+    dx = (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
+    outs = []
+    for tune in (False, True):
+        for prec in (1, 0):
+            sim = gpu_sim(wmb, G, q, b, prec, dx=dx)
+            if tune:
+                chosen = sim.autotune(reps=1)
+                assert chosen, "autotune returned no groups"
+            sim.run_steps(3)
+            outs.append(I.gather(G, [sim.get_state(i) for i in range(G.npatch)]))
+            sim.close()
+    for a, b2 in ((outs[0], outs[2]), (outs[1], outs[3])):
+        assert np.array_equal(a[0], b2[0]) and np.array_equal(a[1], b2[1])
