@@ -81,6 +81,27 @@ __device__ __forceinline__ double sc_lam(const StepConst& s, int d, double) { re
 __device__ __forceinline__ float sc_il(const StepConst& s, int d, float) { return s.fil[d]; }
 __device__ __forceinline__ double sc_il(const StepConst& s, int d, double) { return s.il[d]; }
 
+// Raw buffer access to one patch region: SGPR descriptor, 32-bit VGPR byte
+// offset of the zone, SGPR byte offset of the field (and of a neighbour
+// shift), so no per-load 64-bit address arithmetic is spent.
+constexpr int BUF_DWORD3 = 0x00020000;  // raw dword buffer, gfx9-family format
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t patch_rsrc(void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, BUF_DWORD3);
+}
+__device__ __forceinline__ float bload(float, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ double bload(double, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+}
+
 __device__ __forceinline__ long long sidx(const PatchDev& P, int i, int j, int k) {
     return ((long long)k * P.N[1] + j) * P.N[0] + i;
 }
@@ -327,9 +348,9 @@ __global__ void __launch_bounds__(256) emf_half_kernel(R* __restrict__ pool, con
     if (!bp.valid) return;
     const int g = ghost;
     const R hdt = sc_hdt(*sc, R(0));
-    const int V = (int)P.vol;
-    const int x = (int)sidx(P, bp.i + g, bp.j + g, bp.k + g);
-    const int st[3] = {1, P.N[0], P.N[0] * P.N[1]};
+    const unsigned V = (unsigned)P.vol;
+    const unsigned x = (unsigned)sidx(P, bp.i + g, bp.j + g, bp.k + g);
+    const unsigned st[3] = {1u, (unsigned)P.N[0], (unsigned)(P.N[0] * P.N[1])};
     R* __restrict__ pp = pool + P.base;
     const R* q = pp + (cur ? F_ST1 : F_ST0) * V;
     const R* fl = pp + F_FL2 * V;
@@ -381,9 +402,9 @@ __global__ void __launch_bounds__(256) edge_emf_kernel(R* __restrict__ pool, con
     BoxPos bp = box_pos(P, w.a, bx);
     if (!bp.valid) return;
     const int g = ghost;
-    const int V = (int)P.vol;
-    const int x = (int)sidx(P, bp.i + g, bp.j + g, bp.k + g);
-    const int st[3] = {1, P.N[0], P.N[0] * P.N[1]};
+    const unsigned V = (unsigned)P.vol;
+    const unsigned x = (unsigned)sidx(P, bp.i + g, bp.j + g, bp.k + g);
+    const unsigned st[3] = {1u, (unsigned)P.N[0], (unsigned)(P.N[0] * P.N[1])};
     R* __restrict__ pp = pool + P.base;
     const R* fl = pp + fslot * V;
     const R* er = pp + F_ER * V;
@@ -395,7 +416,7 @@ __global__ void __launch_bounds__(256) edge_emf_kernel(R* __restrict__ pool, con
         bool in = z[c] >= rg.lo_c && z[c] <= P.n[c] + rg.hi_c && z[a] >= rg.lo_o && z[a] <= P.n[a] + rg.hi_o &&
                   z[b] >= rg.lo_o && z[b] <= P.n[b] + rg.hi_o;
         if (!in) continue;
-        const int sa = st[a], sb = st[b];
+        const unsigned sa = st[a], sb = st[b];
         const R* fa = fl + (7 * a) * V;  // flux_a rows
         const R* fb = fl + (7 * b) * V;
         const R* E0 = er + c * V;
@@ -426,9 +447,9 @@ __global__ void __launch_bounds__(256) ct_half_kernel(R* __restrict__ pool, cons
     BoxPos bp = box_pos(P, w.a, bx);
     if (!bp.valid) return;
     const int g = ghost;
-    const int V = (int)P.vol;
-    const int x = (int)sidx(P, bp.i + g, bp.j + g, bp.k + g);
-    const int st[3] = {1, P.N[0], P.N[0] * P.N[1]};
+    const unsigned V = (unsigned)P.vol;
+    const unsigned x = (unsigned)sidx(P, bp.i + g, bp.j + g, bp.k + g);
+    const unsigned st[3] = {1u, (unsigned)P.N[0], (unsigned)(P.N[0] * P.N[1])};
     R* __restrict__ pp = pool + P.base;
     const R* b = pp + ((cur ? F_ST1 : F_ST0) + 8) * V;
     const R* ed = pp + F_ED * V;
@@ -466,9 +487,9 @@ __global__ void __launch_bounds__(256) final_update_kernel(R* __restrict__ pool,
     double sp = 0.0;
     if (bp.valid) {
         const int g = prm.ghost;
-        const int V = (int)P.vol;
-        const int x = (int)sidx(P, bp.i + g, bp.j + g, bp.k + g);
-        const int st[3] = {1, P.N[0], P.N[0] * P.N[1]};
+        const unsigned V = (unsigned)P.vol;
+        const unsigned x = (unsigned)sidx(P, bp.i + g, bp.j + g, bp.k + g);
+        const unsigned st[3] = {1u, (unsigned)P.N[0], (unsigned)(P.N[0] * P.N[1])};
         R* __restrict__ pp = pool + P.base;
         const R* q = pp + (cur ? F_ST1 : F_ST0) * V;
         const R* b = q + 8 * V;
@@ -495,11 +516,11 @@ __global__ void __launch_bounds__(256) final_update_kernel(R* __restrict__ pool,
 #pragma unroll
         for (int d = 0; d < 3; d++) {
             const int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
-            const int s1 = st[a1], s2 = st[a2], sd = st[d];
+            const unsigned s1 = st[a1], s2 = st[a2], sd = st[d];
             const R* E2 = ed + a2 * V;
             const R* E1 = ed + a1 * V;
             R bl = b[d * V + x] - dt * ((E2[x + s1] - E2[x]) * cf.idx[a1] - (E1[x + s2] - E1[x]) * cf.idx[a2]);
-            const int xr = x + sd;
+            const unsigned xr = x + sd;
             R br = b[d * V + xr] - dt * ((E2[xr + s1] - E2[xr]) * cf.idx[a1] - (E1[xr + s2] - E1[xr]) * cf.idx[a2]);
             bn[d * V + x] = bl;
             if (z[d] == P.n[d] - 1) bn[d * V + xr] = br;  // shared right face
@@ -539,6 +560,13 @@ __global__ void __launch_bounds__(256) final_update_kernel(R* __restrict__ pool,
 // sum_k beta_k R_k is assembled there and mapped to conserved variables once.
 // ---------------------------------------------------------------------------
 
+// One LDS record per thread: 7 values padded to 8 so a record is read with
+// vector loads (two 16-byte reads in FP32).
+template <typename R>
+struct alignas(8 * sizeof(R)) Rec8 {
+    R v[8];
+};
+
 template <typename R>
 struct FaceEig {
     R rho, sq, vx, vy, vz, b1, b2, X;
@@ -551,93 +579,99 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
                                                      int cur, const StepConst* __restrict__ sc, int P, int W, int zlo,
                                                      int tlo, int thi) {
     extern __shared__ unsigned char smem_raw[];
-    R* sh = reinterpret_cast<R*>(smem_raw);
     const int nthr = P * W;
-    R* shp = sh;              // 7 x nthr primitives
-    R* shg = sh + 7 * nthr;   // 7 x nthr g-tilde
+    Rec8<R>* shp = reinterpret_cast<Rec8<R>*>(smem_raw);  // zone primitives
+    Rec8<R>* shg = shp + nthr;                             // face g-tilde
 
     constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
     constexpr int FA = (D == 0) ? 1 : 0;                 // fast transverse axis
     constexpr int SA = (D == 0) ? 2 : (D == 1 ? 2 : 1);  // slow transverse axis
+    constexpr unsigned ES = sizeof(R);
 
     const WorkItem wi = work[blockIdx.x];
     if (wi.patch < 0) return;  // padding item (whole block, before any barrier)
     const PatchDev Pt = patches[wi.patch];
-    const int tid = threadIdx.x;
-    int s, w;
-    if (D == 0) {
-        s = tid % P;
-        w = tid / P;
-    } else {
-        w = tid % W;
-        s = tid / W;
-    }
+    // block (P, W) along x for D = x, (W, P) otherwise: consecutive lanes are
+    // consecutive x either way
+    const int s = (D == 0) ? (int)threadIdx.x : (int)threadIdx.y;
+    const int w = (D == 0) ? (int)threadIdx.y : (int)threadIdx.x;
+    const int tid = (D == 0) ? s + P * w : w + W * s;
     const int sstep = (D == 0) ? 1 : W;  // LDS distance between neighbours along the pencil
     const int pen = wi.a + w;            // pencil number in the patch
-    const bool live = (tid < nthr) && (pen <= wi.c);
+    const bool live = pen <= wi.c;
     const int tf = Pt.n[FA] + thi - tlo + 1;
     const int g = prm.ghost;
+    // pen = slow * tf + fast; (pen + 1/2)/tf is at least 1/(2 tf) from an
+    // integer, far above the error of the single-precision reciprocal
+    const int slow = (int)(((float)pen + 0.5f) * __builtin_amdgcn_rcpf((float)tf));
     int zc[3];
     zc[D] = zlo + s;
-    zc[FA] = tlo + pen % tf;
-    zc[SA] = tlo + pen / tf;
-    const int V = (int)Pt.vol;
-    const int st[3] = {1, Pt.N[0], Pt.N[0] * Pt.N[1]};
-    const int x = live ? (zc[0] + g) + st[1] * (zc[1] + g) + st[2] * (zc[2] + g) : 0;
+    zc[FA] = tlo + (pen - slow * tf);
+    zc[SA] = tlo + slow;
+    const unsigned V = (unsigned)Pt.vol;
+    const unsigned st[3] = {1u, (unsigned)Pt.N[0], (unsigned)(Pt.N[0] * Pt.N[1])};
+    const unsigned x = live ? (unsigned)(zc[0] + g) + st[1] * (unsigned)(zc[1] + g) + st[2] * (unsigned)(zc[2] + g) : 0u;
+    const unsigned xo = x * ES;  // zone byte offset (VGPR)
+    const unsigned VB = V * ES;  // field byte stride (SGPR)
     const R lam = sc_lam(*sc, D, R(0));
-    R* __restrict__ pp = pool + Pt.base;
-    const R* q = pp + (cur ? F_ST1 : F_ST0) * V;
+    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + Pt.base, (unsigned)F_TOTAL * VB);
+    const unsigned qs = (unsigned)(cur ? F_ST1 : F_ST0) * VB;  // state copy
+    const R z0 = R(0);
 
     // ---------------- phase A: zone primitives ----------------
     if (live) {
         R u[8];
 #pragma unroll
-        for (int c = 0; c < 8; c++) u[c] = q[c * V + x];
+        for (int c = 0; c < 8; c++) u[c] = bload(z0, rs, xo, qs + c * VB);
         if (STAGE == 1 && D == 0) {
             // Step 2: reference EMF E^r = -v x B from q^n on [-3, n+2]^3
             if (zc[0] >= -3 && zc[0] <= Pt.n[0] + 2) {
-                R* er = pp + F_ER * V;
                 R ir = frcp(u[0]);
                 R vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
-                er[x] = vz * u[5] - vy * u[6];
-                er[V + x] = vx * u[6] - vz * u[4];
-                er[2 * V + x] = vy * u[4] - vx * u[5];
+                bstore(vz * u[5] - vy * u[6], rs, xo, (unsigned)F_ER * VB);
+                bstore(vx * u[6] - vz * u[4], rs, xo, (unsigned)(F_ER + 1) * VB);
+                bstore(vy * u[4] - vx * u[5], rs, xo, (unsigned)(F_ER + 2) * VB);
             }
         }
         if (STAGE == 2) {
             const R hdt = sc_hdt(*sc, R(0));
-            const R* f1 = pp + (F_FL1 + 7 * A1) * V;
-            const R* f2 = pp + (F_FL1 + 7 * A2) * V;
-            const int s1 = st[A1], s2 = st[A2];
+            const unsigned f1 = (unsigned)(F_FL1 + 7 * A1) * VB, f2 = (unsigned)(F_FL1 + 7 * A2) * VB;
+            const unsigned s1 = st[A1] * ES, s2 = st[A2] * ES;
             const R i1 = cf.idx[A1], i2 = cf.idx[A2];
             // rho, m, E (rows 0..4 -> components 0,1,2,3,7)
 #pragma unroll
             for (int r = 0; r < 5; r++) {
                 const int c = r < 4 ? r : 7;
-                R div = (f1[r * V + x + s1] - f1[r * V + x]) * i1 + (f2[r * V + x + s2] - f2[r * V + x]) * i2;
+                R div = (bload(z0, rs, xo, f1 + r * VB + s1) - bload(z0, rs, xo, f1 + r * VB)) * i1 +
+                        (bload(z0, rs, xo, f2 + r * VB + s2) - bload(z0, rs, xo, f2 + r * VB)) * i2;
                 u[c] -= hdt * div;
             }
             // B_D: flux_A1 row 6 (B_{A1+2}) and flux_A2 row 5 (B_{A2+1})
             {
-                R div = (f1[6 * V + x + s1] - f1[6 * V + x]) * i1 + (f2[5 * V + x + s2] - f2[5 * V + x]) * i2;
+                R div = (bload(z0, rs, xo, f1 + 6 * VB + s1) - bload(z0, rs, xo, f1 + 6 * VB)) * i1 +
+                        (bload(z0, rs, xo, f2 + 5 * VB + s2) - bload(z0, rs, xo, f2 + 5 * VB)) * i2;
                 u[4 + D] -= hdt * div;
             }
             // B_A1 only from flux_A2 row 6; B_A2 only from flux_A1 row 5
-            u[4 + A1] -= hdt * ((f2[6 * V + x + s2] - f2[6 * V + x]) * i2);
-            u[4 + A2] -= hdt * ((f1[5 * V + x + s1] - f1[5 * V + x]) * i1);
+            u[4 + A1] -= hdt * ((bload(z0, rs, xo, f2 + 6 * VB + s2) - bload(z0, rs, xo, f2 + 6 * VB)) * i2);
+            u[4 + A2] -= hdt * ((bload(z0, rs, xo, f1 + 5 * VB + s1) - bload(z0, rs, xo, f1 + 5 * VB)) * i1);
             // div-B source (Gardiner & Stone 2008 form): momentum B dB_D/dx_D,
             // B_t v_t minmod(dB_D/dx_D, -dB_t'/dx_t'), energy B_t . S[B_t]
-            const R* b = q + 8 * V;
+            const unsigned bs = qs + 8 * VB;
             R dB[3];
 #pragma unroll
-            for (int a = 0; a < 3; a++) dB[a] = (b[a * V + x + st[a]] - b[a * V + x]) * cf.idx[a];
-            R ir0 = frcp(q[x]);
-            R v1 = q[(1 + A1) * V + x] * ir0, v2 = q[(1 + A2) * V + x] * ir0;
-            R B1 = q[(4 + A1) * V + x], B2 = q[(4 + A2) * V + x];
+            for (int a = 0; a < 3; a++)
+                dB[a] = (bload(z0, rs, xo, bs + a * VB + st[a] * ES) - bload(z0, rs, xo, bs + a * VB)) * cf.idx[a];
+            const R q0 = bload(z0, rs, xo, qs), q1 = bload(z0, rs, xo, qs + (1 + A1) * VB),
+                    q2 = bload(z0, rs, xo, qs + (1 + A2) * VB);
+            const R B0[3] = {bload(z0, rs, xo, qs + 4 * VB), bload(z0, rs, xo, qs + 5 * VB), bload(z0, rs, xo, qs + 6 * VB)};
+            R ir0 = frcp(q0);
+            R v1 = q1 * ir0, v2 = q2 * ir0;
+            R B1 = B0[A1], B2 = B0[A2];
             R sB1 = v1 * minmod2(dB[D], -dB[A2]);
             R sB2 = v2 * minmod2(dB[D], -dB[A1]);
 #pragma unroll
-            for (int c = 0; c < 3; c++) u[1 + c] += hdt * q[(4 + c) * V + x] * dB[D];
+            for (int c = 0; c < 3; c++) u[1 + c] += hdt * B0[c] * dB[D];
             u[4 + A1] += hdt * sB1;
             u[4 + A2] += hdt * sB2;
             u[7] += hdt * (B1 * sB1 + B2 * sB2);
@@ -649,13 +683,16 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
         R b2 = u[4] * u[4] + u[5] * u[5] + u[6] * u[6];
         R pr = cf.gm1 * (u[7] - R(0.5) * rho * (vpar * vpar + vt1 * vt1 + vt2 * vt2) - R(0.5) * b2);
         if (pr < cf.p_floor) pr = cf.p_floor;
-        shp[0 * nthr + tid] = rho;
-        shp[1 * nthr + tid] = vpar;
-        shp[2 * nthr + tid] = vt1;
-        shp[3 * nthr + tid] = vt2;
-        shp[4 * nthr + tid] = u[4 + A1];
-        shp[5 * nthr + tid] = u[4 + A2];
-        shp[6 * nthr + tid] = pr;
+        Rec8<R> rec;
+        rec.v[0] = rho;
+        rec.v[1] = vpar;
+        rec.v[2] = vt1;
+        rec.v[3] = vt2;
+        rec.v[4] = u[4 + A1];
+        rec.v[5] = u[4 + A2];
+        rec.v[6] = pr;
+        rec.v[7] = R(0);
+        shp[tid] = rec;
     }
     __syncthreads();
 
@@ -665,13 +702,11 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
     R bf = R(0);
     const bool face = live && s >= 1;
     if (face) {
-        const R* bsrc = (STAGE == 1) ? (q + (8 + D) * V) : (pp + (F_BH + D) * V);
-        bf = bsrc[x];
+        bf = bload(z0, rs, xo, (STAGE == 1) ? qs + (8 + D) * VB : (unsigned)(F_BH + D) * VB);
         const int tl = tid - sstep;
-        R rl = shp[tl], vxl = shp[nthr + tl], vyl = shp[2 * nthr + tl], vzl = shp[3 * nthr + tl];
-        R b1l = shp[4 * nthr + tl], b2l = shp[5 * nthr + tl], pl = shp[6 * nthr + tl];
-        R rr = shp[tid], vxr = shp[nthr + tid], vyr = shp[2 * nthr + tid], vzr = shp[3 * nthr + tid];
-        R b1r = shp[4 * nthr + tid], b2r = shp[5 * nthr + tid], prr = shp[6 * nthr + tid];
+        const Rec8<R> L = shp[tl], Rr = shp[tid];
+        R rl = L.v[0], vxl = L.v[1], vyl = L.v[2], vzl = L.v[3], b1l = L.v[4], b2l = L.v[5], pl = L.v[6];
+        R rr = Rr.v[0], vxr = Rr.v[1], vyr = Rr.v[2], vzr = Rr.v[3], b1r = Rr.v[4], b2r = Rr.v[5], prr = Rr.v[6];
 
         R bf2 = bf * bf;
         R hl = (cf.ggm * pl + R(0.5) * rl * (vxl * vxl + vyl * vyl + vzl * vzl) + bf2 + b1l * b1l + b2l * b2l) * frcp(rl);
@@ -755,23 +790,26 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
         alpha[5] = Ea + Oa;
         alpha[3] = drho - dp * ia2;
         R ev[7] = {e.vx - e.cf, e.vx - ca, e.vx - e.cs, e.vx, e.vx + e.cs, e.vx + ca, e.vx + e.cf};
+        Rec8<R> gr;
 #pragma unroll
         for (int k = 0; k < 7; k++) {
             nu[k] = lam * ev[k];
-            R gt = R(0.5) * (qvisc(nu[k], cf.eps[k], cf.q4e[k]) - nu[k] * nu[k]) * alpha[k];
-            shg[k * nthr + tid] = gt;
+            gr.v[k] = R(0.5) * (qvisc(nu[k], cf.eps[k], cf.q4e[k]) - nu[k] * nu[k]) * alpha[k];
         }
+        gr.v[7] = R(0);
+        shg[tid] = gr;
     }
     __syncthreads();
 
     // ---------------- phase C: modified flux at faces 2 .. P-2 ----------------
     if (face && s >= 2 && s <= P - 2) {
         R bet[7];
+        const Rec8<R> Gm = shg[tid - sstep], G0 = shg[tid], Gp = shg[tid + sstep];
 #pragma unroll
         for (int k = 0; k < 7; k++) {
-            R gm = shg[k * nthr + tid - sstep];
-            R g0 = shg[k * nthr + tid];
-            R gp = shg[k * nthr + tid + sstep];
+            R gm = Gm.v[k];
+            R g0 = G0.v[k];
+            R gp = Gp.v[k];
             R gL = sweby(g0, gm, cf.beta_l);  // zone s-1: faces s-1 (left), s (right)
             R gR = sweby(gp, g0, cf.beta_l);  // zone s: faces s, s+1
             R gk = (fabs(alpha[k]) > alpha_min(alpha[k])) ? (gR - gL) * frcp(alpha[k]) : R(0);
@@ -801,9 +839,8 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
         R F[2][7];
 #pragma unroll
         for (int side = 0; side < 2; side++) {
-            const int t = side ? tid : tid - sstep;
-            R r = shp[t], vx = shp[nthr + t], vy = shp[2 * nthr + t], vz = shp[3 * nthr + t];
-            R b1 = shp[4 * nthr + t], b2 = shp[5 * nthr + t], pr = shp[6 * nthr + t];
+            const Rec8<R> Z = shp[side ? tid : tid - sstep];
+            R r = Z.v[0], vx = Z.v[1], vy = Z.v[2], vz = Z.v[3], b1 = Z.v[4], b2 = Z.v[5], pr = Z.v[6];
             R bb = bf * bf + b1 * b1 + b2 * b2;
             R pt = pr + R(0.5) * bb;
             R ept = cf.ggm * pr + R(0.5) * r * (vx * vx + vy * vy + vz * vz) + bb;  // E + P*
@@ -825,15 +862,15 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
         out[4] = R(0.5) * (F[0][4] + F[1][4]) - il * c7;
         out[5] = R(0.5) * (F[0][5] + F[1][5]) - il * wb1;
         out[6] = R(0.5) * (F[0][6] + F[1][6]) - il * wb2;
-        R* fo = pp + ((STAGE == 1 ? F_FL1 : F_FL2) + 7 * D) * V;
+        const unsigned fo = (unsigned)((STAGE == 1 ? F_FL1 : F_FL2) + 7 * D) * VB;
         // frame -> lab rows: m_par -> m_D, m_t1 -> m_A1, m_t2 -> m_A2
-        fo[x] = out[0];
-        fo[(1 + D) * V + x] = out[1];
-        fo[(1 + A1) * V + x] = out[2];
-        fo[(1 + A2) * V + x] = out[3];
-        fo[4 * V + x] = out[4];
-        fo[5 * V + x] = out[5];
-        fo[6 * V + x] = out[6];
+        bstore(out[0], rs, xo, fo);
+        bstore(out[1], rs, xo, fo + (1 + D) * VB);
+        bstore(out[2], rs, xo, fo + (1 + A1) * VB);
+        bstore(out[3], rs, xo, fo + (1 + A2) * VB);
+        bstore(out[4], rs, xo, fo + 4 * VB);
+        bstore(out[5], rs, xo, fo + 5 * VB);
+        bstore(out[6], rs, xo, fo + 6 * VB);
     }
 }
 
@@ -946,8 +983,8 @@ hipError_t launch_sweep(int d, int stage, void* pool, const PatchDev* pt, const 
                         const Coef<R>& cf, int cur, const StepConst* sc, int P, int W, int zlo, int tlo, int thi,
                         hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
-    size_t shmem = sizeof(R) * 14 * (size_t)P * W;
-    dim3 blk(P * W);
+    size_t shmem = sizeof(R) * 16 * (size_t)P * W;
+    dim3 blk = (d == 0) ? dim3(P, W) : dim3(W, P);
 #define WMB_SW(DD, SS)                                                                                               \
     hipLaunchKernelGGL((sweep_kernel<R, DD, SS>), dim3(nblk), blk, shmem, st, (R*)pool, pt, wk, prm, cf, cur, sc, P, W, \
                        zlo, tlo, thi)

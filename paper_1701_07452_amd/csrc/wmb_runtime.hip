@@ -360,7 +360,7 @@ int choose_W(int d, int P, size_t es) {
         return W < 1 ? 1 : W;
     }
     int W = 16;
-    while (W > 1 && ((size_t)P * W > 1024 || es * 14 * (size_t)P * W > 64 * 1024)) W /= 2;
+    while (W > 1 && ((size_t)P * W > 1024 || es * 16 * (size_t)P * W > 64 * 1024)) W /= 2;
     return W;
 }
 
@@ -633,7 +633,7 @@ int autotune_t(wmb_ctx* c, int reps) {
                 float best = 1e30f;
                 int bestW = G.W;
                 for (int W : cand) {
-                    if ((size_t)G.P * W > 1024 || es * 14 * (size_t)G.P * W > 64 * 1024 || G.P * W < 64) continue;
+                    if ((size_t)G.P * W > 1024 || es * 16 * (size_t)G.P * W > 64 * 1024 || G.P * W < 64) continue;
                     std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, W);
                     WorkItem* dl = nullptr;
                     CKH(hipMalloc(&dl, sizeof(WorkItem) * items.size()));
