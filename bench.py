@@ -66,6 +66,24 @@ def alg_bytes(kclass, n, g, es, npatch):
     return per * es * npatch
 
 
+def measured_traffic(kclass):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None when the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "turb256_512x32_fp32_hbm_traffic.json")
+    src = os.path.join(ROOT, "paper_1701_07452_amd", "csrc", "wmb_kernels.hip")
+    try:
+        rec = json.load(open(path))
+        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_source_sha256") != cur or kclass not in rec.get("per_launch_bytes", {}):
+        return None
+    return rec["per_launch_bytes"][kclass]["total"]
+
+
 def cpu_baseline(q, b, G, dx, ghost, budget_s=12.0):
     """The FP64 oracle as it stands, timed on this host's cores on a bounded
     sample: a 2x2xk block of the workload's 32^3 patches (periodic sample box),
@@ -102,7 +120,7 @@ def cpu_baseline(q, b, G, dx, ghost, budget_s=12.0):
     }
 
 
-def run_precision(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps):
+def run_precision(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps, tuning=None):
     import torch
 
     from paper_1701_07452_amd import inputs as I
@@ -111,8 +129,11 @@ def run_precision(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps):
     sim = W.Sim(W.make_params(dx=dx, precision=prec, ghost=ghost), G.descs, origins=G.origin, stream=stream)
     for ip, (qp, bp) in enumerate(I.split(G, q, b)):
         sim.set_state(ip, qp, bp)
-    tuning = sim.autotune(reps=3)
-    log("bench: autotuned pencils per block %s" % {"%d/%s/%d" % (k[0], "xyz"[k[1]], k[2]): v for k, v in tuning.items()})
+    if tuning:
+        sim.set_tuning(tuning)
+    else:
+        tuning = sim.autotune(reps=3)
+    log("bench: pencils per block %s" % W.tuning_to_str(tuning))
     sim.run_steps(max(warmup, 1))
     stream.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -134,7 +155,7 @@ def run_precision(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps):
         kern = {c: v / prof_steps for c, v in kern.items()}
     tot, dn, dr, nfl = sim.diagnostics()
     sim.close()
-    return ms, wall, kern, {"max_divb_norm": dn, "max_divb_raw": dr, "floors": nfl}
+    return ms, wall, kern, {"max_divb_norm": dn, "max_divb_raw": dr, "floors": nfl, "tuning": W.tuning_to_str(tuning)}
 
 
 def main():
@@ -146,6 +167,8 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=3)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning32", default="", help="sweep shapes for FP32 (e.g. 1x32=16,...); default: autotune")
+    ap.add_argument("--tuning64", default="", help="sweep shapes for FP64; default: autotune")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -181,14 +204,15 @@ def main():
     zones = G.zones()
 
     log("bench: FP32 batch, %d warm-up + %d timed steps" % (args.warmup, args.steps))
-    ms32, wall32, kern32, diag32 = run_precision(W, G, q, b, dx, W.WMB_FP32, g, args.steps, args.warmup, args.prof_steps)
+    ms32, wall32, kern32, diag32 = run_precision(W, G, q, b, dx, W.WMB_FP32, g, args.steps, args.warmup, args.prof_steps,
+                                                 W.tuning_from_str(args.tuning32))
     value = zones * args.steps / (ms32 / 1e3)
     log("bench: FP32 %.3f ms/step, %.3e zone-updates/s" % (ms32 / args.steps, value))
     fp64 = None
     if not args.no_fp64:
         log("bench: FP64 batch")
         ms64, wall64, kern64, diag64 = run_precision(W, G, q, b, dx, W.WMB_FP64, g, args.steps, args.warmup,
-                                                     args.prof_steps)
+                                                     args.prof_steps, W.tuning_from_str(args.tuning64))
         fp64 = {"value": zones * args.steps / (ms64 / 1e3), "ms_per_step": ms64 / args.steps,
                 "kernels_ms": kern64, **diag64}
         log("bench: FP64 %.3f ms/step" % (ms64 / args.steps))
@@ -201,6 +225,7 @@ def main():
     per_launch = alg_bytes(dom, n, g, 4, G.npatch)
     achieved = per_launch / (kern32[dom] * 1e-3) / 1e9
     step_bytes = sum(alg_bytes(k, n, g, 4, G.npatch) for k in kern32)
+    traffic = measured_traffic(dom)
     roof = {
         "kernel": dom,
         "bound": "hbm",
@@ -208,7 +233,8 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": traffic,
+        "traffic_GBs": round(traffic / (kern32[dom] * 1e-3) / 1e9, 1) if traffic else None,
         "alg_bytes_per_launch": per_launch,
         "avg_launch_ms": kern32[dom],
         "step_alg_bytes": step_bytes,

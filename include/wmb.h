@@ -156,6 +156,13 @@ int wmb_debug_stage(wmb_ctx *c, int32_t patch, int32_t stage, double *out);
    nchosen ints, 0-terminated when shorter.  Synchronous. */
 int wmb_autotune(wmb_ctx *c, int32_t reps, int32_t *chosen, int32_t nchosen);
 
+/* Set the pencils per block of sweep groups directly: quads of (stage 1|2,
+   axis 0..2, edge along the axis, pencils per block), n ints in total (a
+   multiple of 4), as returned by wmb_autotune.  Groups not named keep their
+   shape.  WMB_EINVAL if a shape exceeds 1024 threads or 64 KiB of LDS.
+   Invalidates the captured graphs. */
+int wmb_set_tuning(wmb_ctx *c, const int32_t *quads, int32_t n);
+
 /* Benchmark hook: enqueue one (fill ghosts, compute dt, advance) with the
    same launches the captured graph replays, with a HIP event recorded on the
    context's stream after each kernel class, wait for it, and store the

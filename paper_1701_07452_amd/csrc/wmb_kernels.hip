@@ -346,35 +346,37 @@ __global__ void __launch_bounds__(256) emf_half_kernel(R* __restrict__ pool, con
     const PatchDev P = patches[w.patch];
     BoxPos bp = box_pos(P, w.a, bx);
     if (!bp.valid) return;
+    constexpr unsigned ES = sizeof(R);
     const int g = ghost;
     const R hdt = sc_hdt(*sc, R(0));
-    const unsigned V = (unsigned)P.vol;
-    const unsigned x = (unsigned)sidx(P, bp.i + g, bp.j + g, bp.k + g);
-    const unsigned st[3] = {1u, (unsigned)P.N[0], (unsigned)(P.N[0] * P.N[1])};
-    R* __restrict__ pp = pool + P.base;
-    const R* q = pp + (cur ? F_ST1 : F_ST0) * V;
-    const R* fl = pp + F_FL2 * V;
-    const R* bh = pp + F_BH * V;
-    R* er = pp + F_ER * V;
+    const unsigned VB = (unsigned)P.vol * ES;
+    const unsigned xo = (unsigned)sidx(P, bp.i + g, bp.j + g, bp.k + g) * ES;
+    const unsigned st[3] = {ES, (unsigned)P.N[0] * ES, (unsigned)(P.N[0] * P.N[1]) * ES};
+    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + P.base, (unsigned)F_TOTAL * VB);
+    const unsigned qs = (unsigned)(cur ? F_ST1 : F_ST0) * VB;
+    const R z0 = R(0);
     R u[4];
 #pragma unroll
     for (int c = 0; c < 4; c++) {
         R div = R(0);
 #pragma unroll
         for (int d = 0; d < 3; d++) {
-            const R* f = fl + (7 * d + c) * V;
-            div += (f[x + st[d]] - f[x]) * cf.idx[d];
+            const unsigned f = (unsigned)(F_FL2 + 7 * d + c) * VB;
+            div += (bload(z0, rs, xo, f + st[d]) - bload(z0, rs, xo, f)) * cf.idx[d];
         }
-        u[c] = q[c * V + x] - hdt * div;
+        u[c] = bload(z0, rs, xo, qs + c * VB) - hdt * div;
     }
     R B[3];
 #pragma unroll
-    for (int d = 0; d < 3; d++) B[d] = R(0.5) * (bh[d * V + x] + bh[d * V + x + st[d]]);
+    for (int d = 0; d < 3; d++) {
+        const unsigned f = (unsigned)(F_BH + d) * VB;
+        B[d] = R(0.5) * (bload(z0, rs, xo, f) + bload(z0, rs, xo, f + st[d]));
+    }
     R ir = frcp(u[0]);
     R vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
-    er[x] = vz * B[1] - vy * B[2];
-    er[V + x] = vx * B[2] - vz * B[0];
-    er[2 * V + x] = vy * B[0] - vx * B[1];
+    bstore(vz * B[1] - vy * B[2], rs, xo, (unsigned)F_ER * VB);
+    bstore(vx * B[2] - vz * B[0], rs, xo, (unsigned)(F_ER + 1) * VB);
+    bstore(vy * B[0] - vx * B[1], rs, xo, (unsigned)(F_ER + 2) * VB);
 }
 
 // ---------------------------------------------------------------------------
@@ -401,14 +403,13 @@ __global__ void __launch_bounds__(256) edge_emf_kernel(R* __restrict__ pool, con
     const PatchDev P = patches[w.patch];
     BoxPos bp = box_pos(P, w.a, bx);
     if (!bp.valid) return;
+    constexpr unsigned ES = sizeof(R);
     const int g = ghost;
-    const unsigned V = (unsigned)P.vol;
+    const unsigned VB = (unsigned)P.vol * ES;
     const unsigned x = (unsigned)sidx(P, bp.i + g, bp.j + g, bp.k + g);
     const unsigned st[3] = {1u, (unsigned)P.N[0], (unsigned)(P.N[0] * P.N[1])};
-    R* __restrict__ pp = pool + P.base;
-    const R* fl = pp + fslot * V;
-    const R* er = pp + F_ER * V;
-    R* ed = pp + F_ED * V;
+    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + P.base, (unsigned)F_TOTAL * VB);
+    const R z0 = R(0);
     const int z[3] = {bp.i, bp.j, bp.k};
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -416,19 +417,20 @@ __global__ void __launch_bounds__(256) edge_emf_kernel(R* __restrict__ pool, con
         bool in = z[c] >= rg.lo_c && z[c] <= P.n[c] + rg.hi_c && z[a] >= rg.lo_o && z[a] <= P.n[a] + rg.hi_o &&
                   z[b] >= rg.lo_o && z[b] <= P.n[b] + rg.hi_o;
         if (!in) continue;
-        const unsigned sa = st[a], sb = st[b];
-        const R* fa = fl + (7 * a) * V;  // flux_a rows
-        const R* fb = fl + (7 * b) * V;
-        const R* E0 = er + c * V;
+        const unsigned xo = x * ES, xa = (x - st[a]) * ES, xb = (x - st[b]) * ES, xab = (x - st[a] - st[b]) * ES;
+        const unsigned fa = (unsigned)(fslot + 7 * a) * VB;  // flux_a rows
+        const unsigned fb = (unsigned)(fslot + 7 * b) * VB;
+        const unsigned e0f = (unsigned)(F_ER + c) * VB;
         // flux_a row 5 is B_{a+1} = B_b; flux_b row 6 is B_{b+2} = B_a
-        R Ea_0 = -fa[5 * V + x], Ea_b = -fa[5 * V + x - sb];
-        R Eb_0 = fb[6 * V + x], Eb_a = fb[6 * V + x - sa];
-        R e0 = E0[x], ea = E0[x - sa], eb = E0[x - sb], eab = E0[x - sa - sb];
-        R d1 = upwind_pick(fa[x], ea - Eb_a, e0 - Eb_0);
-        R d2 = upwind_pick(fa[x - sb], Eb_a - eab, Eb_0 - eb);
-        R d3 = upwind_pick(fb[x], eb - Ea_b, e0 - Ea_0);
-        R d4 = upwind_pick(fb[x - sa], Ea_b - eab, Ea_0 - ea);
-        ed[c * V + x] = R(0.25) * ((Ea_0 - d1) + (Ea_b + d2) + (Eb_0 - d3) + (Eb_a + d4));
+        R Ea_0 = -bload(z0, rs, xo, fa + 5 * VB), Ea_b = -bload(z0, rs, xb, fa + 5 * VB);
+        R Eb_0 = bload(z0, rs, xo, fb + 6 * VB), Eb_a = bload(z0, rs, xa, fb + 6 * VB);
+        R e0 = bload(z0, rs, xo, e0f), ea = bload(z0, rs, xa, e0f), eb = bload(z0, rs, xb, e0f),
+          eab = bload(z0, rs, xab, e0f);
+        R d1 = upwind_pick(bload(z0, rs, xo, fa), ea - Eb_a, e0 - Eb_0);
+        R d2 = upwind_pick(bload(z0, rs, xb, fa), Eb_a - eab, Eb_0 - eb);
+        R d3 = upwind_pick(bload(z0, rs, xo, fb), eb - Ea_b, e0 - Ea_0);
+        R d4 = upwind_pick(bload(z0, rs, xa, fb), Ea_b - eab, Ea_0 - ea);
+        bstore(R(0.25) * ((Ea_0 - d1) + (Ea_b + d2) + (Eb_0 - d3) + (Eb_a + d4)), rs, xo, (unsigned)(F_ED + c) * VB);
     }
 }
 
@@ -446,25 +448,25 @@ __global__ void __launch_bounds__(256) ct_half_kernel(R* __restrict__ pool, cons
     const PatchDev P = patches[w.patch];
     BoxPos bp = box_pos(P, w.a, bx);
     if (!bp.valid) return;
+    constexpr unsigned ES = sizeof(R);
     const int g = ghost;
-    const unsigned V = (unsigned)P.vol;
-    const unsigned x = (unsigned)sidx(P, bp.i + g, bp.j + g, bp.k + g);
-    const unsigned st[3] = {1u, (unsigned)P.N[0], (unsigned)(P.N[0] * P.N[1])};
-    R* __restrict__ pp = pool + P.base;
-    const R* b = pp + ((cur ? F_ST1 : F_ST0) + 8) * V;
-    const R* ed = pp + F_ED * V;
-    R* bh = pp + F_BH * V;
+    const unsigned VB = (unsigned)P.vol * ES;
+    const unsigned xo = (unsigned)sidx(P, bp.i + g, bp.j + g, bp.k + g) * ES;
+    const unsigned st[3] = {ES, (unsigned)P.N[0] * ES, (unsigned)(P.N[0] * P.N[1]) * ES};
+    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + P.base, (unsigned)F_TOTAL * VB);
+    const unsigned bs = (unsigned)((cur ? F_ST1 : F_ST0) + 8) * VB;
     const R tau = sc_hdt(*sc, R(0));
+    const R z0 = R(0);
     const int z[3] = {bp.i, bp.j, bp.k};
 #pragma unroll
     for (int d = 0; d < 3; d++) {
         const int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
         bool in = z[a1] >= -1 && z[a1] <= P.n[a1] && z[a2] >= -1 && z[a2] <= P.n[a2];
         if (!in) continue;
-        const R* E2 = ed + a2 * V;
-        const R* E1 = ed + a1 * V;
-        R curl = (E2[x + st[a1]] - E2[x]) * cf.idx[a1] - (E1[x + st[a2]] - E1[x]) * cf.idx[a2];
-        bh[d * V + x] = b[d * V + x] - tau * curl;
+        const unsigned E2 = (unsigned)(F_ED + a2) * VB, E1 = (unsigned)(F_ED + a1) * VB;
+        R curl = (bload(z0, rs, xo, E2 + st[a1]) - bload(z0, rs, xo, E2)) * cf.idx[a1] -
+                 (bload(z0, rs, xo, E1 + st[a2]) - bload(z0, rs, xo, E1)) * cf.idx[a2];
+        bstore(bload(z0, rs, xo, bs + d * VB) - tau * curl, rs, xo, (unsigned)(F_BH + d) * VB);
     }
 }
 
@@ -486,18 +488,16 @@ __global__ void __launch_bounds__(256) final_update_kernel(R* __restrict__ pool,
     BoxPos bp = box_pos(P, w.a, Box{0, -1});
     double sp = 0.0;
     if (bp.valid) {
+        constexpr unsigned ES = sizeof(R);
         const int g = prm.ghost;
-        const unsigned V = (unsigned)P.vol;
-        const unsigned x = (unsigned)sidx(P, bp.i + g, bp.j + g, bp.k + g);
-        const unsigned st[3] = {1u, (unsigned)P.N[0], (unsigned)(P.N[0] * P.N[1])};
-        R* __restrict__ pp = pool + P.base;
-        const R* q = pp + (cur ? F_ST1 : F_ST0) * V;
-        const R* b = q + 8 * V;
-        R* qn = pp + (cur ? F_ST0 : F_ST1) * V;
-        R* bn = qn + 8 * V;
-        const R* fl = pp + F_FL2 * V;
-        const R* ed = pp + F_ED * V;
+        const unsigned VB = (unsigned)P.vol * ES;
+        const unsigned xo = (unsigned)sidx(P, bp.i + g, bp.j + g, bp.k + g) * ES;
+        const unsigned st[3] = {ES, (unsigned)P.N[0] * ES, (unsigned)(P.N[0] * P.N[1]) * ES};
+        const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + P.base, (unsigned)F_TOTAL * VB);
+        const unsigned qs = (unsigned)(cur ? F_ST1 : F_ST0) * VB, bs = qs + 8 * VB;
+        const unsigned qn = (unsigned)(cur ? F_ST0 : F_ST1) * VB, bn = qn + 8 * VB;
         const R dt = sc_dt(*sc, R(0));
+        const R z0 = R(0);
         const int z[3] = {bp.i, bp.j, bp.k};
         R u[8];
         // Step 10 on rho, m, E (flux rows 0..4 map to components 0,1,2,3,7)
@@ -507,28 +507,30 @@ __global__ void __launch_bounds__(256) final_update_kernel(R* __restrict__ pool,
             R div = R(0);
 #pragma unroll
             for (int d = 0; d < 3; d++) {
-                const R* f = fl + (7 * d + r) * V;
-                div += (f[x + st[d]] - f[x]) * cf.idx[d];
+                const unsigned f = (unsigned)(F_FL2 + 7 * d + r) * VB;
+                div += (bload(z0, rs, xo, f + st[d]) - bload(z0, rs, xo, f)) * cf.idx[d];
             }
-            u[c] = q[c * V + x] - dt * div;
+            u[c] = bload(z0, rs, xo, qs + c * VB) - dt * div;
         }
         // Step 11: CT on the two faces of the zone along each axis
 #pragma unroll
         for (int d = 0; d < 3; d++) {
             const int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
-            const unsigned s1 = st[a1], s2 = st[a2], sd = st[d];
-            const R* E2 = ed + a2 * V;
-            const R* E1 = ed + a1 * V;
-            R bl = b[d * V + x] - dt * ((E2[x + s1] - E2[x]) * cf.idx[a1] - (E1[x + s2] - E1[x]) * cf.idx[a2]);
-            const unsigned xr = x + sd;
-            R br = b[d * V + xr] - dt * ((E2[xr + s1] - E2[xr]) * cf.idx[a1] - (E1[xr + s2] - E1[xr]) * cf.idx[a2]);
-            bn[d * V + x] = bl;
-            if (z[d] == P.n[d] - 1) bn[d * V + xr] = br;  // shared right face
+            const unsigned E2 = (unsigned)(F_ED + a2) * VB, E1 = (unsigned)(F_ED + a1) * VB;
+            const unsigned xr = xo + st[d];
+            R bl = bload(z0, rs, xo, bs + d * VB) -
+                   dt * ((bload(z0, rs, xo, E2 + st[a1]) - bload(z0, rs, xo, E2)) * cf.idx[a1] -
+                         (bload(z0, rs, xo, E1 + st[a2]) - bload(z0, rs, xo, E1)) * cf.idx[a2]);
+            R br = bload(z0, rs, xr, bs + d * VB) -
+                   dt * ((bload(z0, rs, xr, E2 + st[a1]) - bload(z0, rs, xr, E2)) * cf.idx[a1] -
+                         (bload(z0, rs, xr, E1 + st[a2]) - bload(z0, rs, xr, E1)) * cf.idx[a2]);
+            bstore(bl, rs, xo, bn + d * VB);
+            if (z[d] == P.n[d] - 1) bstore(br, rs, xr, bn + d * VB);  // shared right face
             u[4 + d] = R(0.5) * (bl + br);
         }
         if (apply_floor(u, prm, cf)) atomicAdd(nfloor, 1ULL);
 #pragma unroll
-        for (int c = 0; c < 8; c++) qn[c * V + x] = u[c];
+        for (int c = 0; c < 8; c++) bstore(u[c], rs, xo, qn + c * VB);
         double ud[8];
 #pragma unroll
         for (int c = 0; c < 8; c++) ud[c] = (double)u[c];

@@ -887,6 +887,29 @@ int wmb_autotune(wmb_ctx* c, int32_t reps, int32_t* chosen, int32_t nchosen) {
     return WMB_OK;
 }
 
+int wmb_set_tuning(wmb_ctx* c, const int32_t* quads, int32_t n) {
+    if (!c || (!quads && n > 0) || n < 0 || n % 4) return WMB_EINVAL;
+    if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
+    for (int k = 0; k + 4 <= n; k += 4) {
+        const int stage = quads[k], d = quads[k + 1], edge = quads[k + 2], W = quads[k + 3];
+        if (stage < 1 || stage > 2 || d < 0 || d > 2 || W < 1) return fail(c, WMB_EINVAL, "bad tuning entry");
+        for (auto& G : c->sweeps[d][stage - 1]) {
+            if (G.n != edge) continue;
+            if ((size_t)G.P * W > 1024 || c->esize * 16 * (size_t)G.P * W > 64 * 1024)
+                return fail(c, WMB_EINVAL, "tuning entry exceeds the block or LDS limit");
+            std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, W);
+            WorkItem* dl = nullptr;
+            int rc = upload(c, &dl, items);
+            if (rc) return rc;
+            G.W = W;
+            G.wl.d = dl;
+            G.wl.n = (int)items.size();
+        }
+    }
+    free_graphs(c);
+    return WMB_OK;
+}
+
 int wmb_profile_step(wmb_ctx* c, double* ms, int32_t nclass) {
     if (!c || !ms) return WMB_EINVAL;
     if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");

@@ -21,7 +21,7 @@ WMB_FP64, WMB_FP32 = 0, 1
 EXPORTS = [
     "wmb_create", "wmb_pool_bytes", "wmb_init_patches", "wmb_set_state", "wmb_get_state", "wmb_get_stored",
     "wmb_fill_ghosts", "wmb_compute_dt", "wmb_advance", "wmb_run_steps", "wmb_diagnostics", "wmb_debug_stage",
-    "wmb_autotune", "wmb_profile_step", "wmb_destroy", "wmb_strerror", "wmb_last_error",
+    "wmb_autotune", "wmb_set_tuning", "wmb_profile_step", "wmb_destroy", "wmb_strerror", "wmb_last_error",
 ]
 KERNEL_CLASSES = ["fill", "dt", "sweep1_x", "sweep1_y", "sweep1_z", "edge1", "ct_half",
                   "sweep2_x", "sweep2_y", "sweep2_z", "emf_half", "edge2", "final"]
@@ -97,6 +97,7 @@ def load_library():
     lib.wmb_debug_stage.argtypes = [vp, C.c_int32, C.c_int32, dp]
     lib.wmb_profile_step.argtypes = [vp, dp, C.c_int32]
     lib.wmb_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.c_int32]
+    lib.wmb_set_tuning.argtypes = [vp, C.POINTER(C.c_int32), C.c_int32]
     lib.wmb_destroy.argtypes = [vp]
     lib.wmb_strerror.argtypes = [C.c_int]
     lib.wmb_strerror.restype = C.c_char_p
@@ -244,6 +245,12 @@ class Sim:
             k += 4
         return out
 
+    def set_tuning(self, tuning):
+        """Apply {(stage, axis, edge): pencils per block} without timing."""
+        flat = [v for (st, ax, e), W in sorted(tuning.items()) for v in (st, ax, e, W)]
+        buf = (C.c_int32 * max(len(flat), 1))(*flat)
+        self._check(self.lib.wmb_set_tuning(self.h, buf, len(flat)))
+
     def profile_step(self):
         """Per-kernel-class durations (ms) of one eager step; advances the state."""
         out = np.zeros(len(KERNEL_CLASSES))
@@ -252,6 +259,20 @@ class Sim:
 
     def synchronize(self):
         self.stream.synchronize()
+
+
+def tuning_to_str(tuning):
+    """{(1, 0, 32): 16, ...} -> '1x32=16,...' (stage, axis letter, edge)."""
+    return ",".join("%d%s%d=%d" % (st, "xyz"[ax], e, W) for (st, ax, e), W in sorted(tuning.items()))
+
+
+def tuning_from_str(s):
+    out = {}
+    for item in filter(None, s.split(",")):
+        key, W = item.split("=")
+        st, ax, e = int(key[0]), "xyz".index(key[1]), int(key[2:])
+        out[(st, ax, e)] = int(W)
+    return out
 
 
 def sim_from_grid(G, q=None, b=None, **params_kw):
