@@ -43,7 +43,7 @@ def alg_bytes(kclass, n, g, es, npatch):
     if kclass == "fill":
         per = 22 * ((n + 2 * g) ** 3 - n ** 3)          # 11 words read + 11 written per ghost zone
     elif kclass == "dt":
-        per = 0                                          # finalize only: the reduction is folded into "final"
+        per = 0                                          # finalize only: the reduction is folded into "update"
     elif kclass.startswith("sweep1"):
         T, P = n + 6, n + 8
         per = 9 * P * T * T + 7 * (P - 3) * T * T        # q + b_par in; 7 flux rows out
@@ -52,15 +52,15 @@ def alg_bytes(kclass, n, g, es, npatch):
     elif kclass.startswith("sweep2"):
         T, P = n + 2, n + 6
         per = (8 + 2 * 7 + 3 + 1) * P * T * T + 7 * (P - 3) * T * T  # q, 2 transverse fluxes, b, b^{n+1/2}; flux out
-    elif kclass in ("edge1", "edge2"):
-        lo, hi = (-2, 2) if kclass == "edge1" else (0, 0)
-        per = (9 + 3 + 3) * box(lo, hi)                  # 3 flux rows x 3 dirs + E^r in; 3 edges out
+    elif kclass == "edge1":
+        per = (9 + 3 + 3) * box(-2, 2)                   # 3 flux rows x 3 dirs + E^r in; 3 edges out
     elif kclass == "ct_half":
-        per = 9 * box(-2, 2)
-    elif kclass == "emf_half":
-        per = (4 + 12 + 3 + 3) * box(-1, 0)
-    elif kclass == "final":
-        per = (8 + 15 + 3 + 3 + 11) * n ** 3
+        per = 9 * box(-2, 2)                             # b^n and 2 x 3 edges in; b^{n+1/2} out
+    elif kclass == "update":
+        # Steps 8-11 fused: q^n rho, m + flux rows 0-3 + b^{n+1/2} over the E^r
+        # box [-1, n]; flux rows 5-6 over the edge box [0, n]; q^n E, flux row 4,
+        # b^n in and q^{n+1}, b^{n+1} out over the interior
+        per = (4 + 12 + 3) * box(-1, 0) + 6 * box(0, 0) + (1 + 3 + 3 + 11) * n ** 3
     else:
         raise KeyError(kclass)
     return per * es * npatch

@@ -86,7 +86,9 @@ int wmb_pool_bytes(const wmb_params *p, int32_t npatch, const wmb_patch_desc *d,
 
 /* Bind the patches to the caller's device pool and stream (hipStream_t, NULL
    = default stream).  Checks the neighbour table (face extents agree, the
-   neighbour of my neighbour is me) and builds the launch plans.  The pool's
+   neighbour of my neighbour is me; every interior edge at least the ghost
+   width; a patch region, 73 words per ghosted zone, at most 4 GiB) and
+   builds the launch plans.  The pool's
    contents are undefined until wmb_set_state has been called for every
    patch.  WMB_ESIZE if pool_bytes < wmb_pool_bytes. */
 int wmb_init_patches(wmb_ctx *c, int32_t npatch, const wmb_patch_desc *d, void *dev_pool,
@@ -141,9 +143,10 @@ int wmb_diagnostics(wmb_ctx *c, double totals[8], double *max_divb_norm, double 
 /* Test hook: copy an intermediate of the last step of one patch over the
    ghosted box, widened to double, in this layout: stage 1 Step-1 fluxes
    (3 x 8 x vol, lab component order, B_par row 0), 3 b^{n+1/2} (3 x vol),
-   5 Step-6/7 fluxes (3 x 8 x vol), 6 Step-9 edge EMFs (3 x vol).  Values
-   outside the ranges the step needs are unspecified.  Other stages (the
-   Step-3 edges are overwritten by Step 9) give WMB_EINVAL.  Synchronous. */
+   5 Step-6/7 fluxes (3 x 8 x vol), 6 Step-9 edge EMFs (3 x vol; only after
+   a step run with wmb_keep_stages on, else WMB_ESTATE).  Values outside the
+   ranges the step needs are unspecified.  Other stages (the Step-3 edges are
+   overwritten by Step 9) give WMB_EINVAL.  Synchronous. */
 int wmb_debug_stage(wmb_ctx *c, int32_t patch, int32_t stage, double *out);
 
 /* Search the block shape of the directional sweeps (pencils per block) for
@@ -163,17 +166,23 @@ int wmb_autotune(wmb_ctx *c, int32_t reps, int32_t *chosen, int32_t nchosen);
    Invalidates the captured graphs. */
 int wmb_set_tuning(wmb_ctx *c, const int32_t *quads, int32_t n);
 
+/* Debugging: with on != 0, later steps also store the Step-9 edge EMFs in
+   device memory for wmb_debug_stage (the fused Steps 8-11 otherwise keep
+   them on chip).  Default off.  Invalidates the captured graphs when it
+   changes. */
+int wmb_keep_stages(wmb_ctx *c, int32_t on);
+
 /* Benchmark hook: enqueue one (fill ghosts, compute dt, advance) with the
    same launches the captured graph replays, with a HIP event recorded on the
    context's stream after each kernel class, wait for it, and store the
    duration in milliseconds of each class in ms[0 .. WMB_NCLASS-1], in this
    order: fill (3 passes), dt (finalize of the reduction that the previous
-   final update folded in), sweep x, y, z (Step 1, the x sweep also forming
-   the Step-2 reference EMF), edge EMFs (Step 3), CT half (Step 4), sweep x,
-   y, z (Steps 5-7), half-step EMF (Step 8), edge EMFs (Step 9), final update
-   (Steps 10-11 and the signal-speed maximum of the new state).  Advances the
-   state by one step.  Synchronous. */
-#define WMB_NCLASS 13
+   update folded in), sweep x, y, z (Step 1, the x sweep also forming the
+   Step-2 reference EMF), edge EMFs (Step 3), CT half (Step 4), sweep x,
+   y, z (Steps 5-7), update (Steps 8-11 fused: half-step EMF, edge EMFs,
+   conservative and CT update, and the signal-speed maximum of the new
+   state).  Advances the state by one step.  Synchronous. */
+#define WMB_NCLASS 11
 int wmb_profile_step(wmb_ctx *c, double *ms, int32_t nclass);
 
 /* Free the context, its tables and graphs (not the pool, not the stream). */

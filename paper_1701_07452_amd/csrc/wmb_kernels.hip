@@ -17,10 +17,10 @@
 //   ct_half           Step 4   b^{n+1/2} = b^n - dt/2 curl E
 //   sweep<d,2>        Steps 5-7  transverse predictor + source, then MHDTVD
 //                              fluxes with B_par = b^{n+1/2}        (hot)
-//   emf_half          Step 8   E^r from the unsplit half update and face-averaged b^{n+1/2}
-//   edge_emf          Step 9
-//   final_update      Steps 10-11  q^{n+1}, b^{n+1}, zone field, FP64 floors,
-//                              and the FP64 signal-speed max of q^{n+1} for the next dt
+//   update            Steps 8-11 fused, marching along z with E^r and the edge
+//                              EMFs in LDS: q^{n+1}, b^{n+1}, zone field, FP64
+//                              floors, and the FP64 signal-speed max of q^{n+1}
+//                              for the next dt
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -333,53 +333,6 @@ __global__ void set_dt_kernel(StepConst* sc, double dt, DevParams p) { write_ste
 __global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ULL; }
 
 // ---------------------------------------------------------------------------
-// Step 8: E^r from the unsplit half update of q^n with the Step-6/7 fluxes
-// (velocity) and the face average of b^{n+1/2} (zone field)
-// ---------------------------------------------------------------------------
-
-template <typename R>
-__global__ void __launch_bounds__(256) emf_half_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
-                                                       const WorkItem* __restrict__ work, Coef<R> cf, int ghost, int cur,
-                                                       const StepConst* __restrict__ sc, Box bx) {
-    const WorkItem w = work[blockIdx.x];
-    if (w.patch < 0) return;  // padding item (whole block)
-    const PatchDev P = patches[w.patch];
-    BoxPos bp = box_pos(P, w.a, bx);
-    if (!bp.valid) return;
-    constexpr unsigned ES = sizeof(R);
-    const int g = ghost;
-    const R hdt = sc_hdt(*sc, R(0));
-    const unsigned VB = (unsigned)P.vol * ES;
-    const unsigned xo = (unsigned)sidx(P, bp.i + g, bp.j + g, bp.k + g) * ES;
-    const unsigned st[3] = {ES, (unsigned)P.N[0] * ES, (unsigned)(P.N[0] * P.N[1]) * ES};
-    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + P.base, (unsigned)F_TOTAL * VB);
-    const unsigned qs = (unsigned)(cur ? F_ST1 : F_ST0) * VB;
-    const R z0 = R(0);
-    R u[4];
-#pragma unroll
-    for (int c = 0; c < 4; c++) {
-        R div = R(0);
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            const unsigned f = (unsigned)(F_FL2 + 7 * d + c) * VB;
-            div += (bload(z0, rs, xo, f + st[d]) - bload(z0, rs, xo, f)) * cf.idx[d];
-        }
-        u[c] = bload(z0, rs, xo, qs + c * VB) - hdt * div;
-    }
-    R B[3];
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        const unsigned f = (unsigned)(F_BH + d) * VB;
-        B[d] = R(0.5) * (bload(z0, rs, xo, f) + bload(z0, rs, xo, f + st[d]));
-    }
-    R ir = frcp(u[0]);
-    R vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
-    bstore(vz * B[1] - vy * B[2], rs, xo, (unsigned)F_ER * VB);
-    bstore(vx * B[2] - vz * B[0], rs, xo, (unsigned)(F_ER + 1) * VB);
-    bstore(vy * B[0] - vx * B[1], rs, xo, (unsigned)(F_ER + 2) * VB);
-}
-
-// ---------------------------------------------------------------------------
 // Steps 3 and 9: upwinded edge EMFs from face fluxes and E^r.  For the edge of
 // component c at the lower corner of the (a, b) = (c+1, c+2) plane, each of
 // the four adjacent face values (-flux_a[B_b] on a-faces, +flux_b[B_a] on
@@ -392,6 +345,25 @@ __global__ void __launch_bounds__(256) emf_half_kernel(R* __restrict__ pool, con
 template <typename R>
 __device__ __forceinline__ R upwind_pick(R f, R dl, R dr) {
     return f > R(0) ? dl : (f < R(0) ? dr : R(0.5) * (dl + dr));
+}
+
+// Edge value of component c at zone byte offset xo: fa, fb are the flux slots
+// (bytes) of directions a and b, sa, sb their strides (bytes); e0, ea, eb, eab
+// are E^r_c of the zone, of the zone one back along a, one back along b and
+// one back along both.
+template <typename R>
+__device__ __forceinline__ R edge_emf(__amdgpu_buffer_rsrc_t rs, unsigned xo, unsigned sa, unsigned sb, unsigned fa,
+                                      unsigned fb, unsigned VB, R e0, R ea, R eb, R eab) {
+    const R z0 = R(0);
+    const unsigned xa = xo - sa, xb = xo - sb;
+    // flux_a row 5 is B_{a+1} = B_b; flux_b row 6 is B_{b+2} = B_a
+    R Ea_0 = -bload(z0, rs, xo + fa + 5 * VB, 0), Ea_b = -bload(z0, rs, xb + fa + 5 * VB, 0);
+    R Eb_0 = bload(z0, rs, xo + fb + 6 * VB, 0), Eb_a = bload(z0, rs, xa + fb + 6 * VB, 0);
+    R d1 = upwind_pick(bload(z0, rs, xo + fa, 0), ea - Eb_a, e0 - Eb_0);
+    R d2 = upwind_pick(bload(z0, rs, xb + fa, 0), Eb_a - eab, Eb_0 - eb);
+    R d3 = upwind_pick(bload(z0, rs, xo + fb, 0), eb - Ea_b, e0 - Ea_0);
+    R d4 = upwind_pick(bload(z0, rs, xa + fb, 0), Ea_b - eab, Ea_0 - ea);
+    return R(0.25) * ((Ea_0 - d1) + (Ea_b + d2) + (Eb_0 - d3) + (Eb_a + d4));
 }
 
 template <typename R>
@@ -421,16 +393,9 @@ __global__ void __launch_bounds__(256) edge_emf_kernel(R* __restrict__ pool, con
         const unsigned fa = (unsigned)(fslot + 7 * a) * VB;  // flux_a rows
         const unsigned fb = (unsigned)(fslot + 7 * b) * VB;
         const unsigned e0f = (unsigned)(F_ER + c) * VB;
-        // flux_a row 5 is B_{a+1} = B_b; flux_b row 6 is B_{b+2} = B_a
-        R Ea_0 = -bload(z0, rs, xo, fa + 5 * VB), Ea_b = -bload(z0, rs, xb, fa + 5 * VB);
-        R Eb_0 = bload(z0, rs, xo, fb + 6 * VB), Eb_a = bload(z0, rs, xa, fb + 6 * VB);
         R e0 = bload(z0, rs, xo, e0f), ea = bload(z0, rs, xa, e0f), eb = bload(z0, rs, xb, e0f),
           eab = bload(z0, rs, xab, e0f);
-        R d1 = upwind_pick(bload(z0, rs, xo, fa), ea - Eb_a, e0 - Eb_0);
-        R d2 = upwind_pick(bload(z0, rs, xb, fa), Eb_a - eab, Eb_0 - eb);
-        R d3 = upwind_pick(bload(z0, rs, xo, fb), eb - Ea_b, e0 - Ea_0);
-        R d4 = upwind_pick(bload(z0, rs, xa, fb), Ea_b - eab, Ea_0 - ea);
-        bstore(R(0.25) * ((Ea_0 - d1) + (Ea_b + d2) + (Eb_0 - d3) + (Eb_a + d4)), rs, xo, (unsigned)(F_ED + c) * VB);
+        bstore(edge_emf(rs, xo, st[a] * ES, st[b] * ES, fa, fb, VB, e0, ea, eb, eab), rs, xo, (unsigned)(F_ED + c) * VB);
     }
 }
 
@@ -470,71 +435,189 @@ __global__ void __launch_bounds__(256) ct_half_kernel(R* __restrict__ pool, cons
     }
 }
 
+// Column tiles of the marching update kernel: tx, ty <= 32 and tx ty <= 256 zones
+// per plane; LDS edge planes are (tx+1)(ty+1) long.
+constexpr int TILE_THREADS = 256;
+constexpr int UPD_ERMAX = 340;  // (tx+2)(ty+2)
+constexpr int UPD_EDMAX = 297;  // (tx+1)(ty+1)
+constexpr int TILE_BIAS = 16;   // tile origins are stored biased (they may be negative)
+
+// q = r / m for 0 <= r < 1927 and 1 <= m <= 34, from a 16-bit reciprocal
+__device__ __forceinline__ int small_div(int r, int recip) { return (r * recip) >> 16; }
+
 // ---------------------------------------------------------------------------
-// Steps 10-11: conservative update, CT with the Step-9 EMFs, zone field from
-// the face average, FP64 floors.  Writes the other state copy, and folds the
-// FP64 signal speed of the new state into smax (the next step's dt).
+// Steps 8-11 fused.  A block owns a column tile of zones [i0, i0+tx) x
+// [j0, j0+ty) (tx, ty <= 32, tx ty <= 256) over the planes [k0, k1) and
+// marches along z.  Per plane k it forms
+//   E^r on plane k+1 over the tile and a one-zone ring (Step 8: velocity of
+//       the unsplit half update of q^n with the Step-6/7 fluxes, zone field
+//       from the face average of b^{n+1/2}),
+//   the Step-9 edge EMFs: E_z on plane k, E_x and E_y on plane k+1 (the same
+//       upwinded average as Step 3, fluxes of Steps 6/7),
+//   and then the zones of plane k: conservative update (Step 10), CT update of
+//       their faces (Step 11), zone field from the face average, FP64 floors,
+//       and the FP64 signal speed folded into smax for the next dt.
+// E^r and the edges live in LDS, two planes each; nothing of Steps 8-9 goes
+// to HBM unless keep_edges asks for the Step-9 edges (debugging).
 // ---------------------------------------------------------------------------
 
 template <typename R>
-__global__ void __launch_bounds__(256) final_update_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
-                                                           const WorkItem* __restrict__ work, DevParams prm, Coef<R> cf,
-                                                           int cur, const StepConst* __restrict__ sc,
-                                                           unsigned long long* __restrict__ nfloor,
-                                                           unsigned long long* __restrict__ smax_bits) {
+__global__ void __launch_bounds__(TILE_THREADS) update_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
+                                                              const WorkItem* __restrict__ work, DevParams prm, Coef<R> cf,
+                                                              int cur, const StepConst* __restrict__ sc,
+                                                              unsigned long long* __restrict__ nfloor,
+                                                              unsigned long long* __restrict__ smax_bits, int keep_edges) {
+    __shared__ R s_er[2 * 3 * UPD_ERMAX];  // [plane & 1][component][(ey+1)(tx+2) + ex+1]
+    __shared__ R s_ed[2 * 3 * UPD_EDMAX];  // [plane & 1][component][j (tx+1) + i]
     const WorkItem w = work[blockIdx.x];
     if (w.patch < 0) return;  // padding item (whole block)
     const PatchDev P = patches[w.patch];
-    BoxPos bp = box_pos(P, w.a, Box{0, -1});
-    double sp = 0.0;
-    if (bp.valid) {
-        constexpr unsigned ES = sizeof(R);
-        const int g = prm.ghost;
-        const unsigned VB = (unsigned)P.vol * ES;
-        const unsigned xo = (unsigned)sidx(P, bp.i + g, bp.j + g, bp.k + g) * ES;
-        const unsigned st[3] = {ES, (unsigned)P.N[0] * ES, (unsigned)(P.N[0] * P.N[1]) * ES};
-        const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + P.base, (unsigned)F_TOTAL * VB);
-        const unsigned qs = (unsigned)(cur ? F_ST1 : F_ST0) * VB, bs = qs + 8 * VB;
-        const unsigned qn = (unsigned)(cur ? F_ST0 : F_ST1) * VB, bn = qn + 8 * VB;
-        const R dt = sc_dt(*sc, R(0));
-        const R z0 = R(0);
-        const int z[3] = {bp.i, bp.j, bp.k};
-        R u[8];
-        // Step 10 on rho, m, E (flux rows 0..4 map to components 0,1,2,3,7)
+    const int i0 = (w.a & 0xffff) - TILE_BIAS, j0 = (w.a >> 16) - TILE_BIAS;
+    const int tx = w.b & 0xffff, ty = w.b >> 16;
+    const int k0 = (w.c & 0xffff) - TILE_BIAS, k1 = (w.c >> 16) - TILE_BIAS;
+    constexpr unsigned ES = sizeof(R);
+    const int g = prm.ghost;
+    const unsigned VB = (unsigned)P.vol * ES;
+    const unsigned s0 = ES, s1 = (unsigned)P.N[0] * ES, s2 = (unsigned)(P.N[0] * P.N[1]) * ES;
+    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + P.base, (unsigned)F_TOTAL * VB);
+    const unsigned qs = (unsigned)(cur ? F_ST1 : F_ST0) * VB, bs = qs + 8 * VB;
+    const unsigned qn = (unsigned)(cur ? F_ST0 : F_ST1) * VB, bn = qn + 8 * VB;
+    const R hdt = sc_hdt(*sc, R(0)), dt = sc_dt(*sc, R(0));
+    const R z0 = R(0);
+    const int t = threadIdx.x;
+    const int TXP = tx + 2, TXE = tx + 1;
+    const int nER = TXP * (ty + 2), nED = TXE * (ty + 1);
+    const int rTXP = 65536 / TXP + 1, rTXE = 65536 / TXE + 1, rTX = 65536 / tx + 1;
+    // byte offset of the zone at tile-local (i, j) on plane k
+    auto zoff = [&](int i, int j, int k) -> unsigned {
+        return (unsigned)sidx(P, i0 + i + g, j0 + j + g, k + g) * ES;
+    };
+
+    // Step 8 on plane k over [-1, tx] x [-1, ty]
+    auto er_plane = [&](int k) {
+        R* dst = s_er + (k & 1) * 3 * UPD_ERMAX;
+        for (int r = t; r < nER; r += TILE_THREADS) {
+            const int ey = small_div(r, rTXP), ex = r - ey * TXP;
+            const unsigned xo = zoff(ex - 1, ey - 1, k);
+            R u[4];
 #pragma unroll
-        for (int r = 0; r < 5; r++) {
-            const int c = r < 4 ? r : 7;
-            R div = R(0);
-#pragma unroll
-            for (int d = 0; d < 3; d++) {
-                const unsigned f = (unsigned)(F_FL2 + 7 * d + r) * VB;
-                div += (bload(z0, rs, xo, f + st[d]) - bload(z0, rs, xo, f)) * cf.idx[d];
+            for (int c = 0; c < 4; c++) {
+                R div = R(0);
+                const unsigned f0 = (unsigned)(F_FL2 + c) * VB, f1 = f0 + 7 * VB, f2 = f1 + 7 * VB;
+                div += (bload(z0, rs, xo, f0 + s0) - bload(z0, rs, xo, f0)) * cf.idx[0];
+                div += (bload(z0, rs, xo, f1 + s1) - bload(z0, rs, xo, f1)) * cf.idx[1];
+                div += (bload(z0, rs, xo, f2 + s2) - bload(z0, rs, xo, f2)) * cf.idx[2];
+                u[c] = bload(z0, rs, xo, qs + c * VB) - hdt * div;
             }
-            u[c] = bload(z0, rs, xo, qs + c * VB) - dt * div;
+            const unsigned h = (unsigned)F_BH * VB;
+            R B0 = R(0.5) * (bload(z0, rs, xo, h) + bload(z0, rs, xo, h + s0));
+            R B1 = R(0.5) * (bload(z0, rs, xo, h + VB) + bload(z0, rs, xo, h + VB + s1));
+            R B2 = R(0.5) * (bload(z0, rs, xo, h + 2 * VB) + bload(z0, rs, xo, h + 2 * VB + s2));
+            R ir = frcp(u[0]);
+            R vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
+            dst[r] = vz * B1 - vy * B2;
+            dst[UPD_ERMAX + r] = vx * B2 - vz * B0;
+            dst[2 * UPD_ERMAX + r] = vy * B0 - vx * B1;
         }
-        // Step 11: CT on the two faces of the zone along each axis
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            const int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
-            const unsigned E2 = (unsigned)(F_ED + a2) * VB, E1 = (unsigned)(F_ED + a1) * VB;
-            const unsigned xr = xo + st[d];
-            R bl = bload(z0, rs, xo, bs + d * VB) -
-                   dt * ((bload(z0, rs, xo, E2 + st[a1]) - bload(z0, rs, xo, E2)) * cf.idx[a1] -
-                         (bload(z0, rs, xo, E1 + st[a2]) - bload(z0, rs, xo, E1)) * cf.idx[a2]);
-            R br = bload(z0, rs, xr, bs + d * VB) -
-                   dt * ((bload(z0, rs, xr, E2 + st[a1]) - bload(z0, rs, xr, E2)) * cf.idx[a1] -
-                         (bload(z0, rs, xr, E1 + st[a2]) - bload(z0, rs, xr, E1)) * cf.idx[a2]);
-            bstore(bl, rs, xo, bn + d * VB);
-            if (z[d] == P.n[d] - 1) bstore(br, rs, xr, bn + d * VB);  // shared right face
-            u[4 + d] = R(0.5) * (bl + br);
+    };
+
+    // Step 9: edge EMFs of component c at the lower corner (i, j, k); for the
+    // (a, b) = (c+1, c+2) plane, a-faces carry -flux_a[B_b] and b-faces
+    // +flux_b[B_a], each extrapolated to the edge from the upwind side
+    // items [rlo, rhi) of the list (E_x | E_y | E_z), each (tx+1)(ty+1) long
+    auto edges = [&](int k, int rlo, int rhi) {
+        for (int r = rlo + t; r < rhi; r += TILE_THREADS) {
+            const int c = r < nED ? 0 : (r < 2 * nED ? 1 : 2);
+            const int e = r - c * nED;
+            const int j = small_div(e, rTXE), i = e - j * TXE;
+            if ((c == 0 && i == tx) || (c == 1 && j == ty)) continue;
+            const unsigned xo = zoff(i, j, k);
+            // strides (bytes) and flux slots of directions a and b
+            const unsigned sa = c == 0 ? s1 : (c == 1 ? s2 : s0), sb = c == 0 ? s2 : (c == 1 ? s0 : s1);
+            const int a = c == 2 ? 0 : c + 1, b = c == 0 ? 2 : c - 1;
+            const unsigned fa = (unsigned)(F_FL2 + 7 * a) * VB, fb = (unsigned)(F_FL2 + 7 * b) * VB;
+            // E^r neighbours in LDS: along x is -1, along y is -(tx+2), along z the other plane
+            const int ri = (j + 1) * TXP + (i + 1);
+            const R* pc = s_er + (k & 1) * 3 * UPD_ERMAX + c * UPD_ERMAX;
+            const R* pp = s_er + ((k - 1) & 1) * 3 * UPD_ERMAX + c * UPD_ERMAX;
+            R e0, ea, eb, eab;
+            if (c == 0) {  // a = y, b = z
+                e0 = pc[ri], ea = pc[ri - TXP], eb = pp[ri], eab = pp[ri - TXP];
+            } else if (c == 1) {  // a = z, b = x
+                e0 = pc[ri], ea = pp[ri], eb = pc[ri - 1], eab = pp[ri - 1];
+            } else {  // a = x, b = y
+                e0 = pc[ri], ea = pc[ri - 1], eb = pc[ri - TXP], eab = pc[ri - 1 - TXP];
+            }
+            R E = edge_emf(rs, xo, sa, sb, fa, fb, VB, e0, ea, eb, eab);
+            s_ed[((k & 1) * 3 + c) * UPD_EDMAX + e] = E;
+            if (keep_edges) bstore(E, rs, xo, (unsigned)(F_ED + c) * VB);
         }
-        if (apply_floor(u, prm, cf)) atomicAdd(nfloor, 1ULL);
+    };
+
+    // the zone this thread updates on every plane
+    const bool owner = t < tx * ty;
+    const int zj = owner ? small_div(t, rTX) : 0, zi = owner ? t - zj * tx : 0;
+    double sp = 0.0;
+
+    er_plane(k0 - 1);
+    er_plane(k0);
+    __syncthreads();
+    edges(k0, 0, 2 * nED);  // E_x, E_y of plane k0
+    __syncthreads();
+    for (int k = k0; k < k1; k++) {
+        er_plane(k + 1);
+        edges(k, 2 * nED, 3 * nED);  // E_z of plane k
+        __syncthreads();
+        edges(k + 1, 0, 2 * nED);  // E_x, E_y of plane k+1
+        __syncthreads();
+        if (owner) {
+            const unsigned xo = zoff(zi, zj, k);
+            R u[8];
 #pragma unroll
-        for (int c = 0; c < 8; c++) bstore(u[c], rs, xo, qn + c * VB);
-        double ud[8];
+            for (int r = 0; r < 5; r++) {
+                const int c = r < 4 ? r : 7;
+                const unsigned f0 = (unsigned)(F_FL2 + r) * VB, f1 = f0 + 7 * VB, f2 = f1 + 7 * VB;
+                R div = R(0);
+                div += (bload(z0, rs, xo, f0 + s0) - bload(z0, rs, xo, f0)) * cf.idx[0];
+                div += (bload(z0, rs, xo, f1 + s1) - bload(z0, rs, xo, f1)) * cf.idx[1];
+                div += (bload(z0, rs, xo, f2 + s2) - bload(z0, rs, xo, f2)) * cf.idx[2];
+                u[c] = bload(z0, rs, xo, qs + c * VB) - dt * div;
+            }
+            const R* ex0 = s_ed + ((k & 1) * 3 + 0) * UPD_EDMAX;  // E_x, plane k
+            const R* ey0 = s_ed + ((k & 1) * 3 + 1) * UPD_EDMAX;  // E_y, plane k
+            const R* ez0 = s_ed + ((k & 1) * 3 + 2) * UPD_EDMAX;  // E_z, plane k
+            const R* ex1 = s_ed + (((k + 1) & 1) * 3 + 0) * UPD_EDMAX;  // E_x, plane k+1
+            const R* ey1 = s_ed + (((k + 1) & 1) * 3 + 1) * UPD_EDMAX;  // E_y, plane k+1
+            const int e = zj * TXE + zi;
+            const R ix = cf.idx[0], iy = cf.idx[1], iz = cf.idx[2];
+            // Step 11 on the two faces of the zone along each axis
+            R bxl = bload(z0, rs, xo, bs) - dt * ((ez0[e + TXE] - ez0[e]) * iy - (ey1[e] - ey0[e]) * iz);
+            R bxr = bload(z0, rs, xo + s0, bs) -
+                    dt * ((ez0[e + 1 + TXE] - ez0[e + 1]) * iy - (ey1[e + 1] - ey0[e + 1]) * iz);
+            R byl = bload(z0, rs, xo, bs + VB) - dt * ((ex1[e] - ex0[e]) * iz - (ez0[e + 1] - ez0[e]) * ix);
+            R byr = bload(z0, rs, xo + s1, bs + VB) -
+                    dt * ((ex1[e + TXE] - ex0[e + TXE]) * iz - (ez0[e + 1 + TXE] - ez0[e + TXE]) * ix);
+            R bzl = bload(z0, rs, xo, bs + 2 * VB) - dt * ((ey0[e + 1] - ey0[e]) * ix - (ex0[e + TXE] - ex0[e]) * iy);
+            R bzr = bload(z0, rs, xo + s2, bs + 2 * VB) -
+                    dt * ((ey1[e + 1] - ey1[e]) * ix - (ex1[e + TXE] - ex1[e]) * iy);
+            bstore(bxl, rs, xo, bn);
+            bstore(byl, rs, xo, bn + VB);
+            bstore(bzl, rs, xo, bn + 2 * VB);
+            // shared right faces of the patch
+            if (i0 + zi == P.n[0] - 1) bstore(bxr, rs, xo + s0, bn);
+            if (j0 + zj == P.n[1] - 1) bstore(byr, rs, xo + s1, bn + VB);
+            if (k == P.n[2] - 1) bstore(bzr, rs, xo + s2, bn + 2 * VB);
+            u[4] = R(0.5) * (bxl + bxr);
+            u[5] = R(0.5) * (byl + byr);
+            u[6] = R(0.5) * (bzl + bzr);
+            if (apply_floor(u, prm, cf)) atomicAdd(nfloor, 1ULL);
 #pragma unroll
-        for (int c = 0; c < 8; c++) ud[c] = (double)u[c];
-        sp = signal_speed(ud, prm);
+            for (int c = 0; c < 8; c++) bstore(u[c], rs, xo, qn + c * VB);
+            double ud[8];
+#pragma unroll
+            for (int c = 0; c < 8; c++) ud[c] = (double)u[c];
+            sp = fmax(sp, signal_speed(ud, prm));
+        }
     }
     block_max_atomic(sp, smax_bits);
 }
@@ -949,14 +1032,6 @@ hipError_t launch_set_dt(StepConst* sc, double dt, const DevParams& prm, hipStre
 }
 
 template <typename R>
-hipError_t launch_emf_half(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const Coef<R>& cf, int g, int cur,
-                           const StepConst* sc, Box bx, hipStream_t st) {
-    if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(emf_half_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, cf, g, cur, sc, bx);
-    return hipGetLastError();
-}
-
-template <typename R>
 hipError_t launch_edge(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, int g, int fslot, Box bx, EdgeRanges rg,
                        hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
@@ -973,10 +1048,12 @@ hipError_t launch_ct_half(void* pool, const PatchDev* pt, const WorkItem* wk, in
 }
 
 template <typename R>
-hipError_t launch_final(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, const Coef<R>& cf,
-                        int cur, const StepConst* sc, unsigned long long* nfl, unsigned long long* smax, hipStream_t st) {
+hipError_t launch_update(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm,
+                         const Coef<R>& cf, int cur, const StepConst* sc, unsigned long long* nfl, unsigned long long* smax,
+                         int keep_edges, hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(final_update_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, prm, cf, cur, sc, nfl, smax);
+    hipLaunchKernelGGL(update_kernel<R>, dim3(nblk), dim3(TILE_THREADS), 0, st, (R*)pool, pt, wk, prm, cf, cur, sc, nfl,
+                       smax, keep_edges);
     return hipGetLastError();
 }
 
@@ -1017,14 +1094,13 @@ hipError_t launch_diag(const void* pool, const PatchDev* pt, const WorkItem* wk,
                                        hipStream_t);                                                                     \
     template hipError_t launch_dt_reduce<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,         \
                                             unsigned long long*, hipStream_t);                                           \
-    template hipError_t launch_emf_half<R>(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int,       \
-                                           const StepConst*, Box, hipStream_t);                                          \
     template hipError_t launch_edge<R>(void*, const PatchDev*, const WorkItem*, int, int, int, Box, EdgeRanges,         \
                                        hipStream_t);                                                                     \
     template hipError_t launch_ct_half<R>(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int,        \
                                           const StepConst*, Box, hipStream_t);                                           \
-    template hipError_t launch_final<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&,  \
-                                        int, const StepConst*, unsigned long long*, unsigned long long*, hipStream_t);   \
+    template hipError_t launch_update<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, \
+                                         int, const StepConst*, unsigned long long*, unsigned long long*, int,          \
+                                         hipStream_t);                                                                   \
     template hipError_t launch_sweep<R>(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&,        \
                                         const Coef<R>&, int, const StepConst*, int, int, int, int, int, hipStream_t);    \
     template hipError_t launch_diag<R>(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,        \

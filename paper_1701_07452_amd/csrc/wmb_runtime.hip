@@ -17,10 +17,9 @@ template <typename R> hipError_t launch_fill(void*, const PatchDev*, const WorkI
 template <typename R> hipError_t launch_dt_reduce(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, unsigned long long*, hipStream_t);
 hipError_t launch_dt_finalize(unsigned long long*, StepConst*, const DevParams&, hipStream_t);
 hipError_t launch_set_dt(StepConst*, double, const DevParams&, hipStream_t);
-template <typename R> hipError_t launch_emf_half(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int, const StepConst*, Box, hipStream_t);
 template <typename R> hipError_t launch_edge(void*, const PatchDev*, const WorkItem*, int, int, int, Box, EdgeRanges, hipStream_t);
 template <typename R> hipError_t launch_ct_half(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int, const StepConst*, Box, hipStream_t);
-template <typename R> hipError_t launch_final(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, unsigned long long*, unsigned long long*, hipStream_t);
+template <typename R> hipError_t launch_update(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, unsigned long long*, unsigned long long*, int, hipStream_t);
 template <typename R> hipError_t launch_sweep(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, int, int, int, int, int, hipStream_t);
 template <typename R> hipError_t launch_diag(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, double*, hipStream_t);
 }  // namespace wmb
@@ -46,8 +45,6 @@ enum SmaxState { SMAX_ZERO = 0, SMAX_CLEAN = 1, SMAX_DIRTY = 2 };
 const Box BOX_INTERIOR{0, -1};
 const Box BOX_EDGE1{-2, 2};
 const Box BOX_CTH{-2, 2};
-const Box BOX_ER2{-1, 0};
-const Box BOX_EDGE2{0, 0};
 
 }  // namespace
 
@@ -66,7 +63,9 @@ struct wmb_ctx {
     int cur = 0;
     PatchDev* d_patch = nullptr;
     DevList wl_fill[3];
-    DevList wl_int, wl_diag, wl_edge1, wl_cth, wl_er2, wl_edge2;
+    DevList wl_int, wl_diag, wl_edge1, wl_cth, wl_upd;
+    bool keep_edges = false;  // Steps 8-11 also store the Step-9 edges (debugging)
+    bool edges_kept = false;  // the last step stored them
     int smax_state = SMAX_ZERO;
     std::vector<SweepGroup> sweeps[3][2];
     unsigned long long* d_smax = nullptr;
@@ -184,13 +183,18 @@ uint64_t region_bytes(const wmb_patch_desc& d, int g, size_t es) {
     return (b + 255) & ~uint64_t(255);
 }
 
-int check_table(int32_t np, const wmb_patch_desc* d, int g, std::string& why) {
+int check_table(int32_t np, const wmb_patch_desc* d, int g, size_t es, std::string& why) {
     for (int i = 0; i < np; i++) {
         for (int a = 0; a < 3; a++)
             if (d[i].n[a] < g) {
                 why = "patch " + std::to_string(i) + ": interior edge smaller than the ghost width";
                 return WMB_EINVAL;
             }
+        // kernels address a patch region with 32-bit byte offsets
+        if (region_bytes(d[i], g, es) > 0xFFFFFFFFull) {
+            why = "patch " + std::to_string(i) + ": region above 4 GiB (32-bit offsets)";
+            return WMB_EINVAL;
+        }
         if (d[i].nbr[13] != i) {
             why = "patch " + std::to_string(i) + ": nbr[13] must be the patch itself";
             return WMB_EINVAL;
@@ -290,18 +294,11 @@ int run_step(wmb_ctx* c) {
         }
         mark(c);
     }
-    e = launch_emf_half<R>(c->pool, c->d_patch, c->wl_er2.d, c->wl_er2.n, coef<R>(c), c->p.ghost, cur, c->d_sc, BOX_ER2,
-                           c->stream);
-    STEPCK("emf_half");
+    e = launch_update<R>(c->pool, c->d_patch, c->wl_upd.d, c->wl_upd.n, c->dp, coef<R>(c), cur, c->d_sc, c->d_nfloor,
+                         c->d_smax, c->keep_edges ? 1 : 0, c->stream);
+    STEPCK("update");
     mark(c);
-    e = launch_edge<R>(c->pool, c->d_patch, c->wl_edge2.d, c->wl_edge2.n, c->p.ghost, F_FL2, BOX_EDGE2,
-                       EdgeRanges{0, -1, 0, 0}, c->stream);
-    STEPCK("edge_emf2");
-    mark(c);
-    e = launch_final<R>(c->pool, c->d_patch, c->wl_int.d, c->wl_int.n, c->dp, coef<R>(c), cur, c->d_sc, c->d_nfloor,
-                        c->d_smax, c->stream);
-    STEPCK("final_update");
-    mark(c);
+    c->edges_kept = c->keep_edges;
 #undef STEPCK
     c->cur ^= 1;
     // the final update folds the new state's signal speeds into smax
@@ -329,6 +326,38 @@ int build_box_list(wmb_ctx* c, Box bx, DevList& out, bool xcd = true) {
         for (int b = 0; b < nb; b++) items.push_back(WorkItem{p, b, 0, 0});
     }
     if (xcd) items = xcd_order(items);
+    out.n = (int)items.size();
+    return upload(c, &out.d, items);
+}
+
+// Column tiles of the marching kernels over the in-plane box [lo, n+hi]^2
+// (x, y) and the planes [zlo, n+zhi]: each patch's box is cut into near-equal
+// parts of at most 32 zones along x, then along y into parts with at most
+// 256 zones per tile plane and 32 per edge.  Item fields (origins biased by
+// 16, they may be negative): a = i0 | j0 << 16, b = tx | ty << 16,
+// c = k0 | k1 << 16 with k1 exclusive.
+constexpr int TILE_BIAS = 16;
+int build_tile_list(wmb_ctx* c, int lo, int hi, int zlo, int zhi, DevList& out) {
+    std::vector<WorkItem> items;
+    for (int p = 0; p < c->npatch; p++) {
+        const int* n = c->desc[p].n;
+        const int ex = n[0] + hi - lo + 1, ey = n[1] + hi - lo + 1;
+        const int mx = (ex + 31) / 32;
+        const int txmax = (ex + mx - 1) / mx;
+        int tymax = 256 / txmax;
+        if (tymax > 32) tymax = 32;
+        const int my = (ey + tymax - 1) / tymax;
+        const int k0 = zlo + TILE_BIAS, k1 = n[2] + zhi + 1 + TILE_BIAS;
+        for (int by = 0; by < my; by++) {
+            const int j0 = lo + (int)((long long)ey * by / my), j1 = lo + (int)((long long)ey * (by + 1) / my);
+            for (int bx = 0; bx < mx; bx++) {
+                const int i0 = lo + (int)((long long)ex * bx / mx), i1 = lo + (int)((long long)ex * (bx + 1) / mx);
+                items.push_back(WorkItem{p, (i0 + TILE_BIAS) | ((j0 + TILE_BIAS) << 16), (i1 - i0) | ((j1 - j0) << 16),
+                                         k0 | (k1 << 16)});
+            }
+        }
+    }
+    items = xcd_order(items);
     out.n = (int)items.size();
     return upload(c, &out.d, items);
 }
@@ -550,6 +579,7 @@ int debug_stage_t(wmb_ctx* c, int ip, int stage, double* out) {
     }
     int slot = stage == 3 ? F_BH : (stage == 6 ? F_ED : -1);
     if (slot < 0) return fail(c, WMB_EINVAL, "stage not kept after the step (2: Step-3 edges are overwritten by Step 9)");
+    if (stage == 6 && !c->edges_kept) return fail(c, WMB_ESTATE, "Step-9 edges are stored only by steps run with wmb_keep_stages on");
     for (int k = 0; k < 3; k++) {
         int rc = fetch(slot + k);
         if (rc) return rc;
@@ -721,7 +751,7 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     if (c->inited) return fail(c, WMB_EORDER, "patches already initialised");
     if (npatch <= 0 || !d || !dev_pool) return fail(c, WMB_EINVAL, "bad arguments");
     std::string why;
-    if (check_table(npatch, d, c->p.ghost, why)) return fail(c, WMB_EINVAL, why);
+    if (check_table(npatch, d, c->p.ghost, c->esize, why)) return fail(c, WMB_EINVAL, why);
     uint64_t need = 0;
     wmb_pool_bytes(&c->p, npatch, d, &need);
     if (pool_bytes < need)
@@ -759,8 +789,7 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     if ((rc = build_box_list(c, BOX_INTERIOR, c->wl_diag, false))) return rc;
     if ((rc = build_box_list(c, BOX_EDGE1, c->wl_edge1))) return rc;
     if ((rc = build_box_list(c, BOX_CTH, c->wl_cth))) return rc;
-    if ((rc = build_box_list(c, BOX_ER2, c->wl_er2))) return rc;
-    if ((rc = build_box_list(c, BOX_EDGE2, c->wl_edge2))) return rc;
+    if ((rc = build_tile_list(c, 0, -1, 0, -1, c->wl_upd))) return rc;
     if ((rc = build_sweeps(c))) return rc;
     if ((rc = dev_alloc(c, &c->d_smax, 1))) return rc;
     if ((rc = dev_alloc(c, &c->d_sc, 1))) return rc;
@@ -907,6 +936,13 @@ int wmb_set_tuning(wmb_ctx* c, const int32_t* quads, int32_t n) {
         }
     }
     free_graphs(c);
+    return WMB_OK;
+}
+
+int wmb_keep_stages(wmb_ctx* c, int32_t on) {
+    if (!c) return WMB_EINVAL;
+    if (c->keep_edges != (on != 0)) free_graphs(c);  // the update launch carries the flag
+    c->keep_edges = on != 0;
     return WMB_OK;
 }
 

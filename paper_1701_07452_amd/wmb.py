@@ -21,10 +21,11 @@ WMB_FP64, WMB_FP32 = 0, 1
 EXPORTS = [
     "wmb_create", "wmb_pool_bytes", "wmb_init_patches", "wmb_set_state", "wmb_get_state", "wmb_get_stored",
     "wmb_fill_ghosts", "wmb_compute_dt", "wmb_advance", "wmb_run_steps", "wmb_diagnostics", "wmb_debug_stage",
-    "wmb_autotune", "wmb_set_tuning", "wmb_profile_step", "wmb_destroy", "wmb_strerror", "wmb_last_error",
+    "wmb_autotune", "wmb_set_tuning", "wmb_keep_stages", "wmb_profile_step", "wmb_destroy", "wmb_strerror",
+    "wmb_last_error",
 ]
 KERNEL_CLASSES = ["fill", "dt", "sweep1_x", "sweep1_y", "sweep1_z", "edge1", "ct_half",
-                  "sweep2_x", "sweep2_y", "sweep2_z", "emf_half", "edge2", "final"]
+                  "sweep2_x", "sweep2_y", "sweep2_z", "update"]
 
 
 class WmbError(RuntimeError):
@@ -98,6 +99,7 @@ def load_library():
     lib.wmb_profile_step.argtypes = [vp, dp, C.c_int32]
     lib.wmb_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.c_int32]
     lib.wmb_set_tuning.argtypes = [vp, C.POINTER(C.c_int32), C.c_int32]
+    lib.wmb_keep_stages.argtypes = [vp, C.c_int32]
     lib.wmb_destroy.argtypes = [vp]
     lib.wmb_strerror.argtypes = [C.c_int]
     lib.wmb_strerror.restype = C.c_char_p
@@ -250,6 +252,10 @@ class Sim:
         flat = [v for (st, ax, e), W in sorted(tuning.items()) for v in (st, ax, e, W)]
         buf = (C.c_int32 * max(len(flat), 1))(*flat)
         self._check(self.lib.wmb_set_tuning(self.h, buf, len(flat)))
+
+    def keep_stages(self, on=True):
+        """Let later steps store the Step-9 edges for debug_stage(6)."""
+        self._check(self.lib.wmb_keep_stages(self.h, 1 if on else 0))
 
     def profile_step(self):
         """Per-kernel-class durations (ms) of one eager step; advances the state."""
