@@ -448,18 +448,36 @@ __device__ __forceinline__ int small_div(int r, int recip) { return (r * recip) 
 // ---------------------------------------------------------------------------
 // Steps 8-11 fused.  A block owns a column tile of zones [i0, i0+tx) x
 // [j0, j0+ty) (tx, ty <= 32, tx ty <= 256) over the planes [k0, k1) and
-// marches along z.  Per plane k it forms
-//   E^r on plane k+1 over the tile and a one-zone ring (Step 8: velocity of
-//       the unsplit half update of q^n with the Step-6/7 fluxes, zone field
-//       from the face average of b^{n+1/2}),
-//   the Step-9 edge EMFs: E_z on plane k, E_x and E_y on plane k+1 (the same
-//       upwinded average as Step 3, fluxes of Steps 6/7),
-//   and then the zones of plane k: conservative update (Step 10), CT update of
-//       their faces (Step 11), zone field from the face average, FP64 floors,
-//       and the FP64 signal speed folded into smax for the next dt.
-// E^r and the edges live in LDS, two planes each; nothing of Steps 8-9 goes
-// to HBM unless keep_edges asks for the Step-9 edges (debugging).
+// marches along z.  Iteration k forms
+//   phase 1  E^r on plane k+1 over the tile and a one-zone ring (Step 8:
+//            velocity of the unsplit half update of q^n with the Step-6/7
+//            fluxes, zone field from the face average of b^{n+1/2}),
+//   phase 2  the Step-9 edge EMFs of plane k+1 (the Step-3 upwinded average
+//            with the fluxes of Steps 6/7),
+//   phase 3  the zones of plane k: conservative update (Step 10), CT update
+//            of their faces (Step 11), zone field from the face average,
+//            FP64 floors, and the FP64 signal speed folded into smax.
+// E^r and the edges live in LDS, two planes each.  Every value that a later
+// plane needs again is carried in registers (z-face fluxes and fields, the
+// plane-below fluxes of the E_x and E_y edges, the divergence of the own
+// zone formed in phase 1), so each datum is read from memory once per step
+// and the L2 only serves reuse within a plane.  Nothing of Steps 8-9 goes to
+// HBM unless keep_edges asks for the Step-9 edges (debugging).
 // ---------------------------------------------------------------------------
+
+// Upwinded edge value from preloaded face data (see edge_emf): Ea_0, Ea_b the
+// a-face values -flux_a[B_b] at the zone and one back along b; Eb_0, Eb_a the
+// b-face values +flux_b[B_a] at the zone and one back along a; m* the mass
+// fluxes across the same faces; e* the E^r of the four zones.
+template <typename R>
+__device__ __forceinline__ R edge_combine(R Ea_0, R Ea_b, R Eb_0, R Eb_a, R ma_0, R ma_b, R mb_0, R mb_a, R e0, R ea,
+                                          R eb, R eab) {
+    R d1 = upwind_pick(ma_0, ea - Eb_a, e0 - Eb_0);
+    R d2 = upwind_pick(ma_b, Eb_a - eab, Eb_0 - eb);
+    R d3 = upwind_pick(mb_0, eb - Ea_b, e0 - Ea_0);
+    R d4 = upwind_pick(mb_a, Ea_b - eab, Ea_0 - ea);
+    return R(0.25) * ((Ea_0 - d1) + (Ea_b + d2) + (Eb_0 - d3) + (Eb_a + d4));
+}
 
 template <typename R>
 __global__ void __launch_bounds__(TILE_THREADS) update_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
@@ -482,124 +500,166 @@ __global__ void __launch_bounds__(TILE_THREADS) update_kernel(R* __restrict__ po
     const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + P.base, (unsigned)F_TOTAL * VB);
     const unsigned qs = (unsigned)(cur ? F_ST1 : F_ST0) * VB, bs = qs + 8 * VB;
     const unsigned qn = (unsigned)(cur ? F_ST0 : F_ST1) * VB, bn = qn + 8 * VB;
+    const unsigned FX = (unsigned)F_FL2 * VB, FY = FX + 7 * VB, FZ = FY + 7 * VB, BH = (unsigned)F_BH * VB;
     const R hdt = sc_hdt(*sc, R(0)), dt = sc_dt(*sc, R(0));
+    const R ix = cf.idx[0], iy = cf.idx[1], iz = cf.idx[2];
     const R z0 = R(0);
     const int t = threadIdx.x;
     const int TXP = tx + 2, TXE = tx + 1;
-    const int nER = TXP * (ty + 2), nED = TXE * (ty + 1);
-    const int rTXP = 65536 / TXP + 1, rTXE = 65536 / TXE + 1, rTX = 65536 / tx + 1;
-    // byte offset of the zone at tile-local (i, j) on plane k
     auto zoff = [&](int i, int j, int k) -> unsigned {
         return (unsigned)sidx(P, i0 + i + g, j0 + j + g, k + g) * ES;
     };
+    auto ld = [&](unsigned voff, unsigned soff) -> R { return bload(z0, rs, voff, soff); };
 
-    // Step 8 on plane k over [-1, tx] x [-1, ty]
-    auto er_plane = [&](int k) {
-        R* dst = s_er + (k & 1) * 3 * UPD_ERMAX;
-        for (int r = t; r < nER; r += TILE_THREADS) {
-            const int ey = small_div(r, rTXP), ex = r - ey * TXP;
-            const unsigned xo = zoff(ex - 1, ey - 1, k);
-            R u[4];
-#pragma unroll
-            for (int c = 0; c < 4; c++) {
-                R div = R(0);
-                const unsigned f0 = (unsigned)(F_FL2 + c) * VB, f1 = f0 + 7 * VB, f2 = f1 + 7 * VB;
-                div += (bload(z0, rs, xo, f0 + s0) - bload(z0, rs, xo, f0)) * cf.idx[0];
-                div += (bload(z0, rs, xo, f1 + s1) - bload(z0, rs, xo, f1)) * cf.idx[1];
-                div += (bload(z0, rs, xo, f2 + s2) - bload(z0, rs, xo, f2)) * cf.idx[2];
-                u[c] = bload(z0, rs, xo, qs + c * VB) - hdt * div;
-            }
-            const unsigned h = (unsigned)F_BH * VB;
-            R B0 = R(0.5) * (bload(z0, rs, xo, h) + bload(z0, rs, xo, h + s0));
-            R B1 = R(0.5) * (bload(z0, rs, xo, h + VB) + bload(z0, rs, xo, h + VB + s1));
-            R B2 = R(0.5) * (bload(z0, rs, xo, h + 2 * VB) + bload(z0, rs, xo, h + 2 * VB + s2));
-            R ir = frcp(u[0]);
-            R vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
-            dst[r] = vz * B1 - vy * B2;
-            dst[UPD_ERMAX + r] = vx * B2 - vz * B0;
-            dst[2 * UPD_ERMAX + r] = vy * B0 - vx * B1;
-        }
-    };
-
-    // Step 9: edge EMFs of component c at the lower corner (i, j, k); for the
-    // (a, b) = (c+1, c+2) plane, a-faces carry -flux_a[B_b] and b-faces
-    // +flux_b[B_a], each extrapolated to the edge from the upwind side
-    // items [rlo, rhi) of the list (E_x | E_y | E_z), each (tx+1)(ty+1) long
-    auto edges = [&](int k, int rlo, int rhi) {
-        for (int r = rlo + t; r < rhi; r += TILE_THREADS) {
-            const int c = r < nED ? 0 : (r < 2 * nED ? 1 : 2);
-            const int e = r - c * nED;
-            const int j = small_div(e, rTXE), i = e - j * TXE;
-            if ((c == 0 && i == tx) || (c == 1 && j == ty)) continue;
-            const unsigned xo = zoff(i, j, k);
-            // strides (bytes) and flux slots of directions a and b
-            const unsigned sa = c == 0 ? s1 : (c == 1 ? s2 : s0), sb = c == 0 ? s2 : (c == 1 ? s0 : s1);
-            const int a = c == 2 ? 0 : c + 1, b = c == 0 ? 2 : c - 1;
-            const unsigned fa = (unsigned)(F_FL2 + 7 * a) * VB, fb = (unsigned)(F_FL2 + 7 * b) * VB;
-            // E^r neighbours in LDS: along x is -1, along y is -(tx+2), along z the other plane
-            const int ri = (j + 1) * TXP + (i + 1);
-            const R* pc = s_er + (k & 1) * 3 * UPD_ERMAX + c * UPD_ERMAX;
-            const R* pp = s_er + ((k - 1) & 1) * 3 * UPD_ERMAX + c * UPD_ERMAX;
-            R e0, ea, eb, eab;
-            if (c == 0) {  // a = y, b = z
-                e0 = pc[ri], ea = pc[ri - TXP], eb = pp[ri], eab = pp[ri - TXP];
-            } else if (c == 1) {  // a = z, b = x
-                e0 = pc[ri], ea = pp[ri], eb = pc[ri - 1], eab = pp[ri - 1];
-            } else {  // a = x, b = y
-                e0 = pc[ri], ea = pc[ri - 1], eb = pc[ri - TXP], eab = pc[ri - 1 - TXP];
-            }
-            R E = edge_emf(rs, xo, sa, sb, fa, fb, VB, e0, ea, eb, eab);
-            s_ed[((k & 1) * 3 + c) * UPD_EDMAX + e] = E;
-            if (keep_edges) bstore(E, rs, xo, (unsigned)(F_ED + c) * VB);
-        }
-    };
-
-    // the zone this thread updates on every plane
+    // own zone (every thread of a full tile), ring zone of E^r, extra edge position
     const bool owner = t < tx * ty;
-    const int zj = owner ? small_div(t, rTX) : 0, zi = owner ? t - zj * tx : 0;
+    const int zj = owner ? small_div(t, 65536 / tx + 1) : 0, zi = owner ? t - zj * tx : 0;
+    const int nring = 2 * TXP + 2 * ty;
+    const bool ring = t < nring;
+    int rx = 0, ry = 0;
+    if (t < TXP) {
+        rx = t - 1, ry = -1;
+    } else if (t < 2 * TXP) {
+        rx = t - TXP - 1, ry = ty;
+    } else if (t < 2 * TXP + ty) {
+        rx = -1, ry = t - 2 * TXP;
+    } else {
+        rx = tx, ry = t - 2 * TXP - ty;
+    }
+    const bool extra = t <= tx + ty;  // edges on the column i = tx, then on the row j = ty
+    const int xi = t <= ty ? tx : t - ty - 1, xj = t <= ty ? t : ty;
+    const int xmask = (xi < tx ? 1 : 0) | (xj < ty ? 2 : 0) | 4;
+
+    // Step 8 at tile-local zone (ex, ey) of plane p.  fz, bz: flux_z rows 0-3 and
+    // b^{n+1/2}_z on the lower z-face (carried from plane p-1, loaded when
+    // fresh); replaced by those of the upper face.  uf, if given, receives
+    // q - dt div F of rows 0-3 for the final update of the zone.
+    auto er_item = [&](int ex, int ey, int p, R(&fz)[4], R& bz, bool fresh, R* uf) {
+        const unsigned xo = zoff(ex, ey, p);
+        R u[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            const unsigned cf0 = FX + c * VB, cf1 = FY + c * VB, cf2 = FZ + c * VB;
+            if (fresh) fz[c] = ld(xo, cf2);
+            const R fzn = ld(xo + s2, cf2);
+            R div = R(0);
+            div += (ld(xo + s0, cf0) - ld(xo, cf0)) * ix;
+            div += (ld(xo + s1, cf1) - ld(xo, cf1)) * iy;
+            div += (fzn - fz[c]) * iz;
+            const R q = ld(xo, qs + c * VB);
+            u[c] = q - hdt * div;
+            if (uf) uf[c] = q - dt * div;
+            fz[c] = fzn;
+        }
+        if (fresh) bz = ld(xo, BH + 2 * VB);
+        const R bzn = ld(xo + s2, BH + 2 * VB);
+        R B0 = R(0.5) * (ld(xo, BH) + ld(xo + s0, BH));
+        R B1 = R(0.5) * (ld(xo, BH + VB) + ld(xo + s1, BH + VB));
+        R B2 = R(0.5) * (bz + bzn);
+        bz = bzn;
+        R ir = frcp(u[0]);
+        R vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
+        R* dst = s_er + (p & 1) * 3 * UPD_ERMAX + (ey + 1) * TXP + (ex + 1);
+        dst[0] = vz * B1 - vy * B2;
+        dst[UPD_ERMAX] = vx * B2 - vz * B0;
+        dst[2 * UPD_ERMAX] = vy * B0 - vx * B1;
+    };
+
+    // Step 9 at tile-local edge position (i, j) of plane p, components in mask
+    // (bit c).  cx: flux_y rows 0 and 5, cy: flux_x rows 0 and 6, both at (i, j)
+    // of plane p-1 (carried, loaded when fresh); replaced by those of plane p.
+    auto ed_item = [&](int i, int j, int p, int mask, R(&cx)[2], R(&cy)[2], bool fresh) {
+        const unsigned xo = zoff(i, j, p);
+        const int ri = (j + 1) * TXP + (i + 1), e = j * TXE + i;
+        const R* ec = s_er + (p & 1) * 3 * UPD_ERMAX + ri;        // E^r of plane p at the edge's zone
+        const R* ep = s_er + ((p - 1) & 1) * 3 * UPD_ERMAX + ri;  // plane p-1
+        R* dst = s_ed + (p & 1) * 3 * UPD_EDMAX + e;
+        if (mask & 1) {  // E_x: a = y, b = z
+            if (fresh) cx[0] = ld(xo - s2, FY), cx[1] = ld(xo - s2, FY + 5 * VB);
+            const R ma = ld(xo, FY), fa5 = ld(xo, FY + 5 * VB);
+            const R mb = ld(xo, FZ), fb6 = ld(xo, FZ + 6 * VB), mba = ld(xo - s1, FZ), fb6a = ld(xo - s1, FZ + 6 * VB);
+            const R E = edge_combine(-fa5, -cx[1], fb6, fb6a, ma, cx[0], mb, mba, ec[0], ec[-TXP], ep[0], ep[-TXP]);
+            dst[0] = E;
+            if (keep_edges) bstore(E, rs, xo, (unsigned)F_ED * VB);
+            cx[0] = ma, cx[1] = fa5;
+        }
+        if (mask & 2) {  // E_y: a = z, b = x
+            if (fresh) cy[0] = ld(xo - s2, FX), cy[1] = ld(xo - s2, FX + 6 * VB);
+            const R ma = ld(xo, FZ), fa5 = ld(xo, FZ + 5 * VB), mab = ld(xo - s0, FZ), fa5b = ld(xo - s0, FZ + 5 * VB);
+            const R mb = ld(xo, FX), fb6 = ld(xo, FX + 6 * VB);
+            const R* c1 = ec + UPD_ERMAX;
+            const R* p1 = ep + UPD_ERMAX;
+            const R E = edge_combine(-fa5, -fa5b, fb6, cy[1], ma, mab, mb, cy[0], c1[0], p1[0], c1[-1], p1[-1]);
+            dst[UPD_EDMAX] = E;
+            if (keep_edges) bstore(E, rs, xo, (unsigned)(F_ED + 1) * VB);
+            cy[0] = mb, cy[1] = fb6;
+        }
+        if (mask & 4) {  // E_z: a = x, b = y
+            const R ma = ld(xo, FX), fa5 = ld(xo, FX + 5 * VB), mab = ld(xo - s1, FX), fa5b = ld(xo - s1, FX + 5 * VB);
+            const R mb = ld(xo, FY), fb6 = ld(xo, FY + 6 * VB), mba = ld(xo - s0, FY), fb6a = ld(xo - s0, FY + 6 * VB);
+            const R* c2 = ec + 2 * UPD_ERMAX;
+            const R E = edge_combine(-fa5, -fa5b, fb6, fb6a, ma, mab, mb, mba, c2[0], c2[-1], c2[-TXP], c2[-1 - TXP]);
+            dst[2 * UPD_EDMAX] = E;
+            if (keep_edges) bstore(E, rs, xo, (unsigned)(F_ED + 2) * VB);
+        }
+    };
+
+    // carried registers: E^r items (own, ring), edge items (own, extra), final update
+    R fz_o[4], fz_r[4], bz_o = R(0), bz_r = R(0);
+    R cx_o[2], cy_o[2], cx_x[2], cy_x[2];
+    R ufc[4], ufn[4];  // q - dt div F (rows 0-3) of the own zone on planes k and k+1
+    R fz4 = R(0), bzc = R(0);  // flux_z row 4 and b^{n+1}_z on the lower face of plane k
     double sp = 0.0;
 
-    er_plane(k0 - 1);
-    er_plane(k0);
+    // prologue: E^r of planes k0-1 and k0, edges of plane k0
+    if (owner) er_item(zi, zj, k0 - 1, fz_o, bz_o, true, nullptr);
+    if (ring) er_item(rx, ry, k0 - 1, fz_r, bz_r, true, nullptr);
+    if (owner) er_item(zi, zj, k0, fz_o, bz_o, false, ufc);
+    if (ring) er_item(rx, ry, k0, fz_r, bz_r, false, nullptr);
     __syncthreads();
-    edges(k0, 0, 2 * nED);  // E_x, E_y of plane k0
+    if (owner) ed_item(zi, zj, k0, 7, cx_o, cy_o, true);
+    if (extra) ed_item(xi, xj, k0, xmask, cx_x, cy_x, true);
     __syncthreads();
     for (int k = k0; k < k1; k++) {
-        er_plane(k + 1);
-        edges(k, 2 * nED, 3 * nED);  // E_z of plane k
+        if (owner) er_item(zi, zj, k + 1, fz_o, bz_o, false, ufn);
+        if (ring) er_item(rx, ry, k + 1, fz_r, bz_r, false, nullptr);
         __syncthreads();
-        edges(k + 1, 0, 2 * nED);  // E_x, E_y of plane k+1
+        if (owner) ed_item(zi, zj, k + 1, 7, cx_o, cy_o, false);
+        if (extra) ed_item(xi, xj, k + 1, xmask, cx_x, cy_x, false);
         __syncthreads();
         if (owner) {
             const unsigned xo = zoff(zi, zj, k);
             R u[8];
 #pragma unroll
-            for (int r = 0; r < 5; r++) {
-                const int c = r < 4 ? r : 7;
-                const unsigned f0 = (unsigned)(F_FL2 + r) * VB, f1 = f0 + 7 * VB, f2 = f1 + 7 * VB;
+            for (int c = 0; c < 4; c++) u[c] = ufc[c];
+            // Step 10 on E (flux row 4)
+            {
+                if (k == k0) fz4 = ld(xo, FZ + 4 * VB);
+                const R fz4n = ld(xo + s2, FZ + 4 * VB);
                 R div = R(0);
-                div += (bload(z0, rs, xo, f0 + s0) - bload(z0, rs, xo, f0)) * cf.idx[0];
-                div += (bload(z0, rs, xo, f1 + s1) - bload(z0, rs, xo, f1)) * cf.idx[1];
-                div += (bload(z0, rs, xo, f2 + s2) - bload(z0, rs, xo, f2)) * cf.idx[2];
-                u[c] = bload(z0, rs, xo, qs + c * VB) - dt * div;
+                div += (ld(xo + s0, FX + 4 * VB) - ld(xo, FX + 4 * VB)) * ix;
+                div += (ld(xo + s1, FY + 4 * VB) - ld(xo, FY + 4 * VB)) * iy;
+                div += (fz4n - fz4) * iz;
+                u[7] = ld(xo, qs + 7 * VB) - dt * div;
+                fz4 = fz4n;
             }
-            const R* ex0 = s_ed + ((k & 1) * 3 + 0) * UPD_EDMAX;  // E_x, plane k
-            const R* ey0 = s_ed + ((k & 1) * 3 + 1) * UPD_EDMAX;  // E_y, plane k
-            const R* ez0 = s_ed + ((k & 1) * 3 + 2) * UPD_EDMAX;  // E_z, plane k
-            const R* ex1 = s_ed + (((k + 1) & 1) * 3 + 0) * UPD_EDMAX;  // E_x, plane k+1
-            const R* ey1 = s_ed + (((k + 1) & 1) * 3 + 1) * UPD_EDMAX;  // E_y, plane k+1
+            const R* ex0 = s_ed + (k & 1) * 3 * UPD_EDMAX;  // E_x, plane k
+            const R* ey0 = ex0 + UPD_EDMAX;                  // E_y, plane k
+            const R* ez0 = ex0 + 2 * UPD_EDMAX;              // E_z, plane k
+            const R* ex1 = s_ed + ((k + 1) & 1) * 3 * UPD_EDMAX;  // E_x, plane k+1
+            const R* ey1 = ex1 + UPD_EDMAX;                        // E_y, plane k+1
             const int e = zj * TXE + zi;
-            const R ix = cf.idx[0], iy = cf.idx[1], iz = cf.idx[2];
-            // Step 11 on the two faces of the zone along each axis
-            R bxl = bload(z0, rs, xo, bs) - dt * ((ez0[e + TXE] - ez0[e]) * iy - (ey1[e] - ey0[e]) * iz);
-            R bxr = bload(z0, rs, xo + s0, bs) -
-                    dt * ((ez0[e + 1 + TXE] - ez0[e + 1]) * iy - (ey1[e + 1] - ey0[e + 1]) * iz);
-            R byl = bload(z0, rs, xo, bs + VB) - dt * ((ex1[e] - ex0[e]) * iz - (ez0[e + 1] - ez0[e]) * ix);
-            R byr = bload(z0, rs, xo + s1, bs + VB) -
+            // Step 11 on the two faces of the zone along each axis (the lower
+            // z-face is the upper one of the plane below)
+            R bxl = ld(xo, bs) - dt * ((ez0[e + TXE] - ez0[e]) * iy - (ey1[e] - ey0[e]) * iz);
+            R bxr = ld(xo + s0, bs) - dt * ((ez0[e + 1 + TXE] - ez0[e + 1]) * iy - (ey1[e + 1] - ey0[e + 1]) * iz);
+            R byl = ld(xo, bs + VB) - dt * ((ex1[e] - ex0[e]) * iz - (ez0[e + 1] - ez0[e]) * ix);
+            R byr = ld(xo + s1, bs + VB) -
                     dt * ((ex1[e + TXE] - ex0[e + TXE]) * iz - (ez0[e + 1 + TXE] - ez0[e + TXE]) * ix);
-            R bzl = bload(z0, rs, xo, bs + 2 * VB) - dt * ((ey0[e + 1] - ey0[e]) * ix - (ex0[e + TXE] - ex0[e]) * iy);
-            R bzr = bload(z0, rs, xo + s2, bs + 2 * VB) -
-                    dt * ((ey1[e + 1] - ey1[e]) * ix - (ex1[e + TXE] - ex1[e]) * iy);
+            if (k == k0) bzc = ld(xo, bs + 2 * VB) - dt * ((ey0[e + 1] - ey0[e]) * ix - (ex0[e + TXE] - ex0[e]) * iy);
+            R bzl = bzc;
+            R bzr = ld(xo + s2, bs + 2 * VB) - dt * ((ey1[e + 1] - ey1[e]) * ix - (ex1[e + TXE] - ex1[e]) * iy);
+            bzc = bzr;
             bstore(bxl, rs, xo, bn);
             bstore(byl, rs, xo, bn + VB);
             bstore(bzl, rs, xo, bn + 2 * VB);
@@ -617,6 +677,8 @@ __global__ void __launch_bounds__(TILE_THREADS) update_kernel(R* __restrict__ po
 #pragma unroll
             for (int c = 0; c < 8; c++) ud[c] = (double)u[c];
             sp = fmax(sp, signal_speed(ud, prm));
+#pragma unroll
+            for (int c = 0; c < 4; c++) ufc[c] = ufn[c];
         }
     }
     block_max_atomic(sp, smax_bits);
