@@ -52,10 +52,10 @@ def alg_bytes(kclass, n, g, es, npatch):
     elif kclass.startswith("sweep2"):
         T, P = n + 2, n + 6
         per = (8 + 2 * 7 + 3 + 1) * P * T * T + 7 * (P - 3) * T * T  # q, 2 transverse fluxes, b, b^{n+1/2}; flux out
-    elif kclass == "edge1":
-        per = (9 + 3 + 3) * box(-2, 2)                   # 3 flux rows x 3 dirs + E^r in; 3 edges out
     elif kclass == "ct_half":
-        per = 9 * box(-2, 2)                             # b^n and 2 x 3 edges in; b^{n+1/2} out
+        # Steps 3-4 fused: Step-1 flux rows 0, 5, 6 (3 dirs), E^r and b^n in,
+        # b^{n+1/2} out, over the box [-2, n+2]^3
+        per = (9 + 3 + 3 + 3) * box(-2, 2)
     elif kclass == "update":
         # Steps 8-11 fused: q^n rho, m + flux rows 0-3 + b^{n+1/2} over the E^r
         # box [-1, n]; flux rows 5-6 over the edge box [0, n]; q^n E, flux row 4,

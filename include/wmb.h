@@ -178,11 +178,12 @@ int wmb_keep_stages(wmb_ctx *c, int32_t on);
    duration in milliseconds of each class in ms[0 .. WMB_NCLASS-1], in this
    order: fill (3 passes), dt (finalize of the reduction that the previous
    update folded in), sweep x, y, z (Step 1, the x sweep also forming the
-   Step-2 reference EMF), edge EMFs (Step 3), CT half (Step 4), sweep x,
-   y, z (Steps 5-7), update (Steps 8-11 fused: half-step EMF, edge EMFs,
-   conservative and CT update, and the signal-speed maximum of the new
-   state).  Advances the state by one step.  Synchronous. */
-#define WMB_NCLASS 11
+   Step-2 reference EMF), CT half (Steps 3-4 fused: edge EMFs and
+   b^{n+1/2}), sweep x, y, z (Steps 5-7), update (Steps 8-11 fused:
+   half-step EMF, edge EMFs, conservative and CT update, and the
+   signal-speed maximum of the new state).  Advances the state by one step.
+   Synchronous. */
+#define WMB_NCLASS 10
 int wmb_profile_step(wmb_ctx *c, double *ms, int32_t nclass);
 
 /* Free the context, its tables and graphs (not the pool, not the stream). */

@@ -69,20 +69,15 @@ enum : int {
 
 struct WorkItem {
     int patch;
-    int a;  // box kernels: block index in the patch; sweeps: first fast-transverse coord
-    int b;  // sweeps: slow-transverse coord
-    int c;  // sweeps: last fast-transverse coord (inclusive)
+    int a;  // box kernels: block index in the patch; sweeps: first fast-transverse coord;
+            // tiles: i0 | j0 << 16 (biased)
+    int b;  // sweeps: slow-transverse coord; tiles: tx | ty << 16
+    int c;  // sweeps: last fast-transverse coord (inclusive); tiles: k0 | k1 << 16 (biased, k1 exclusive)
 };
 
 // Box kernels: interior-relative inclusive ranges [lo, n + hi] per axis.
 struct Box {
     int lo, hi;
-};
-
-// Per-component ranges of the edge-EMF kernel: along the edge's own axis
-// [lo_c, n + hi_c], along the two others [lo_o, n + hi_o].
-struct EdgeRanges {
-    int lo_c, hi_c, lo_o, hi_o;
 };
 
 }  // namespace wmb

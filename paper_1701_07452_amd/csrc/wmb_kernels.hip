@@ -13,8 +13,8 @@
 //   dt_finalize       dt = cfl / smax, kept in device memory
 //   sweep<d,1>        Step 1   MHDTVD fluxes from q^n, B_par = b^n    (hot);
 //                              the x sweep also writes E^r (Step 2)
-//   edge_emf          Step 3   upwinded edge EMFs
-//   ct_half           Step 4   b^{n+1/2} = b^n - dt/2 curl E
+//   ct_half           Steps 3-4 fused, marching along z with the edge EMFs in
+//                              LDS: b^{n+1/2} = b^n - dt/2 curl E
 //   sweep<d,2>        Steps 5-7  transverse predictor + source, then MHDTVD
 //                              fluxes with B_par = b^{n+1/2}        (hot)
 //   update            Steps 8-11 fused, marching along z with E^r and the edge
@@ -347,95 +347,21 @@ __device__ __forceinline__ R upwind_pick(R f, R dl, R dr) {
     return f > R(0) ? dl : (f < R(0) ? dr : R(0.5) * (dl + dr));
 }
 
-// Edge value of component c at zone byte offset xo: fa, fb are the flux slots
-// (bytes) of directions a and b, sa, sb their strides (bytes); e0, ea, eb, eab
-// are E^r_c of the zone, of the zone one back along a, one back along b and
-// one back along both.
+// Upwinded edge value from preloaded face data: Ea_0, Ea_b the
+// a-face values -flux_a[B_b] at the zone and one back along b; Eb_0, Eb_a the
+// b-face values +flux_b[B_a] at the zone and one back along a; m* the mass
+// fluxes across the same faces; e* the E^r of the four zones.
 template <typename R>
-__device__ __forceinline__ R edge_emf(__amdgpu_buffer_rsrc_t rs, unsigned xo, unsigned sa, unsigned sb, unsigned fa,
-                                      unsigned fb, unsigned VB, R e0, R ea, R eb, R eab) {
-    const R z0 = R(0);
-    const unsigned xa = xo - sa, xb = xo - sb;
-    // flux_a row 5 is B_{a+1} = B_b; flux_b row 6 is B_{b+2} = B_a
-    R Ea_0 = -bload(z0, rs, xo + fa + 5 * VB, 0), Ea_b = -bload(z0, rs, xb + fa + 5 * VB, 0);
-    R Eb_0 = bload(z0, rs, xo + fb + 6 * VB, 0), Eb_a = bload(z0, rs, xa + fb + 6 * VB, 0);
-    R d1 = upwind_pick(bload(z0, rs, xo + fa, 0), ea - Eb_a, e0 - Eb_0);
-    R d2 = upwind_pick(bload(z0, rs, xb + fa, 0), Eb_a - eab, Eb_0 - eb);
-    R d3 = upwind_pick(bload(z0, rs, xo + fb, 0), eb - Ea_b, e0 - Ea_0);
-    R d4 = upwind_pick(bload(z0, rs, xa + fb, 0), Ea_b - eab, Ea_0 - ea);
+__device__ __forceinline__ R edge_combine(R Ea_0, R Ea_b, R Eb_0, R Eb_a, R ma_0, R ma_b, R mb_0, R mb_a, R e0, R ea,
+                                          R eb, R eab) {
+    R d1 = upwind_pick(ma_0, ea - Eb_a, e0 - Eb_0);
+    R d2 = upwind_pick(ma_b, Eb_a - eab, Eb_0 - eb);
+    R d3 = upwind_pick(mb_0, eb - Ea_b, e0 - Ea_0);
+    R d4 = upwind_pick(mb_a, Ea_b - eab, Ea_0 - ea);
     return R(0.25) * ((Ea_0 - d1) + (Ea_b + d2) + (Eb_0 - d3) + (Eb_a + d4));
 }
 
-template <typename R>
-__global__ void __launch_bounds__(256) edge_emf_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
-                                                       const WorkItem* __restrict__ work, int ghost, int fslot, Box bx,
-                                                       EdgeRanges rg) {
-    const WorkItem w = work[blockIdx.x];
-    if (w.patch < 0) return;  // padding item (whole block)
-    const PatchDev P = patches[w.patch];
-    BoxPos bp = box_pos(P, w.a, bx);
-    if (!bp.valid) return;
-    constexpr unsigned ES = sizeof(R);
-    const int g = ghost;
-    const unsigned VB = (unsigned)P.vol * ES;
-    const unsigned x = (unsigned)sidx(P, bp.i + g, bp.j + g, bp.k + g);
-    const unsigned st[3] = {1u, (unsigned)P.N[0], (unsigned)(P.N[0] * P.N[1])};
-    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + P.base, (unsigned)F_TOTAL * VB);
-    const R z0 = R(0);
-    const int z[3] = {bp.i, bp.j, bp.k};
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-        const int a = (c + 1) % 3, b = (c + 2) % 3;
-        bool in = z[c] >= rg.lo_c && z[c] <= P.n[c] + rg.hi_c && z[a] >= rg.lo_o && z[a] <= P.n[a] + rg.hi_o &&
-                  z[b] >= rg.lo_o && z[b] <= P.n[b] + rg.hi_o;
-        if (!in) continue;
-        const unsigned xo = x * ES, xa = (x - st[a]) * ES, xb = (x - st[b]) * ES, xab = (x - st[a] - st[b]) * ES;
-        const unsigned fa = (unsigned)(fslot + 7 * a) * VB;  // flux_a rows
-        const unsigned fb = (unsigned)(fslot + 7 * b) * VB;
-        const unsigned e0f = (unsigned)(F_ER + c) * VB;
-        R e0 = bload(z0, rs, xo, e0f), ea = bload(z0, rs, xa, e0f), eb = bload(z0, rs, xb, e0f),
-          eab = bload(z0, rs, xab, e0f);
-        bstore(edge_emf(rs, xo, st[a] * ES, st[b] * ES, fa, fb, VB, e0, ea, eb, eab), rs, xo, (unsigned)(F_ED + c) * VB);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Step 4: b^{n+1/2} = b^n - (dt/2) curl E (Stokes form on each face); face b_d
-// computed where z_d in [-2, n+2] and the transverse coords in [-1, n]
-// ---------------------------------------------------------------------------
-
-template <typename R>
-__global__ void __launch_bounds__(256) ct_half_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
-                                                      const WorkItem* __restrict__ work, Coef<R> cf, int ghost, int cur,
-                                                      const StepConst* __restrict__ sc, Box bx) {
-    const WorkItem w = work[blockIdx.x];
-    if (w.patch < 0) return;  // padding item (whole block)
-    const PatchDev P = patches[w.patch];
-    BoxPos bp = box_pos(P, w.a, bx);
-    if (!bp.valid) return;
-    constexpr unsigned ES = sizeof(R);
-    const int g = ghost;
-    const unsigned VB = (unsigned)P.vol * ES;
-    const unsigned xo = (unsigned)sidx(P, bp.i + g, bp.j + g, bp.k + g) * ES;
-    const unsigned st[3] = {ES, (unsigned)P.N[0] * ES, (unsigned)(P.N[0] * P.N[1]) * ES};
-    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + P.base, (unsigned)F_TOTAL * VB);
-    const unsigned bs = (unsigned)((cur ? F_ST1 : F_ST0) + 8) * VB;
-    const R tau = sc_hdt(*sc, R(0));
-    const R z0 = R(0);
-    const int z[3] = {bp.i, bp.j, bp.k};
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        const int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
-        bool in = z[a1] >= -1 && z[a1] <= P.n[a1] && z[a2] >= -1 && z[a2] <= P.n[a2];
-        if (!in) continue;
-        const unsigned E2 = (unsigned)(F_ED + a2) * VB, E1 = (unsigned)(F_ED + a1) * VB;
-        R curl = (bload(z0, rs, xo, E2 + st[a1]) - bload(z0, rs, xo, E2)) * cf.idx[a1] -
-                 (bload(z0, rs, xo, E1 + st[a2]) - bload(z0, rs, xo, E1)) * cf.idx[a2];
-        bstore(bload(z0, rs, xo, bs + d * VB) - tau * curl, rs, xo, (unsigned)(F_BH + d) * VB);
-    }
-}
-
-// Column tiles of the marching update kernel: tx, ty <= 32 and tx ty <= 256 zones
+// Column tiles of the marching kernels: tx, ty <= 32 and tx ty <= 256 zones
 // per plane; LDS edge planes are (tx+1)(ty+1) long.
 constexpr int TILE_THREADS = 256;
 constexpr int UPD_ERMAX = 340;  // (tx+2)(ty+2)
@@ -444,6 +370,127 @@ constexpr int TILE_BIAS = 16;   // tile origins are stored biased (they may be n
 
 // q = r / m for 0 <= r < 1927 and 1 <= m <= 34, from a 16-bit reciprocal
 __device__ __forceinline__ int small_div(int r, int recip) { return (r * recip) >> 16; }
+
+// ---------------------------------------------------------------------------
+// Steps 3-4 fused.  A block owns a column tile of the in-plane box
+// [-2, n+2]^2 and marches over the planes z in [-2, n+2].  Iteration k forms
+//   phase 1  the Step-3 edge EMFs of plane k+1 (Step-1 fluxes, E^r of Step 2)
+//            into LDS, three planes deep, so one barrier a plane suffices,
+//   phase 2  b^{n+1/2} = b^n - (dt/2) curl E (Step 4, Stokes form) on the
+//            faces of plane k that the corrector reads: b_d with z_d in
+//            [-2, n+2] and the transverse coordinates in [-1, n].
+// The plane-below fluxes and E^r of the E_x and E_y edges are carried in
+// registers, so each datum is read once.  An edge is needed only where its
+// own coordinate is in [-1, n] and the others in [-2, n+2]; those outside
+// are formed (from in-bounds ghost memory) but never read.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(TILE_THREADS) ct_half_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
+                                                               const WorkItem* __restrict__ work, Coef<R> cf, int ghost,
+                                                               int cur, const StepConst* __restrict__ sc) {
+    __shared__ R s_ed[3 * 3 * UPD_EDMAX];  // [plane mod 3][component][j (tx+1) + i]
+    const WorkItem w = work[blockIdx.x];
+    if (w.patch < 0) return;  // padding item (whole block)
+    const PatchDev P = patches[w.patch];
+    const int i0 = (w.a & 0xffff) - TILE_BIAS, j0 = (w.a >> 16) - TILE_BIAS;
+    const int tx = w.b & 0xffff, ty = w.b >> 16;
+    const int k0 = (w.c & 0xffff) - TILE_BIAS, k1 = (w.c >> 16) - TILE_BIAS;
+    constexpr unsigned ES = sizeof(R);
+    const int g = ghost;
+    const unsigned VB = (unsigned)P.vol * ES;
+    const unsigned s0 = ES, s1 = (unsigned)P.N[0] * ES, s2 = (unsigned)(P.N[0] * P.N[1]) * ES;
+    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + P.base, (unsigned)F_TOTAL * VB);
+    const unsigned bs = (unsigned)((cur ? F_ST1 : F_ST0) + 8) * VB;
+    const unsigned FX = (unsigned)F_FL1 * VB, FY = FX + 7 * VB, FZ = FY + 7 * VB, ER = (unsigned)F_ER * VB;
+    const R tau = sc_hdt(*sc, R(0));
+    const R ix = cf.idx[0], iy = cf.idx[1], iz = cf.idx[2];
+    const R z0 = R(0);
+    const int t = threadIdx.x;
+    const int TXE = tx + 1;
+    auto zoff = [&](int i, int j, int k) -> unsigned {
+        return (unsigned)sidx(P, i0 + i + g, j0 + j + g, k + g) * ES;
+    };
+    auto ld = [&](unsigned voff, unsigned soff) -> R { return bload(z0, rs, voff, soff); };
+
+    const bool owner = t < tx * ty;
+    const int zj = owner ? small_div(t, 65536 / tx + 1) : 0, zi = owner ? t - zj * tx : 0;
+    const bool extra = t <= tx + ty;  // edges on the column i = tx, then on the row j = ty
+    const int xi = t <= ty ? tx : t - ty - 1, xj = t <= ty ? t : ty;
+    const int xmask = (xi < tx ? 1 : 0) | (xj < ty ? 2 : 0) | 4;
+
+    // Step 3 at tile-local edge position (i, j) of plane p, components in mask.
+    // cx: m_y, flux_y[B_z], E^r_x at (i, j) and E^r_x at (i, j-1) of plane p-1;
+    // cy: m_x, flux_x[B_z], E^r_y at (i, j) and E^r_y at (i-1, j) of plane p-1
+    // (carried, loaded when fresh); replaced by those of plane p.
+    auto ed_item = [&](int i, int j, int p, int mask, R(&cx)[4], R(&cy)[4], bool fresh) {
+        const unsigned xo = zoff(i, j, p);
+        R* dst = s_ed + ((p + 3) % 3) * 3 * UPD_EDMAX + j * TXE + i;
+        if (mask & 1) {  // E_x: a = y, b = z
+            if (fresh) {
+                cx[0] = ld(xo - s2, FY), cx[1] = ld(xo - s2, FY + 5 * VB);
+                cx[2] = ld(xo - s2, ER), cx[3] = ld(xo - s2 - s1, ER);
+            }
+            const R ma = ld(xo, FY), fa5 = ld(xo, FY + 5 * VB);
+            const R mb = ld(xo, FZ), fb6 = ld(xo, FZ + 6 * VB), mba = ld(xo - s1, FZ), fb6a = ld(xo - s1, FZ + 6 * VB);
+            const R e0 = ld(xo, ER), ea = ld(xo - s1, ER);
+            dst[0] = edge_combine(-fa5, -cx[1], fb6, fb6a, ma, cx[0], mb, mba, e0, ea, cx[2], cx[3]);
+            cx[0] = ma, cx[1] = fa5, cx[2] = e0, cx[3] = ea;
+        }
+        if (mask & 2) {  // E_y: a = z, b = x
+            if (fresh) {
+                cy[0] = ld(xo - s2, FX), cy[1] = ld(xo - s2, FX + 6 * VB);
+                cy[2] = ld(xo - s2, ER + VB), cy[3] = ld(xo - s2 - s0, ER + VB);
+            }
+            const R ma = ld(xo, FZ), fa5 = ld(xo, FZ + 5 * VB), mab = ld(xo - s0, FZ), fa5b = ld(xo - s0, FZ + 5 * VB);
+            const R mb = ld(xo, FX), fb6 = ld(xo, FX + 6 * VB);
+            const R e0 = ld(xo, ER + VB), eb = ld(xo - s0, ER + VB);
+            dst[UPD_EDMAX] = edge_combine(-fa5, -fa5b, fb6, cy[1], ma, mab, mb, cy[0], e0, cy[2], eb, cy[3]);
+            cy[0] = mb, cy[1] = fb6, cy[2] = e0, cy[3] = eb;
+        }
+        if (mask & 4) {  // E_z: a = x, b = y
+            const R ma = ld(xo, FX), fa5 = ld(xo, FX + 5 * VB), mab = ld(xo - s1, FX), fa5b = ld(xo - s1, FX + 5 * VB);
+            const R mb = ld(xo, FY), fb6 = ld(xo, FY + 6 * VB), mba = ld(xo - s0, FY), fb6a = ld(xo - s0, FY + 6 * VB);
+            const unsigned ez = ER + 2 * VB;
+            dst[2 * UPD_EDMAX] = edge_combine(-fa5, -fa5b, fb6, fb6a, ma, mab, mb, mba, ld(xo, ez), ld(xo - s0, ez),
+                                              ld(xo - s1, ez), ld(xo - s0 - s1, ez));
+        }
+    };
+
+    R cx_o[4], cy_o[4], cx_x[4], cy_x[4];
+    const int gi = i0 + zi, gj = j0 + zj;
+    const bool ix_in = gi >= -1 && gi <= P.n[0], jy_in = gj >= -1 && gj <= P.n[1];
+    const int e = zj * TXE + zi;
+
+    if (owner) ed_item(zi, zj, k0, 7, cx_o, cy_o, true);
+    if (extra) ed_item(xi, xj, k0, xmask, cx_x, cy_x, true);
+    for (int k = k0; k < k1; k++) {
+        if (owner) ed_item(zi, zj, k + 1, 7, cx_o, cy_o, false);
+        if (extra) ed_item(xi, xj, k + 1, xmask, cx_x, cy_x, false);
+        __syncthreads();
+        if (owner) {
+            const bool kz_in = k >= -1 && k <= P.n[2];
+            const unsigned xo = zoff(zi, zj, k);
+            const R* ex0 = s_ed + ((k + 3) % 3) * 3 * UPD_EDMAX;  // E_x, plane k
+            const R* ey0 = ex0 + UPD_EDMAX;
+            const R* ez0 = ex0 + 2 * UPD_EDMAX;
+            const R* ex1 = s_ed + ((k + 4) % 3) * 3 * UPD_EDMAX;  // E_x, plane k+1
+            const R* ey1 = ex1 + UPD_EDMAX;
+            if (jy_in && kz_in) {
+                R curl = (ez0[e + TXE] - ez0[e]) * iy - (ey1[e] - ey0[e]) * iz;
+                bstore(ld(xo, bs) - tau * curl, rs, xo, (unsigned)F_BH * VB);
+            }
+            if (ix_in && kz_in) {
+                R curl = (ex1[e] - ex0[e]) * iz - (ez0[e + 1] - ez0[e]) * ix;
+                bstore(ld(xo, bs + VB) - tau * curl, rs, xo, (unsigned)(F_BH + 1) * VB);
+            }
+            if (ix_in && jy_in) {
+                R curl = (ey0[e + 1] - ey0[e]) * ix - (ex0[e + TXE] - ex0[e]) * iy;
+                bstore(ld(xo, bs + 2 * VB) - tau * curl, rs, xo, (unsigned)(F_BH + 2) * VB);
+            }
+        }
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Steps 8-11 fused.  A block owns a column tile of zones [i0, i0+tx) x
@@ -464,20 +511,6 @@ __device__ __forceinline__ int small_div(int r, int recip) { return (r * recip) 
 // and the L2 only serves reuse within a plane.  Nothing of Steps 8-9 goes to
 // HBM unless keep_edges asks for the Step-9 edges (debugging).
 // ---------------------------------------------------------------------------
-
-// Upwinded edge value from preloaded face data (see edge_emf): Ea_0, Ea_b the
-// a-face values -flux_a[B_b] at the zone and one back along b; Eb_0, Eb_a the
-// b-face values +flux_b[B_a] at the zone and one back along a; m* the mass
-// fluxes across the same faces; e* the E^r of the four zones.
-template <typename R>
-__device__ __forceinline__ R edge_combine(R Ea_0, R Ea_b, R Eb_0, R Eb_a, R ma_0, R ma_b, R mb_0, R mb_a, R e0, R ea,
-                                          R eb, R eab) {
-    R d1 = upwind_pick(ma_0, ea - Eb_a, e0 - Eb_0);
-    R d2 = upwind_pick(ma_b, Eb_a - eab, Eb_0 - eb);
-    R d3 = upwind_pick(mb_0, eb - Ea_b, e0 - Ea_0);
-    R d4 = upwind_pick(mb_a, Ea_b - eab, Ea_0 - ea);
-    return R(0.25) * ((Ea_0 - d1) + (Ea_b + d2) + (Eb_0 - d3) + (Eb_a + d4));
-}
 
 template <typename R>
 __global__ void __launch_bounds__(TILE_THREADS) update_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
@@ -1094,18 +1127,10 @@ hipError_t launch_set_dt(StepConst* sc, double dt, const DevParams& prm, hipStre
 }
 
 template <typename R>
-hipError_t launch_edge(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, int g, int fslot, Box bx, EdgeRanges rg,
-                       hipStream_t st) {
-    if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(edge_emf_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, g, fslot, bx, rg);
-    return hipGetLastError();
-}
-
-template <typename R>
 hipError_t launch_ct_half(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const Coef<R>& cf, int g, int cur,
-                          const StepConst* sc, Box bx, hipStream_t st) {
+                          const StepConst* sc, hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(ct_half_kernel<R>, dim3(nblk), dim3(256), 0, st, (R*)pool, pt, wk, cf, g, cur, sc, bx);
+    hipLaunchKernelGGL(ct_half_kernel<R>, dim3(nblk), dim3(TILE_THREADS), 0, st, (R*)pool, pt, wk, cf, g, cur, sc);
     return hipGetLastError();
 }
 
@@ -1156,10 +1181,8 @@ hipError_t launch_diag(const void* pool, const PatchDev* pt, const WorkItem* wk,
                                        hipStream_t);                                                                     \
     template hipError_t launch_dt_reduce<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,         \
                                             unsigned long long*, hipStream_t);                                           \
-    template hipError_t launch_edge<R>(void*, const PatchDev*, const WorkItem*, int, int, int, Box, EdgeRanges,         \
-                                       hipStream_t);                                                                     \
     template hipError_t launch_ct_half<R>(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int,        \
-                                          const StepConst*, Box, hipStream_t);                                           \
+                                          const StepConst*, hipStream_t);                                                \
     template hipError_t launch_update<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, \
                                          int, const StepConst*, unsigned long long*, unsigned long long*, int,          \
                                          hipStream_t);                                                                   \

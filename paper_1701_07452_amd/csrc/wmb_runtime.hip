@@ -17,8 +17,7 @@ template <typename R> hipError_t launch_fill(void*, const PatchDev*, const WorkI
 template <typename R> hipError_t launch_dt_reduce(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, unsigned long long*, hipStream_t);
 hipError_t launch_dt_finalize(unsigned long long*, StepConst*, const DevParams&, hipStream_t);
 hipError_t launch_set_dt(StepConst*, double, const DevParams&, hipStream_t);
-template <typename R> hipError_t launch_edge(void*, const PatchDev*, const WorkItem*, int, int, int, Box, EdgeRanges, hipStream_t);
-template <typename R> hipError_t launch_ct_half(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int, const StepConst*, Box, hipStream_t);
+template <typename R> hipError_t launch_ct_half(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int, const StepConst*, hipStream_t);
 template <typename R> hipError_t launch_update(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, unsigned long long*, unsigned long long*, int, hipStream_t);
 template <typename R> hipError_t launch_sweep(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, int, int, int, int, int, hipStream_t);
 template <typename R> hipError_t launch_diag(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, double*, hipStream_t);
@@ -43,8 +42,6 @@ enum SmaxState { SMAX_ZERO = 0, SMAX_CLEAN = 1, SMAX_DIRTY = 2 };
 
 // Box of each box kernel, interior-relative [lo, n + hi]
 const Box BOX_INTERIOR{0, -1};
-const Box BOX_EDGE1{-2, 2};
-const Box BOX_CTH{-2, 2};
 
 }  // namespace
 
@@ -63,7 +60,7 @@ struct wmb_ctx {
     int cur = 0;
     PatchDev* d_patch = nullptr;
     DevList wl_fill[3];
-    DevList wl_int, wl_diag, wl_edge1, wl_cth, wl_upd;
+    DevList wl_int, wl_diag, wl_cth, wl_upd;
     bool keep_edges = false;  // Steps 8-11 also store the Step-9 edges (debugging)
     bool edges_kept = false;  // the last step stored them
     int smax_state = SMAX_ZERO;
@@ -278,12 +275,7 @@ int run_step(wmb_ctx* c) {
         }
         mark(c);
     }
-    e = launch_edge<R>(c->pool, c->d_patch, c->wl_edge1.d, c->wl_edge1.n, c->p.ghost, F_FL1, BOX_EDGE1,
-                       EdgeRanges{-1, 0, -2, 2}, c->stream);
-    STEPCK("edge_emf1");
-    mark(c);
-    e = launch_ct_half<R>(c->pool, c->d_patch, c->wl_cth.d, c->wl_cth.n, coef<R>(c), c->p.ghost, cur, c->d_sc, BOX_CTH,
-                          c->stream);
+    e = launch_ct_half<R>(c->pool, c->d_patch, c->wl_cth.d, c->wl_cth.n, coef<R>(c), c->p.ghost, cur, c->d_sc, c->stream);
     STEPCK("ct_half");
     mark(c);
     for (int d = 0; d < 3; d++) {
@@ -644,11 +636,8 @@ int autotune_t(wmb_ctx* c, int reps) {
                     e = launch_sweep<R>(d, 1, c->pool, c->d_patch, G.wl.d, G.wl.n, c->dp, coef<R>(c), c->cur, c->d_sc, G.P,
                                         G.W, G.zlo, G.tlo, G.thi, c->stream);
             if (e == hipSuccess)
-                e = launch_edge<R>(c->pool, c->d_patch, c->wl_edge1.d, c->wl_edge1.n, c->p.ghost, F_FL1, BOX_EDGE1,
-                                   EdgeRanges{-1, 0, -2, 2}, c->stream);
-            if (e == hipSuccess)
                 e = launch_ct_half<R>(c->pool, c->d_patch, c->wl_cth.d, c->wl_cth.n, coef<R>(c), c->p.ghost, c->cur,
-                                      c->d_sc, BOX_CTH, c->stream);
+                                      c->d_sc, c->stream);
             if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("autotune: ") + hipGetErrorString(e));
         }
         for (int d = 0; d < 3; d++) {
@@ -787,8 +776,7 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     if ((rc = build_fill_lists(c))) return rc;
     if ((rc = build_box_list(c, BOX_INTERIOR, c->wl_int))) return rc;
     if ((rc = build_box_list(c, BOX_INTERIOR, c->wl_diag, false))) return rc;
-    if ((rc = build_box_list(c, BOX_EDGE1, c->wl_edge1))) return rc;
-    if ((rc = build_box_list(c, BOX_CTH, c->wl_cth))) return rc;
+    if ((rc = build_tile_list(c, -2, 2, -2, 2, c->wl_cth))) return rc;
     if ((rc = build_tile_list(c, 0, -1, 0, -1, c->wl_upd))) return rc;
     if ((rc = build_sweeps(c))) return rc;
     if ((rc = dev_alloc(c, &c->d_smax, 1))) return rc;

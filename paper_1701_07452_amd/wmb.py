@@ -24,7 +24,7 @@ EXPORTS = [
     "wmb_autotune", "wmb_set_tuning", "wmb_keep_stages", "wmb_profile_step", "wmb_destroy", "wmb_strerror",
     "wmb_last_error",
 ]
-KERNEL_CLASSES = ["fill", "dt", "sweep1_x", "sweep1_y", "sweep1_z", "edge1", "ct_half",
+KERNEL_CLASSES = ["fill", "dt", "sweep1_x", "sweep1_y", "sweep1_z", "ct_half",
                   "sweep2_x", "sweep2_y", "sweep2_z", "update"]
 
 
