@@ -55,10 +55,13 @@ __device__ __forceinline__ R qvisc(R chi, R eps, R q4e) {
     return ac;
 }
 
-// g_i = SIGN(gp) * SWEBY(gp, gm) (Appendix A), Sweby family with parameter beta
-template <typename R>
+// g_i = SIGN(gp) * SWEBY(gp, gm) (Appendix A), Sweby family with parameter
+// beta; MM: beta = 1 (minmod), where both arguments of the outer max agree
+// exactly and one branch is dropped (bitwise the same result)
+template <bool MM, typename R>
 __device__ __forceinline__ R sweby(R gp, R gm, R beta) {
     R s = sgn1(gp);
+    if (MM) return s * fmax(R(0), fmin(fabs(gp), s * gm));
     R t1 = fmin(beta * fabs(gp), s * gm);
     R t2 = fmin(fabs(gp), beta * s * gm);
     return s * fmax(R(0), fmax(t1, t2));
@@ -361,14 +364,15 @@ __device__ __forceinline__ R edge_combine(R Ea_0, R Ea_b, R Eb_0, R Eb_a, R ma_0
     return R(0.25) * ((Ea_0 - d1) + (Ea_b + d2) + (Eb_0 - d3) + (Eb_a + d4));
 }
 
-// Column tiles of the marching kernels: tx, ty <= 32 and tx ty <= 256 zones
-// per plane; LDS edge planes are (tx+1)(ty+1) long.
+// Column tiles of the marching kernels: tx <= 40 (Steps 3-4) or 32 (Steps
+// 8-11), ty <= 32 and tx ty <= 256 zones per plane; LDS edge planes are
+// (tx+1)(ty+1) <= 297 long, E^r planes (tx+2)(ty+2) <= 340 (tx <= 32).
 constexpr int TILE_THREADS = 256;
-constexpr int UPD_ERMAX = 340;  // (tx+2)(ty+2)
-constexpr int UPD_EDMAX = 297;  // (tx+1)(ty+1)
-constexpr int TILE_BIAS = 16;   // tile origins are stored biased (they may be negative)
+constexpr int UPD_ERMAX = 340;
+constexpr int UPD_EDMAX = 297;
+constexpr int TILE_BIAS = 16;  // tile origins are stored biased (they may be negative)
 
-// q = r / m for 0 <= r < 1927 and 1 <= m <= 34, from a 16-bit reciprocal
+// q = r / m for r, m >= 1 with r m < 65536, from a 16-bit reciprocal
 __device__ __forceinline__ int small_div(int r, int recip) { return (r * recip) >> 16; }
 
 // ---------------------------------------------------------------------------
@@ -753,7 +757,7 @@ struct FaceEig {
     R a2, a, cf, cs, alf, als, by, bz, s;
 };
 
-template <typename R, int D, int STAGE>
+template <typename R, int D, int STAGE, bool MM>
 __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
                                                      const WorkItem* __restrict__ work, DevParams prm, Coef<R> cf,
                                                      int cur, const StepConst* __restrict__ sc, int P, int W, int zlo,
@@ -990,8 +994,8 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
             R gm = Gm.v[k];
             R g0 = G0.v[k];
             R gp = Gp.v[k];
-            R gL = sweby(g0, gm, cf.beta_l);  // zone s-1: faces s-1 (left), s (right)
-            R gR = sweby(gp, g0, cf.beta_l);  // zone s: faces s, s+1
+            R gL = sweby<MM>(g0, gm, cf.beta_l);  // zone s-1: faces s-1 (left), s (right)
+            R gR = sweby<MM>(gp, g0, cf.beta_l);  // zone s: faces s, s+1
             R gk = (fabs(alpha[k]) > alpha_min(alpha[k])) ? (gR - gL) * frcp(alpha[k]) : R(0);
             bet[k] = qvisc(nu[k] + gk, cf.eps[k], cf.q4e[k]) * alpha[k] - (gL + gR);
         }
@@ -1151,9 +1155,16 @@ hipError_t launch_sweep(int d, int stage, void* pool, const PatchDev* pt, const 
     if (nblk <= 0) return hipSuccess;
     size_t shmem = sizeof(R) * 16 * (size_t)P * W;
     dim3 blk = (d == 0) ? dim3(P, W) : dim3(W, P);
-#define WMB_SW(DD, SS)                                                                                               \
-    hipLaunchKernelGGL((sweep_kernel<R, DD, SS>), dim3(nblk), blk, shmem, st, (R*)pool, pt, wk, prm, cf, cur, sc, P, W, \
-                       zlo, tlo, thi)
+    const bool mm = cf.beta_l == R(1);
+#define WMB_SW(DD, SS)                                                                                                  \
+    do {                                                                                                                \
+        if (mm)                                                                                                         \
+            hipLaunchKernelGGL((sweep_kernel<R, DD, SS, true>), dim3(nblk), blk, shmem, st, (R*)pool, pt, wk, prm, cf,  \
+                               cur, sc, P, W, zlo, tlo, thi);                                                           \
+        else                                                                                                            \
+            hipLaunchKernelGGL((sweep_kernel<R, DD, SS, false>), dim3(nblk), blk, shmem, st, (R*)pool, pt, wk, prm, cf, \
+                               cur, sc, P, W, zlo, tlo, thi);                                                           \
+    } while (0)
     if (stage == 1) {
         if (d == 0) WMB_SW(0, 1);
         else if (d == 1) WMB_SW(1, 1);

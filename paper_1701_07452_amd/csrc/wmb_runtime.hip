@@ -324,17 +324,18 @@ int build_box_list(wmb_ctx* c, Box bx, DevList& out, bool xcd = true) {
 
 // Column tiles of the marching kernels over the in-plane box [lo, n+hi]^2
 // (x, y) and the planes [zlo, n+zhi]: each patch's box is cut into near-equal
-// parts of at most 32 zones along x, then along y into parts with at most
-// 256 zones per tile plane and 32 per edge.  Item fields (origins biased by
-// 16, they may be negative): a = i0 | j0 << 16, b = tx | ty << 16,
-// c = k0 | k1 << 16 with k1 exclusive.
+// parts of at most txmax zones along x (whole rows where they fit, so tile
+// rows cut no cache lines), then along y into parts with at most 256 zones
+// per tile plane and 32 per edge.  Item fields (origins biased by 16, they
+// may be negative): a = i0 | j0 << 16, b = tx | ty << 16, c = k0 | k1 << 16
+// with k1 exclusive.
 constexpr int TILE_BIAS = 16;
-int build_tile_list(wmb_ctx* c, int lo, int hi, int zlo, int zhi, DevList& out) {
+int build_tile_list(wmb_ctx* c, int lo, int hi, int zlo, int zhi, int txmax_allowed, DevList& out) {
     std::vector<WorkItem> items;
     for (int p = 0; p < c->npatch; p++) {
         const int* n = c->desc[p].n;
         const int ex = n[0] + hi - lo + 1, ey = n[1] + hi - lo + 1;
-        const int mx = (ex + 31) / 32;
+        const int mx = (ex + txmax_allowed - 1) / txmax_allowed;
         const int txmax = (ex + mx - 1) / mx;
         int tymax = 256 / txmax;
         if (tymax > 32) tymax = 32;
@@ -776,8 +777,10 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     if ((rc = build_fill_lists(c))) return rc;
     if ((rc = build_box_list(c, BOX_INTERIOR, c->wl_int))) return rc;
     if ((rc = build_box_list(c, BOX_INTERIOR, c->wl_diag, false))) return rc;
-    if ((rc = build_tile_list(c, -2, 2, -2, 2, c->wl_cth))) return rc;
-    if ((rc = build_tile_list(c, 0, -1, 0, -1, c->wl_upd))) return rc;
+    // Steps 3-4: tiles up to 40 zones wide ((tx+1)(ty+1) <= 297 edges a plane);
+    // Steps 8-11: up to 32 ((tx+2)(ty+2) <= 340 E^r zones a plane)
+    if ((rc = build_tile_list(c, -2, 2, -2, 2, 40, c->wl_cth))) return rc;
+    if ((rc = build_tile_list(c, 0, -1, 0, -1, 32, c->wl_upd))) return rc;
     if ((rc = build_sweeps(c))) return rc;
     if ((rc = dev_alloc(c, &c->d_smax, 1))) return rc;
     if ((rc = dev_alloc(c, &c->d_sc, 1))) return rc;
