@@ -40,8 +40,11 @@ def alg_bytes(kclass, n, g, es, npatch):
     def box(lo, hi):
         return (n + hi - lo + 1) ** 3
 
+    N = n + 2 * g
     if kclass == "fill":
-        per = 22 * ((n + 2 * g) ** 3 - n ** 3)          # 11 words read + 11 written per ghost zone
+        # y and z passes (the step before wrote the x-ghosts): 11 words read +
+        # 11 written per ghost zone of whole y-ghost rows and z-ghost planes
+        per = 22 * (2 * g * N * n + 2 * g * N * N)
     elif kclass == "dt":
         per = 0                                          # finalize only: the reduction is folded into "update"
     elif kclass.startswith("sweep1"):
@@ -61,6 +64,7 @@ def alg_bytes(kclass, n, g, es, npatch):
         # box [-1, n]; flux rows 5-6 over the edge box [0, n]; q^n E, flux row 4,
         # b^n in and q^{n+1}, b^{n+1} out over the interior
         per = (4 + 12 + 3) * box(-1, 0) + 6 * box(0, 0) + (1 + 3 + 3 + 11) * n ** 3
+        per += 11 * 2 * g * n * n                        # the x-ghosts it writes into the neighbours
     else:
         raise KeyError(kclass)
     return per * es * npatch

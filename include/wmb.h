@@ -125,12 +125,17 @@ int wmb_compute_dt(wmb_ctx *c, double *dt_out);
    the current state and returns WMB_ECFL if it is larger by more than 1e-12
    relative; this check synchronises).  dt <= 0: use the device-resident dt of
    the last wmb_compute_dt.  Floors (rho_floor, p_floor) are applied in FP64
-   and counted. */
+   and counted.  The step also writes the new state of the first and last
+   ghost-width zones of every interior row into the x-neighbours' ghosts (the
+   x part of the next ghost exchange); other ghosts are left to
+   wmb_fill_ghosts. */
 int wmb_advance(wmb_ctx *c, double dt);
 
 /* nsteps x (fill ghosts, compute dt, advance) with dt kept on the device,
-   replayed from a captured HIP graph (captured on the first call).  Enqueue
-   only; this is the timed call. */
+   replayed from a captured HIP graph (captured on the first call).  The
+   graph's ghost exchange runs the y and z passes only (the step before wrote
+   the x-ghosts); the x pass is enqueued first when the state was set since.
+   Enqueue only; this is the timed call. */
 int wmb_run_steps(wmb_ctx *c, int32_t nsteps);
 
 /* FP64 diagnostics over all interiors: totals[8] = sum over zones of q times

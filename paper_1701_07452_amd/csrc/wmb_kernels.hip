@@ -8,7 +8,8 @@
 //   fill_pass<x,y,z>  ghost exchange in three dependent passes: x-ghosts of
 //                     interior rows, then whole y-ghost rows, then whole
 //                     z-ghost planes (each ghost value written once, rows and
-//                     planes copied contiguously)
+//                     planes copied contiguously); after a step the x pass is
+//                     already done by the update kernel
 //   dt_reduce         FP64 max signal speed (only when no fused value exists)
 //   dt_finalize       dt = cfl / smax, kept in device memory
 //   sweep<d,1>        Step 1   MHDTVD fluxes from q^n, B_par = b^n    (hot);
@@ -513,7 +514,10 @@ __global__ void __launch_bounds__(TILE_THREADS) ct_half_kernel(R* __restrict__ p
 // plane-below fluxes of the E_x and E_y edges, the divergence of the own
 // zone formed in phase 1), so each datum is read from memory once per step
 // and the L2 only serves reuse within a plane.  Nothing of Steps 8-9 goes to
-// HBM unless keep_edges asks for the Step-9 edges (debugging).
+// HBM unless keep_edges asks for the Step-9 edges (debugging).  The new state
+// of the first and last g zones of each interior row is also written into the
+// x-ghosts of the x-neighbours, so the next ghost exchange needs only its y
+// and z passes.
 // ---------------------------------------------------------------------------
 
 template <typename R>
@@ -710,6 +714,28 @@ __global__ void __launch_bounds__(TILE_THREADS) update_kernel(R* __restrict__ po
             if (apply_floor(u, prm, cf)) atomicAdd(nfloor, 1ULL);
 #pragma unroll
             for (int c = 0; c < 8; c++) bstore(u[c], rs, xo, qn + c * VB);
+            // ghost exchange along x, pushed: the first and last g zones of an
+            // interior row are the x-ghosts of the -x and +x neighbours (same
+            // row and plane, face neighbours share the y-z extent)
+            const int gi = i0 + zi;
+            if (gi < g || gi >= P.n[0] - g) {
+                const bool left = gi < g;
+#pragma unroll
+                for (int side = 0; side < 2; side++) {
+                    if (side == 0 ? !left : !(gi >= P.n[0] - g)) continue;
+                    const PatchDev Q = patches[P.nb[side]];
+                    const int qi = side == 0 ? Q.n[0] + gi : gi - P.n[0];
+                    const unsigned QB = (unsigned)Q.vol * ES;
+                    const __amdgpu_buffer_rsrc_t rq = patch_rsrc(pool + Q.base, (unsigned)F_TOTAL * QB);
+                    const unsigned yo = (unsigned)sidx(Q, qi + g, j0 + zj + g, k + g) * ES;
+                    const unsigned qq = (unsigned)(cur ? F_ST0 : F_ST1) * QB;
+#pragma unroll
+                    for (int c = 0; c < 8; c++) bstore(u[c], rq, yo, qq + c * QB);
+                    bstore(bxl, rq, yo, qq + 8 * QB);
+                    bstore(byl, rq, yo, qq + 9 * QB);
+                    bstore(bzl, rq, yo, qq + 10 * QB);
+                }
+            }
             double ud[8];
 #pragma unroll
             for (int c = 0; c < 8; c++) ud[c] = (double)u[c];
@@ -1103,12 +1129,16 @@ __global__ void __launch_bounds__(256) diag_kernel(const R* __restrict__ pool, c
 // host-side launch wrappers
 // ---------------------------------------------------------------------------
 
+// the passes in mask (1: x, 2: y, 4: z), in that order
 template <typename R>
 hipError_t launch_fill(void* pool, const PatchDev* pt, const WorkItem* const wl[3], const int nw[3], int g, int cur,
-                       hipStream_t st) {
-    if (nw[0] > 0) hipLaunchKernelGGL((fill_pass_kernel<R, 0>), dim3(nw[0]), dim3(256), 0, st, (R*)pool, pt, wl[0], g, cur);
-    if (nw[1] > 0) hipLaunchKernelGGL((fill_pass_kernel<R, 1>), dim3(nw[1]), dim3(256), 0, st, (R*)pool, pt, wl[1], g, cur);
-    if (nw[2] > 0) hipLaunchKernelGGL((fill_pass_kernel<R, 2>), dim3(nw[2]), dim3(256), 0, st, (R*)pool, pt, wl[2], g, cur);
+                       int mask, hipStream_t st) {
+    if ((mask & 1) && nw[0] > 0)
+        hipLaunchKernelGGL((fill_pass_kernel<R, 0>), dim3(nw[0]), dim3(256), 0, st, (R*)pool, pt, wl[0], g, cur);
+    if ((mask & 2) && nw[1] > 0)
+        hipLaunchKernelGGL((fill_pass_kernel<R, 1>), dim3(nw[1]), dim3(256), 0, st, (R*)pool, pt, wl[1], g, cur);
+    if ((mask & 4) && nw[2] > 0)
+        hipLaunchKernelGGL((fill_pass_kernel<R, 2>), dim3(nw[2]), dim3(256), 0, st, (R*)pool, pt, wl[2], g, cur);
     return hipGetLastError();
 }
 
@@ -1188,7 +1218,7 @@ hipError_t launch_diag(const void* pool, const PatchDev* pt, const WorkItem* wk,
 
 // explicit instantiations
 #define WMB_INST(R)                                                                                                      \
-    template hipError_t launch_fill<R>(void*, const PatchDev*, const WorkItem* const[3], const int[3], int, int,       \
+    template hipError_t launch_fill<R>(void*, const PatchDev*, const WorkItem* const[3], const int[3], int, int, int,  \
                                        hipStream_t);                                                                     \
     template hipError_t launch_dt_reduce<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,         \
                                             unsigned long long*, hipStream_t);                                           \

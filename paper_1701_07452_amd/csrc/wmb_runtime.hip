@@ -13,7 +13,7 @@
 #include "wmb_internal.h"
 
 namespace wmb {
-template <typename R> hipError_t launch_fill(void*, const PatchDev*, const WorkItem* const[3], const int[3], int, int, hipStream_t);
+template <typename R> hipError_t launch_fill(void*, const PatchDev*, const WorkItem* const[3], const int[3], int, int, int, hipStream_t);
 template <typename R> hipError_t launch_dt_reduce(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, unsigned long long*, hipStream_t);
 hipError_t launch_dt_finalize(unsigned long long*, StepConst*, const DevParams&, hipStream_t);
 hipError_t launch_set_dt(StepConst*, double, const DevParams&, hipStream_t);
@@ -40,6 +40,10 @@ struct SweepGroup {
 // What the device signal-speed maximum (smax) holds relative to the current state.
 enum SmaxState { SMAX_ZERO = 0, SMAX_CLEAN = 1, SMAX_DIRTY = 2 };
 
+// Ghost-exchange passes (x, y, z); the update kernel writes the x-ghosts of
+// the state it produces, so a fill after a step needs only FILL_YZ.
+enum { FILL_X = 1, FILL_YZ = 6, FILL_ALL = 7 };
+
 // Box of each box kernel, interior-relative [lo, n + hi]
 const Box BOX_INTERIOR{0, -1};
 
@@ -62,6 +66,7 @@ struct wmb_ctx {
     DevList wl_fill[3];
     DevList wl_int, wl_diag, wl_cth, wl_upd;
     bool keep_edges = false;  // Steps 8-11 also store the Step-9 edges (debugging)
+    bool xg_valid = false;    // the current copy's x-ghosts (interior rows) hold the neighbours' values
     bool edges_kept = false;  // the last step stored them
     int smax_state = SMAX_ZERO;
     std::vector<SweepGroup> sweeps[3][2];
@@ -234,11 +239,12 @@ void mark(wmb_ctx* c) {
 }
 
 template <typename R>
-int run_fill(wmb_ctx* c) {
+int run_fill(wmb_ctx* c, int mask) {
     const WorkItem* wl[3] = {c->wl_fill[0].d, c->wl_fill[1].d, c->wl_fill[2].d};
     const int nw[3] = {c->wl_fill[0].n, c->wl_fill[1].n, c->wl_fill[2].n};
-    hipError_t e = launch_fill<R>(c->pool, c->d_patch, wl, nw, c->p.ghost, c->cur, c->stream);
+    hipError_t e = launch_fill<R>(c->pool, c->d_patch, wl, nw, c->p.ghost, c->cur, mask, c->stream);
     if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("fill_ghosts: ") + hipGetErrorString(e));
+    if (mask & FILL_X) c->xg_valid = true;
     mark(c);
     return WMB_OK;
 }
@@ -291,6 +297,7 @@ int run_step(wmb_ctx* c) {
     STEPCK("update");
     mark(c);
     c->edges_kept = c->keep_edges;
+    c->xg_valid = true;  // the update wrote the x-ghosts of the new copy
 #undef STEPCK
     c->cur ^= 1;
     // the final update folds the new state's signal speeds into smax
@@ -298,7 +305,9 @@ int run_step(wmb_ctx* c) {
     return WMB_OK;
 }
 
-int dispatch_fill(wmb_ctx* c) { return c->esize == 4 ? run_fill<float>(c) : run_fill<double>(c); }
+int dispatch_fill(wmb_ctx* c, int mask = FILL_ALL) {
+    return c->esize == 4 ? run_fill<float>(c, mask) : run_fill<double>(c, mask);
+}
 int ensure_smax(wmb_ctx* c) {
     if (c->smax_state == SMAX_CLEAN) return WMB_OK;
     return c->esize == 4 ? run_reduce<float>(c) : run_reduce<double>(c);
@@ -447,26 +456,34 @@ void free_graphs(wmb_ctx* c) {
 // update refills smax for the next replay).  Replays require smax to hold the
 // current state's maximum at their start.
 int capture_graphs(wmb_ctx* c) {
+    // nothing runs during capture: the host-side state flags are restored
     const int saved_state = c->smax_state;
+    const bool saved_xg = c->xg_valid, saved_kept = c->edges_kept;
+    const int cur_start = c->cur;
+    auto restore = [&]() {
+        c->cur = cur_start;
+        c->smax_state = saved_state;
+        c->xg_valid = saved_xg;
+        c->edges_kept = saved_kept;
+    };
     for (int k = 0; k < 2; k++) {
         const int cur0 = c->cur;
         CKH(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
-        int rc = dispatch_fill(c);
+        int rc = dispatch_fill(c, FILL_YZ);
         if (!rc) rc = run_finalize(c);
         if (!rc) rc = dispatch_step(c);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->stream, &g);
-        if (rc) {
+        if (rc || e != hipSuccess) {
             if (g) hipGraphDestroy(g);
-            c->smax_state = saved_state;
-            return rc;
+            restore();
+            return rc ? rc : fail(c, WMB_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
         }
-        if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
         c->graph[cur0] = g;
         CKH(hipGraphInstantiate(&c->gexec[cur0], g, nullptr, nullptr, 0));
         // dispatch_step flipped cur; the second capture covers the other copy
     }
-    c->smax_state = saved_state;  // nothing ran during capture
+    restore();
     return WMB_OK;
 }
 
@@ -800,6 +817,7 @@ int wmb_set_state(wmb_ctx* c, int32_t patch, const double* q, const double* b) {
     if (!c) return WMB_EINVAL;
     if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
     if (patch < 0 || patch >= c->npatch || !q || !b) return fail(c, WMB_EINVAL, "bad patch or null array");
+    c->xg_valid = false;  // the neighbours' x-ghosts of this patch are stale
     return c->esize == 4 ? set_state_t<float>(c, patch, q, b) : set_state_t<double>(c, patch, q, b);
 }
 
@@ -862,12 +880,14 @@ int wmb_run_steps(wmb_ctx* c, int32_t nsteps) {
         }
     }
     int rc = ensure_smax(c);
+    if (!rc && !c->xg_valid) rc = dispatch_fill(c, FILL_X);  // the graphs start at the y pass
     if (rc) return rc;
     for (int s = 0; s < nsteps; s++) {
         CKH(hipGraphLaunch(c->gexec[c->cur], c->stream));
         c->cur ^= 1;
     }
     c->smax_state = SMAX_CLEAN;
+    c->xg_valid = true;
     return WMB_OK;
 }
 
@@ -942,13 +962,14 @@ int wmb_profile_step(wmb_ctx* c, double* ms, int32_t nclass) {
     if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
     if (nclass < WMB_NCLASS) return fail(c, WMB_EINVAL, "ms must hold WMB_NCLASS entries");
     int rc = ensure_smax(c);
+    if (!rc && !c->xg_valid) rc = dispatch_fill(c, FILL_X);  // as before a graph replay
     if (rc) return rc;
     hipEvent_t ev[WMB_NCLASS + 1];
     for (int i = 0; i <= WMB_NCLASS; i++) CKH(hipEventCreate(&ev[i]));
     CKH(hipEventRecord(ev[0], c->stream));
     c->marks = ev + 1;
     c->nmark = 0;
-    rc = dispatch_fill(c);
+    rc = dispatch_fill(c, FILL_YZ);
     if (!rc) rc = run_finalize(c);
     if (!rc) rc = dispatch_step(c);
     c->marks = nullptr;
