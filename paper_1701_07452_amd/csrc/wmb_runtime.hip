@@ -3,6 +3,7 @@
 // diagnostics plumbing, HIP-graph capture of one step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -134,13 +135,44 @@ int dev_alloc(wmb_ctx* c, T** ptr, size_t count) {
 
 // Workgroups are dispatched to the 8 XCDs round-robin by workgroup id, and
 // each XCD has its own L2.  Reorder a work list so that all blocks of a patch
-// run on the same XCD (patch p -> XCD p mod 8) in their original order: block
-// id 8 j + x takes the j-th item of XCD x's queue.  Queues are padded with
+// run on one XCD, in their original order: block id 8 j + x takes the j-th
+// item of XCD x's queue.  Patches go to XCDs by their item count in this list,
+// largest first, each to the least loaded XCD (so that neither the patch
+// numbering nor uneven patch sizes leave XCDs idle); queues are padded with
 // empty items (patch = -1) that exit at once.
 constexpr int NXCD = 8;
 std::vector<WorkItem> xcd_order(const std::vector<WorkItem>& items) {
+    // item count and first appearance of every patch in the list
+    std::vector<int> order;
+    std::vector<long long> count;
+    std::vector<int> slot;  // patch -> index in order
+    for (const WorkItem& w : items) {
+        if (w.patch >= (int)slot.size()) slot.resize(w.patch + 1, -1);
+        if (slot[w.patch] < 0) {
+            slot[w.patch] = (int)order.size();
+            order.push_back(w.patch);
+            count.push_back(0);
+        }
+        count[slot[w.patch]]++;
+    }
+    std::vector<int> byload(order.size());
+    for (size_t i = 0; i < byload.size(); i++) byload[i] = (int)i;
+    std::stable_sort(byload.begin(), byload.end(), [&](int a, int b) { return count[a] > count[b]; });
+    std::vector<int> xcd_of(order.size(), 0);
+    long long load[NXCD] = {0};
+    for (int i : byload) {
+        int best = 0;
+        for (int x = 1; x < NXCD; x++)
+            if (load[x] < load[best]) best = x;
+        xcd_of[i] = best;
+        load[best] += count[i];
+    }
+    // each XCD's queue: its patches largest first, items of a patch in list order
     std::vector<std::vector<WorkItem>> q(NXCD);
-    for (const WorkItem& w : items) q[w.patch % NXCD].push_back(w);
+    std::vector<std::vector<WorkItem>> per(order.size());
+    for (const WorkItem& w : items) per[slot[w.patch]].push_back(w);
+    for (int i : byload)
+        for (const WorkItem& w : per[i]) q[xcd_of[i]].push_back(w);
     size_t len = 0;
     for (auto& v : q) len = v.size() > len ? v.size() : len;
     std::vector<WorkItem> out;
