@@ -173,6 +173,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning32", default="", help="sweep shapes for FP32 (e.g. 1x32=16,...); default: autotune")
     ap.add_argument("--tuning64", default="", help="sweep shapes for FP64; default: autotune")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven 400-patch batch (reported beside)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -220,6 +221,23 @@ def main():
         fp64 = {"value": zones * args.steps / (ms64 / 1e3), "ms_per_step": ms64 / args.steps,
                 "kernels_ms": kern64, **diag64}
         log("bench: FP64 %.3f ms/step" % (ms64 / args.steps))
+
+    uneven = None
+    if not args.no_uneven and args.prof_steps > 0:
+        # the uneven batch (patch edges from {16, 24, 32, 48, 64} per slab, 8 x 10 x 5
+        # patches, turbulence seed 170107454, dx = 1/256): FP32, reported beside
+        Gu = I.uneven_grid()
+        Nz, Ny, Nx = Gu.shape
+        log("bench: uneven batch, %d patches, %d zones" % (Gu.npatch, Gu.zones()))
+        qu, bu = I.turbulence(None, seed=170107454, shape=Gu.shape, box=(Nx / 256, Ny / 256, Nz / 256))
+        msu, wallu, kernu, diagu = run_precision(W, Gu, qu, bu, (1.0 / 256,) * 3, W.WMB_FP32, g, args.steps,
+                                                 args.warmup, 1)
+        del qu, bu
+        uneven = {"workload": "uneven batch: 400 patches, 8 x 10 x 5 slabs with edges from {16,24,32,48,64}, "
+                              "turbulence, ghost %d, FP32" % g,
+                  "zones": Gu.zones(), "patches": Gu.npatch, "ms_per_step": msu / args.steps,
+                  "value": Gu.zones() * args.steps / (msu / 1e3), "kernels_ms": kernu, **diagu}
+        log("bench: uneven FP32 %.3f ms/step, %.3e zone-updates/s" % (msu / args.steps, uneven["value"]))
 
     if not kern32:  # counter-collection runs skip the per-kernel pass
         print(json.dumps({"metric": METRIC, "value": value, "unit": "zone-updates/s", "partial": True}), flush=True)
@@ -272,6 +290,7 @@ def main():
         "kernels_ms": kern32,
         "fp32_diag": diag32,
         "fp64": fp64,
+        "uneven_fp32": uneven,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

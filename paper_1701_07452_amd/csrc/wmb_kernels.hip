@@ -844,6 +844,9 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
             }
         }
         if (STAGE == 2) {
+            // q^n values the div-B source needs (before the update below)
+            const R q0 = u[0], q1 = u[1 + A1], q2 = u[1 + A2];
+            const R B0[3] = {u[4], u[5], u[6]};
             const R hdt = sc_hdt(*sc, R(0));
             const unsigned f1 = (unsigned)(F_FL1 + 7 * A1) * VB, f2 = (unsigned)(F_FL1 + 7 * A2) * VB;
             const unsigned s1 = st[A1] * ES, s2 = st[A2] * ES;
@@ -872,9 +875,6 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
 #pragma unroll
             for (int a = 0; a < 3; a++)
                 dB[a] = (bload(z0, rs, xo, bs + a * VB + st[a] * ES) - bload(z0, rs, xo, bs + a * VB)) * cf.idx[a];
-            const R q0 = bload(z0, rs, xo, qs), q1 = bload(z0, rs, xo, qs + (1 + A1) * VB),
-                    q2 = bload(z0, rs, xo, qs + (1 + A2) * VB);
-            const R B0[3] = {bload(z0, rs, xo, qs + 4 * VB), bload(z0, rs, xo, qs + 5 * VB), bload(z0, rs, xo, qs + 6 * VB)};
             R ir0 = frcp(q0);
             R v1 = q1 * ir0, v2 = q2 * ir0;
             R B1 = B0[A1], B2 = B0[A2];
