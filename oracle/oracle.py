@@ -40,6 +40,8 @@ class OracleParams(C.Structure):
         ("degen_tol", C.c_double),
         ("ghost", C.c_int32),
         ("pad_", C.c_int32),
+        ("rho_protect", C.c_double),
+        ("p_protect", C.c_double),
     ]
 
 
@@ -49,7 +51,8 @@ class _PatchDesc(C.Structure):
 
 def default_params(dx=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, cfl=0.4, ghost=5,
                    eps=(0.1, 0.0, 0.1, 0.0, 0.1, 0.0, 0.1), limiter_beta=1.0,
-                   rho_floor=1e-10, p_floor=1e-10, degen_tol=1e-12) -> OracleParams:
+                   rho_floor=1e-10, p_floor=1e-10, degen_tol=1e-12, rho_protect=0.0,
+                   p_protect=0.0) -> OracleParams:
     p = OracleParams()
     p.gamma = gamma
     p.cfl = cfl
@@ -62,6 +65,8 @@ def default_params(dx=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, cfl=0.4, ghost=5,
         p.dx[a] = dx[a]
     p.degen_tol = degen_tol
     p.ghost = ghost
+    p.rho_protect = rho_protect
+    p.p_protect = p_protect
     return p
 
 
@@ -95,6 +100,7 @@ def _load():
         lib.orc_phys_flux.argtypes = [dp, C.c_double, dp]
         lib.orc_eigensystem.argtypes = [dp, dp, C.POINTER(OracleParams), dp, dp, dp]
         lib.orc_line_fluxes.argtypes = [C.POINTER(OracleParams), C.c_int, dp, dp, C.c_double, dp]
+        lib.orc_hll_flux.argtypes = [dp, dp, C.POINTER(OracleParams), dp]
         lib.orc_num_threads.restype = C.c_int
         _lib = lib
     return _lib
@@ -123,6 +129,16 @@ def eigensystem(uL, uR, params: OracleParams):
     L = np.zeros(49)
     lib.orc_eigensystem(_p(uL), _p(uR), C.byref(params), _p(lam), _p(R), _p(L))
     return lam, R.reshape(7, 7), L.reshape(7, 7)
+
+
+def hll_flux(uL, uR, params: OracleParams):
+    """HLL flux of the protection path for two frame-ordered 8-states."""
+    lib = _load()
+    uL = np.ascontiguousarray(uL, dtype=np.float64)
+    uR = np.ascontiguousarray(uR, dtype=np.float64)
+    out = np.zeros(8)
+    lib.orc_hll_flux(_p(uL), _p(uR), C.byref(params), _p(out))
+    return out
 
 
 def line_fluxes(params: OracleParams, q8: np.ndarray, bf: np.ndarray, lam: float) -> np.ndarray:

@@ -62,6 +62,8 @@ typedef struct {
     double degen_tol;    /* relative threshold of the eigenvector degeneracy rules */
     int32_t ghost;       /* ghost width g */
     int32_t pad_;
+    double rho_protect;  /* protection floor on density (0: off) */
+    double p_protect;    /* protection floor on pressure (0: off) */
 } orc_params;
 
 typedef struct {
@@ -138,6 +140,7 @@ typedef struct {
     double lam[7];
     double R[7][7]; /* R[c][k]: component c of right eigenvector k (conserved) */
     double L[7][7]; /* L[k][c]: left eigenvector k (conserved) */
+    double a2raw;   /* Roe sound speed squared before the floor clamp */
 } orc_eig;
 
 static void prim_of(const double u[8], double gam, double *rho, double v[3], double bt[2], double *bpar, double *p)
@@ -176,6 +179,7 @@ static void roe_eigensystem(const double uL[8], const double uR[8], const orc_pa
     double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
     double bt2 = bt[0] * bt[0] + bt[1] * bt[1];
     double a2 = (gam - 1.0) * (h - 0.5 * v2 - (bx * bx + bt2) / rho) - (gam - 2.0) * X;
+    es->a2raw = a2;
     double a2min = gam * P->p_floor / rho;
     if (a2 < a2min) a2 = a2min;
 
@@ -372,6 +376,70 @@ static void face_state(double rho, const double v[3], const double bt[2], double
            0.5 * (bpar * bpar + bt[0] * bt[0] + bt[1] * bt[1]);
 }
 
+/* Fast speed along the sweep axis of a frame state (B_par = u[4]). */
+static double frame_fast_speed(const double u[8], double gam)
+{
+    double rho, v[3], bt[2], bpar, p;
+    prim_of(u, gam, &rho, v, bt, &bpar, &p);
+    double a2 = gam * p / rho;
+    double ca2 = bpar * bpar / rho;
+    double bp2 = (bt[0] * bt[0] + bt[1] * bt[1]) / rho;
+    double dprime = a2 - ca2 - bp2;
+    double d = sqrt(dprime * dprime + 4.0 * a2 * bp2);
+    return sqrt(0.5 * (a2 + ca2 + bp2 + d));
+}
+
+/*
+ * HLL flux (Appendix A, protection path; Einfeldt's HLLE bounds):
+ *   u = (b+ F_L - b- F_R)/(b+ - b-) + b+ b-/(b+ - b-) (u_R - u_L),
+ *   b+ = max(lmax, v_R + c_f,R, 0),  b- = min(lmin, v_L - c_f,L, 0),
+ * lmin, lmax the smallest and largest Roe eigenvalues of the face.  The
+ * printed formula adds b- F_{i+1}, which with b- = -b+ would give
+ * (F_L - F_R)/2; the sign that makes the flux consistent (u(q,q) = F(q)) is
+ * taken, and the garbled speed subscripts are read as the left and right
+ * states of the face.
+ */
+static void hll_flux(const double uL[8], const double uR[8], double lmin, double lmax, double gam, double out[8])
+{
+    double FL[8], FR[8];
+    orc_phys_flux(uL, gam, FL);
+    orc_phys_flux(uR, gam, FR);
+    double vL = uL[1] / uL[0], vR = uR[1] / uR[0];
+    double bp = fmax(fmax(lmax, vR + frame_fast_speed(uR, gam)), 0.0);
+    double bm = fmin(fmin(lmin, vL - frame_fast_speed(uL, gam)), 0.0);
+    double den = bp - bm;
+    for (int c = 0; c < 8; c++) out[c] = (bp * FL[c] - bm * FR[c]) / den + bp * bm / den * (uR[c] - uL[c]);
+}
+
+void orc_hll_flux(const double uL[8], const double uR[8], const orc_params *P, double out[8])
+{
+    orc_eig es;
+    roe_eigensystem(uL, uR, P, &es);
+    hll_flux(uL, uR, es.lam[0], es.lam[6], P->gamma, out);
+}
+
+/*
+ * Protection trigger of a face (reading of "the protection floor is
+ * exceeded", Appendix A): with a protection floor set, the face switches to
+ * HLL if the Roe sound speed squared is not positive, or if one of the six
+ * states inside the Roe fan, u_L + sum_{k<m} alpha_k R_k (m = 1..6), has a
+ * density below rho_protect or a pressure below p_protect.
+ */
+static int protect_face(const double uL[8], const orc_eig *es, const double alpha[7], const orc_params *P)
+{
+    if (!(P->rho_protect > 0.0 || P->p_protect > 0.0)) return 0;
+    if (es->a2raw <= 0.0) return 1;
+    double w[8];
+    memcpy(w, uL, sizeof w);
+    for (int m = 0; m < 6; m++) {
+        for (int c = 0; c < 7; c++) w[C7[c]] += alpha[m] * es->R[c][m];
+        double b2 = w[4] * w[4] + w[5] * w[5] + w[6] * w[6];
+        double p = (P->gamma - 1.0) * (w[7] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / w[0] - 0.5 * b2);
+        if (w[0] < P->rho_protect || p < P->p_protect) return 1;
+    }
+    return 0;
+}
+
 /*
  * Modified fluxes on one line of m zones in a sweep frame.
  *   q8[s*8 + c] : zone s, frame-ordered zone-centred state
@@ -379,7 +447,9 @@ static void face_state(double rho, const double v[3], const double bt[2], double
  *   bf[s]       : B_par on the left face of zone s (face s lies between s-1, s)
  *   lam         : dt / dx_par
  *   out[s*8+c]  : modified flux at face s, written for faces 2 .. m-2; NaN elsewhere
- * The B_par row of every flux is 0.
+ * The B_par row of every flux is 0.  A face the protection trigger flags takes
+ * the HLL flux instead, and its g-tilde is taken as 0 in the limiter of its
+ * two zones (it contributes no anti-diffusion to its neighbours).
  */
 void orc_line_fluxes(const orc_params *P, int m, const double *q8, const double *bf, double lam, double *out)
 {
@@ -395,6 +465,9 @@ void orc_line_fluxes(const orc_params *P, int m, const double *q8, const double 
     double(*Rk)[7][7] = malloc(sizeof(double) * 49 * m);
     double(*FL)[8] = malloc(sizeof(double) * 8 * m);
     double(*FR)[8] = malloc(sizeof(double) * 8 * m);
+    double(*UL)[8] = malloc(sizeof(double) * 8 * m), (*UR)[8] = malloc(sizeof(double) * 8 * m);
+    double(*lmm)[2] = malloc(sizeof(double) * 2 * m);
+    int *prot = calloc((size_t)m, sizeof(int));
 
     /* zone primitives; pressure from the zone-centred field, clamped at the floor */
     for (int s = 0; s < m; s++) {
@@ -427,6 +500,13 @@ void orc_line_fluxes(const orc_params *P, int m, const double *q8, const double 
             gt[s][k] = 0.5 * (Qvisc(nu[s][k], P->eps[k]) - nu[s][k] * nu[s][k]) * a;
         }
         memcpy(Rk[s], es.R, sizeof(es.R));
+        prot[s] = protect_face(uL, &es, al[s], P);
+        if (prot[s])
+            for (int k = 0; k < 7; k++) gt[s][k] = 0.0;
+        memcpy(UL[s], uL, sizeof uL);
+        memcpy(UR[s], uR, sizeof uR);
+        lmm[s][0] = es.lam[0];
+        lmm[s][1] = es.lam[6];
     }
     /* zone limiter values g_{k,i} from the g-tilde of its two faces */
     for (int s = 1; s < m - 1; s++)
@@ -442,12 +522,17 @@ void orc_line_fluxes(const orc_params *P, int m, const double *q8, const double 
             for (int c = 0; c < 7; c++) f7[c] += beta * Rk[s][c][k];
         }
         double *o = out + (size_t)s * 8;
+        if (prot[s]) {
+            hll_flux(UL[s], UR[s], lmm[s][0], lmm[s][1], gam, o);
+            o[4] = 0.0;
+            continue;
+        }
         for (int c = 0; c < 8; c++) o[c] = 0.5 * (FL[s][c] + FR[s][c]);
         for (int c = 0; c < 7; c++) o[C7[c]] -= f7[c] / (2.0 * lam);
         o[4] = 0.0;
     }
     free(rho); free(pr); free(v); free(bt); free(al); free(nu); free(gt); free(gz);
-    free(Rk); free(FL); free(FR);
+    free(Rk); free(FL); free(FR); free(UL); free(UR); free(lmm); free(prot);
 }
 
 /* ------------------------------------------------------------------------ */
