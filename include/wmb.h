@@ -63,6 +63,13 @@ typedef struct wmb_params {
     double degen_tol;    /* degeneracy threshold of the eigenvectors (e.g. 1e-12) */
     int32_t ghost;       /* ghost width g, >= 4 (the paper uses 5, Sect. 5.1) */
     int32_t precision;   /* WMB_FP64 or WMB_FP32 */
+    double rho_protect;  /* protection floors (Appendix A, last paragraph): a face */
+    double p_protect;    /* whose Roe sound speed squared is not positive, or one of
+                            whose six Roe-fan intermediate states u_L + sum_{k<m}
+                            alpha_k R_k has rho < rho_protect or P < p_protect,
+                            takes the HLL flux instead of the MHDTVD flux (and
+                            contributes no g-tilde to its zones' limiters); both 0
+                            (the default) switch the protection off */
 } wmb_params;
 
 typedef struct wmb_patch_desc {
@@ -77,7 +84,8 @@ typedef struct wmb_patch_desc {
 typedef struct wmb_ctx wmb_ctx;
 
 /* Create a context.  Validates p (gamma > 1, cfl in (0,1], ghost >= 4,
-   dx > 0, precision known).  *out receives the context. */
+   dx > 0, precision known, protection floors >= 0).  *out receives the
+   context. */
 int wmb_create(const wmb_params *p, wmb_ctx **out);
 
 /* Device bytes the caller must provide for npatch patches: two state copies
@@ -141,9 +149,11 @@ int wmb_run_steps(wmb_ctx *c, int32_t nsteps);
 /* FP64 diagnostics over all interiors: totals[8] = sum over zones of q times
    the zone volume; max_divb_raw = max |div b| with div b = sum_d (b_d(+) -
    b_d(-)) / dx_d; max_divb_norm = max_divb_raw * min(dx) / B_rms; n_floored =
-   floor activations since wmb_init_patches.  Any output pointer may be NULL. */
+   floor activations since wmb_init_patches; n_protected = faces that took the
+   HLL flux since wmb_init_patches (every computed face of every stage,
+   including faces in the ghost halo).  Any output pointer may be NULL. */
 int wmb_diagnostics(wmb_ctx *c, double totals[8], double *max_divb_norm, double *max_divb_raw,
-                    int64_t *n_floored);
+                    int64_t *n_floored, int64_t *n_protected);
 
 /* Test hook: copy an intermediate of the last step of one patch over the
    ghosted box, widened to double, in this layout: stage 1 Step-1 fluxes

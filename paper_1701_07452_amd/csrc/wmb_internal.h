@@ -39,6 +39,7 @@ struct Coef {
     R beta_l, p_floor, rho_floor, tol, tol2;
     R idx[3];                    // 1 / dx_d
     R eps[7], q4e[7];            // epsilon_k and 1/(4 epsilon_k) (0 where epsilon_k = 0)
+    R rho_prot, p_prot;          // protection floors (0: off)
 };
 
 // One patch inside the device pool: structure of arrays over the ghosted box

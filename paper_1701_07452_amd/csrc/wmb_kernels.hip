@@ -783,11 +783,58 @@ struct FaceEig {
     R a2, a, cf, cs, alf, als, by, bz, s;
 };
 
-template <typename R, int D, int STAGE, bool MM>
+// Protection trigger of a face (protection floors set): the Roe sound speed
+// squared before its floor clamp is not positive, or one of the six states
+// inside the Roe fan, u_L + sum_{k<m} alpha_k R_k (m = 1..6), has a density
+// below rho_prot or a pressure below p_prot.  The fan is walked in the
+// primitive-like variables (rho, v, B_t, P'), each wave's increment mapped to
+// conserved variables at the Roe state; u_L is the left rebuilt face state.
+template <typename R>
+__device__ __forceinline__ bool fan_below_floor(R rl, R vxl, R vyl, R vzl, R b1l, R b2l, R pl, R bf,
+                                                const FaceEig<R>& e, R a2raw, const R alpha[7], const Coef<R>& cf) {
+    if (a2raw <= R(0)) return true;
+    R w0 = rl, w1 = rl * vxl, w2 = rl * vyl, w3 = rl * vzl, w5 = b1l, w6 = b2l;
+    R w7 = pl * cf.igm1 + R(0.5) * rl * (vxl * vxl + vyl * vyl + vzl * vzl) + R(0.5) * (bf * bf + b1l * b1l + b2l * b2l);
+    const R v2 = e.vx * e.vx + e.vy * e.vy + e.vz * e.vz;
+    const R eh = R(0.5) * v2 + cf.gm2 * e.X * cf.igm1;
+    const R sqa = e.sq * e.a, ra2 = e.rho * e.a2;
+    bool low = false;
+#pragma unroll
+    for (int m = 0; m < 6; m++) {
+        // primitive-like right eigenvector of wave m (ascending eigenvalue order)
+        R dr, dvp, dv1, dv2, db1, db2, dp;
+        const R sg = m < 3 ? R(-1) : R(1);
+        if (m == 0) {  // fast, v - cf
+            dr = e.rho * e.alf, dvp = sg * e.alf * e.cf, dv1 = -sg * e.als * e.cs * e.s * e.by,
+            dv2 = -sg * e.als * e.cs * e.s * e.bz, db1 = sqa * e.als * e.by, db2 = sqa * e.als * e.bz, dp = ra2 * e.alf;
+        } else if (m == 1 || m == 5) {  // Alfven
+            dr = R(0), dvp = R(0), dv1 = -e.bz, dv2 = e.by, db1 = sg * e.s * e.sq * e.bz, db2 = -sg * e.s * e.sq * e.by,
+            dp = R(0);
+        } else if (m == 3) {  // entropy
+            dr = R(1), dvp = R(0), dv1 = R(0), dv2 = R(0), db1 = R(0), db2 = R(0), dp = R(0);
+        } else {  // slow, v -/+ cs
+            dr = e.rho * e.als, dvp = sg * e.als * e.cs, dv1 = sg * e.alf * e.cf * e.s * e.by,
+            dv2 = sg * e.alf * e.cf * e.s * e.bz, db1 = -sqa * e.alf * e.by, db2 = -sqa * e.alf * e.bz, dp = ra2 * e.als;
+        }
+        const R am = alpha[m];
+        w0 += am * dr;
+        w1 += am * (e.vx * dr + e.rho * dvp);
+        w2 += am * (e.vy * dr + e.rho * dv1);
+        w3 += am * (e.vz * dr + e.rho * dv2);
+        w5 += am * db1;
+        w6 += am * db2;
+        w7 += am * (eh * dr + e.rho * (e.vx * dvp + e.vy * dv1 + e.vz * dv2) + e.b1 * db1 + e.b2 * db2 + dp * cf.igm1);
+        const R pm = cf.gm1 * (w7 - R(0.5) * (w1 * w1 + w2 * w2 + w3 * w3) / w0 - R(0.5) * (bf * bf + w5 * w5 + w6 * w6));
+        low |= (w0 < cf.rho_prot) || (pm < cf.p_prot);
+    }
+    return low;
+}
+
+template <typename R, int D, int STAGE, bool MM, bool PROT>
 __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
                                                      const WorkItem* __restrict__ work, DevParams prm, Coef<R> cf,
                                                      int cur, const StepConst* __restrict__ sc, int P, int W, int zlo,
-                                                     int tlo, int thi) {
+                                                     int tlo, int thi, unsigned long long* __restrict__ nprot) {
     extern __shared__ unsigned char smem_raw[];
     const int nthr = P * W;
     Rec8<R>* shp = reinterpret_cast<Rec8<R>*>(smem_raw);  // zone primitives
@@ -909,7 +956,8 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
     // ---------------- phase B: face s between zones s-1 and s ----------------
     FaceEig<R> e;
     R alpha[7], nu[7];
-    R bf = R(0);
+    R bf = R(0), a2raw = R(0);
+    bool prot = false;
     const bool face = live && s >= 1;
     if (face) {
         bf = bload(z0, rs, xo, (STAGE == 1) ? qs + (8 + D) * VB : (unsigned)(F_BH + D) * VB);
@@ -936,6 +984,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
         R bt2 = e.b1 * e.b1 + e.b2 * e.b2;
         R irho = frcp(e.rho);
         R a2 = cf.gm1 * (h - R(0.5) * v2 - (bf2 + bt2) * irho) - cf.gm2 * e.X;
+        a2raw = a2;
         R a2min = cf.gam * cf.p_floor * irho;
         if (a2 < a2min) a2 = a2min;
         R ca2 = bf2 * irho, bp2 = bt2 * irho;
@@ -1007,6 +1056,13 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
             gr.v[k] = R(0.5) * (qvisc(nu[k], cf.eps[k], cf.q4e[k]) - nu[k] * nu[k]) * alpha[k];
         }
         gr.v[7] = R(0);
+        if (PROT) {
+            // protected face: HLL flux in phase C, no g-tilde for the limiters
+            prot = fan_below_floor(rl, vxl, vyl, vzl, b1l, b2l, pl, bf, e, a2raw, alpha, cf);
+            if (prot)
+#pragma unroll
+                for (int k = 0; k < 7; k++) gr.v[k] = R(0);
+        }
         shg[tid] = gr;
     }
     __syncthreads();
@@ -1072,6 +1128,36 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
         out[4] = R(0.5) * (F[0][4] + F[1][4]) - il * c7;
         out[5] = R(0.5) * (F[0][5] + F[1][5]) - il * wb1;
         out[6] = R(0.5) * (F[0][6] + F[1][6]) - il * wb2;
+        if (PROT && prot) {
+            // HLL (Einfeldt bounds): (b+ F_L - b- F_R + b+ b- (u_R - u_L)) / (b+ - b-)
+            R U[2][7], vfs[2];
+#pragma unroll
+            for (int side = 0; side < 2; side++) {
+                const Rec8<R> Z = shp[side ? tid : tid - sstep];
+                R r = Z.v[0], vx = Z.v[1], vy = Z.v[2], vz = Z.v[3], b1 = Z.v[4], b2 = Z.v[5], pr = Z.v[6];
+                U[side][0] = r;
+                U[side][1] = r * vx;
+                U[side][2] = r * vy;
+                U[side][3] = r * vz;
+                U[side][4] = pr * cf.igm1 + R(0.5) * r * (vx * vx + vy * vy + vz * vz) +
+                             R(0.5) * (bf * bf + b1 * b1 + b2 * b2);
+                U[side][5] = b1;
+                U[side][6] = b2;
+                // fast speed of the rebuilt state along the sweep
+                R ir = frcp(r);
+                R fa2 = cf.gam * pr * ir, fca2 = bf * bf * ir, fbp2 = (b1 * b1 + b2 * b2) * ir;
+                R fdp = fa2 - fca2 - fbp2;
+                R fcf = fsqrt(R(0.5) * (fa2 + fca2 + fbp2 + fsqrt(fdp * fdp + R(4) * fa2 * fbp2)));
+                vfs[side] = side ? vx + fcf : vx - fcf;
+            }
+            const R bp = fmax(fmax(e.vx + e.cf, vfs[1]), R(0));
+            const R bm = fmin(fmin(e.vx - e.cf, vfs[0]), R(0));
+            const R iden = frcp(bp - bm);
+#pragma unroll
+            for (int r = 0; r < 7; r++)
+                out[r] = (bp * F[0][r] - bm * F[1][r]) * iden + bp * bm * iden * (U[1][r] - U[0][r]);
+            atomicAdd(nprot, 1ULL);
+        }
         const unsigned fo = (unsigned)((STAGE == 1 ? F_FL1 : F_FL2) + 7 * D) * VB;
         // frame -> lab rows: m_par -> m_D, m_t1 -> m_A1, m_t2 -> m_A2
         bstore(out[0], rs, xo, fo);
@@ -1181,19 +1267,21 @@ hipError_t launch_update(void* pool, const PatchDev* pt, const WorkItem* wk, int
 template <typename R>
 hipError_t launch_sweep(int d, int stage, void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm,
                         const Coef<R>& cf, int cur, const StepConst* sc, int P, int W, int zlo, int tlo, int thi,
-                        hipStream_t st) {
+                        unsigned long long* nprot, hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
     size_t shmem = sizeof(R) * 16 * (size_t)P * W;
     dim3 blk = (d == 0) ? dim3(P, W) : dim3(W, P);
     const bool mm = cf.beta_l == R(1);
-#define WMB_SW(DD, SS)                                                                                                  \
-    do {                                                                                                                \
-        if (mm)                                                                                                         \
-            hipLaunchKernelGGL((sweep_kernel<R, DD, SS, true>), dim3(nblk), blk, shmem, st, (R*)pool, pt, wk, prm, cf,  \
-                               cur, sc, P, W, zlo, tlo, thi);                                                           \
-        else                                                                                                            \
-            hipLaunchKernelGGL((sweep_kernel<R, DD, SS, false>), dim3(nblk), blk, shmem, st, (R*)pool, pt, wk, prm, cf, \
-                               cur, sc, P, W, zlo, tlo, thi);                                                           \
+    const bool pr = cf.rho_prot > R(0) || cf.p_prot > R(0);
+#define WMB_SW1(DD, SS, MM, PR)                                                                                       \
+    hipLaunchKernelGGL((sweep_kernel<R, DD, SS, MM, PR>), dim3(nblk), blk, shmem, st, (R*)pool, pt, wk, prm, cf, cur, sc, \
+                       P, W, zlo, tlo, thi, nprot)
+#define WMB_SW(DD, SS)                                                                                                \
+    do {                                                                                                              \
+        if (mm && !pr) WMB_SW1(DD, SS, true, false);                                                                  \
+        else if (mm) WMB_SW1(DD, SS, true, true);                                                                     \
+        else if (!pr) WMB_SW1(DD, SS, false, false);                                                                  \
+        else WMB_SW1(DD, SS, false, true);                                                                            \
     } while (0)
     if (stage == 1) {
         if (d == 0) WMB_SW(0, 1);
@@ -1204,6 +1292,7 @@ hipError_t launch_sweep(int d, int stage, void* pool, const PatchDev* pt, const 
         else if (d == 1) WMB_SW(1, 2);
         else WMB_SW(2, 2);
     }
+#undef WMB_SW1
 #undef WMB_SW
     return hipGetLastError();
 }
@@ -1228,7 +1317,8 @@ hipError_t launch_diag(const void* pool, const PatchDev* pt, const WorkItem* wk,
                                          int, const StepConst*, unsigned long long*, unsigned long long*, int,          \
                                          hipStream_t);                                                                   \
     template hipError_t launch_sweep<R>(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&,        \
-                                        const Coef<R>&, int, const StepConst*, int, int, int, int, int, hipStream_t);    \
+                                        const Coef<R>&, int, const StepConst*, int, int, int, int, int,                  \
+                                        unsigned long long*, hipStream_t);                                               \
     template hipError_t launch_diag<R>(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,        \
                                        double*, hipStream_t);
 WMB_INST(float)

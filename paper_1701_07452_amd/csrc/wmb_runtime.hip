@@ -20,7 +20,7 @@ hipError_t launch_dt_finalize(unsigned long long*, StepConst*, const DevParams&,
 hipError_t launch_set_dt(StepConst*, double, const DevParams&, hipStream_t);
 template <typename R> hipError_t launch_ct_half(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int, const StepConst*, hipStream_t);
 template <typename R> hipError_t launch_update(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, unsigned long long*, unsigned long long*, int, hipStream_t);
-template <typename R> hipError_t launch_sweep(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, int, int, int, int, int, hipStream_t);
+template <typename R> hipError_t launch_sweep(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, int, int, int, int, int, unsigned long long*, hipStream_t);
 template <typename R> hipError_t launch_diag(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, double*, hipStream_t);
 }  // namespace wmb
 
@@ -108,6 +108,8 @@ void make_coef(const wmb_params& p, Coef<R>& cf) {
         cf.eps[k] = (R)p.eps[k];
         cf.q4e[k] = p.eps[k] > 0.0 ? (R)(0.25 / p.eps[k]) : (R)0;
     }
+    cf.rho_prot = (R)p.rho_protect;
+    cf.p_prot = (R)p.p_protect;
 }
 
 int fail(wmb_ctx* c, int code, const std::string& msg) {
@@ -202,6 +204,7 @@ int check_params(const wmb_params* p) {
     if (!(p->rho_floor > 0.0) || !(p->p_floor > 0.0)) return WMB_EINVAL;
     if (!(p->degen_tol >= 0.0 && p->degen_tol < 1e-2)) return WMB_EINVAL;
     if (p->precision != WMB_FP64 && p->precision != WMB_FP32) return WMB_EINVAL;
+    if (!(p->rho_protect >= 0.0) || !(p->p_protect >= 0.0)) return WMB_EINVAL;
     return WMB_OK;
 }
 
@@ -308,7 +311,7 @@ int run_step(wmb_ctx* c) {
     for (int d = 0; d < 3; d++) {
         for (auto& G : c->sweeps[d][0]) {
             e = launch_sweep<R>(d, 1, c->pool, c->d_patch, G.wl.d, G.wl.n, c->dp, coef<R>(c), cur, c->d_sc, G.P, G.W,
-                                G.zlo, G.tlo, G.thi, c->stream);
+                                G.zlo, G.tlo, G.thi, c->d_nfloor + 1, c->stream);
             STEPCK("sweep1");
         }
         mark(c);
@@ -319,7 +322,7 @@ int run_step(wmb_ctx* c) {
     for (int d = 0; d < 3; d++) {
         for (auto& G : c->sweeps[d][1]) {
             e = launch_sweep<R>(d, 2, c->pool, c->d_patch, G.wl.d, G.wl.n, c->dp, coef<R>(c), cur, c->d_sc, G.P, G.W,
-                                G.zlo, G.tlo, G.thi, c->stream);
+                                G.zlo, G.tlo, G.thi, c->d_nfloor + 1, c->stream);
             STEPCK("sweep2");
         }
         mark(c);
@@ -631,13 +634,13 @@ int debug_stage_t(wmb_ctx* c, int ip, int stage, double* out) {
 }
 
 template <typename R>
-int diagnostics_t(wmb_ctx* c, double totals[8], double* dn, double* dr, int64_t* nfl) {
+int diagnostics_t(wmb_ctx* c, double totals[8], double* dn, double* dr, int64_t* nfl, int64_t* npr) {
     hipError_t e = launch_diag<R>(c->pool, c->d_patch, c->wl_diag.d, c->wl_diag.n, c->dp, c->cur, c->d_partial, c->stream);
     if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("diag: ") + hipGetErrorString(e));
     std::vector<double> part((size_t)c->wl_diag.n * 10);
     CKH(hipMemcpyAsync(part.data(), c->d_partial, sizeof(double) * part.size(), hipMemcpyDeviceToHost, c->stream));
-    unsigned long long nf = 0;
-    CKH(hipMemcpyAsync(&nf, c->d_nfloor, sizeof(nf), hipMemcpyDeviceToHost, c->stream));
+    unsigned long long cnt[2] = {0, 0};
+    CKH(hipMemcpyAsync(cnt, c->d_nfloor, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
     CKH(hipStreamSynchronize(c->stream));
     double sum[9] = {0}, comp[9] = {0}, mx = 0.0;
     for (int b = 0; b < c->wl_diag.n; b++) {
@@ -658,7 +661,8 @@ int diagnostics_t(wmb_ctx* c, double totals[8], double* dn, double* dr, int64_t*
     double dmin = std::fmin(c->p.dx[0], std::fmin(c->p.dx[1], c->p.dx[2]));
     if (dr) *dr = mx;
     if (dn) *dn = mx * dmin / brms;
-    if (nfl) *nfl = (int64_t)nf;
+    if (nfl) *nfl = (int64_t)cnt[0];
+    if (npr) *npr = (int64_t)cnt[1];
     return WMB_OK;
 }
 
@@ -684,7 +688,7 @@ int autotune_t(wmb_ctx* c, int reps) {
             for (int d = 0; d < 3 && e == hipSuccess; d++)
                 for (auto& G : c->sweeps[d][0])
                     e = launch_sweep<R>(d, 1, c->pool, c->d_patch, G.wl.d, G.wl.n, c->dp, coef<R>(c), c->cur, c->d_sc, G.P,
-                                        G.W, G.zlo, G.tlo, G.thi, c->stream);
+                                        G.W, G.zlo, G.tlo, G.thi, c->d_nfloor + 2, c->stream);
             if (e == hipSuccess)
                 e = launch_ct_half<R>(c->pool, c->d_patch, c->wl_cth.d, c->wl_cth.n, coef<R>(c), c->p.ghost, c->cur,
                                       c->d_sc, c->stream);
@@ -712,7 +716,7 @@ int autotune_t(wmb_ctx* c, int reps) {
                     for (int r = 0; r <= reps && e == hipSuccess; r++) {
                         CKH(hipEventRecord(e0, c->stream));
                         e = launch_sweep<R>(d, stage + 1, c->pool, c->d_patch, dl, (int)items.size(), c->dp, coef<R>(c),
-                                            c->cur, c->d_sc, G.P, W, G.zlo, G.tlo, G.thi, c->stream);
+                                            c->cur, c->d_sc, G.P, W, G.zlo, G.tlo, G.thi, c->d_nfloor + 2, c->stream);
                         CKH(hipEventRecord(e1, c->stream));
                         CKH(hipEventSynchronize(e1));
                         float t = 0.f;
@@ -833,11 +837,12 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     if ((rc = build_sweeps(c))) return rc;
     if ((rc = dev_alloc(c, &c->d_smax, 1))) return rc;
     if ((rc = dev_alloc(c, &c->d_sc, 1))) return rc;
-    if ((rc = dev_alloc(c, &c->d_nfloor, 1))) return rc;
+    // counters: floor activations, protected faces, and a sink for tuning runs
+    if ((rc = dev_alloc(c, &c->d_nfloor, 3))) return rc;
     if ((rc = dev_alloc(c, &c->d_partial, (size_t)c->wl_diag.n * 10))) return rc;
     CKH(hipMemsetAsync(c->d_smax, 0, sizeof(unsigned long long), c->stream));
     CKH(hipMemsetAsync(c->d_sc, 0, sizeof(StepConst), c->stream));
-    CKH(hipMemsetAsync(c->d_nfloor, 0, sizeof(unsigned long long), c->stream));
+    CKH(hipMemsetAsync(c->d_nfloor, 0, 3 * sizeof(unsigned long long), c->stream));
     CKH(hipStreamSynchronize(c->stream));
     c->cur = 0;
     c->smax_state = SMAX_ZERO;
@@ -923,11 +928,12 @@ int wmb_run_steps(wmb_ctx* c, int32_t nsteps) {
     return WMB_OK;
 }
 
-int wmb_diagnostics(wmb_ctx* c, double totals[8], double* max_divb_norm, double* max_divb_raw, int64_t* n_floored) {
+int wmb_diagnostics(wmb_ctx* c, double totals[8], double* max_divb_norm, double* max_divb_raw, int64_t* n_floored,
+                    int64_t* n_protected) {
     if (!c) return WMB_EINVAL;
     if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
-    return c->esize == 4 ? diagnostics_t<float>(c, totals, max_divb_norm, max_divb_raw, n_floored)
-                         : diagnostics_t<double>(c, totals, max_divb_norm, max_divb_raw, n_floored);
+    return c->esize == 4 ? diagnostics_t<float>(c, totals, max_divb_norm, max_divb_raw, n_floored, n_protected)
+                         : diagnostics_t<double>(c, totals, max_divb_norm, max_divb_raw, n_floored, n_protected);
 }
 
 int wmb_debug_stage(wmb_ctx* c, int32_t patch, int32_t stage, double* out) {

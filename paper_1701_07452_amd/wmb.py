@@ -46,6 +46,8 @@ class Params(C.Structure):
         ("degen_tol", C.c_double),
         ("ghost", C.c_int32),
         ("precision", C.c_int32),
+        ("rho_protect", C.c_double),
+        ("p_protect", C.c_double),
     ]
 
 
@@ -55,7 +57,7 @@ class PatchDesc(C.Structure):
 
 def make_params(dx=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, cfl=0.4, ghost=5, precision=WMB_FP64,
                 eps=(0.1, 0.0, 0.1, 0.0, 0.1, 0.0, 0.1), limiter_beta=1.0, rho_floor=1e-10, p_floor=1e-10,
-                degen_tol=1e-12) -> Params:
+                degen_tol=1e-12, rho_protect=0.0, p_protect=0.0) -> Params:
     p = Params()
     p.gamma = gamma
     p.cfl = cfl
@@ -69,6 +71,8 @@ def make_params(dx=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, cfl=0.4, ghost=5, precision
     p.degen_tol = degen_tol
     p.ghost = ghost
     p.precision = precision
+    p.rho_protect = rho_protect
+    p.p_protect = p_protect
     return p
 
 
@@ -94,7 +98,7 @@ def load_library():
     lib.wmb_compute_dt.argtypes = [vp, dp]
     lib.wmb_advance.argtypes = [vp, C.c_double]
     lib.wmb_run_steps.argtypes = [vp, C.c_int32]
-    lib.wmb_diagnostics.argtypes = [vp, dp, dp, dp, C.POINTER(C.c_int64)]
+    lib.wmb_diagnostics.argtypes = [vp, dp, dp, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.wmb_debug_stage.argtypes = [vp, C.c_int32, C.c_int32, dp]
     lib.wmb_profile_step.argtypes = [vp, dp, C.c_int32]
     lib.wmb_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.c_int32]
@@ -227,8 +231,14 @@ class Sim:
         dn = np.zeros(1)
         dr = np.zeros(1)
         nf = C.c_int64(0)
-        self._check(self.lib.wmb_diagnostics(self.h, _dp(tot), _dp(dn), _dp(dr), C.byref(nf)))
+        self._check(self.lib.wmb_diagnostics(self.h, _dp(tot), _dp(dn), _dp(dr), C.byref(nf), None))
         return tot, float(dn[0]), float(dr[0]), int(nf.value)
+
+    def protected_faces(self):
+        """Faces that took the HLL flux (protection floors) since creation."""
+        npr = C.c_int64(0)
+        self._check(self.lib.wmb_diagnostics(self.h, None, None, None, None, C.byref(npr)))
+        return int(npr.value)
 
     def debug_stage(self, ip, stage):
         sh = self.stored_shape(ip)

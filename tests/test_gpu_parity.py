@@ -467,3 +467,82 @@ def test_accuracy_report_256_10_steps(wmb):
     assert f32["rho"]["rel_l1"] <= 1e-5 and f32["E"]["rel_l1"] <= 1e-5
     assert f32["divb_norm"] <= 1e-6
     assert f64["rho"]["max_rel"] <= 1e-12 and f64["E"]["max_rel"] <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# protection path (Appendix A, last paragraph): HLL at protected faces
+# ---------------------------------------------------------------------------
+
+def _run_pair(wmb, G, q, b, prec, nsteps, **kw):
+    sim = gpu_sim(wmb, G, q, b, prec, **kw)
+    orc = oracle_sim(G, q, b, **{k: v for k, v in kw.items() if k != "precision"})
+    sim.run_steps(nsteps)
+    for _ in range(nsteps):
+        orc.fill_ghosts()
+        orc.advance(orc.compute_dt())
+    return sim, orc
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_protection_strong_rarefaction(wmb, prec):
+    """Einfeldt-type line (rho = 1, P = 0.4, v = -/+3, gamma = 1.4, B_x = 0.1)
+    along x: a strong rarefaction and a strong shock.  Protection floors 1e-3:
+    FP64 matches the oracle to 1e-10 of each field's scale, FP32 to 1e-4 in
+    relative L1; faces were protected, the state stays positive and no floor
+    fired.  Without protection the oracle needs its floors here."""
+    G = I.patch_grid([32, 32], [8], [8])
+    q, b = I.shock_tube_x(G.shape, gamma=1.4, left=(1.0, -3.0, 0.0, 0.0, 0.0, 0.0, 0.4),
+                          right=(1.0, 3.0, 0.0, 0.0, 0.0, 0.0, 0.4), bx=0.1)
+    kw = dict(dx=(1 / 64,) * 3, gamma=1.4, rho_floor=1e-12, p_floor=1e-12, rho_protect=1e-3, p_protect=1e-3)
+    sim, orc = _run_pair(wmb, G, q, b, prec, 6, **kw)
+    assert sim.protected_faces() > 0
+    qg, bg = I.gather(G, [sim.get_state(i) for i in range(G.npatch)])
+    qo, bo = oracle_gather(G, orc)
+    _, _, _, nfl = sim.diagnostics()
+    _, _, _, nflo = orc.diagnostics()
+    assert nfl == 0 and nflo == 0
+    rho, e = qg[0], qg[7]
+    p = 0.4 * (e - 0.5 * (qg[1] ** 2 + qg[2] ** 2 + qg[3] ** 2) / rho - 0.5 * (qg[4:7] ** 2).sum(0))
+    assert rho.min() > 0 and p.min() > 0
+    if prec == 0:
+        for c in range(8):
+            scale = max(np.abs(qo[c]).max(), np.abs(qo[1:4]).max() if 1 <= c <= 3 else 0.0, 1e-300)
+            assert np.abs(qg[c] - qo[c]).max() <= 1e-10 * scale, c
+    else:
+        assert _rel_l1(qg[0], qo[0]) <= 1e-4 and _rel_l1(qg[7], qo[7]) <= 1e-4
+    sim.close()
+    orc.close()
+    # the same line without protection: the floors are needed
+    plain = oracle_sim(G, q, b, dx=(1 / 64,) * 3, gamma=1.4, rho_floor=1e-12, p_floor=1e-12)
+    for _ in range(6):
+        plain.fill_ghosts()
+        plain.advance(plain.compute_dt())
+    assert plain.diagnostics()[3] > 0
+    plain.close()
+
+
+def test_protection_high_contrast_fp64(wmb):
+    """Mach-5 lognormal-density recipe at 32^3 as 8 x 16^3 with protection
+    floors 0.05 (many faces protected): FP64 GPU = oracle to 1e-10 after 3
+    steps, totals conserved, protection counted."""
+    q, b = I.high_contrast_turbulence(32)
+    G = I.uniform_grid(32, 16)
+    kw = dict(dx=(1 / 32,) * 3, rho_floor=1e-8, p_floor=1e-8, rho_protect=0.05, p_protect=0.05)
+    sim, orc = _run_pair(wmb, G, q, b, 0, 3, **kw)
+    assert sim.protected_faces() > 0
+    qg, bg = I.gather(G, [sim.get_state(i) for i in range(G.npatch)])
+    qo, bo = oracle_gather(G, orc)
+    for c in range(8):
+        scale = np.abs(qo[1:4]).max() if 1 <= c <= 3 else (np.abs(qo[4:7]).max() if 4 <= c <= 6 else np.abs(qo[c]).max())
+        assert np.abs(qg[c] - qo[c]).max() <= 1e-10 * scale, c
+    assert np.abs(bg - bo).max() <= 1e-10 * np.abs(bo).max()
+    sim.close()
+    orc.close()
+
+
+def test_protection_off_counts_nothing(wmb):
+    G, (q, b) = CASES["uniform8"]()
+    sim = gpu_sim(wmb, G, q, b, 1, dx=(1 / 16,) * 3)
+    sim.run_steps(2)
+    assert sim.protected_faces() == 0
+    sim.close()
