@@ -40,6 +40,8 @@ __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x)
 __device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
 // smallest |alpha| divided by in the limiter's gamma (FP32: keeps the hardware
 // reciprocal away from denormals; FP64: exact zero test)
 __device__ __forceinline__ float alpha_min(float) { return 1e-30f; }
@@ -935,7 +937,10 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
             apply_floor(u, prm, cf);
         }
         R rho = u[0];
-        R ir = frcp(rho);
+        // 1/sqrt(rho) once per zone: the faces form sqrt(rho), 1/rho and the
+        // Roe density's reciprocal from it
+        R rsq = frsq(rho);
+        R ir = rsq * rsq;
         R vpar = u[1 + D] * ir, vt1 = u[1 + A1] * ir, vt2 = u[1 + A2] * ir;
         R b2 = u[4] * u[4] + u[5] * u[5] + u[6] * u[6];
         R pr = cf.gm1 * (u[7] - R(0.5) * rho * (vpar * vpar + vt1 * vt1 + vt2 * vt2) - R(0.5) * b2);
@@ -948,7 +953,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
         rec.v[4] = u[4 + A1];
         rec.v[5] = u[4 + A2];
         rec.v[6] = pr;
-        rec.v[7] = R(0);
+        rec.v[7] = rsq;
         shp[tid] = rec;
     }
     __syncthreads();
@@ -967,9 +972,10 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
         R rr = Rr.v[0], vxr = Rr.v[1], vyr = Rr.v[2], vzr = Rr.v[3], b1r = Rr.v[4], b2r = Rr.v[5], prr = Rr.v[6];
 
         R bf2 = bf * bf;
-        R hl = (cf.ggm * pl + R(0.5) * rl * (vxl * vxl + vyl * vyl + vzl * vzl) + bf2 + b1l * b1l + b2l * b2l) * frcp(rl);
-        R hr = (cf.ggm * prr + R(0.5) * rr * (vxr * vxr + vyr * vyr + vzr * vzr) + bf2 + b1r * b1r + b2r * b2r) * frcp(rr);
-        R sl = fsqrt(rl), sr = fsqrt(rr);
+        const R rsl = L.v[7], rsr = Rr.v[7];  // 1/sqrt(rho) of the two zones
+        R hl = (cf.ggm * pl + R(0.5) * rl * (vxl * vxl + vyl * vyl + vzl * vzl) + bf2 + b1l * b1l + b2l * b2l) * (rsl * rsl);
+        R hr = (cf.ggm * prr + R(0.5) * rr * (vxr * vxr + vyr * vyr + vzr * vzr) + bf2 + b1r * b1r + b2r * b2r) * (rsr * rsr);
+        R sl = rl * rsl, sr = rr * rsr;
         R isum = frcp(sl + sr);
         e.rho = sl * sr;
         e.vx = (sl * vxl + sr * vxr) * isum;
@@ -982,7 +988,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
         e.X = (db1 * db1 + db2 * db2) * R(0.5) * isum * isum;
         R v2 = e.vx * e.vx + e.vy * e.vy + e.vz * e.vz;
         R bt2 = e.b1 * e.b1 + e.b2 * e.b2;
-        R irho = frcp(e.rho);
+        R irho = rsl * rsr;  // 1 / (sqrt(rho_L) sqrt(rho_R))
         R a2 = cf.gm1 * (h - R(0.5) * v2 - (bf2 + bt2) * irho) - cf.gm2 * e.X;
         a2raw = a2;
         R a2min = cf.gam * cf.p_floor * irho;
@@ -991,7 +997,8 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
         R dpr = a2 - ca2 - bp2;
         R dd = fsqrt(dpr * dpr + R(4) * a2 * bp2);
         R cf2 = R(0.5) * (a2 + ca2 + bp2 + dd);
-        R cs2 = a2 * ca2 * frcp(cf2);
+        const R rcf = frsq(cf2);  // 1/cf
+        R cs2 = a2 * ca2 * (rcf * rcf);
         if (dd <= cf.tol * (a2 + ca2 + bp2)) {
             e.alf = R(1);
             e.als = R(0);
@@ -1012,15 +1019,16 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
             e.by = R(0.70710678118654752440);
             e.bz = R(0.70710678118654752440);
         } else {
-            R ib = frcp(fsqrt(bt2));
+            R ib = frsq(bt2);
             e.by = e.b1 * ib;
             e.bz = e.b2 * ib;
         }
         e.s = bf >= R(0) ? R(1) : R(-1);
-        e.sq = fsqrt(e.rho);
+        const R isq = frsq(e.rho), ra = frsq(a2);  // 1/sqrt(rho), 1/a
+        e.sq = e.rho * isq;
         e.a2 = a2;
-        e.a = fsqrt(a2);
-        e.cf = fsqrt(cf2);
+        e.a = a2 * ra;
+        e.cf = cf2 * rcf;
         e.cs = fsqrt(cs2);
         R ca = fsqrt(ca2);
 
@@ -1030,10 +1038,9 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
         R dp = (prr - pl) + e.X * drho;
         R dvpar = e.by * dvy + e.bz * dvz, dvper = -e.bz * dvy + e.by * dvz;
         R dbpar = e.by * db1 + e.bz * db2, dbper = -e.bz * db1 + e.by * db2;
-        R ia2 = frcp(a2);
+        R ia2 = ra * ra;
         R i2a2 = R(0.5) * ia2;
-        R isq = frcp(e.sq);
-        R ipa = R(0.5) * isq * frcp(e.a);
+        R ipa = R(0.5) * isq * ra;
         R pterm = dp * irho * i2a2;
         R Ef = e.alf * pterm + e.als * dbpar * ipa;
         R Of = (e.alf * e.cf * dvx - e.als * e.cs * e.s * dvpar) * i2a2;
