@@ -124,13 +124,13 @@ def cpu_baseline(q, b, G, dx, ghost, budget_s=12.0):
     }
 
 
-def run_precision(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps, tuning=None):
+def run_precision(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps, tuning=None, **params):
     import torch
 
     from paper_1701_07452_amd import inputs as I
 
     stream = torch.cuda.Stream()
-    sim = W.Sim(W.make_params(dx=dx, precision=prec, ghost=ghost), G.descs, origins=G.origin, stream=stream)
+    sim = W.Sim(W.make_params(dx=dx, precision=prec, ghost=ghost, **params), G.descs, origins=G.origin, stream=stream)
     for ip, (qp, bp) in enumerate(I.split(G, q, b)):
         sim.set_state(ip, qp, bp)
     if tuning:
@@ -158,8 +158,10 @@ def run_precision(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps, tuning
     if kern:
         kern = {c: v / prof_steps for c, v in kern.items()}
     tot, dn, dr, nfl = sim.diagnostics()
+    nprot = sim.protected_faces()
     sim.close()
-    return ms, wall, kern, {"max_divb_norm": dn, "max_divb_raw": dr, "floors": nfl, "tuning": W.tuning_to_str(tuning)}
+    return ms, wall, kern, {"max_divb_norm": dn, "max_divb_raw": dr, "floors": nfl, "protected_faces": nprot,
+                            "tuning": W.tuning_to_str(tuning)}
 
 
 def main():
@@ -174,6 +176,9 @@ def main():
     ap.add_argument("--tuning32", default="", help="sweep shapes for FP32 (e.g. 1x32=16,...); default: autotune")
     ap.add_argument("--tuning64", default="", help="sweep shapes for FP64; default: autotune")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven 400-patch batch (reported beside)")
+    ap.add_argument("--protection", action="store_true",
+                    help="also time the Mach-5 lognormal-density batch (384^3 as 512 x 48^3, FP32) with the protection "
+                         "floors off and on (reported beside)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -239,6 +244,23 @@ def main():
                   "value": Gu.zones() * args.steps / (msu / 1e3), "kernels_ms": kernu, **diagu}
         log("bench: uneven FP32 %.3f ms/step, %.3e zone-updates/s" % (msu / args.steps, uneven["value"]))
 
+    protection = None
+    if args.protection:
+        Nh = 384
+        Gh = I.uniform_grid(Nh, 48)
+        log("bench: Mach-5 lognormal batch %d^3 as %d x 48^3" % (Nh, Gh.npatch))
+        qh, bh = I.high_contrast_turbulence(Nh)
+        protection = {"workload": "Mach-5 solenoidal turbulence, lognormal rho (sigma 1.5), beta 1, %d^3 as %d "
+                                  "patches of 48^3, ghost %d, FP32, floors 1e-8" % (Nh, Gh.npatch, g)}
+        for tag, pf in (("off", 0.0), ("on", 1e-4)):
+            msh, _, kernh, diagh = run_precision(W, Gh, qh, bh, (1.0 / Nh,) * 3, W.WMB_FP32, g, 10, args.warmup, 1,
+                                                 rho_floor=1e-8, p_floor=1e-8, rho_protect=pf, p_protect=pf)
+            protection[tag] = {"protect_floor": pf, "ms_per_step": msh / 10, "value": Gh.zones() * 10 / (msh / 1e3),
+                               "kernels_ms": kernh, **diagh}
+            log("bench: protection %s: %.3f ms/step, %d protected faces, %d floors" %
+                (tag, msh / 10, diagh["protected_faces"], diagh["floors"]))
+        del qh, bh
+
     if not kern32:  # counter-collection runs skip the per-kernel pass
         print(json.dumps({"metric": METRIC, "value": value, "unit": "zone-updates/s", "partial": True}), flush=True)
         return
@@ -291,6 +313,7 @@ def main():
         "fp32_diag": diag32,
         "fp64": fp64,
         "uneven_fp32": uneven,
+        "protection_fp32": protection,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
