@@ -597,6 +597,25 @@ void orc_set_state(orc_sim *S, int ip, const double *q, const double *b)
                 for (int c = 0; c < 8; c++) pt->q[c * pt->vol + dst] = q[c * n3 + src];
                 for (int c = 0; c < 3; c++) pt->b[c * pt->vol + dst] = b[c * n3 + src];
             }
+    /* A patch owns its right face along an axis that ends at a domain
+       boundary (no neighbour owns it): it starts as a copy of the face to its
+       left (zero gradient, as the ghosts beyond it). */
+    for (int a = 0; a < 3; a++) {
+        int fo[3] = {0, 0, 0};
+        fo[a] = 1;
+        if (pt->nbr[9 * (fo[2] + 1) + 3 * (fo[1] + 1) + (fo[0] + 1)] >= 0) continue;
+        int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
+        for (int t2 = 0; t2 < pt->n[a2]; t2++)
+            for (int t1 = 0; t1 < pt->n[a1]; t1++) {
+                int c3[3];
+                c3[a1] = t1 + g;
+                c3[a2] = t2 + g;
+                c3[a] = pt->n[a] + g;
+                size_t dst = IDX(pt, c3[0], c3[1], c3[2]);
+                c3[a] -= 1;
+                pt->b[a * pt->vol + dst] = pt->b[a * pt->vol + IDX(pt, c3[0], c3[1], c3[2])];
+            }
+    }
 }
 
 void orc_get_state(const orc_sim *S, int ip, double *q, double *b)
@@ -634,6 +653,15 @@ void orc_set_stored(orc_sim *S, int ip, const double *q, const double *b)
 /* Ghost exchange: every ghost zone (and ghost face) of a patch is a copy of the
    interior zone (face) of the neighbour that covers it; the patch's right
    boundary face along an axis is the neighbour's own left face. */
+/*
+ * Ghost exchange (Sect. 4.1): every ghost zone and ghost face takes the value
+ * of the zone or face that covers it in the domain.  Along an axis whose
+ * neighbour entry is -1 (a domain boundary) the domain is extended by zero
+ * gradient (outflow): the index is clamped to the boundary zone, and for the
+ * face field normal to that axis to the boundary face, which the patch then
+ * owns.  The offsets left after clamping name the neighbour that covers the
+ * ghost (a face, edge or corner neighbour, or the patch itself).
+ */
 void orc_fill_ghosts(orc_sim *S)
 {
     int g = S->P.ghost;
@@ -642,24 +670,44 @@ void orc_fill_ghosts(orc_sim *S)
         for (int k = 0; k < pt->N[2]; k++)
             for (int j = 0; j < pt->N[1]; j++)
                 for (int i = 0; i < pt->N[0]; i++) {
-                    int r[3] = {i - g, j - g, k - g}, off[3], src[3];
+                    int r[3] = {i - g, j - g, k - g}, off[3];
                     int interior = 1;
                     for (int a = 0; a < 3; a++) {
                         off[a] = (r[a] < 0) ? -1 : (r[a] >= pt->n[a] ? 1 : 0);
                         if (off[a]) interior = 0;
                     }
                     if (interior) continue;
+                    /* clamp along axes that end at a domain boundary */
+                    int rz[3], rf[3]; /* zone-field index, and face index along the same axis */
+                    for (int a = 0; a < 3; a++) {
+                        rz[a] = r[a];
+                        rf[a] = r[a];
+                        if (off[a] == 0) continue;
+                        int fo[3] = {0, 0, 0};
+                        fo[a] = off[a];
+                        int face_nb = pt->nbr[9 * (fo[2] + 1) + 3 * (fo[1] + 1) + (fo[0] + 1)];
+                        if (face_nb < 0) {
+                            rz[a] = off[a] < 0 ? 0 : pt->n[a] - 1;
+                            rf[a] = off[a] < 0 ? 0 : pt->n[a];
+                            off[a] = 0;
+                        }
+                    }
                     int nb = pt->nbr[9 * (off[2] + 1) + 3 * (off[1] + 1) + (off[0] + 1)];
                     const orc_patch *qn = &S->p[nb];
+                    /* source index for the zone fields and for each face component */
+                    int sz[3], sf[3][3];
                     for (int a = 0; a < 3; a++) {
-                        if (off[a] < 0) src[a] = r[a] + qn->n[a];
-                        else if (off[a] > 0) src[a] = r[a] - pt->n[a];
-                        else src[a] = r[a];
+                        int shift = off[a] < 0 ? qn->n[a] : (off[a] > 0 ? -pt->n[a] : 0);
+                        sz[a] = rz[a] + shift;
+                        for (int c = 0; c < 3; c++) sf[c][a] = (c == a ? rf[a] : rz[a]) + shift;
                     }
                     size_t d = IDX(pt, i, j, k);
-                    size_t s = IDX(qn, src[0] + g, src[1] + g, src[2] + g);
+                    size_t s = IDX(qn, sz[0] + g, sz[1] + g, sz[2] + g);
                     for (int c = 0; c < 8; c++) pt->q[c * pt->vol + d] = qn->q[c * qn->vol + s];
-                    for (int c = 0; c < 3; c++) pt->b[c * pt->vol + d] = qn->b[c * qn->vol + s];
+                    for (int c = 0; c < 3; c++) {
+                        size_t sc = IDX(qn, sf[c][0] + g, sf[c][1] + g, sf[c][2] + g);
+                        pt->b[c * pt->vol + d] = qn->b[c * qn->vol + sc];
+                    }
                 }
     }
 }

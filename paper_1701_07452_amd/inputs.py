@@ -33,11 +33,12 @@ GAMMA = 5.0 / 3.0
 
 @dataclass
 class PatchGrid:
-    """Tensor-product tiling of a periodic box into patches.
+    """Tensor-product tiling of a box into patches.
 
     sizes[a] lists the interior edge length of each slab along axis a (x, y, z).
     Patch id = (kz * py + jy) * px + ix.  nbr[27] follows the offset order
-    9 (dz+1) + 3 (dy+1) + (dx+1), periodic.
+    9 (dz+1) + 3 (dy+1) + (dx+1); periodic axes wrap, along the others an
+    offset that leaves the box is -1 (a domain boundary, outflow).
     """
     sizes: tuple
     descs: list = field(default_factory=list)
@@ -61,7 +62,7 @@ class PatchGrid:
         return int(np.prod(self.shape))
 
 
-def patch_grid(sizes_x, sizes_y, sizes_z) -> PatchGrid:
+def patch_grid(sizes_x, sizes_y, sizes_z, periodic=(True, True, True)) -> PatchGrid:
     sizes = (tuple(int(s) for s in sizes_x), tuple(int(s) for s in sizes_y), tuple(int(s) for s in sizes_z))
     G = PatchGrid(sizes)
     px, py, pz = G.nblocks
@@ -74,20 +75,22 @@ def patch_grid(sizes_x, sizes_y, sizes_z) -> PatchGrid:
                 for dz in (-1, 0, 1):
                     for dy in (-1, 0, 1):
                         for dx in (-1, 0, 1):
-                            nbr.append((((kz + dz) % pz) * py + (jy + dy) % py) * px + (ix + dx) % px)
+                            c = [ix + dx, jy + dy, kz + dz]
+                            inside = all(periodic[a] or 0 <= c[a] < (px, py, pz)[a] for a in range(3))
+                            nbr.append((((kz + dz) % pz) * py + (jy + dy) % py) * px + (ix + dx) % px if inside else -1)
                 G.descs.append((n, nbr))
                 G.origin.append((int(offs[0][ix]), int(offs[1][jy]), int(offs[2][kz])))
     return G
 
 
-def uniform_grid(N, n) -> PatchGrid:
+def uniform_grid(N, n, periodic=(True, True, True)) -> PatchGrid:
     """N^3 box (N may be a 3-tuple x,y,z) cut into patches of edge n (tuple ok)."""
     Nt = (N, N, N) if np.isscalar(N) else tuple(N)
     nt = (n, n, n) if np.isscalar(n) else tuple(n)
     for a in range(3):
         if Nt[a] % nt[a]:
             raise ValueError("box not divisible by patch size")
-    return patch_grid([nt[0]] * (Nt[0] // nt[0]), [nt[1]] * (Nt[1] // nt[1]), [nt[2]] * (Nt[2] // nt[2]))
+    return patch_grid([nt[0]] * (Nt[0] // nt[0]), [nt[1]] * (Nt[1] // nt[1]), [nt[2]] * (Nt[2] // nt[2]), periodic)
 
 
 def uneven_grid(nb=(8, 10, 5), choices=(16, 24, 32, 48, 64), seed=170107453) -> PatchGrid:
