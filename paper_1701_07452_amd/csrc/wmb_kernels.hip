@@ -46,6 +46,12 @@ __device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
 // reciprocal away from denormals; FP64: exact zero test)
 __device__ __forceinline__ float alpha_min(float) { return 1e-30f; }
 __device__ __forceinline__ double alpha_min(double) { return 0.0; }
+// the limiter's gamma = dg / alpha.  FP64 divides: for a denormal alpha the
+// reciprocal overflows to inf and 0 * inf would give NaN, while the quotient
+// is finite (0 for dg = 0).  FP32 multiplies by the hardware reciprocal
+// (alpha_min keeps alpha normal).
+__device__ __forceinline__ float gdiv(float dg, float alpha) { return dg * frcp(alpha); }
+__device__ __forceinline__ double gdiv(double dg, double alpha) { return dg / alpha; }
 
 template <typename R>
 __device__ __forceinline__ R sgn1(R x) { return x >= R(0) ? R(1) : R(-1); }
@@ -200,15 +206,19 @@ __global__ void __launch_bounds__(256) fill_pass_kernel(R* __restrict__ pool, co
     const WorkItem w = work[blockIdx.x];
     if (w.patch < 0) return;  // padding item (whole block)
     const PatchDev D = patches[w.patch];
+    // along a later pass's axis that ends at a domain boundary on the right,
+    // the rows reach the boundary face n the patch owns: that later pass
+    // copies the normal face there onto itself, so it must be in place
+    const int wy = D.nb[3] < 0, wz = D.nb[5] < 0;
     int ex, ey, ez;
     if (AX == 0) {
         ex = 2 * g;
-        ey = D.n[1];
-        ez = D.n[2];
+        ey = D.n[1] + wy;
+        ez = D.n[2] + wz;
     } else if (AX == 1) {
         ex = D.N[0];
         ey = 2 * g;
-        ez = D.n[2];
+        ez = D.n[2] + wz;
     } else {
         ex = D.N[0];
         ey = D.N[1];
@@ -234,19 +244,25 @@ __global__ void __launch_bounds__(256) fill_pass_kernel(R* __restrict__ pool, co
         d[1] = p.j;
         d[2] = side ? D.n[2] + p.k : p.k;
     }
-    const PatchDev S = patches[D.nb[2 * AX + side]];
+    // a domain boundary (no neighbour, -1): zero-gradient extension from the
+    // patch itself, the normal face field from the boundary face it owns
+    const int nbq = D.nb[2 * AX + side];
+    const bool wall = nbq < 0;
+    const PatchDev S = wall ? D : patches[nbq];
     s[0] = d[0];
     s[1] = d[1];
     s[2] = d[2];
     // left ghost r = d - g < 0 comes from the neighbour's r + n_src; right ghost
     // r >= n_dst from the neighbour's r - n_dst
-    s[AX] = side ? d[AX] - D.n[AX] : d[AX] + S.n[AX];
+    s[AX] = wall ? (side ? g + D.n[AX] - 1 : g) : (side ? d[AX] - D.n[AX] : d[AX] + S.n[AX]);
     const long long di = sidx(D, d[0], d[1], d[2]);
     const long long si = sidx(S, s[0], s[1], s[2]);
+    const long long sif = wall && side ? si + stride_of(D, AX) : si;  // boundary face n for b_AX
     R* dbase = pool + D.base + (long long)(cur ? F_ST1 : F_ST0) * D.vol;
     const R* sbase = pool + S.base + (long long)(cur ? F_ST1 : F_ST0) * S.vol;
 #pragma unroll
-    for (int c = 0; c < 11; c++) dbase[(long long)c * D.vol + di] = sbase[(long long)c * S.vol + si];
+    for (int c = 0; c < 11; c++)
+        dbase[(long long)c * D.vol + di] = sbase[(long long)c * S.vol + (c == 8 + AX ? sif : si)];
 }
 
 // ---------------------------------------------------------------------------
@@ -718,14 +734,17 @@ __global__ void __launch_bounds__(TILE_THREADS) update_kernel(R* __restrict__ po
             for (int c = 0; c < 8; c++) bstore(u[c], rs, xo, qn + c * VB);
             // ghost exchange along x, pushed: the first and last g zones of an
             // interior row are the x-ghosts of the -x and +x neighbours (same
-            // row and plane, face neighbours share the y-z extent)
+            // row and plane, face neighbours share the y-z extent); at a domain
+            // boundary (no neighbour) the boundary zone fills the patch's own
+            // x-ghosts by zero gradient, b_x from the boundary face
             const int gi = i0 + zi;
-            if (gi < g || gi >= P.n[0] - g) {
-                const bool left = gi < g;
 #pragma unroll
-                for (int side = 0; side < 2; side++) {
-                    if (side == 0 ? !left : !(gi >= P.n[0] - g)) continue;
-                    const PatchDev Q = patches[P.nb[side]];
+            for (int side = 0; side < 2; side++) {
+                const bool mine = side == 0 ? gi < g : gi >= P.n[0] - g;
+                if (!mine) continue;
+                const int nbq = P.nb[side];
+                if (nbq >= 0) {
+                    const PatchDev Q = patches[nbq];
                     const int qi = side == 0 ? Q.n[0] + gi : gi - P.n[0];
                     const unsigned QB = (unsigned)Q.vol * ES;
                     const __amdgpu_buffer_rsrc_t rq = patch_rsrc(pool + Q.base, (unsigned)F_TOTAL * QB);
@@ -736,6 +755,23 @@ __global__ void __launch_bounds__(TILE_THREADS) update_kernel(R* __restrict__ po
                     bstore(bxl, rq, yo, qq + 8 * QB);
                     bstore(byl, rq, yo, qq + 9 * QB);
                     bstore(bzl, rq, yo, qq + 10 * QB);
+                    // the upper y and z faces of the last row / plane: the
+                    // boundary faces a wall-ended axis owns (elsewhere the
+                    // y/z exchange overwrites them)
+                    if (j0 + zj == P.n[1] - 1) bstore(byr, rq, yo + (unsigned)Q.N[0] * ES, qq + 9 * QB);
+                    if (k == P.n[2] - 1) bstore(bzr, rq, yo + (unsigned)(Q.N[0] * Q.N[1]) * ES, qq + 10 * QB);
+                } else if (gi == (side == 0 ? 0 : P.n[0] - 1)) {
+                    const R bxg = side == 0 ? bxl : bxr;  // the boundary face
+                    for (int m = 1; m <= g; m++) {
+                        const unsigned yo = side == 0 ? xo - (unsigned)m * s0 : xo + (unsigned)m * s0;
+#pragma unroll
+                        for (int c = 0; c < 8; c++) bstore(u[c], rs, yo, qn + c * VB);
+                        bstore(byl, rs, yo, bn + VB);
+                        bstore(bzl, rs, yo, bn + 2 * VB);
+                        if (side == 0 || m >= 2) bstore(bxg, rs, yo, bn);  // face n itself is stored above
+                        if (j0 + zj == P.n[1] - 1) bstore(byr, rs, yo + s1, bn + VB);
+                        if (k == P.n[2] - 1) bstore(bzr, rs, yo + s2, bn + 2 * VB);
+                    }
                 }
             }
             double ud[8];
@@ -1085,7 +1121,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
             R gp = Gp.v[k];
             R gL = sweby<MM>(g0, gm, cf.beta_l);  // zone s-1: faces s-1 (left), s (right)
             R gR = sweby<MM>(gp, g0, cf.beta_l);  // zone s: faces s, s+1
-            R gk = (fabs(alpha[k]) > alpha_min(alpha[k])) ? (gR - gL) * frcp(alpha[k]) : R(0);
+            R gk = (fabs(alpha[k]) > alpha_min(alpha[k])) ? gdiv(gR - gL, alpha[k]) : R(0);
             bet[k] = qvisc(nu[k] + gk, cf.eps[k], cf.q4e[k]) * alpha[k] - (gL + gR);
         }
         // correction sum_k beta_k R_k in (rho, v, B_t, P), then mapped to conserved

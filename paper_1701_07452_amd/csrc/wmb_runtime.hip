@@ -238,11 +238,24 @@ int check_table(int32_t np, const wmb_patch_desc* d, int g, size_t es, std::stri
         }
         for (int t = 0; t < 27; t++) {
             int q = d[i].nbr[t];
-            if (q < 0 || q >= np) {
+            int off[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
+            // edge and corner neighbours are reached through face neighbours
+            // (z, then y, then x): the ghost exchange copies along that chain;
+            // a step that leaves the domain (-1, a domain boundary) makes the
+            // entry -1
+            int r = i;
+            if (off[2] && r >= 0) r = d[r].nbr[9 * (off[2] + 1) + 4];
+            if (off[1] && r >= 0) r = d[r].nbr[9 + 3 * (off[1] + 1) + 1];
+            if (off[0] && r >= 0) r = d[r].nbr[12 + off[0] + 1];
+            if (q < -1 || q >= np) {
                 why = "patch " + std::to_string(i) + ": neighbour id out of range";
                 return WMB_EINVAL;
             }
-            int off[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
+            if (r != q) {
+                why = "patch " + std::to_string(i) + ": edge/corner neighbour inconsistent with the face neighbours";
+                return WMB_EINVAL;
+            }
+            if (q < 0) continue;
             for (int a = 0; a < 3; a++)
                 if (off[a] == 0 && d[q].n[a] != d[i].n[a]) {
                     why = "patch " + std::to_string(i) + ": neighbour " + std::to_string(q) + " extent mismatch";
@@ -252,16 +265,6 @@ int check_table(int32_t np, const wmb_patch_desc* d, int g, size_t es, std::stri
             int back = 9 * (1 - off[2]) + 3 * (1 - off[1]) + (1 - off[0]);
             if (d[q].nbr[back] != i) {
                 why = "patch " + std::to_string(i) + ": neighbour table not symmetric";
-                return WMB_EINVAL;
-            }
-            // edge and corner neighbours are reached through face neighbours
-            // (z, then y, then x): the ghost exchange copies along that chain
-            int r = i;
-            if (off[2]) r = d[r].nbr[9 * (off[2] + 1) + 4];
-            if (off[1]) r = d[r].nbr[9 + 3 * (off[1] + 1) + 1];
-            if (off[0]) r = d[r].nbr[12 + off[0] + 1];
-            if (r != q) {
-                why = "patch " + std::to_string(i) + ": edge/corner neighbour inconsistent with the face neighbours";
                 return WMB_EINVAL;
             }
         }
@@ -405,9 +408,12 @@ int build_fill_lists(wmb_ctx* c) {
         std::vector<WorkItem> items;
         for (int p = 0; p < c->npatch; p++) {
             const int* n = c->desc[p].n;
+            // rows reach the owned boundary face along a later axis that ends
+            // at a domain boundary on the right (the kernel's extents)
+            const int wy = c->hpatch[p].nb[3] < 0, wz = c->hpatch[p].nb[5] < 0;
             long long e;
-            if (ax == 0) e = 2LL * g * n[1] * n[2];
-            else if (ax == 1) e = 2LL * g * (n[0] + 2 * g) * n[2];
+            if (ax == 0) e = 2LL * g * (n[1] + wy) * (n[2] + wz);
+            else if (ax == 1) e = 2LL * g * (n[0] + 2 * g) * (n[2] + wz);
             else e = 2LL * g * (n[0] + 2 * g) * (n[1] + 2 * g);
             int nb = (int)((e + 255) / 256);
             for (int b = 0; b < nb; b++) items.push_back(WorkItem{p, b, 0, 0});
@@ -570,6 +576,22 @@ int set_state_t(wmb_ctx* c, int ip, const double* q, const double* b) {
     for (int f = 0; f < 11; f++) {
         const double* src = f < 8 ? q + f * n3 : b + (f - 8) * n3;
         to_device_layout<R>(src, buf.data(), P, g, n3);
+        const int a = f - 8;
+        if (a >= 0 && P.nb[2 * a + 1] < 0) {
+            // the patch owns its right face along an axis that ends at a domain
+            // boundary: it starts as a copy of the face to its left
+            const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
+            const long long st = a == 0 ? 1LL : (a == 1 ? (long long)P.N[0] : (long long)P.N[0] * P.N[1]);
+            for (int t2 = 0; t2 < P.n[a2]; t2++)
+                for (int t1 = 0; t1 < P.n[a1]; t1++) {
+                    int c3[3];
+                    c3[a] = g + P.n[a];
+                    c3[a1] = g + t1;
+                    c3[a2] = g + t2;
+                    const long long x = ((long long)c3[2] * P.N[1] + c3[1]) * P.N[0] + c3[0];
+                    buf[(size_t)x] = buf[(size_t)(x - st)];
+                }
+        }
         CKH(hipMemcpyAsync(base + (long long)f * P.vol, buf.data(), sizeof(R) * P.vol, hipMemcpyHostToDevice, c->stream));
         CKH(hipStreamSynchronize(c->stream));
     }

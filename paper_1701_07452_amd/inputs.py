@@ -429,6 +429,25 @@ def orszag_tang_3d(N, gamma=GAMMA):
     return q, b
 
 
+def orszag_tang_2d(N, nz=5, gamma=GAMMA):
+    """The planar Orszag-Tang vortex (Sect. 6) on the unit square, as a box
+    N x N x nz with zones of 1/N (periodic; every z-plane the same):
+    v = (-sin 2pi y, sin 2pi x, 0), rho = 25/(36 pi), P = 5/(12 pi), field
+    from the edge potential A_z = (4 pi)^-1/2 [cos(2 pi y)/(2 pi) + cos(4 pi x)/(4 pi)]."""
+    shape = (nz, N, N)
+    dx = (1.0 / N,) * 3
+    (xc, yc, zc), (xf, yf, zf) = coords(shape, dx)
+    B0 = 1.0 / math.sqrt(4.0 * math.pi)
+    Zc, Yf, Xf = np.meshgrid(zc, yf, xf, indexing="ij")
+    Az = B0 * (np.cos(2 * math.pi * Yf) / (2 * math.pi) + np.cos(4 * math.pi * Xf) / (4 * math.pi))
+    zero = np.zeros(shape)
+    b = curl_of_edge_potential(zero, zero, Az, dx)
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    v = [-np.sin(2 * math.pi * Y), np.sin(2 * math.pi * X), zero]
+    q = conserved(np.full(shape, 25.0 / (36.0 * math.pi)), v, face_average(b), 5.0 / (12.0 * math.pi), gamma)
+    return q, b
+
+
 def random_smooth(shape, seed, dx=None, amp=0.1, nmodes=3, gamma=GAMMA, B0=(0.7, -0.4, 0.5)):
     """Smooth random state on a periodic box: a few low Fourier modes of random
     amplitude in rho, v, P and in an edge vector potential (so div b = 0)."""
