@@ -124,7 +124,7 @@ def cpu_baseline(q, b, G, dx, ghost, budget_s=12.0):
     }
 
 
-def run_precision(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps, tuning=None, **params):
+def run_precision(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps, tuning=None, freeze=(), **params):
     import torch
 
     from paper_1701_07452_amd import inputs as I
@@ -138,8 +138,17 @@ def run_precision(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps, tuning
     else:
         tuning = sim.autotune(reps=3)
     log("bench: pencils per block %s" % W.tuning_to_str(tuning))
-    sim.run_steps(max(warmup, 1))
+    sim.run_steps(max(warmup, 1))  # captures the graphs
     stream.synchronize()
+    freeze_ms = None
+    if freeze:
+        # freeze patches between graph replays: the same graphs run on
+        t0 = time.perf_counter()
+        for ip in freeze:
+            sim.set_active(ip, False)
+        freeze_ms = (time.perf_counter() - t0) * 1e3 / len(freeze)
+        sim.run_steps(1)
+        stream.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -160,8 +169,9 @@ def run_precision(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps, tuning
     tot, dn, dr, nfl = sim.diagnostics()
     nprot = sim.protected_faces()
     sim.close()
+    extra = {"freeze_ms_per_patch": freeze_ms} if freeze else {}
     return ms, wall, kern, {"max_divb_norm": dn, "max_divb_raw": dr, "floors": nfl, "protected_faces": nprot,
-                            "tuning": W.tuning_to_str(tuning)}
+                            "tuning": W.tuning_to_str(tuning), **extra}
 
 
 def main():
@@ -179,6 +189,8 @@ def main():
     ap.add_argument("--protection", action="store_true",
                     help="also time the Mach-5 lognormal-density batch (384^3 as 512 x 48^3, FP32) with the protection "
                          "floors off and on (reported beside)")
+    ap.add_argument("--frozen", action="store_true",
+                    help="also time the FP32 batch with every other patch frozen (checkerboard), graphs reused")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -261,6 +273,20 @@ def main():
                 (tag, msh / 10, diagh["protected_faces"], diagh["floors"]))
         del qh, bh
 
+    frozen = None
+    if args.frozen:
+        px, py, pz = G.nblocks
+        half = [(k * py + j) * px + i for k in range(pz) for j in range(py) for i in range(px) if (i + j + k) % 2]
+        log("bench: FP32 batch with %d of %d patches frozen" % (len(half), G.npatch))
+        msf, _, kernf, diagf = run_precision(W, G, q, b, dx, W.WMB_FP32, g, args.steps, args.warmup, 1,
+                                             W.tuning_from_str(args.tuning32) or None, freeze=half)
+        active = zones - len(half) * n ** 3
+        frozen = {"workload": "the FP32 batch with every other patch (checkerboard) frozen after graph capture",
+                  "frozen_patches": len(half), "active_zones": active, "ms_per_step": msf / args.steps,
+                  "value": active * args.steps / (msf / 1e3), "kernels_ms": kernf, **diagf}
+        log("bench: frozen half: %.3f ms/step, %.3e active zone-updates/s, %.2f ms per set_active" %
+            (msf / args.steps, frozen["value"], diagf["freeze_ms_per_patch"]))
+
     if not kern32:  # counter-collection runs skip the per-kernel pass
         print(json.dumps({"metric": METRIC, "value": value, "unit": "zone-updates/s", "partial": True}), flush=True)
         return
@@ -314,6 +340,7 @@ def main():
         "fp64": fp64,
         "uneven_fp32": uneven,
         "protection_fp32": protection,
+        "frozen_half_fp32": frozen,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -181,6 +181,20 @@ int wmb_autotune(wmb_ctx *c, int32_t reps, int32_t *chosen, int32_t nchosen);
    Invalidates the captured graphs. */
 int wmb_set_tuning(wmb_ctx *c, const int32_t *quads, int32_t n);
 
+/* Freeze (active = 0) or thaw (active != 0) one patch without touching the
+   launch plan or the captured graphs (Sect. 2.1: patches may become
+   inactive, left out of the update, for load balancing and mesh refinement;
+   here its pool memory stays reserved).  A frozen
+   patch keeps its state: no kernel updates it, it adds nothing to the CFL
+   maximum or to the floor and protection counters, and it serves its
+   neighbours as fixed ghost data (its work items exit at once).  Its state
+   then reads the same in both internal state copies, which freezing
+   establishes by refreshing every ghost and copying the patch's stored box;
+   wmb_set_state on a frozen patch does the same.  The face it shares with an
+   active neighbour stays the frozen patch's.  Diagnostics still cover every
+   patch.  All patches start active.  Synchronous. */
+int wmb_set_active(wmb_ctx *c, int32_t patch, int32_t active);
+
 /* Debugging: with on != 0, later steps also store the Step-9 edge EMFs in
    device memory for wmb_debug_stage (the fused Steps 8-11 otherwise keep
    them on chip).  Default off.  Invalidates the captured graphs when it

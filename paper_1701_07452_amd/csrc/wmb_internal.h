@@ -48,8 +48,8 @@ struct Coef {
 struct PatchDev {
     int n[3];
     int N[3];
-    int nb[6];  // face neighbours: -x, +x, -y, +y, -z, +z
-    int pad_;
+    int nb[6];   // face neighbours: -x, +x, -y, +y, -z, +z (-1: domain boundary)
+    int active;  // 0: frozen (no kernel updates it; its state is the same in both copies)
     long long base;
     long long vol;
 };

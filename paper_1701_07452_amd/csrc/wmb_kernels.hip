@@ -317,6 +317,7 @@ __global__ void __launch_bounds__(256) dt_reduce_kernel(const R* __restrict__ po
     const WorkItem w = work[blockIdx.x];
     if (w.patch < 0) return;  // padding item (whole block)
     const PatchDev P = patches[w.patch];
+    if (!P.active) return;  // frozen patch (whole block)
     BoxPos bp = box_pos(P, w.a, Box{0, -1});
     double s = 0.0;
     if (bp.valid) {
@@ -416,6 +417,7 @@ __global__ void __launch_bounds__(TILE_THREADS) ct_half_kernel(R* __restrict__ p
     const WorkItem w = work[blockIdx.x];
     if (w.patch < 0) return;  // padding item (whole block)
     const PatchDev P = patches[w.patch];
+    if (!P.active) return;  // frozen patch (whole block, before any barrier)
     const int i0 = (w.a & 0xffff) - TILE_BIAS, j0 = (w.a >> 16) - TILE_BIAS;
     const int tx = w.b & 0xffff, ty = w.b >> 16;
     const int k0 = (w.c & 0xffff) - TILE_BIAS, k1 = (w.c >> 16) - TILE_BIAS;
@@ -549,6 +551,7 @@ __global__ void __launch_bounds__(TILE_THREADS) update_kernel(R* __restrict__ po
     const WorkItem w = work[blockIdx.x];
     if (w.patch < 0) return;  // padding item (whole block)
     const PatchDev P = patches[w.patch];
+    if (!P.active) return;  // frozen patch (whole block, before any barrier)
     const int i0 = (w.a & 0xffff) - TILE_BIAS, j0 = (w.a >> 16) - TILE_BIAS;
     const int tx = w.b & 0xffff, ty = w.b >> 16;
     const int k0 = (w.c & 0xffff) - TILE_BIAS, k1 = (w.c >> 16) - TILE_BIAS;
@@ -723,7 +726,9 @@ __global__ void __launch_bounds__(TILE_THREADS) update_kernel(R* __restrict__ po
             bstore(byl, rs, xo, bn + VB);
             bstore(bzl, rs, xo, bn + 2 * VB);
             // shared right faces of the patch
-            if (i0 + zi == P.n[0] - 1) bstore(bxr, rs, xo + s0, bn);
+            // (face n along x is the +x neighbour's face 0, which it writes
+            // here itself: pushed, or pulled below when it is frozen)
+            if (i0 + zi == P.n[0] - 1 && P.nb[1] < 0) bstore(bxr, rs, xo + s0, bn);
             if (j0 + zj == P.n[1] - 1) bstore(byr, rs, xo + s1, bn + VB);
             if (k == P.n[2] - 1) bstore(bzr, rs, xo + s2, bn + 2 * VB);
             u[4] = R(0.5) * (bxl + bxr);
@@ -760,6 +765,23 @@ __global__ void __launch_bounds__(TILE_THREADS) update_kernel(R* __restrict__ po
                     // y/z exchange overwrites them)
                     if (j0 + zj == P.n[1] - 1) bstore(byr, rq, yo + (unsigned)Q.N[0] * ES, qq + 9 * QB);
                     if (k == P.n[2] - 1) bstore(bzr, rq, yo + (unsigned)(Q.N[0] * Q.N[1]) * ES, qq + 10 * QB);
+                    if (!Q.active) {
+                        // a frozen neighbour pushes nothing: pull its zone into
+                        // this patch's own x-ghost (its state is the same in
+                        // both copies); the mirror image of the push above
+                        const int xs = side == 0 ? gi : gi + 2 * g;                    // own ghost, stored x
+                        const int xq = side == 0 ? Q.n[0] + gi : gi - P.n[0] + 2 * g;  // Q's zone, stored x
+                        const unsigned yq = (unsigned)sidx(Q, xq, j0 + zj + g, k + g) * ES;
+                        const unsigned yp = (unsigned)sidx(P, xs, j0 + zj + g, k + g) * ES;
+                        const unsigned qc = (unsigned)(cur ? F_ST1 : F_ST0) * QB;
+#pragma unroll
+                        for (int c = 0; c < 11; c++) bstore(bload(z0, rq, yq, qc + c * QB), rs, yp, qn + c * VB);
+                        if (j0 + zj == P.n[1] - 1)
+                            bstore(bload(z0, rq, yq + (unsigned)Q.N[0] * ES, qc + 9 * QB), rs, yp + s1, bn + VB);
+                        if (k == P.n[2] - 1)
+                            bstore(bload(z0, rq, yq + (unsigned)(Q.N[0] * Q.N[1]) * ES, qc + 10 * QB), rs, yp + s2,
+                                   bn + 2 * VB);
+                    }
                 } else if (gi == (side == 0 ? 0 : P.n[0] - 1)) {
                     const R bxg = side == 0 ? bxl : bxr;  // the boundary face
                     for (int m = 1; m <= g; m++) {
@@ -886,6 +908,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
     const WorkItem wi = work[blockIdx.x];
     if (wi.patch < 0) return;  // padding item (whole block, before any barrier)
     const PatchDev Pt = patches[wi.patch];
+    if (!Pt.active) return;  // frozen patch (whole block, before any barrier)
     // block (P, W) along x for D = x, (W, P) otherwise: consecutive lanes are
     // consecutive x either way
     const int s = (D == 0) ? (int)threadIdx.x : (int)threadIdx.y;

@@ -844,7 +844,7 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
         P.base = (long long)(off / c->esize);
         const int faces[6] = {12, 14, 10, 16, 4, 22};
         for (int t = 0; t < 6; t++) P.nb[t] = d[i].nbr[faces[t]];
-        P.pad_ = 0;
+        P.active = 1;
         off += region_bytes(d[i], g, c->esize);
     }
     int rc;
@@ -872,12 +872,16 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     return WMB_OK;
 }
 
+int freeze_sync(wmb_ctx* c, int patch);
+
 int wmb_set_state(wmb_ctx* c, int32_t patch, const double* q, const double* b) {
     if (!c) return WMB_EINVAL;
     if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
     if (patch < 0 || patch >= c->npatch || !q || !b) return fail(c, WMB_EINVAL, "bad patch or null array");
     c->xg_valid = false;  // the neighbours' x-ghosts of this patch are stale
-    return c->esize == 4 ? set_state_t<float>(c, patch, q, b) : set_state_t<double>(c, patch, q, b);
+    int rc = c->esize == 4 ? set_state_t<float>(c, patch, q, b) : set_state_t<double>(c, patch, q, b);
+    if (!rc && !c->hpatch[patch].active) rc = freeze_sync(c, patch);
+    return rc;
 }
 
 int wmb_get_state(wmb_ctx* c, int32_t patch, double* q, double* b) {
@@ -1007,6 +1011,43 @@ int wmb_set_tuning(wmb_ctx* c, const int32_t* quads, int32_t n) {
         }
     }
     free_graphs(c);
+    return WMB_OK;
+}
+
+// A frozen patch reads the same in both state copies, ghosts included, so
+// that its neighbours can pull from it whichever copy is current: refresh
+// every ghost of the current copy, then copy the patch's whole stored box
+// into the other one.
+int freeze_sync(wmb_ctx* c, int patch) {
+    const PatchDev& P = c->hpatch[patch];
+    int rc = dispatch_fill(c, FILL_ALL);
+    if (rc) return rc;
+    const size_t bytes = (size_t)11 * P.vol * c->esize;
+    char* pool = (char*)c->pool;
+    const long long cur0 = (long long)(c->cur ? F_ST1 : F_ST0), oth0 = (long long)(c->cur ? F_ST0 : F_ST1);
+    CKH(hipMemcpyAsync(pool + (P.base + oth0 * P.vol) * c->esize, pool + (P.base + cur0 * P.vol) * c->esize, bytes,
+                       hipMemcpyDeviceToDevice, c->stream));
+    CKH(hipStreamSynchronize(c->stream));
+    return WMB_OK;
+}
+
+int wmb_set_active(wmb_ctx* c, int32_t patch, int32_t active) {
+    if (!c) return WMB_EINVAL;
+    if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
+    if (patch < 0 || patch >= c->npatch) return fail(c, WMB_EINVAL, "bad patch");
+    PatchDev& P = c->hpatch[patch];
+    const int on = active != 0;
+    if (P.active == on) return WMB_OK;
+    if (!on) {
+        int rc = freeze_sync(c, patch);
+        if (rc) return rc;
+    }
+    P.active = on;
+    CKH(hipMemcpyAsync(c->d_patch + patch, &P, sizeof(PatchDev), hipMemcpyHostToDevice, c->stream));
+    CKH(hipStreamSynchronize(c->stream));
+    // the folded signal-speed maximum no longer covers the active set
+    if (c->smax_state == SMAX_CLEAN) c->smax_state = SMAX_DIRTY;
+    c->xg_valid = false;
     return WMB_OK;
 }
 

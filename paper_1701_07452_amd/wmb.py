@@ -21,8 +21,8 @@ WMB_FP64, WMB_FP32 = 0, 1
 EXPORTS = [
     "wmb_create", "wmb_pool_bytes", "wmb_init_patches", "wmb_set_state", "wmb_get_state", "wmb_get_stored",
     "wmb_fill_ghosts", "wmb_compute_dt", "wmb_advance", "wmb_run_steps", "wmb_diagnostics", "wmb_debug_stage",
-    "wmb_autotune", "wmb_set_tuning", "wmb_keep_stages", "wmb_profile_step", "wmb_destroy", "wmb_strerror",
-    "wmb_last_error",
+    "wmb_autotune", "wmb_set_tuning", "wmb_keep_stages", "wmb_set_active", "wmb_profile_step", "wmb_destroy",
+    "wmb_strerror", "wmb_last_error",
 ]
 KERNEL_CLASSES = ["fill", "dt", "sweep1_x", "sweep1_y", "sweep1_z", "ct_half",
                   "sweep2_x", "sweep2_y", "sweep2_z", "update"]
@@ -104,6 +104,7 @@ def load_library():
     lib.wmb_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.c_int32]
     lib.wmb_set_tuning.argtypes = [vp, C.POINTER(C.c_int32), C.c_int32]
     lib.wmb_keep_stages.argtypes = [vp, C.c_int32]
+    lib.wmb_set_active.argtypes = [vp, C.c_int32, C.c_int32]
     lib.wmb_destroy.argtypes = [vp]
     lib.wmb_strerror.argtypes = [C.c_int]
     lib.wmb_strerror.restype = C.c_char_p
@@ -262,6 +263,10 @@ class Sim:
         flat = [v for (st, ax, e), W in sorted(tuning.items()) for v in (st, ax, e, W)]
         buf = (C.c_int32 * max(len(flat), 1))(*flat)
         self._check(self.lib.wmb_set_tuning(self.h, buf, len(flat)))
+
+    def set_active(self, ip, on=True):
+        """Freeze (on=False) or thaw a patch; the captured graphs stay valid."""
+        self._check(self.lib.wmb_set_active(self.h, int(ip), 1 if on else 0))
 
     def keep_stages(self, on=True):
         """Let later steps store the Step-9 edges for debug_stage(6)."""
