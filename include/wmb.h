@@ -192,7 +192,9 @@ int wmb_set_tuning(wmb_ctx *c, const int32_t *quads, int32_t n);
    establishes by refreshing every ghost and copying the patch's stored box;
    wmb_set_state on a frozen patch does the same.  The face it shares with an
    active neighbour stays the frozen patch's.  Diagnostics still cover every
-   patch.  All patches start active.  Synchronous. */
+   patch.  With every patch frozen the CFL maximum is empty: dt comes out
+   +inf and steps change nothing.  All patches start active.  WMB_EINVAL for
+   a patch index out of range.  Synchronous. */
 int wmb_set_active(wmb_ctx *c, int32_t patch, int32_t active);
 
 /* Debugging: with on != 0, later steps also store the Step-9 edge EMFs in
