@@ -5,9 +5,10 @@
  * Steps 1-11) with the MHDTVD flux of Appendix A.
  *
  * The verbs follow the paper's statement of the problem (Sect. 2.1, 4.1): a
- * periodic world grid cut into patches with their own boundary zones; ghost
- * zones filled between patches; a global CFL reduction for dt (Sect. 4.1.1);
- * a solver that updates the patch arrays; state read back.
+ * world grid (periodic, or with outflow ends as in the shock tubes of Sect. 6)
+ * cut into patches with their own boundary zones; ghost zones filled between
+ * patches; a global CFL reduction for dt (Sect. 4.1.1); a solver that updates
+ * the patch arrays; state read back.
  *
  * Conventions shared by every entry point
  *   - Return value: WMB_OK (0) or a negative WMB_E* code.  Nothing aborts or
@@ -76,8 +77,10 @@ typedef struct wmb_patch_desc {
     int32_t n[3];      /* interior zones along x, y, z (each >= ghost) */
     int32_t nbr[27];   /* patch id at offset (dz,dy,dx) in {-1,0,1}^3, index
                           9(dz+1) + 3(dy+1) + (dx+1); the caller resolves
-                          periodic wrap; nbr[13] is the patch itself.  Face
-                          neighbours must share the face extent. */
+                          periodic wrap; nbr[13] is the patch itself; -1 where
+                          the offset leaves the domain (an outflow boundary:
+                          zero-gradient ghosts).  Face neighbours must share
+                          the face extent. */
     int64_t origin[3]; /* global zone offset (diagnostics only) */
 } wmb_patch_desc;
 
@@ -104,7 +107,11 @@ int wmb_init_patches(wmb_ctx *c, int32_t npatch, const wmb_patch_desc *d, void *
 
 /* Upload one patch's interior state (host arrays, layout above).  Rounds to
    FP32 in FP32 mode.  WMB_ESTATE if any value is non-finite, rho <= 0, or the
-   pressure (from E with the zone-centred field) is <= 0. */
+   pressure (from E with the zone-centred field) is <= 0.  Along an axis whose
+   +side is a domain boundary the patch owns its right face n (no neighbour
+   holds it): it starts as a copy of face n-1.  On a frozen patch (see
+   wmb_set_active) the call also refreshes every ghost and makes both internal
+   state copies equal. */
 int wmb_set_state(wmb_ctx *c, int32_t patch, const double *q, const double *b);
 
 /* Read one patch's interior state (and its own left faces) back to host
@@ -118,10 +125,14 @@ int wmb_get_stored(wmb_ctx *c, int32_t patch, double *q, double *b);
 /* Enqueue the ghost exchange (Sect. 4.1, local patch copies): every ghost
    zone and ghost face of every patch becomes a copy of the neighbour's
    interior value covering it; a patch's right-boundary face is the
-   neighbour's own left face.  Bitwise copies. */
+   neighbour's own left face.  Beyond a domain boundary (-1 in the table) a
+   ghost zone copies the nearest interior zone (its index clamped into
+   [0, n-1] along that axis) and the face component normal to the boundary
+   copies the boundary face (index clamped into [0, n]); edges and corners
+   compose the clamps axis by axis.  Bitwise copies. */
 int wmb_fill_ghosts(wmb_ctx *c);
 
-/* CFL reduction in FP64 over all interior zones:
+/* CFL reduction in FP64 over all interior zones of the active patches:
    dt = cfl * min_{zones, d} dx_d / (|v_d| + c_f,d), with c_f,d the fast speed
    (Sect. 5) taking B_d as the longitudinal field.  The result stays in device
    memory for wmb_advance(c, 0) / wmb_run_steps; if dt_out != NULL it is also
@@ -135,8 +146,10 @@ int wmb_compute_dt(wmb_ctx *c, double *dt_out);
    the last wmb_compute_dt.  Floors (rho_floor, p_floor) are applied in FP64
    and counted.  The step also writes the new state of the first and last
    ghost-width zones of every interior row into the x-neighbours' ghosts (the
-   x part of the next ghost exchange); other ghosts are left to
-   wmb_fill_ghosts. */
+   x part of the next ghost exchange; at a domain boundary the patch's own
+   x-ghosts by zero gradient; next to a frozen neighbour it copies that
+   neighbour's zones into its own x-ghosts instead); other ghosts are left to
+   wmb_fill_ghosts.  Frozen patches are not advanced. */
 int wmb_advance(wmb_ctx *c, double dt);
 
 /* nsteps x (fill ghosts, compute dt, advance) with dt kept on the device,
