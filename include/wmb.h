@@ -155,7 +155,10 @@ int wmb_advance(wmb_ctx *c, double dt);
 /* nsteps x (fill ghosts, compute dt, advance) with dt kept on the device,
    replayed from a captured HIP graph (captured on the first call).  The
    graph's ghost exchange runs the y and z passes only (the step before wrote
-   the x-ghosts); the x pass is enqueued first when the state was set since.
+   the x-ghosts), on a branch of its own beside the part of the Step-1 x sweep
+   whose pencils have interior transverse coordinates (the overlap of
+   exchange and interior work of Sect. 4); the x pass is enqueued first when
+   the state was set since.  Results are bitwise those of the eager calls.
    Enqueue only; this is the timed call. */
 int wmb_run_steps(wmb_ctx *c, int32_t nsteps);
 

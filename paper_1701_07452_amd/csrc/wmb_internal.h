@@ -70,10 +70,13 @@ enum : int {
 
 struct WorkItem {
     int patch;
-    int a;  // box kernels: block index in the patch; sweeps: first fast-transverse coord;
+    int a;  // box kernels: block index in the patch; sweeps: first pencil of the block
+            // (numbered fast-transverse first within the item's rectangle);
             // tiles: i0 | j0 << 16 (biased)
-    int b;  // sweeps: slow-transverse coord; tiles: tx | ty << 16
-    int c;  // sweeps: last fast-transverse coord (inclusive); tiles: k0 | k1 << 16 (biased, k1 exclusive)
+    int b;  // sweeps: the pencil rectangle, (flo + 512) | (slo + 512) << 10 | fcnt << 20
+            // (first fast and slow transverse coords, pencils along fast);
+            // tiles: tx | ty << 16
+    int c;  // sweeps: last pencil (inclusive); tiles: k0 | k1 << 16 (biased, k1 exclusive)
 };
 
 // Box kernels: interior-relative inclusive ranges [lo, n + hi] per axis.

@@ -894,7 +894,7 @@ template <typename R, int D, int STAGE, bool MM, bool PROT>
 __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
                                                      const WorkItem* __restrict__ work, DevParams prm, Coef<R> cf,
                                                      int cur, const StepConst* __restrict__ sc, int P, int W, int zlo,
-                                                     int tlo, int thi, unsigned long long* __restrict__ nprot) {
+                                                     unsigned long long* __restrict__ nprot) {
     extern __shared__ unsigned char smem_raw[];
     const int nthr = P * W;
     Rec8<R>* shp = reinterpret_cast<Rec8<R>*>(smem_raw);  // zone primitives
@@ -915,17 +915,19 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
     const int w = (D == 0) ? (int)threadIdx.y : (int)threadIdx.x;
     const int tid = (D == 0) ? s + P * w : w + W * s;
     const int sstep = (D == 0) ? 1 : W;  // LDS distance between neighbours along the pencil
-    const int pen = wi.a + w;            // pencil number in the patch
+    const int pen = wi.a + w;            // pencil number in the item's rectangle
     const bool live = pen <= wi.c;
-    const int tf = Pt.n[FA] + thi - tlo + 1;
+    // the item's rectangle of pencils in the transverse plane: tf pencils
+    // along the fast axis from flo, rows along the slow axis from slo
+    const int flo = (wi.b & 1023) - 512, slo = ((wi.b >> 10) & 1023) - 512, tf = wi.b >> 20;
     const int g = prm.ghost;
     // pen = slow * tf + fast; (pen + 1/2)/tf is at least 1/(2 tf) from an
     // integer, far above the error of the single-precision reciprocal
     const int slow = (int)(((float)pen + 0.5f) * __builtin_amdgcn_rcpf((float)tf));
     int zc[3];
     zc[D] = zlo + s;
-    zc[FA] = tlo + (pen - slow * tf);
-    zc[SA] = tlo + slow;
+    zc[FA] = flo + (pen - slow * tf);
+    zc[SA] = slo + slow;
     const unsigned V = (unsigned)Pt.vol;
     const unsigned st[3] = {1u, (unsigned)Pt.N[0], (unsigned)(Pt.N[0] * Pt.N[1])};
     const unsigned x = live ? (unsigned)(zc[0] + g) + st[1] * (unsigned)(zc[1] + g) + st[2] * (unsigned)(zc[2] + g) : 0u;
@@ -1332,7 +1334,7 @@ hipError_t launch_update(void* pool, const PatchDev* pt, const WorkItem* wk, int
 
 template <typename R>
 hipError_t launch_sweep(int d, int stage, void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm,
-                        const Coef<R>& cf, int cur, const StepConst* sc, int P, int W, int zlo, int tlo, int thi,
+                        const Coef<R>& cf, int cur, const StepConst* sc, int P, int W, int zlo,
                         unsigned long long* nprot, hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
     size_t shmem = sizeof(R) * 16 * (size_t)P * W;
@@ -1341,7 +1343,7 @@ hipError_t launch_sweep(int d, int stage, void* pool, const PatchDev* pt, const 
     const bool pr = cf.rho_prot > R(0) || cf.p_prot > R(0);
 #define WMB_SW1(DD, SS, MM, PR)                                                                                       \
     hipLaunchKernelGGL((sweep_kernel<R, DD, SS, MM, PR>), dim3(nblk), blk, shmem, st, (R*)pool, pt, wk, prm, cf, cur, sc, \
-                       P, W, zlo, tlo, thi, nprot)
+                       P, W, zlo, nprot)
 #define WMB_SW(DD, SS)                                                                                                \
     do {                                                                                                              \
         if (mm && !pr) WMB_SW1(DD, SS, true, false);                                                                  \
@@ -1383,8 +1385,8 @@ hipError_t launch_diag(const void* pool, const PatchDev* pt, const WorkItem* wk,
                                          int, const StepConst*, unsigned long long*, unsigned long long*, int,          \
                                          hipStream_t);                                                                   \
     template hipError_t launch_sweep<R>(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&,        \
-                                        const Coef<R>&, int, const StepConst*, int, int, int, int, int,                  \
-                                        unsigned long long*, hipStream_t);                                               \
+                                        const Coef<R>&, int, const StepConst*, int, int, int, unsigned long long*,       \
+                                        hipStream_t);                                                                    \
     template hipError_t launch_diag<R>(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,        \
                                        double*, hipStream_t);
 WMB_INST(float)

@@ -20,7 +20,7 @@ hipError_t launch_dt_finalize(unsigned long long*, StepConst*, const DevParams&,
 hipError_t launch_set_dt(StepConst*, double, const DevParams&, hipStream_t);
 template <typename R> hipError_t launch_ct_half(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int, const StepConst*, hipStream_t);
 template <typename R> hipError_t launch_update(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, unsigned long long*, unsigned long long*, int, hipStream_t);
-template <typename R> hipError_t launch_sweep(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, int, int, int, int, int, unsigned long long*, hipStream_t);
+template <typename R> hipError_t launch_sweep(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, int, int, int, unsigned long long*, hipStream_t);
 template <typename R> hipError_t launch_diag(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, double*, hipStream_t);
 }  // namespace wmb
 
@@ -35,7 +35,9 @@ struct DevList {
 
 struct SweepGroup {
     int P, W, zlo, tlo, thi, n;
-    DevList wl;
+    DevList wl;            // every pencil of the transverse range [tlo, n+thi]^2
+    DevList wl_in, wl_fr;  // Step-1 x sweep only: the pencils with both transverse
+                           // coords interior, and the frame around them
 };
 
 // What the device signal-speed maximum (smax) holds relative to the current state.
@@ -62,6 +64,10 @@ struct wmb_ctx {
     uint64_t pool_bytes = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // second stream and fork/join events of the captured step: the y/z ghost
+    // exchange runs beside the interior part of the Step-1 x sweep
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int cur = 0;
     PatchDev* d_patch = nullptr;
     DevList wl_fill[3];
@@ -305,16 +311,35 @@ int run_finalize(wmb_ctx* c) {
     return WMB_OK;
 }
 
+// One step.  split: the y/z ghost exchange was forked onto the side stream
+// (ev_join marks its end); the Step-1 x sweep first covers the pencils whose
+// transverse coords are interior, which read only the x-ghosts the previous
+// update wrote, then waits for the exchange and covers the frame.
 template <typename R>
-int run_step(wmb_ctx* c) {
+int run_step(wmb_ctx* c, bool split = false) {
     hipError_t e;
     const int cur = c->cur;
 #define STEPCK(what)                                                                        \
     if (e != hipSuccess) return fail(c, WMB_EHIP, std::string(what) + ": " + hipGetErrorString(e))
     for (int d = 0; d < 3; d++) {
+        if (split && d == 0) {
+            for (auto& G : c->sweeps[0][0]) {
+                e = launch_sweep<R>(0, 1, c->pool, c->d_patch, G.wl_in.d, G.wl_in.n, c->dp, coef<R>(c), cur, c->d_sc,
+                                    G.P, G.W, G.zlo, c->d_nfloor + 1, c->stream);
+                STEPCK("sweep1");
+            }
+            CKH(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+            for (auto& G : c->sweeps[0][0]) {
+                e = launch_sweep<R>(0, 1, c->pool, c->d_patch, G.wl_fr.d, G.wl_fr.n, c->dp, coef<R>(c), cur, c->d_sc,
+                                    G.P, G.W, G.zlo, c->d_nfloor + 1, c->stream);
+                STEPCK("sweep1");
+            }
+            mark(c);
+            continue;
+        }
         for (auto& G : c->sweeps[d][0]) {
             e = launch_sweep<R>(d, 1, c->pool, c->d_patch, G.wl.d, G.wl.n, c->dp, coef<R>(c), cur, c->d_sc, G.P, G.W,
-                                G.zlo, G.tlo, G.thi, c->d_nfloor + 1, c->stream);
+                                G.zlo, c->d_nfloor + 1, c->stream);
             STEPCK("sweep1");
         }
         mark(c);
@@ -325,7 +350,7 @@ int run_step(wmb_ctx* c) {
     for (int d = 0; d < 3; d++) {
         for (auto& G : c->sweeps[d][1]) {
             e = launch_sweep<R>(d, 2, c->pool, c->d_patch, G.wl.d, G.wl.n, c->dp, coef<R>(c), cur, c->d_sc, G.P, G.W,
-                                G.zlo, G.tlo, G.thi, c->d_nfloor + 1, c->stream);
+                                G.zlo, c->d_nfloor + 1, c->stream);
             STEPCK("sweep2");
         }
         mark(c);
@@ -354,7 +379,22 @@ int dispatch_dt(wmb_ctx* c) {
     int rc = ensure_smax(c);
     return rc ? rc : run_finalize(c);
 }
-int dispatch_step(wmb_ctx* c) { return c->esize == 4 ? run_step<float>(c) : run_step<double>(c); }
+int dispatch_step(wmb_ctx* c, bool split = false) {
+    return c->esize == 4 ? run_step<float>(c, split) : run_step<double>(c, split);
+}
+// the y/z ghost exchange on the side stream, forked from and joined (by the
+// split step, through ev_join) back into the main stream
+int fork_fill_yz(wmb_ctx* c) {
+    const WorkItem* wl[3] = {c->wl_fill[0].d, c->wl_fill[1].d, c->wl_fill[2].d};
+    const int nw[3] = {c->wl_fill[0].n, c->wl_fill[1].n, c->wl_fill[2].n};
+    CKH(hipEventRecord(c->ev_fork, c->stream));
+    CKH(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    hipError_t e = c->esize == 4 ? launch_fill<float>(c->pool, c->d_patch, wl, nw, c->p.ghost, c->cur, FILL_YZ, c->side)
+                                 : launch_fill<double>(c->pool, c->d_patch, wl, nw, c->p.ghost, c->cur, FILL_YZ, c->side);
+    if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("fill_ghosts: ") + hipGetErrorString(e));
+    CKH(hipEventRecord(c->ev_join, c->side));
+    return WMB_OK;
+}
 
 int build_box_list(wmb_ctx* c, Box bx, DevList& out, bool xcd = true) {
     std::vector<WorkItem> items;
@@ -436,19 +476,58 @@ int choose_W(int d, int P, size_t es) {
     return W;
 }
 
-// pencils of every patch whose edge along d is n, W consecutive pencils a block
-std::vector<WorkItem> sweep_items(const wmb_ctx* c, int d, int n, int tlo, int thi, int W) {
+// Which pencils of the transverse range [tlo, n+thi]^2 a list covers: all, the
+// interior rectangle [0, n)^2, or the frame between the two.
+enum SweepPart { PART_ALL, PART_INTERIOR, PART_FRAME };
+
+// pencils of every patch whose edge along d is n, W consecutive pencils of one
+// rectangle a block
+std::vector<WorkItem> sweep_items(const wmb_ctx* c, int d, int n, int tlo, int thi, int W, SweepPart part = PART_ALL) {
     const int FA = (d == 0) ? 1 : 0;
     const int SA = (d == 0) ? 2 : (d == 1 ? 2 : 1);
+    struct Rect {
+        int flo, fcnt, slo, scnt;
+    };
     std::vector<WorkItem> items;
     for (int p = 0; p < c->npatch; p++) {
         if (c->desc[p].n[d] != n) continue;
-        int tf = c->desc[p].n[FA] + thi - tlo + 1, ts = c->desc[p].n[SA] + thi - tlo + 1;
-        int npen = tf * ts;
-        for (int p0 = 0; p0 < npen; p0 += W)
-            items.push_back(WorkItem{p, p0, 0, (p0 + W - 1 < npen - 1) ? p0 + W - 1 : npen - 1});
+        const int nf = c->desc[p].n[FA], ns = c->desc[p].n[SA];
+        const int tf = nf + thi - tlo + 1;
+        std::vector<Rect> rects;
+        if (part == PART_ALL) rects.push_back({tlo, tf, tlo, ns + thi - tlo + 1});
+        if (part == PART_INTERIOR) rects.push_back({0, nf, 0, ns});
+        if (part == PART_FRAME) {
+            rects.push_back({tlo, tf, tlo, -tlo});   // slow in [tlo, -1]
+            rects.push_back({tlo, tf, ns, thi + 1});  // slow in [ns, ns + thi]
+            rects.push_back({tlo, -tlo, 0, ns});     // fast in [tlo, -1]
+            rects.push_back({nf, thi + 1, 0, ns});   // fast in [nf, nf + thi]
+        }
+        for (const Rect& r : rects) {
+            const int npen = r.fcnt * r.scnt;
+            const int code = (r.flo + 512) | ((r.slo + 512) << 10) | (r.fcnt << 20);
+            for (int p0 = 0; p0 < npen; p0 += W)
+                items.push_back(WorkItem{p, p0, code, (p0 + W - 1 < npen - 1) ? p0 + W - 1 : npen - 1});
+        }
     }
     return xcd_order(items);
+}
+
+// (Re)build a group's work lists for W pencils a block.
+int set_group_W(wmb_ctx* c, int d, int stage, SweepGroup& G, int W) {
+    std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, W);
+    int rc = upload(c, &G.wl.d, items);
+    if (rc) return rc;
+    G.wl.n = (int)items.size();
+    if (d == 0 && stage == 0) {
+        items = sweep_items(c, d, G.n, G.tlo, G.thi, W, PART_INTERIOR);
+        if ((rc = upload(c, &G.wl_in.d, items))) return rc;
+        G.wl_in.n = (int)items.size();
+        items = sweep_items(c, d, G.n, G.tlo, G.thi, W, PART_FRAME);
+        if ((rc = upload(c, &G.wl_fr.d, items))) return rc;
+        G.wl_fr.n = (int)items.size();
+    }
+    G.W = W;
+    return WMB_OK;
 }
 
 int build_sweeps(wmb_ctx* c) {
@@ -472,10 +551,7 @@ int build_sweeps(wmb_ctx* c) {
                 G.tlo = tlo;
                 G.thi = thi;
                 G.n = n;
-                G.W = choose_W(d, G.P, c->esize);
-                std::vector<WorkItem> items = sweep_items(c, d, n, tlo, thi, G.W);
-                G.wl.n = (int)items.size();
-                int rc = upload(c, &G.wl.d, items);
+                int rc = set_group_W(c, d, stage, G, choose_W(d, G.P, c->esize));
                 if (rc) return rc;
                 c->sweeps[d][stage].push_back(G);
             }
@@ -510,9 +586,9 @@ int capture_graphs(wmb_ctx* c) {
     for (int k = 0; k < 2; k++) {
         const int cur0 = c->cur;
         CKH(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
-        int rc = dispatch_fill(c, FILL_YZ);
+        int rc = fork_fill_yz(c);
         if (!rc) rc = run_finalize(c);
-        if (!rc) rc = dispatch_step(c);
+        if (!rc) rc = dispatch_step(c, true);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->stream, &g);
         if (rc || e != hipSuccess) {
@@ -710,7 +786,7 @@ int autotune_t(wmb_ctx* c, int reps) {
             for (int d = 0; d < 3 && e == hipSuccess; d++)
                 for (auto& G : c->sweeps[d][0])
                     e = launch_sweep<R>(d, 1, c->pool, c->d_patch, G.wl.d, G.wl.n, c->dp, coef<R>(c), c->cur, c->d_sc, G.P,
-                                        G.W, G.zlo, G.tlo, G.thi, c->d_nfloor + 2, c->stream);
+                                        G.W, G.zlo, c->d_nfloor + 2, c->stream);
             if (e == hipSuccess)
                 e = launch_ct_half<R>(c->pool, c->d_patch, c->wl_cth.d, c->wl_cth.n, coef<R>(c), c->p.ghost, c->cur,
                                       c->d_sc, c->stream);
@@ -738,7 +814,7 @@ int autotune_t(wmb_ctx* c, int reps) {
                     for (int r = 0; r <= reps && e == hipSuccess; r++) {
                         CKH(hipEventRecord(e0, c->stream));
                         e = launch_sweep<R>(d, stage + 1, c->pool, c->d_patch, dl, (int)items.size(), c->dp, coef<R>(c),
-                                            c->cur, c->d_sc, G.P, W, G.zlo, G.tlo, G.thi, c->d_nfloor + 2, c->stream);
+                                            c->cur, c->d_sc, G.P, W, G.zlo, c->d_nfloor + 2, c->stream);
                         CKH(hipEventRecord(e1, c->stream));
                         CKH(hipEventSynchronize(e1));
                         float t = 0.f;
@@ -753,13 +829,8 @@ int autotune_t(wmb_ctx* c, int reps) {
                     }
                 }
                 if (bestW != G.W) {
-                    std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, bestW);
-                    WorkItem* dl = nullptr;
-                    int rc2 = upload(c, &dl, items);
+                    int rc2 = set_group_W(c, d, stage, G, bestW);
                     if (rc2) return rc2;
-                    G.W = bestW;
-                    G.wl.d = dl;
-                    G.wl.n = (int)items.size();
                 }
             }
         }
@@ -831,6 +902,9 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
         CKH(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
         c->own_stream = true;
     }
+    CKH(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    CKH(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    CKH(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     const int g = c->p.ghost;
     uint64_t off = 0;
     c->hpatch.resize(npatch);
@@ -1001,13 +1075,8 @@ int wmb_set_tuning(wmb_ctx* c, const int32_t* quads, int32_t n) {
             if (G.n != edge) continue;
             if ((size_t)G.P * W > 1024 || c->esize * 16 * (size_t)G.P * W > 64 * 1024)
                 return fail(c, WMB_EINVAL, "tuning entry exceeds the block or LDS limit");
-            std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, W);
-            WorkItem* dl = nullptr;
-            int rc = upload(c, &dl, items);
+            int rc = set_group_W(c, d, stage - 1, G, W);
             if (rc) return rc;
-            G.W = W;
-            G.wl.d = dl;
-            G.wl.n = (int)items.size();
         }
     }
     free_graphs(c);
@@ -1092,6 +1161,12 @@ int wmb_destroy(wmb_ctx* c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     free_graphs(c);
     for (void* p : c->owned) hipFree(p);
+    if (c->side) {
+        hipStreamSynchronize(c->side);
+        hipStreamDestroy(c->side);
+    }
+    if (c->ev_fork) hipEventDestroy(c->ev_fork);
+    if (c->ev_join) hipEventDestroy(c->ev_join);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
     delete c;
     return WMB_OK;
