@@ -468,8 +468,21 @@ int build_fill_lists(wmb_ctx* c) {
 
 int choose_W(int d, int P, size_t es) {
     if (d == 0) {
-        int W = 256 / P;
-        return W < 1 ? 1 : W;
+        // about 256 threads a block, packed into whole 64-lane waves: the
+        // pencil count whose P * W wastes the fewest lanes, nearest to 256
+        int best = 256 / P < 1 ? 1 : 256 / P;
+        double bs = -1.0;
+        for (int W = 1; (size_t)P * W <= 1024 && es * 16 * (size_t)P * W <= 64 * 1024; W++) {
+            const int t = P * W;
+            if (t < 128 && (size_t)P * (W + 1) <= 1024) continue;
+            const double fill = (double)t / (double)((t + 63) / 64 * 64);
+            const double score = fill - 0.02 * (t > 256 ? t - 256 : 256 - t) / 64.0;
+            if (score > bs) {
+                bs = score;
+                best = W;
+            }
+        }
+        return best;
     }
     int W = 16;
     while (W > 1 && ((size_t)P * W > 1024 || es * 16 * (size_t)P * W > 64 * 1024)) W /= 2;
@@ -795,7 +808,9 @@ int autotune_t(wmb_ctx* c, int reps) {
         for (int d = 0; d < 3; d++) {
             for (auto& G : c->sweeps[d][stage]) {
                 std::vector<int> cand;
-                const int opts_x[] = {1, 2, 3, 4, 6, 8, 12, 16, 24};
+                // pencil counts around the 64-lane wave: 5, 10 and 20 pencils
+                // of 38 zones fill whole waves to 99%
+                const int opts_x[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24};
                 const int opts_t[] = {2, 4, 8, 16, 32};
                 if (d == 0)
                     for (int W : opts_x) cand.push_back(W);
