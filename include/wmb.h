@@ -71,6 +71,10 @@ typedef struct wmb_params {
                             takes the HLL flux instead of the MHDTVD flux (and
                             contributes no g-tilde to its zones' limiters); both 0
                             (the default) switch the protection off */
+    int32_t dt_lag;      /* 0 (default): dt of step n from the state q^n.  1: from
+                            q^(n-1), the state one step earlier (the first step of
+                            a run from q^0): the paper delays the dt reduction by
+                            one step to overlap it with work (Sect. 4.1.1) */
 } wmb_params;
 
 typedef struct wmb_patch_desc {
@@ -87,8 +91,8 @@ typedef struct wmb_patch_desc {
 typedef struct wmb_ctx wmb_ctx;
 
 /* Create a context.  Validates p (gamma > 1, cfl in (0,1], ghost >= 4,
-   dx > 0, precision known, protection floors >= 0).  *out receives the
-   context. */
+   dx > 0, precision known, protection floors >= 0, dt_lag 0 or 1).  *out
+   receives the context. */
 int wmb_create(const wmb_params *p, wmb_ctx **out);
 
 /* Device bytes the caller must provide for npatch patches: two state copies
@@ -136,7 +140,10 @@ int wmb_fill_ghosts(wmb_ctx *c);
    dt = cfl * min_{zones, d} dx_d / (|v_d| + c_f,d), with c_f,d the fast speed
    (Sect. 5) taking B_d as the longitudinal field.  The result stays in device
    memory for wmb_advance(c, 0) / wmb_run_steps; if dt_out != NULL it is also
-   copied to the host (synchronising the stream). */
+   copied to the host (synchronising the stream).  With dt_lag = 1 the steps
+   of wmb_run_steps use the maximum of the state one step earlier; a run
+   whose state was set from the host, or follows this call, starts again
+   from the current state. */
 int wmb_compute_dt(wmb_ctx *c, double *dt_out);
 
 /* One CTU+CT step (Sect. 5.2, Steps 1-11) of every patch.  Ghosts must be

@@ -18,7 +18,7 @@ struct DevParams {
     double dx[3];
     double degen_tol;
     int ghost;
-    int pad_;
+    int dt_lag;  // 1: dt of a step from the signal-speed maximum of the state one step earlier
 };
 
 // Per-step constants derived from dt, written on the device by the dt

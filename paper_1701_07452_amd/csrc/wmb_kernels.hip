@@ -345,15 +345,25 @@ __device__ __forceinline__ void write_step_const(StepConst* sc, double dt, const
     }
 }
 
+// smax_bits[0]: the maximum of the current state (folded by the update that
+// produced it, or reduced explicitly); smax_bits[1]: that of the state one
+// step earlier (0 right after an explicit reduction: nothing to lag behind).
+// With dt_lag the step takes the earlier one (Sect. 4.1.1).
 __global__ void dt_finalize_kernel(unsigned long long* smax_bits, StepConst* sc, DevParams p) {
-    double smax = __longlong_as_double((long long)*smax_bits);
-    write_step_const(sc, p.cfl / smax, p);
-    *smax_bits = 0ULL;
+    const unsigned long long cur = smax_bits[0], prev = smax_bits[1];
+    const unsigned long long use = (p.dt_lag && prev != 0ULL) ? prev : cur;
+    write_step_const(sc, p.cfl / __longlong_as_double((long long)use), p);
+    smax_bits[1] = cur;
+    smax_bits[0] = 0ULL;
 }
 
 __global__ void set_dt_kernel(StepConst* sc, double dt, DevParams p) { write_step_const(sc, dt, p); }
 
-__global__ void zero_u64_kernel(unsigned long long* p) { *p = 0ULL; }
+// clears both signal-speed slots before an explicit reduction
+__global__ void zero_u64_kernel(unsigned long long* p) {
+    p[0] = 0ULL;
+    p[1] = 0ULL;
+}
 
 // ---------------------------------------------------------------------------
 // Steps 3 and 9: upwinded edge EMFs from face fluxes and E^r.  For the edge of

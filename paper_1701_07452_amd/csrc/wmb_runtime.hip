@@ -211,6 +211,7 @@ int check_params(const wmb_params* p) {
     if (!(p->degen_tol >= 0.0 && p->degen_tol < 1e-2)) return WMB_EINVAL;
     if (p->precision != WMB_FP64 && p->precision != WMB_FP32) return WMB_EINVAL;
     if (!(p->rho_protect >= 0.0) || !(p->p_protect >= 0.0)) return WMB_EINVAL;
+    if (p->dt_lag != 0 && p->dt_lag != 1) return WMB_EINVAL;
     return WMB_OK;
 }
 
@@ -884,6 +885,7 @@ int wmb_create(const wmb_params* p, wmb_ctx** out) {
     for (int a = 0; a < 3; a++) c->dp.dx[a] = p->dx[a];
     c->dp.degen_tol = p->degen_tol;
     c->dp.ghost = p->ghost;
+    c->dp.dt_lag = p->dt_lag;
     *out = c;
     return WMB_OK;
 }
@@ -946,12 +948,12 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     if ((rc = build_tile_list(c, -2, 2, -2, 2, 40, c->wl_cth))) return rc;
     if ((rc = build_tile_list(c, 0, -1, 0, -1, 32, c->wl_upd))) return rc;
     if ((rc = build_sweeps(c))) return rc;
-    if ((rc = dev_alloc(c, &c->d_smax, 1))) return rc;
+    if ((rc = dev_alloc(c, &c->d_smax, 2))) return rc;
     if ((rc = dev_alloc(c, &c->d_sc, 1))) return rc;
     // counters: floor activations, protected faces, and a sink for tuning runs
     if ((rc = dev_alloc(c, &c->d_nfloor, 3))) return rc;
     if ((rc = dev_alloc(c, &c->d_partial, (size_t)c->wl_diag.n * 10))) return rc;
-    CKH(hipMemsetAsync(c->d_smax, 0, sizeof(unsigned long long), c->stream));
+    CKH(hipMemsetAsync(c->d_smax, 0, 2 * sizeof(unsigned long long), c->stream));
     CKH(hipMemsetAsync(c->d_sc, 0, sizeof(StepConst), c->stream));
     CKH(hipMemsetAsync(c->d_nfloor, 0, 3 * sizeof(unsigned long long), c->stream));
     CKH(hipStreamSynchronize(c->stream));

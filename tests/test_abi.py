@@ -40,12 +40,17 @@ def test_create_validates_params(lib):
     assert lib.wmb_create(C.byref(good), C.byref(h)) == 0
     assert lib.wmb_destroy(h) == 0
     for field, val in [("gamma", 1.0), ("cfl", 0.0), ("ghost", 3), ("precision", 7), ("limiter_beta", 2.5),
-                       ("p_floor", 0.0)]:
+                       ("p_floor", 0.0), ("rho_protect", -1.0), ("dt_lag", 2)]:
         p = wmb.make_params()
         setattr(p, field, val)
         h = C.c_void_p()
         assert lib.wmb_create(C.byref(p), C.byref(h)) == wmb.WMB_EINVAL, field
     assert lib.wmb_strerror(wmb.WMB_ECFL).decode().startswith("dt above")
+    # the last field of the struct is read (a layout mismatch would misplace it)
+    p = wmb.make_params(dt_lag=1)
+    h = C.c_void_p()
+    assert lib.wmb_create(C.byref(p), C.byref(h)) == 0
+    assert lib.wmb_destroy(h) == 0
 
 
 def test_pool_bytes(lib):

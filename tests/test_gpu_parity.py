@@ -703,3 +703,44 @@ def test_frozen_patches_uneven_fp32(wmb):
         assert _rel_l1(qg[c], qo[c]) <= 1e-5, c
     sim.close()
     orc.close()
+
+
+# ---------------------------------------------------------------------------
+# dt lagged by one step (the delayed global reduction of Sect. 4.1.1)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_dt_lag_one_step(wmb, prec):
+    """dt_lag = 1: step n takes the CFL dt of q^(n-1) (step 0 that of q^0).
+    8 graph-replayed steps against the oracle stepped on the lagged dt
+    sequence: FP64 within 1e-11, FP32 within 1e-5 relative L1; without the
+    lag the same run differs (the dt sequences differ)."""
+    G, (q, b) = CASES["uniform8"]()
+    if prec == 1:
+        q, b = as_f32(q), as_f32(b)
+    dx = (1.0 / 16,) * 3
+    sim = gpu_sim(wmb, G, q, b, prec, dx=dx, dt_lag=1)
+    sim.run_steps(8)
+    orc = oracle_sim(G, q, b, dx=dx)
+    prev = None
+    for _ in range(8):
+        orc.fill_ghosts()
+        d = orc.compute_dt()
+        orc.advance(d if prev is None else prev)
+        prev = d
+    qg, bg = I.gather(G, [sim.get_state(i) for i in range(G.npatch)])
+    qo, bo = oracle_gather(G, orc)
+    if prec == 0:
+        for c in range(8):
+            assert rel_max(qg[c], qo[c]) <= 1e-11, c
+        assert rel_max(bg, bo) <= 1e-11
+    else:
+        for c in (0, 7):
+            assert _rel_l1(qg[c], qo[c]) <= 1e-5, c
+    plain = gpu_sim(wmb, G, q, b, prec, dx=dx)
+    plain.run_steps(8)
+    qp, _ = I.gather(G, [plain.get_state(i) for i in range(G.npatch)])
+    assert np.abs(qp - qg).max() > 1e-9 * np.abs(qg).max()
+    plain.close()
+    sim.close()
+    orc.close()
