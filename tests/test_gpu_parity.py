@@ -639,7 +639,8 @@ def test_outflow_blast_all_walls_fp64(wmb):
 def _frozen_run(W, G, q, b, prec, frozen, nsteps, thaw_after=None):
     """GPU run with the patches in `frozen` frozen (graph path: the captured
     graphs are reused across set_active), against the oracle stepped on the
-    GPU's dt with the frozen patches reset to their state after each step."""
+    GPU's dt with the frozen patches' stored boxes (state, owned boundary
+    faces, ghosts) reset after each step to what they held when frozen."""
     N = G.shape
     dx = (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
     sim = gpu_sim(W, G, q, b, prec, dx=dx)
@@ -647,22 +648,22 @@ def _frozen_run(W, G, q, b, prec, frozen, nsteps, thaw_after=None):
     sim.run_steps(1)  # captures the graphs with every patch active
     orc.fill_ghosts()
     orc.advance(orc.compute_dt())
-    held = {}
+    held, held_orc = {}, {}
     for f in frozen:
         sim.set_active(f, False)
         held[f] = sim.get_state(f)
-        # the oracle holds the GPU's state of the frozen patch (FP32: rounded)
-        orc.set_state(f, *held[f])
+        held_orc[f] = orc.get_stored(f)
     for s in range(nsteps):
         if thaw_after is not None and s == thaw_after:
             sim.set_active(frozen[0], True)
             held.pop(frozen[0])
+            held_orc.pop(frozen[0])
         dt = sim.compute_dt()
         sim.run_steps(1)
         orc.fill_ghosts()
         orc.advance(dt)
-        for f, st in held.items():
-            orc.set_state(f, *st)
+        for f, st in held_orc.items():
+            orc.set_stored(f, *st)
     return sim, orc, held
 
 
@@ -673,6 +674,26 @@ def test_frozen_patches_fp64(wmb):
     freeze are reused."""
     G, (q, b) = CASES["uniform8"]()
     sim, orc, held = _frozen_run(wmb, G, q, b, 0, [1, 6], 5, thaw_after=3)
+    for f, (qf, bf) in held.items():
+        qa, ba = sim.get_state(f)
+        assert np.array_equal(qa, qf) and np.array_equal(ba, bf), f
+    qg, bg = I.gather(G, [sim.get_state(i) for i in range(G.npatch)])
+    qo, bo = oracle_gather(G, orc)
+    for c in range(8):
+        assert rel_max(qg[c], qo[c]) <= 1e-11, c
+    assert rel_max(bg, bo) <= 1e-11
+    sim.close()
+    orc.close()
+
+
+def test_frozen_patches_next_to_walls_fp64(wmb):
+    """Frozen patches beside domain boundaries: outflow along x and y,
+    periodic z, 2 x 2 x 1 patches of 8 x 8 x 10, two patches frozen for 4
+    steps (one of them a corner of two walls): FP64 within 1e-11 of the
+    reference run; frozen states bitwise unchanged."""
+    G = I.patch_grid([8, 8], [8, 8], [10], periodic=(False, False, True))
+    q, b = I.random_smooth(G.shape, 41)
+    sim, orc, held = _frozen_run(wmb, G, q, b, 0, [0, 3], 4)
     for f, (qf, bf) in held.items():
         qa, ba = sim.get_state(f)
         assert np.array_equal(qa, qf) and np.array_equal(ba, bf), f
