@@ -164,9 +164,10 @@ int wmb_advance(wmb_ctx *c, double dt);
    graph's ghost exchange runs the y and z passes only (the step before wrote
    the x-ghosts), on a branch of its own beside the part of the Step-1 x sweep
    whose pencils have interior transverse coordinates (the overlap of
-   exchange and interior work of Sect. 4); the x pass is enqueued first when
-   the state was set since.  Results are bitwise those of the eager calls.
-   Enqueue only; this is the timed call. */
+   exchange and interior work of Sect. 4); the three sweeps of each stage
+   run as concurrent branches (library-owned streams, default priority); the
+   x pass is enqueued first when the state was set since.  Results are
+   bitwise those of the eager calls.  Enqueue only; this is the timed call. */
 int wmb_run_steps(wmb_ctx *c, int32_t nsteps);
 
 /* FP64 diagnostics over all interiors: totals[8] = sum over zones of q times

@@ -66,8 +66,9 @@ struct wmb_ctx {
     bool own_stream = false;
     // second stream and fork/join events of the captured step: the y/z ghost
     // exchange runs beside the interior part of the Step-1 x sweep
-    hipStream_t side = nullptr;
+    hipStream_t side = nullptr, side2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_br[6] = {};  // fork/join of the three sweep branches of a stage
     int cur = 0;
     PatchDev* d_patch = nullptr;
     DevList wl_fill[3];
@@ -312,49 +313,80 @@ int run_finalize(wmb_ctx* c) {
     return WMB_OK;
 }
 
-// One step.  split: the y/z ghost exchange was forked onto the side stream
-// (ev_join marks its end); the Step-1 x sweep first covers the pencils whose
-// transverse coords are interior, which read only the x-ghosts the previous
-// update wrote, then waits for the exchange and covers the frame.
+// One step.  split (the captured graph): the y/z ghost exchange was forked
+// onto the side stream (ev_join marks its end).  The three sweeps of a stage
+// are independent (each writes its own flux array), so they run as three
+// branches: x on the main stream, y on the side stream, z on the second side
+// stream, joined before Steps 3-4 and before Steps 8-11.  The Step-1 x sweep
+// first covers the pencils whose transverse coords are interior, which read
+// only the x-ghosts the previous update wrote, then waits for the exchange
+// and covers the frame.
 template <typename R>
 int run_step(wmb_ctx* c, bool split = false) {
     hipError_t e;
     const int cur = c->cur;
 #define STEPCK(what)                                                                        \
     if (e != hipSuccess) return fail(c, WMB_EHIP, std::string(what) + ": " + hipGetErrorString(e))
-    for (int d = 0; d < 3; d++) {
-        if (split && d == 0) {
-            for (auto& G : c->sweeps[0][0]) {
-                e = launch_sweep<R>(0, 1, c->pool, c->d_patch, G.wl_in.d, G.wl_in.n, c->dp, coef<R>(c), cur, c->d_sc,
-                                    G.P, G.W, G.zlo, c->d_nfloor + 1, c->stream);
-                STEPCK("sweep1");
-            }
-            CKH(hipStreamWaitEvent(c->stream, c->ev_join, 0));
-            for (auto& G : c->sweeps[0][0]) {
-                e = launch_sweep<R>(0, 1, c->pool, c->d_patch, G.wl_fr.d, G.wl_fr.n, c->dp, coef<R>(c), cur, c->d_sc,
-                                    G.P, G.W, G.zlo, c->d_nfloor + 1, c->stream);
-                STEPCK("sweep1");
-            }
-            mark(c);
-            continue;
+    auto sweeps = [&](int d, int stage, const DevList SweepGroup::*wl, hipStream_t st) -> hipError_t {
+        for (auto& G : c->sweeps[d][stage - 1]) {
+            const DevList& L = G.*wl;
+            hipError_t r = launch_sweep<R>(d, stage, c->pool, c->d_patch, L.d, L.n, c->dp, coef<R>(c), cur, c->d_sc, G.P,
+                                           G.W, G.zlo, c->d_nfloor + 1, st);
+            if (r != hipSuccess) return r;
         }
-        for (auto& G : c->sweeps[d][0]) {
-            e = launch_sweep<R>(d, 1, c->pool, c->d_patch, G.wl.d, G.wl.n, c->dp, coef<R>(c), cur, c->d_sc, G.P, G.W,
-                                G.zlo, c->d_nfloor + 1, c->stream);
+        return hipSuccess;
+    };
+    if (split) {
+        // Step 1: y after the exchange on its stream, z waits for it on the
+        // second; both also wait for this step's dt (finalized on the main
+        // stream before this call)
+        CKH(hipEventRecord(c->ev_br[5], c->stream));
+        CKH(hipStreamWaitEvent(c->side, c->ev_br[5], 0));
+        CKH(hipStreamWaitEvent(c->side2, c->ev_br[5], 0));
+        CKH(hipStreamWaitEvent(c->side2, c->ev_join, 0));
+        e = sweeps(1, 1, &SweepGroup::wl, c->side);
+        STEPCK("sweep1");
+        e = sweeps(2, 1, &SweepGroup::wl, c->side2);
+        STEPCK("sweep1");
+        CKH(hipEventRecord(c->ev_br[0], c->side));
+        CKH(hipEventRecord(c->ev_br[1], c->side2));
+        e = sweeps(0, 1, &SweepGroup::wl_in, c->stream);
+        STEPCK("sweep1");
+        CKH(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+        e = sweeps(0, 1, &SweepGroup::wl_fr, c->stream);
+        STEPCK("sweep1");
+        CKH(hipStreamWaitEvent(c->stream, c->ev_br[0], 0));
+        CKH(hipStreamWaitEvent(c->stream, c->ev_br[1], 0));
+    } else {
+        for (int d = 0; d < 3; d++) {
+            e = sweeps(d, 1, &SweepGroup::wl, c->stream);
             STEPCK("sweep1");
+            mark(c);
         }
-        mark(c);
     }
     e = launch_ct_half<R>(c->pool, c->d_patch, c->wl_cth.d, c->wl_cth.n, coef<R>(c), c->p.ghost, cur, c->d_sc, c->stream);
     STEPCK("ct_half");
     mark(c);
-    for (int d = 0; d < 3; d++) {
-        for (auto& G : c->sweeps[d][1]) {
-            e = launch_sweep<R>(d, 2, c->pool, c->d_patch, G.wl.d, G.wl.n, c->dp, coef<R>(c), cur, c->d_sc, G.P, G.W,
-                                G.zlo, c->d_nfloor + 1, c->stream);
+    if (split) {
+        CKH(hipEventRecord(c->ev_br[2], c->stream));
+        CKH(hipStreamWaitEvent(c->side, c->ev_br[2], 0));
+        CKH(hipStreamWaitEvent(c->side2, c->ev_br[2], 0));
+        e = sweeps(1, 2, &SweepGroup::wl, c->side);
+        STEPCK("sweep2");
+        e = sweeps(2, 2, &SweepGroup::wl, c->side2);
+        STEPCK("sweep2");
+        CKH(hipEventRecord(c->ev_br[3], c->side));
+        CKH(hipEventRecord(c->ev_br[4], c->side2));
+        e = sweeps(0, 2, &SweepGroup::wl, c->stream);
+        STEPCK("sweep2");
+        CKH(hipStreamWaitEvent(c->stream, c->ev_br[3], 0));
+        CKH(hipStreamWaitEvent(c->stream, c->ev_br[4], 0));
+    } else {
+        for (int d = 0; d < 3; d++) {
+            e = sweeps(d, 2, &SweepGroup::wl, c->stream);
             STEPCK("sweep2");
+            mark(c);
         }
-        mark(c);
     }
     e = launch_update<R>(c->pool, c->d_patch, c->wl_upd.d, c->wl_upd.n, c->dp, coef<R>(c), cur, c->d_sc, c->d_nfloor,
                          c->d_smax, c->keep_edges ? 1 : 0, c->stream);
@@ -920,8 +952,10 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
         c->own_stream = true;
     }
     CKH(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    CKH(hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking));
     CKH(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     CKH(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    for (auto& ev : c->ev_br) CKH(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     const int g = c->p.ghost;
     uint64_t off = 0;
     c->hpatch.resize(npatch);
@@ -1178,12 +1212,15 @@ int wmb_destroy(wmb_ctx* c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     free_graphs(c);
     for (void* p : c->owned) hipFree(p);
-    if (c->side) {
-        hipStreamSynchronize(c->side);
-        hipStreamDestroy(c->side);
-    }
+    for (hipStream_t sd : {c->side, c->side2})
+        if (sd) {
+            hipStreamSynchronize(sd);
+            hipStreamDestroy(sd);
+        }
     if (c->ev_fork) hipEventDestroy(c->ev_fork);
     if (c->ev_join) hipEventDestroy(c->ev_join);
+    for (hipEvent_t ev : c->ev_br)
+        if (ev) hipEventDestroy(ev);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
     delete c;
     return WMB_OK;
