@@ -639,7 +639,7 @@ int capture_graphs(wmb_ctx* c) {
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->stream, &g);
         if (rc || e != hipSuccess) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             restore();
             return rc ? rc : fail(c, WMB_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
         }
@@ -870,7 +870,7 @@ int autotune_t(wmb_ctx* c, int reps) {
                         CKH(hipEventElapsedTime(&t, e0, e1));
                         if (r > 0) tot += t;  // first launch is a warm-up
                     }
-                    hipFree(dl);
+                    (void)hipFree(dl);  // the candidate list of one timing
                     if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("autotune: ") + hipGetErrorString(e));
                     if (tot < best) {
                         best = tot;
@@ -884,8 +884,8 @@ int autotune_t(wmb_ctx* c, int reps) {
             }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     free_graphs(c);  // launch plans changed
     return WMB_OK;
 }
@@ -1204,25 +1204,25 @@ int wmb_profile_step(wmb_ctx* c, double* ms, int32_t nclass) {
             ms[i] = t;
         }
     }
-    for (int i = 0; i <= WMB_NCLASS; i++) hipEventDestroy(ev[i]);
+    for (int i = 0; i <= WMB_NCLASS; i++) (void)hipEventDestroy(ev[i]);
     return rc;
 }
 
 int wmb_destroy(wmb_ctx* c) {
     if (!c) return WMB_OK;
-    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);  // teardown: nothing to report
     free_graphs(c);
-    for (void* p : c->owned) hipFree(p);
+    for (void* p : c->owned) (void)hipFree(p);
     for (hipStream_t sd : {c->side, c->side2})
         if (sd) {
-            hipStreamSynchronize(sd);
-            hipStreamDestroy(sd);
+            (void)hipStreamSynchronize(sd);
+            (void)hipStreamDestroy(sd);
         }
-    if (c->ev_fork) hipEventDestroy(c->ev_fork);
-    if (c->ev_join) hipEventDestroy(c->ev_join);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     for (hipEvent_t ev : c->ev_br)
-        if (ev) hipEventDestroy(ev);
-    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+        if (ev) (void)hipEventDestroy(ev);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return WMB_OK;
 }
