@@ -189,6 +189,8 @@ def main():
     ap.add_argument("--protection", action="store_true",
                     help="also time the Mach-5 lognormal-density batch (384^3 as 512 x 48^3, FP32) with the protection "
                          "floors off and on (reported beside)")
+    ap.add_argument("--outflow", action="store_true",
+                    help="also time the FP32 batch with outflow boundaries on every side of the domain")
     ap.add_argument("--frozen", action="store_true",
                     help="also time the FP32 batch with every other patch frozen (checkerboard), graphs reused")
     ap.add_argument("--calib-copy", action="store_true",
@@ -273,6 +275,17 @@ def main():
                 (tag, msh / 10, diagh["protected_faces"], diagh["floors"]))
         del qh, bh
 
+    outflow = None
+    if args.outflow:
+        Go = I.uniform_grid(N, n, periodic=(False, False, False))
+        log("bench: FP32 batch with outflow on every side")
+        mso, _, kerno, diago = run_precision(W, Go, q, b, dx, W.WMB_FP32, g, args.steps, args.warmup, 1,
+                                             W.tuning_from_str(args.tuning32) or None)
+        outflow = {"workload": "the FP32 batch with outflow (zero-gradient) boundaries on all six sides",
+                   "ms_per_step": mso / args.steps, "value": zones * args.steps / (mso / 1e3), "kernels_ms": kerno,
+                   **diago}
+        log("bench: outflow: %.3f ms/step, %.3e zone-updates/s" % (mso / args.steps, outflow["value"]))
+
     frozen = None
     if args.frozen:
         px, py, pz = G.nblocks
@@ -341,6 +354,7 @@ def main():
         "uneven_fp32": uneven,
         "protection_fp32": protection,
         "frozen_half_fp32": frozen,
+        "outflow_fp32": outflow,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
