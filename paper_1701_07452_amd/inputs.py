@@ -353,14 +353,24 @@ def cp_alfven(N, khat=(1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0), box=(3.0, 1.5, 1.5), ga
 # spectral random fields
 # --------------------------------------------------------------------------
 
-def gaussian_field(shape, seed, ncomp=3, slope=-11.0 / 6.0, box=None, solenoidal=False, rng=None):
+def gaussian_field(shape, seed, ncomp=3, slope=-11.0 / 6.0, box=None, solenoidal=False, rng=None, workers=None):
     """Gaussian random field with |k|^slope amplitude for 1 <= |k| <= N/2 (k in
-    units of 2 pi / L per axis), zero mean.  Returns (ncomp,) + shape."""
+    units of 2 pi / L per axis), zero mean.  Returns (ncomp,) + shape.
+    workers: threads for the FFTs (scipy.fft), for the largest boxes; None
+    keeps numpy's FFT."""
     rng = np.random.default_rng(seed) if rng is None else rng
     Nz, Ny, Nx = shape
     box = box or (1.0, 1.0, 1.0)
     noise = rng.standard_normal((ncomp,) + shape)
-    fk = np.fft.rfftn(noise, axes=(1, 2, 3))
+    if workers is None:
+        rfftn, irfftn = np.fft.rfftn, np.fft.irfftn
+    else:
+        import scipy.fft as sf
+
+        rfftn = lambda a, axes: sf.rfftn(a, axes=axes, workers=workers)  # noqa: E731
+        irfftn = lambda a, s, axes: sf.irfftn(a, s=s, axes=axes, workers=workers)  # noqa: E731
+    fk = rfftn(noise, axes=(1, 2, 3))
+    del noise
     kz = np.fft.fftfreq(Nz, d=1.0 / Nz)
     ky = np.fft.fftfreq(Ny, d=1.0 / Ny)
     kx = np.fft.rfftfreq(Nx, d=1.0 / Nx)
@@ -377,7 +387,7 @@ def gaussian_field(shape, seed, ncomp=3, slope=-11.0 / 6.0, box=None, solenoidal
         fk[0] -= KX * kdot / k2
         fk[1] -= KY * kdot / k2
         fk[2] -= KZ * kdot / k2
-    f = np.fft.irfftn(fk, s=shape, axes=(1, 2, 3))
+    f = irfftn(fk, s=shape, axes=(1, 2, 3))
     f -= f.mean(axis=(1, 2, 3), keepdims=True)
     return f
 
@@ -395,15 +405,21 @@ def turbulence(N, seed=170107452, mach=1.0, rho0=1.0, p0=1.0, B0=(0.1, 0.0, 0.0)
     return q, b
 
 
-def high_contrast_turbulence(N, seed_rho=170107455, seed_v=170107456, sigma_ln=1.5, mach=5.0, gamma=GAMMA):
+def high_contrast_turbulence(N, seed_rho=170107455, seed_v=170107456, sigma_ln=1.5, mach=5.0, gamma=GAMMA,
+                             workers=None, log=None):
     """Lognormal density (sigma_ln), P = 1, B = (sqrt2, 0, 0) (beta 1), solenoidal
-    velocity at rms Mach `mach` of the c_s = sqrt(gamma)."""
+    velocity at rms Mach `mach` of the c_s = sqrt(gamma).  workers: FFT threads
+    (see gaussian_field); log: optional callable told when each field is done."""
     shape = (N, N, N)
-    lr = gaussian_field(shape, seed_rho, 1)[0]
+    lr = gaussian_field(shape, seed_rho, 1, workers=workers)[0]
+    if log:
+        log("log density field done")
     lr *= sigma_ln / lr.std()
     rho = np.exp(lr)
     rho /= rho.mean()
-    v = gaussian_field(shape, seed_v, 3, solenoidal=True)
+    v = gaussian_field(shape, seed_v, 3, solenoidal=True, workers=workers)
+    if log:
+        log("velocity field done")
     cs = math.sqrt(gamma)
     v *= mach * cs / math.sqrt(float(np.mean(np.sum(v ** 2, axis=0))))
     b = uniform_faces(shape, (math.sqrt(2.0), 0.0, 0.0))

@@ -7,6 +7,8 @@ spec tolerance (relative L1 <= 1e-5 on rho and E after 10 steps,
 normalised div b <= 1e-6); graph replay, determinism and restart bitwise.
 """
 import math
+import os
+import time
 
 import numpy as np
 import pytest
@@ -299,15 +301,20 @@ def W_ghost(sim):
     return int(sim.params.ghost)
 
 
-def _sampled_full_size(W, G, q, b, prec, samples, tol_max, tol_l1, nsteps_before=1, dx=None):
-    """Full-size batch in the benchmark's launch configuration (graph replay);
-    sampled patches are recomputed one by one by the oracle from the GPU's
-    ghost-filled stored box and the GPU's dt."""
+def _sampled_full_size(W, G, q, b, prec, samples, tol_max, tol_l1, nsteps_before=1, dx=None, log=None):
+    """Full-size batch in the benchmark's launch configuration (graph replay,
+    ghost width 4); sampled patches are recomputed one by one by the oracle
+    from the GPU's ghost-filled stored box and the GPU's dt."""
     N = G.shape
     dx = dx or (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
-    sim = gpu_sim(W, G, q, b, prec, dx=dx)
+    sim = gpu_sim(W, G, q, b, prec, dx=dx, ghost=4)
+    if log:
+        log("state uploaded")
     sim.run_steps(nsteps_before)
     sim.fill_ghosts()
+    if log:
+        sim.synchronize()
+        log("%d steps done" % nsteps_before)
     stored = {ip: sim.get_stored(ip) for ip in samples}
     dt = sim.compute_dt()
     sim.run_steps(1)  # fill + dt + step, as timed
@@ -328,11 +335,14 @@ def _sampled_full_size(W, G, q, b, prec, samples, tol_max, tol_l1, nsteps_before
             scale[c] = np.abs(qo[1:4]).max()
         for c in (4, 5, 6):
             scale[c] = np.abs(qo[4:7]).max()
+        ms = [float(np.abs(qg[c] - qo[c]).max() / max(scale[c], 1e-300)) for c in range(8)]
+        worst = max(worst, max(ms))
+        l1 = max(_rel_l1(qg[0], qo[0]), _rel_l1(qg[7], qo[7]))
+        if log:
+            log("patch %d: worst rel max %.2e, rel L1 (rho, E) %.2e" % (ip, max(ms), l1))
+        assert l1 <= tol_l1, (ip, l1)
         for c in range(8):
-            m = float(np.abs(qg[c] - qo[c]).max() / max(scale[c], 1e-300))
-            worst = max(worst, m)
-            assert m <= tol_max, (ip, c, m)
-        assert _rel_l1(qg[0], qo[0]) <= tol_l1 and _rel_l1(qg[7], qo[7]) <= tol_l1
+            assert ms[c] <= tol_max, (ip, c, ms[c])
         bscale = max(np.abs(bo).max(), 1e-300)
         for c in range(3):
             assert np.abs(bg[c] - bo[c]).max() / bscale <= tol_max, (ip, "b", c)
@@ -429,6 +439,25 @@ def test_c5_recipe_high_contrast_fp32_sampled(wmb):
     G = I.uniform_grid(192, 48)
     w = _sampled_full_size(wmb, G, q, b, 1, [0, 37], 1e-4, 1e-6, nsteps_before=1)
     print("high-contrast 192^3 fp32 sampled worst rel max %.2e" % w)
+
+
+@pytest.mark.skipif(os.environ.get("WMB_FULL_SIZE") != "1",
+                    reason="768^3 needs a 210 GB pool and minutes of host set-up; run with WMB_FULL_SIZE=1")
+def test_c5_full_size_768_fp32_sampled(wmb):
+    """The high-contrast workload at its full size: 768^3 as 4096 patches of
+    48^3, FP32, in the benchmark's launch configuration. After 19 steps,
+    three sampled patches (a corner, the middle, the last) are recomputed
+    one step by the oracle from the GPU's ghost-filled boxes and dt: relative
+    L1 of rho and E within 1e-6, and every field within 1e-3 of its group's
+    scale (in the Mach-5 shocked flow FP32 rounding at the limiter's branch
+    points reaches 1.5e-4 in single zones)."""
+    t0 = time.time()
+    log = lambda what: print("c5 768^3: %s (%.0f s)" % (what, time.time() - t0), flush=True)  # noqa: E731
+    q, b = I.high_contrast_turbulence(768, workers=-1, log=log)
+    log("initial state built")
+    G = I.uniform_grid(768, 48)
+    w = _sampled_full_size(wmb, G, q, b, 1, [0, 2047, 4095], 1e-3, 1e-6, nsteps_before=19, log=log)
+    log("sampled worst rel max %.2e" % w)
 
 
 @pytest.mark.slow
