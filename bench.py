@@ -198,7 +198,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+        print("bench.py: the library runs on one GPU only; --gpus %d is not supported "
               "(the multi-GPU sharding is a documented design, not built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
