@@ -419,9 +419,10 @@ void orc_hll_flux(const double uL[8], const double uR[8], const orc_params *P, d
 }
 
 /*
- * Protection trigger of a face (reading of "the protection floor is
- * exceeded", Appendix A): with a protection floor set, the face switches to
- * HLL if the Roe sound speed squared is not positive, or if one of the six
+ * Protection trigger of a face (reading of Appendix A, last paragraph, which
+ * switches to HLL once a protection floor is crossed): with a protection
+ * floor set, the face switches to HLL if the Roe sound speed squared is not
+ * positive, or if one of the six
  * states inside the Roe fan, u_L + sum_{k<m} alpha_k R_k (m = 1..6), has a
  * density below rho_protect or a pressure below p_protect.
  */
