@@ -794,3 +794,67 @@ def test_dt_lag_one_step(wmb, prec):
     plain.close()
     sim.close()
     orc.close()
+
+
+# ---------------------------------------------------------------------------
+# features together
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_protection_with_outflow_ends(wmb, prec):
+    """The Einfeldt-type line (v = -/+3 out of the middle, gamma 1.4) with
+    outflow at both x ends and protection floors 1e-3: the rarefaction
+    empties the middle while material leaves through the ends.  FP64 within
+    1e-10 of each field group's scale, FP32 within 1e-4 relative L1;
+    positive density, no floor fired."""
+    G = I.patch_grid([32, 32], [8], [8], periodic=(False, True, True))
+    q, b = I.shock_tube_x(G.shape, gamma=1.4, left=(1.0, -3.0, 0.0, 0.0, 0.0, 0.0, 0.4),
+                          right=(1.0, 3.0, 0.0, 0.0, 0.0, 0.0, 0.4), bx=0.1)
+    if prec == 1:
+        q, b = as_f32(q), as_f32(b)
+    kw = dict(dx=(1 / 64,) * 3, gamma=1.4, rho_floor=1e-12, p_floor=1e-12, rho_protect=1e-3, p_protect=1e-3)
+    sim, orc = _run_pair(wmb, G, q, b, prec, 8, **kw)
+    assert sim.protected_faces() > 0
+    qg, bg = I.gather(G, [sim.get_state(i) for i in range(G.npatch)])
+    qo, bo = oracle_gather(G, orc)
+    _, _, _, nfl = sim.diagnostics()
+    assert nfl == 0 and qg[0].min() > 0
+    if prec == 0:
+        for c in range(8):
+            scale = np.abs(qo[1:4]).max() if 1 <= c <= 3 else (np.abs(qo[4:7]).max() if 4 <= c <= 6 else np.abs(qo[c]).max())
+            assert np.abs(qg[c] - qo[c]).max() <= 1e-10 * max(scale, 1e-300), c
+    else:
+        for c in (0, 7):
+            assert _rel_l1(qg[c], qo[c]) <= 1e-4, c
+    sim.close()
+    orc.close()
+
+
+def test_outflow_blast_all_walls_fp32(wmb):
+    """The walled blast of the FP64 test (24^3 as 8 patches, centre on a zone
+    centre, 6 steps) in FP32 against the FP64 oracle: relative L1 of rho and
+    E within 1e-5, normalised div b at FP32 round-off."""
+    N = 24
+    shape = (N, N, N)
+    dx = (1.0 / N,) * 3
+    (xc, yc, zc), _ = I.coords(shape, dx)
+    Z, Y, X = np.meshgrid(zc - zc[10], yc - yc[12], xc - xc[11], indexing="ij")
+    p = np.where(np.sqrt(X ** 2 + Y ** 2 + Z ** 2) < 0.1, 10.0, 0.1)
+    b = I.uniform_faces(shape, (0.5, 0.3, 0.0))
+    q = I.conserved(np.ones(shape), [np.zeros(shape)] * 3, I.face_average(b), p)
+    q, b = as_f32(q), as_f32(b)
+    G = I.uniform_grid(N, 12, periodic=(False, False, False))
+    sim = gpu_sim(wmb, G, q, b, 1, dx=dx)
+    orc = oracle_sim(G, q, b, dx=dx)
+    sim.run_steps(6)
+    for _ in range(6):
+        orc.fill_ghosts()
+        orc.advance(orc.compute_dt())
+    qg, _ = I.gather(G, [sim.get_state(i) for i in range(G.npatch)])
+    qo, _ = oracle_gather(G, orc)
+    for c in (0, 7):
+        assert _rel_l1(qg[c], qo[c]) <= 1e-5, c
+    _, dn, _, nfl = sim.diagnostics()
+    assert dn < 1e-5 and nfl == 0
+    sim.close()
+    orc.close()
