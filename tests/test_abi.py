@@ -63,3 +63,61 @@ def test_pool_bytes(lib):
     vol = 42 ** 3
     assert b32 >= 8 * 73 * vol * 4 and b64 >= 8 * 73 * vol * 8
     assert b64 == 2 * b32
+
+
+C_PROGRAM = r"""
+#include <stdio.h>
+#include <string.h>
+#include "wmb.h"
+
+int main(void) {
+    wmb_params p;
+    memset(&p, 0, sizeof p);
+    p.gamma = 5.0 / 3.0;
+    p.cfl = 0.4;
+    for (int k = 0; k < 7; k++) p.eps[k] = (k % 2 == 0) ? 0.1 : 0.0;
+    p.limiter_beta = 1.0;
+    p.rho_floor = 1e-10;
+    p.p_floor = 1e-10;
+    for (int a = 0; a < 3; a++) p.dx[a] = 1.0 / 32;
+    p.degen_tol = 1e-12;
+    p.ghost = 4;
+    p.precision = WMB_FP32;
+    wmb_ctx *c = NULL;
+    int rc = wmb_create(&p, &c);
+    int rc_bad;
+    p.dt_lag = 3;
+    {
+        wmb_ctx *d = NULL;
+        rc_bad = wmb_create(&p, &d);
+    }
+    printf("%zu %zu %d %d %s\n", sizeof(wmb_params), sizeof(wmb_patch_desc), rc, rc_bad, wmb_strerror(WMB_ESIZE));
+    return wmb_destroy(c);
+}
+"""
+
+
+def test_header_is_c_and_links(lib, tmp_path):
+    """The header compiles as C99 with gcc (-Wall -Werror); a C program links
+    against libwmb.so, creates and destroys a context and reads an error
+    string (no GPU needed); its struct sizes equal the ctypes binding's."""
+    import shutil
+    import subprocess
+
+    from paper_1701_07452_amd import build, wmb
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    src = tmp_path / "abi.c"
+    src.write_text(C_PROGRAM)
+    exe = tmp_path / "abi"
+    libdir = os.path.dirname(build.LIB)
+    cmd = ["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe),
+           "-L", libdir, "-l:libwmb.so", "-Wl,-rpath," + libdir, "-Wl,-rpath,/opt/rocm/lib"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stderr
+    sp, sd, rc, rc_bad, msg = out.stdout.split(" ", 4)
+    assert int(sp) == C.sizeof(wmb.Params) and int(sd) == C.sizeof(wmb.PatchDesc)
+    assert int(rc) == 0 and int(rc_bad) == wmb.WMB_EINVAL
+    assert msg.strip() == lib.wmb_strerror(wmb.WMB_ESIZE).decode()
