@@ -441,6 +441,28 @@ def test_c5_recipe_high_contrast_fp32_sampled(wmb):
     print("high-contrast 192^3 fp32 sampled worst rel max %.2e" % w)
 
 
+def test_full_size_determinism_256_fp32(wmb):
+    """P15 at full size with the concurrent step graph: two independent runs
+    of 3 steps of the 256^3 batch (512 x 32^3, FP32, ghost 4, graph replay
+    with concurrent sweep branches) end in bitwise the same state."""
+    import hashlib
+
+    q, b = I.turbulence(256)
+    G = I.uniform_grid(256, 32)
+    digests = []
+    for _ in range(2):
+        sim = gpu_sim(wmb, G, q, b, 1, dx=(1 / 256,) * 3, ghost=4)
+        sim.run_steps(3)
+        h = hashlib.sha256()
+        for ip in range(G.npatch):
+            qa, ba = sim.get_state(ip)
+            h.update(qa.tobytes())
+            h.update(ba.tobytes())
+        digests.append(h.hexdigest())
+        sim.close()
+    assert digests[0] == digests[1]
+
+
 @pytest.mark.skipif(os.environ.get("WMB_FULL_SIZE") != "1",
                     reason="768^3 needs a 210 GB pool and minutes of host set-up; run with WMB_FULL_SIZE=1")
 def test_c5_full_size_768_fp32_sampled(wmb):
