@@ -228,11 +228,16 @@ uint64_t region_bytes(const wmb_patch_desc& d, int g, size_t es) {
     return (b + 255) & ~uint64_t(255);
 }
 
+// largest interior edge accepted (keeps the box volume arithmetic far from
+// overflow; the 4 GiB region limit below is the binding one)
+constexpr int kMaxEdge = 65536;
+
 int check_table(int32_t np, const wmb_patch_desc* d, int g, size_t es, std::string& why) {
     for (int i = 0; i < np; i++) {
         for (int a = 0; a < 3; a++)
-            if (d[i].n[a] < g) {
-                why = "patch " + std::to_string(i) + ": interior edge smaller than the ghost width";
+            if (d[i].n[a] < g || d[i].n[a] > kMaxEdge) {
+                why = "patch " + std::to_string(i) + ": interior edge below the ghost width or above " +
+                      std::to_string(kMaxEdge);
                 return WMB_EINVAL;
             }
         // kernels address a patch region with 32-bit byte offsets
@@ -244,6 +249,14 @@ int check_table(int32_t np, const wmb_patch_desc* d, int g, size_t es, std::stri
             why = "patch " + std::to_string(i) + ": nbr[13] must be the patch itself";
             return WMB_EINVAL;
         }
+        for (int t = 0; t < 27; t++)
+            if (d[i].nbr[t] < -1 || d[i].nbr[t] >= np) {
+                why = "patch " + std::to_string(i) + ": neighbour id out of range";
+                return WMB_EINVAL;
+            }
+    }
+    // every id is in range from here on, so the chains below index d safely
+    for (int i = 0; i < np; i++) {
         for (int t = 0; t < 27; t++) {
             int q = d[i].nbr[t];
             int off[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
@@ -255,10 +268,6 @@ int check_table(int32_t np, const wmb_patch_desc* d, int g, size_t es, std::stri
             if (off[2] && r >= 0) r = d[r].nbr[9 * (off[2] + 1) + 4];
             if (off[1] && r >= 0) r = d[r].nbr[9 + 3 * (off[1] + 1) + 1];
             if (off[0] && r >= 0) r = d[r].nbr[12 + off[0] + 1];
-            if (q < -1 || q >= np) {
-                why = "patch " + std::to_string(i) + ": neighbour id out of range";
-                return WMB_EINVAL;
-            }
             if (r != q) {
                 why = "patch " + std::to_string(i) + ": edge/corner neighbour inconsistent with the face neighbours";
                 return WMB_EINVAL;
@@ -925,6 +934,9 @@ int wmb_create(const wmb_params* p, wmb_ctx** out) {
 
 int wmb_pool_bytes(const wmb_params* p, int32_t npatch, const wmb_patch_desc* d, uint64_t* bytes) {
     if (check_params(p) || npatch <= 0 || !d || !bytes) return WMB_EINVAL;
+    for (int i = 0; i < npatch; i++)
+        for (int a = 0; a < 3; a++)
+            if (d[i].n[a] < 1 || d[i].n[a] > kMaxEdge) return WMB_EINVAL;
     uint64_t tot = 0;
     for (int i = 0; i < npatch; i++) tot += region_bytes(d[i], p->ghost, esize_of(p));
     *bytes = tot;

@@ -121,3 +121,47 @@ def test_header_is_c_and_links(lib, tmp_path):
     assert int(sp) == C.sizeof(wmb.Params) and int(sd) == C.sizeof(wmb.PatchDesc)
     assert int(rc) == 0 and int(rc_bad) == wmb.WMB_EINVAL
     assert msg.strip() == lib.wmb_strerror(wmb.WMB_ESIZE).decode()
+
+
+def test_patch_table_checks_reject_malformed_tables(lib):
+    """wmb_init_patches validates the neighbour table before it touches the
+    device: random corruptions of a valid 3 x 2 x 2 table (ids out of range,
+    wrong self entry, asymmetric or inconsistent edges, bad extents, huge
+    edges) are all rejected with WMB_EINVAL, without a crash.  A table whose
+    corrupted entry points outside the patch list is checked before any chain
+    through it is followed.  (The valid table itself passes the check; on a
+    machine without a GPU the call then fails later, in HIP.)"""
+    import numpy as np
+
+    from paper_1701_07452_amd import inputs as I
+    from paper_1701_07452_amd import wmb
+
+    G = I.patch_grid([8, 8, 8], [8, 8], [8, 8], periodic=(True, False, True))
+    good = wmb.descs_to_c(G.descs, G.origin)
+    n = len(G.descs)
+    rng = np.random.default_rng(7)
+    cases = 0
+    for trial in range(400):
+        d = (wmb.PatchDesc * n)()
+        C.memmove(d, good, C.sizeof(d))
+        i = int(rng.integers(n))
+        kind = trial % 5
+        if kind == 0:  # id out of range (either side), on a face entry
+            d[i].nbr[int(rng.choice([4, 10, 12, 14, 16, 22]))] = int(rng.choice([-2, n, n + 1000, 2 ** 30]))
+        elif kind == 1:  # self entry
+            d[i].nbr[13] = (i + 1) % n
+        elif kind == 2:  # some other entry moved to another patch
+            t = int(rng.choice([t for t in range(27) if t != 13]))
+            d[i].nbr[t] = (d[i].nbr[t] + 1 + int(rng.integers(n - 1))) % n if d[i].nbr[t] >= 0 else int(rng.integers(n))
+        elif kind == 3:  # an extent that breaks the face-sharing rule, or below the ghost width
+            d[i].n[int(rng.integers(3))] = int(rng.choice([3, 9, 12]))
+        else:  # an absurd edge
+            d[i].n[int(rng.integers(3))] = int(rng.choice([70000, 2 ** 31 - 1]))
+        h = C.c_void_p()
+        p = wmb.make_params(ghost=4)
+        assert lib.wmb_create(C.byref(p), C.byref(h)) == 0
+        rc = lib.wmb_init_patches(h, n, d, C.c_void_p(1), C.c_uint64(1 << 40), None)
+        assert rc == wmb.WMB_EINVAL, (trial, kind, rc)
+        assert lib.wmb_destroy(h) == 0
+        cases += 1
+    assert cases == 400
