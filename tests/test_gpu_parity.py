@@ -164,6 +164,42 @@ def test_steps_fp64(wmb, case):
     sim.close()
 
 
+# The smallest patches the library accepts (an interior edge equal to the
+# ghost width: every zone is among the first and the last g of its row, so
+# the update pushes it to both x-neighbours) and ghost widths above the
+# stencil's 4; non-cubic patches, self-neighbours along z in the last case.
+EDGE_CASES = {
+    "g4_edge4": (4, lambda: I.patch_grid([4, 6], [4, 5], [4, 4])),
+    "g5_edge5": (5, lambda: I.patch_grid([5, 5], [5, 7], [6])),
+    "g7_edge7": (7, lambda: I.patch_grid([7, 9], [8], [7, 7])),
+}
+
+
+@pytest.mark.parametrize("case", sorted(EDGE_CASES))
+def test_minimum_patch_edges_fp64(wmb, case):
+    """FP64, 6 steps through the step graph (device dt) against the oracle on
+    its own dt: within 1e-11 of each field's scale; the step counts match."""
+    g, grid = EDGE_CASES[case]
+    G = grid()
+    N = G.shape
+    q, b = I.random_smooth(N, 17)
+    dx = (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
+    sim = gpu_sim(wmb, G, q, b, 0, dx=dx, ghost=g)
+    orc = oracle_sim(G, q, b, dx=dx, ghost=g)
+    sim.run_steps(6)
+    for _ in range(6):
+        orc.fill_ghosts()
+        orc.advance(orc.compute_dt())
+    qg, bg = I.gather(G, [sim.get_state(i) for i in range(G.npatch)])
+    qo, bo = oracle_gather(G, orc)
+    sim.close()
+    orc.close()
+    for c in range(8):
+        assert rel_max(qg[c], qo[c]) < 1e-11, (c, rel_max(qg[c], qo[c]))
+    for c in range(3):
+        assert rel_max(bg[c], bo[c]) < 1e-11
+
+
 def _rel_l1(a, ref):
     return float(np.abs(a - ref).sum() / np.abs(ref).sum())
 
