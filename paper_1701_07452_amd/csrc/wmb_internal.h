@@ -79,6 +79,13 @@ struct WorkItem {
     int c;  // sweeps: last pencil (inclusive); tiles: k0 | k1 << 16 (biased, k1 exclusive)
 };
 
+// Column tiles of the Steps 8-11 kernel: the largest tile plane (one thread a
+// zone, the block size).  FP32 may take 512 (fewer ring zones of E^r per tile
+// zone at the same occupancy) where the patches' tiles fill such blocks; FP64
+// (about 150 VGPRs) keeps 256, which lets three blocks share a CU where a
+// 512-thread block would run alone.
+constexpr int upd_tile_zones_max(int esize) { return esize == 4 ? 512 : 256; }
+
 // Box kernels: interior-relative inclusive ranges [lo, n + hi] per axis.
 struct Box {
     int lo, hi;

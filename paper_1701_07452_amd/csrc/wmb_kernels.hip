@@ -295,9 +295,9 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// block max (every thread of a 256-thread block must call) + atomicMax
+// block max (every thread of a block of at most 1024 threads must call) + atomicMax
 __device__ __forceinline__ void block_max_atomic(double s, unsigned long long* smax_bits) {
-    __shared__ double red[4];
+    __shared__ double red[16];
     s = wave_max(s);
     int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) red[wid] = s;
@@ -394,12 +394,19 @@ __device__ __forceinline__ R edge_combine(R Ea_0, R Ea_b, R Eb_0, R Eb_a, R ma_0
     return R(0.25) * ((Ea_0 - d1) + (Ea_b + d2) + (Eb_0 - d3) + (Eb_a + d4));
 }
 
-// Column tiles of the marching kernels: tx <= 40 (Steps 3-4) or 32 (Steps
-// 8-11), ty <= 32 and tx ty <= 256 zones per plane; LDS edge planes are
-// (tx+1)(ty+1) <= 297 long, E^r planes (tx+2)(ty+2) <= 340 (tx <= 32).
+// Column tiles of the marching kernels, ty <= 32.  Steps 3-4: tx <= 40 and
+// tx ty <= 256 zones per plane, LDS edge planes (tx+1)(ty+1) <= 297 long.
+// Steps 8-11: tx <= 32 and tx ty <= Z <= upd_tile_zones_max (the block size:
+// 256 or 512), so tx + ty <= 32 + Z/32: edge planes (tx+1)(ty+1) <= Z + 33 +
+// Z/32 long, E^r planes (tx+2)(ty+2) <= Z + 68 + Z/16.
 constexpr int TILE_THREADS = 256;
-constexpr int UPD_ERMAX = 340;
-constexpr int UPD_EDMAX = 297;
+constexpr int CTH_EDMAX = 297;
+template <typename R>
+struct UpdTile {
+    static constexpr int threads = upd_tile_zones_max((int)sizeof(R));
+    static constexpr int er = threads + 68 + threads / 16;
+    static constexpr int ed = threads + 33 + threads / 32;
+};
 constexpr int TILE_BIAS = 16;  // tile origins are stored biased (they may be negative)
 
 // q = r / m for r, m >= 1 with r m < 65536, from a 16-bit reciprocal
@@ -423,7 +430,7 @@ template <typename R>
 __global__ void __launch_bounds__(TILE_THREADS) ct_half_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
                                                                const WorkItem* __restrict__ work, Coef<R> cf, int ghost,
                                                                int cur, const StepConst* __restrict__ sc) {
-    __shared__ R s_ed[3 * 3 * UPD_EDMAX];  // [plane mod 3][component][j (tx+1) + i]
+    __shared__ R s_ed[3 * 3 * CTH_EDMAX];  // [plane mod 3][component][j (tx+1) + i]
     const WorkItem w = work[blockIdx.x];
     if (w.patch < 0) return;  // padding item (whole block)
     const PatchDev P = patches[w.patch];
@@ -460,7 +467,7 @@ __global__ void __launch_bounds__(TILE_THREADS) ct_half_kernel(R* __restrict__ p
     // (carried, loaded when fresh); replaced by those of plane p.
     auto ed_item = [&](int i, int j, int p, int mask, R(&cx)[4], R(&cy)[4], bool fresh) {
         const unsigned xo = zoff(i, j, p);
-        R* dst = s_ed + ((p + 3) % 3) * 3 * UPD_EDMAX + j * TXE + i;
+        R* dst = s_ed + ((p + 3) % 3) * 3 * CTH_EDMAX + j * TXE + i;
         if (mask & 1) {  // E_x: a = y, b = z
             if (fresh) {
                 cx[0] = ld(xo - s2, FY), cx[1] = ld(xo - s2, FY + 5 * VB);
@@ -480,14 +487,14 @@ __global__ void __launch_bounds__(TILE_THREADS) ct_half_kernel(R* __restrict__ p
             const R ma = ld(xo, FZ), fa5 = ld(xo, FZ + 5 * VB), mab = ld(xo - s0, FZ), fa5b = ld(xo - s0, FZ + 5 * VB);
             const R mb = ld(xo, FX), fb6 = ld(xo, FX + 6 * VB);
             const R e0 = ld(xo, ER + VB), eb = ld(xo - s0, ER + VB);
-            dst[UPD_EDMAX] = edge_combine(-fa5, -fa5b, fb6, cy[1], ma, mab, mb, cy[0], e0, cy[2], eb, cy[3]);
+            dst[CTH_EDMAX] = edge_combine(-fa5, -fa5b, fb6, cy[1], ma, mab, mb, cy[0], e0, cy[2], eb, cy[3]);
             cy[0] = mb, cy[1] = fb6, cy[2] = e0, cy[3] = eb;
         }
         if (mask & 4) {  // E_z: a = x, b = y
             const R ma = ld(xo, FX), fa5 = ld(xo, FX + 5 * VB), mab = ld(xo - s1, FX), fa5b = ld(xo - s1, FX + 5 * VB);
             const R mb = ld(xo, FY), fb6 = ld(xo, FY + 6 * VB), mba = ld(xo - s0, FY), fb6a = ld(xo - s0, FY + 6 * VB);
             const unsigned ez = ER + 2 * VB;
-            dst[2 * UPD_EDMAX] = edge_combine(-fa5, -fa5b, fb6, fb6a, ma, mab, mb, mba, ld(xo, ez), ld(xo - s0, ez),
+            dst[2 * CTH_EDMAX] = edge_combine(-fa5, -fa5b, fb6, fb6a, ma, mab, mb, mba, ld(xo, ez), ld(xo - s0, ez),
                                               ld(xo - s1, ez), ld(xo - s0 - s1, ez));
         }
     };
@@ -506,11 +513,11 @@ __global__ void __launch_bounds__(TILE_THREADS) ct_half_kernel(R* __restrict__ p
         if (owner) {
             const bool kz_in = k >= -1 && k <= P.n[2];
             const unsigned xo = zoff(zi, zj, k);
-            const R* ex0 = s_ed + ((k + 3) % 3) * 3 * UPD_EDMAX;  // E_x, plane k
-            const R* ey0 = ex0 + UPD_EDMAX;
-            const R* ez0 = ex0 + 2 * UPD_EDMAX;
-            const R* ex1 = s_ed + ((k + 4) % 3) * 3 * UPD_EDMAX;  // E_x, plane k+1
-            const R* ey1 = ex1 + UPD_EDMAX;
+            const R* ex0 = s_ed + ((k + 3) % 3) * 3 * CTH_EDMAX;  // E_x, plane k
+            const R* ey0 = ex0 + CTH_EDMAX;
+            const R* ez0 = ex0 + 2 * CTH_EDMAX;
+            const R* ex1 = s_ed + ((k + 4) % 3) * 3 * CTH_EDMAX;  // E_x, plane k+1
+            const R* ey1 = ex1 + CTH_EDMAX;
             if (jy_in && kz_in) {
                 R curl = (ez0[e + TXE] - ez0[e]) * iy - (ey1[e] - ey0[e]) * iz;
                 bstore(ld(xo, bs) - tau * curl, rs, xo, (unsigned)F_BH * VB);
@@ -529,7 +536,7 @@ __global__ void __launch_bounds__(TILE_THREADS) ct_half_kernel(R* __restrict__ p
 
 // ---------------------------------------------------------------------------
 // Steps 8-11 fused.  A block owns a column tile of zones [i0, i0+tx) x
-// [j0, j0+ty) (tx, ty <= 32, tx ty <= 256) over the planes [k0, k1) and
+// [j0, j0+ty) (tx, ty <= 32, tx ty <= its block size) over the planes [k0, k1) and
 // marches along z.  Iteration k forms
 //   phase 1  E^r on plane k+1 over the tile and a one-zone ring (Step 8:
 //            velocity of the unsplit half update of q^n with the Step-6/7
@@ -551,11 +558,12 @@ __global__ void __launch_bounds__(TILE_THREADS) ct_half_kernel(R* __restrict__ p
 // ---------------------------------------------------------------------------
 
 template <typename R>
-__global__ void __launch_bounds__(TILE_THREADS) update_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
+__global__ void __launch_bounds__(UpdTile<R>::threads) update_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
                                                               const WorkItem* __restrict__ work, DevParams prm, Coef<R> cf,
                                                               int cur, const StepConst* __restrict__ sc,
                                                               unsigned long long* __restrict__ nfloor,
                                                               unsigned long long* __restrict__ smax_bits, int keep_edges) {
+    constexpr int UPD_ERMAX = UpdTile<R>::er, UPD_EDMAX = UpdTile<R>::ed;
     __shared__ R s_er[2 * 3 * UPD_ERMAX];  // [plane & 1][component][(ey+1)(tx+2) + ex+1]
     __shared__ R s_ed[2 * 3 * UPD_EDMAX];  // [plane & 1][component][j (tx+1) + i]
     const WorkItem w = work[blockIdx.x];
@@ -1335,9 +1343,10 @@ hipError_t launch_ct_half(void* pool, const PatchDev* pt, const WorkItem* wk, in
 template <typename R>
 hipError_t launch_update(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm,
                          const Coef<R>& cf, int cur, const StepConst* sc, unsigned long long* nfl, unsigned long long* smax,
-                         int keep_edges, hipStream_t st) {
+                         int keep_edges, int threads, hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(update_kernel<R>, dim3(nblk), dim3(TILE_THREADS), 0, st, (R*)pool, pt, wk, prm, cf, cur, sc, nfl,
+    if (threads < 64 || threads > UpdTile<R>::threads || threads % 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(update_kernel<R>, dim3(nblk), dim3(threads), 0, st, (R*)pool, pt, wk, prm, cf, cur, sc, nfl,
                        smax, keep_edges);
     return hipGetLastError();
 }
@@ -1392,7 +1401,7 @@ hipError_t launch_diag(const void* pool, const PatchDev* pt, const WorkItem* wk,
     template hipError_t launch_ct_half<R>(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int,        \
                                           const StepConst*, hipStream_t);                                                \
     template hipError_t launch_update<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, \
-                                         int, const StepConst*, unsigned long long*, unsigned long long*, int,          \
+                                         int, const StepConst*, unsigned long long*, unsigned long long*, int, int,     \
                                          hipStream_t);                                                                   \
     template hipError_t launch_sweep<R>(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&,        \
                                         const Coef<R>&, int, const StepConst*, int, int, int, unsigned long long*,       \

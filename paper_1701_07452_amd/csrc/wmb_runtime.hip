@@ -19,7 +19,7 @@ template <typename R> hipError_t launch_dt_reduce(void*, const PatchDev*, const 
 hipError_t launch_dt_finalize(unsigned long long*, StepConst*, const DevParams&, hipStream_t);
 hipError_t launch_set_dt(StepConst*, double, const DevParams&, hipStream_t);
 template <typename R> hipError_t launch_ct_half(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int, const StepConst*, hipStream_t);
-template <typename R> hipError_t launch_update(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, unsigned long long*, unsigned long long*, int, hipStream_t);
+template <typename R> hipError_t launch_update(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, unsigned long long*, unsigned long long*, int, int, hipStream_t);
 template <typename R> hipError_t launch_sweep(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, int, int, int, unsigned long long*, hipStream_t);
 template <typename R> hipError_t launch_diag(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, double*, hipStream_t);
 }  // namespace wmb
@@ -73,6 +73,7 @@ struct wmb_ctx {
     PatchDev* d_patch = nullptr;
     DevList wl_fill[3];
     DevList wl_int, wl_diag, wl_cth, wl_upd;
+    int upd_zones = 256;  // zones a tile plane of Steps 8-11 (the update's block size)
     bool keep_edges = false;  // Steps 8-11 also store the Step-9 edges (debugging)
     bool xg_valid = false;    // the current copy's x-ghosts (interior rows) hold the neighbours' values
     bool edges_kept = false;  // the last step stored them
@@ -399,7 +400,7 @@ int run_step(wmb_ctx* c, bool split = false) {
         }
     }
     e = launch_update<R>(c->pool, c->d_patch, c->wl_upd.d, c->wl_upd.n, c->dp, coef<R>(c), cur, c->d_sc, c->d_nfloor,
-                         c->d_smax, c->keep_edges ? 1 : 0, c->stream);
+                         c->d_smax, c->keep_edges ? 1 : 0, c->upd_zones, c->stream);
     STEPCK("update");
     mark(c);
     c->edges_kept = c->keep_edges;
@@ -455,19 +456,19 @@ int build_box_list(wmb_ctx* c, Box bx, DevList& out, bool xcd = true) {
 // Column tiles of the marching kernels over the in-plane box [lo, n+hi]^2
 // (x, y) and the planes [zlo, n+zhi]: each patch's box is cut into near-equal
 // parts of at most txmax zones along x (whole rows where they fit, so tile
-// rows cut no cache lines), then along y into parts with at most 256 zones
+// rows cut no cache lines), then along y into parts with at most maxz zones
 // per tile plane and 32 per edge.  Item fields (origins biased by 16, they
 // may be negative): a = i0 | j0 << 16, b = tx | ty << 16, c = k0 | k1 << 16
 // with k1 exclusive.
 constexpr int TILE_BIAS = 16;
-int build_tile_list(wmb_ctx* c, int lo, int hi, int zlo, int zhi, int txmax_allowed, DevList& out) {
+int build_tile_list(wmb_ctx* c, int lo, int hi, int zlo, int zhi, int txmax_allowed, int maxz, DevList& out) {
     std::vector<WorkItem> items;
     for (int p = 0; p < c->npatch; p++) {
         const int* n = c->desc[p].n;
         const int ex = n[0] + hi - lo + 1, ey = n[1] + hi - lo + 1;
         const int mx = (ex + txmax_allowed - 1) / txmax_allowed;
         const int txmax = (ex + mx - 1) / mx;
-        int tymax = 256 / txmax;
+        int tymax = maxz / txmax;
         if (tymax > 32) tymax = 32;
         const int my = (ey + tymax - 1) / tymax;
         const int k0 = zlo + TILE_BIAS, k1 = n[2] + zhi + 1 + TILE_BIAS;
@@ -483,6 +484,30 @@ int build_tile_list(wmb_ctx* c, int lo, int hi, int zlo, int zhi, int txmax_allo
     items = xcd_order(items);
     out.n = (int)items.size();
     return upload(c, &out.d, items);
+}
+
+// Zones a tile plane of Steps 8-11 (the update's block size): the largest
+// that upd_tile_zones_max allows, unless the patches' tiles would leave more
+// of its threads idle than 256-zone tiles do (patches whose x-y planes hold
+// fewer zones than a block)
+int choose_upd_zones(const wmb_ctx* c) {
+    const int zmax = upd_tile_zones_max((int)c->esize);
+    if (zmax <= 256) return 256;
+    const int Z[2] = {256, zmax};
+    double fill[2];
+    for (int v = 0; v < 2; v++) {
+        long long zones = 0, slots = 0;
+        for (int p = 0; p < c->npatch; p++) {
+            // the column-tile cut of build_tile_list for the interior x-y plane
+            const int ex = c->desc[p].n[0], ey = c->desc[p].n[1];
+            const int mx = (ex + 31) / 32, txmax = (ex + mx - 1) / mx;
+            const int tymax = std::min(32, Z[v] / txmax), my = (ey + tymax - 1) / tymax;
+            zones += (long long)ex * ey;
+            slots += (long long)mx * my * Z[v];
+        }
+        fill[v] = (double)zones / (double)slots;
+    }
+    return fill[1] >= fill[0] ? zmax : 256;
 }
 
 int build_fill_lists(wmb_ctx* c) {
@@ -990,10 +1015,12 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     if ((rc = build_fill_lists(c))) return rc;
     if ((rc = build_box_list(c, BOX_INTERIOR, c->wl_int))) return rc;
     if ((rc = build_box_list(c, BOX_INTERIOR, c->wl_diag, false))) return rc;
-    // Steps 3-4: tiles up to 40 zones wide ((tx+1)(ty+1) <= 297 edges a plane);
-    // Steps 8-11: up to 32 ((tx+2)(ty+2) <= 340 E^r zones a plane)
-    if ((rc = build_tile_list(c, -2, 2, -2, 2, 40, c->wl_cth))) return rc;
-    if ((rc = build_tile_list(c, 0, -1, 0, -1, 32, c->wl_upd))) return rc;
+    // Steps 3-4: tiles up to 40 zones wide and 256 a plane ((tx+1)(ty+1) <= 297
+    // edges); Steps 8-11: up to 32 wide and upd_tile_zones a plane (the LDS
+    // planes of the kernel are sized for both)
+    if ((rc = build_tile_list(c, -2, 2, -2, 2, 40, 256, c->wl_cth))) return rc;
+    c->upd_zones = choose_upd_zones(c);
+    if ((rc = build_tile_list(c, 0, -1, 0, -1, 32, c->upd_zones, c->wl_upd))) return rc;
     if ((rc = build_sweeps(c))) return rc;
     if ((rc = dev_alloc(c, &c->d_smax, 2))) return rc;
     if ((rc = dev_alloc(c, &c->d_sc, 1))) return rc;
