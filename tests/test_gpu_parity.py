@@ -3,7 +3,7 @@
 Bars: ghost exchange bitwise; FP64 path within 1e-11 of the oracle's scale
 after several steps (FMA contraction and the algebraically equivalent
 characteristic projection are the only differences); FP32 path within the
-spec tolerance (relative L1 <= 1e-5 on rho and E after 10 steps,
+target tolerance (relative L1 <= 1e-5 on rho and E after 10 steps,
 normalised div b <= 1e-6); graph replay, determinism and restart bitwise.
 """
 import math
@@ -526,7 +526,7 @@ def test_c5_full_size_768_fp32_sampled(wmb):
 
 @pytest.mark.slow
 def test_accuracy_report_256_10_steps(wmb):
-    """North-star accuracy on the benchmark workload (256^3 as 512 x 32^3,
+    """Accuracy against the target tolerance on the benchmark workload (256^3 as 512 x 32^3,
     ghost 4) after 10 steps: GPU FP32 batch and GPU FP64 batch against the FP64
     oracle over the whole box.  FP32: relative L1 <= 1e-5 on rho and E,
     normalised div b <= 1e-6; FP64: <= 1e-12."""
