@@ -243,8 +243,15 @@ def test_steps_fp32_tolerance(wmb, setup):
     sim.close()
 
 
-def test_run_steps_graph_equals_eager_and_determinism(wmb):
-    G, (q, b) = CASES["uneven"]()
+@pytest.mark.parametrize("grid", ["uneven", "cube32"])
+def test_run_steps_graph_equals_eager_and_determinism(wmb, grid):
+    """Graph replay (concurrent branches) equals eager launches, and two
+    graph runs agree, bitwise.  FP32; the 32^3 patches of cube32 run the
+    Steps 8-11 kernel on 512-zone tiles."""
+    if grid == "uneven":
+        G, (q, b) = CASES["uneven"]()
+    else:
+        G, (q, b) = I.uniform_grid(64, 32), I.random_smooth((64, 64, 64), 14)
     N = G.shape
     dx = (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
     outs = []
