@@ -426,6 +426,18 @@ def test_full_size_uneven_400_fp32_sampled(wmb):
     print("uneven fp32 sampled worst rel max %.2e" % w)
 
 
+def test_full_size_uneven_400_fp64_sampled(wmb):
+    """Uneven batch in FP64: the largest and the smallest patch and one more,
+    recomputed by the oracle, within 1e-12 of each field's scale."""
+    G = I.uneven_grid()
+    Nz, Ny, Nx = G.shape
+    q, b = I.turbulence(None, seed=170107454, shape=G.shape, box=(Nx / 256, Ny / 256, Nz / 256))
+    sizes = [np.prod(n) for n, _ in G.descs]
+    samples = [int(np.argmax(sizes)), int(np.argmin(sizes)), 211]
+    w = _sampled_full_size(wmb, G, q, b, 0, samples, 1e-12, 1e-13, dx=(1 / 256,) * 3)
+    print("uneven fp64 sampled worst rel max %.2e" % w)
+
+
 def test_autotune_does_not_change_results(wmb):
     """The sweep block shape is a scheduling choice only: results bitwise equal."""
     G, (q, b) = CASES["uneven"]()
