@@ -148,10 +148,12 @@ int dev_alloc(wmb_ctx* c, T** ptr, size_t count) {
 // run on one XCD, in their original order: block id 8 j + x takes the j-th
 // item of XCD x's queue.  Patches go to XCDs by their item count in this list,
 // largest first, each to the least loaded XCD (so that neither the patch
-// numbering nor uneven patch sizes leave XCDs idle); queues are padded with
-// empty items (patch = -1) that exit at once.
+// numbering nor uneven patch sizes leave XCDs idle), or, where the caller
+// asks for it and every patch has as many items, in contiguous runs of the
+// list order; queues are padded with empty items (patch = -1) that exit at
+// once.
 constexpr int NXCD = 8;
-std::vector<WorkItem> xcd_order(const std::vector<WorkItem>& items) {
+std::vector<WorkItem> xcd_order(const std::vector<WorkItem>& items, bool contiguous = false) {
     // item count and first appearance of every patch in the list
     std::vector<int> order;
     std::vector<long long> count;
@@ -177,12 +179,23 @@ std::vector<WorkItem> xcd_order(const std::vector<WorkItem>& items) {
         xcd_of[i] = best;
         load[best] += count[i];
     }
-    // each XCD's queue: its patches largest first, items of a patch in list order
     std::vector<std::vector<WorkItem>> q(NXCD);
     std::vector<std::vector<WorkItem>> per(order.size());
     for (const WorkItem& w : items) per[slot[w.patch]].push_back(w);
-    for (int i : byload)
-        for (const WorkItem& w : per[i]) q[xcd_of[i]].push_back(w);
+    if (contiguous && !order.empty() &&
+        std::all_of(count.begin(), count.end(), [&](long long v) { return v == count[0]; })) {
+        // patches in list order (spatial, x fastest) cut into NXCD runs of
+        // near-equal length, each run's items in list order: x- and
+        // y-neighbours share an XCD and its L2.  Asked for by lists of
+        // identical patches only (equal item counts then mean equal work).
+        const long long np = (long long)order.size();
+        for (long long i = 0; i < np; i++)
+            for (const WorkItem& w : per[i]) q[(int)((2 * i + 1) * NXCD / (2 * np))].push_back(w);
+    } else {
+        // each XCD's queue: its patches largest first, items of a patch in list order
+        for (int i : byload)
+            for (const WorkItem& w : per[i]) q[xcd_of[i]].push_back(w);
+    }
     size_t len = 0;
     for (auto& v : q) len = v.size() > len ? v.size() : len;
     std::vector<WorkItem> out;
@@ -461,7 +474,17 @@ int build_box_list(wmb_ctx* c, Box bx, DevList& out, bool xcd = true) {
 // may be negative): a = i0 | j0 << 16, b = tx | ty << 16, c = k0 | k1 << 16
 // with k1 exclusive.
 constexpr int TILE_BIAS = 16;
-int build_tile_list(wmb_ctx* c, int lo, int hi, int zlo, int zhi, int txmax_allowed, int maxz, DevList& out) {
+// every patch has the same interior extents (then equal item counts in a
+// list mean equal work, and xcd_order may cut the patches into runs)
+bool same_shape(const wmb_ctx* c) {
+    for (int p = 1; p < c->npatch; p++)
+        for (int a = 0; a < 3; a++)
+            if (c->desc[p].n[a] != c->desc[0].n[a]) return false;
+    return true;
+}
+
+int build_tile_list(wmb_ctx* c, int lo, int hi, int zlo, int zhi, int txmax_allowed, int maxz, bool contiguous,
+                    DevList& out) {
     std::vector<WorkItem> items;
     for (int p = 0; p < c->npatch; p++) {
         const int* n = c->desc[p].n;
@@ -481,7 +504,7 @@ int build_tile_list(wmb_ctx* c, int lo, int hi, int zlo, int zhi, int txmax_allo
             }
         }
     }
-    items = xcd_order(items);
+    items = xcd_order(items, contiguous);
     out.n = (int)items.size();
     return upload(c, &out.d, items);
 }
@@ -526,7 +549,7 @@ int build_fill_lists(wmb_ctx* c) {
             int nb = (int)((e + 255) / 256);
             for (int b = 0; b < nb; b++) items.push_back(WorkItem{p, b, 0, 0});
         }
-        items = xcd_order(items);
+        items = xcd_order(items, same_shape(c));
         c->wl_fill[ax].n = (int)items.size();
         int rc = upload(c, &c->wl_fill[ax].d, items);
         if (rc) return rc;
@@ -1018,9 +1041,13 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     // Steps 3-4: tiles up to 40 zones wide and 256 a plane ((tx+1)(ty+1) <= 297
     // edges); Steps 8-11: up to 32 wide and upd_tile_zones a plane (the LDS
     // planes of the kernel are sized for both)
-    if ((rc = build_tile_list(c, -2, 2, -2, 2, 40, 256, c->wl_cth))) return rc;
+    if ((rc = build_tile_list(c, -2, 2, -2, 2, 40, 256, false, c->wl_cth))) return rc;
     c->upd_zones = choose_upd_zones(c);
-    if ((rc = build_tile_list(c, 0, -1, 0, -1, 32, c->upd_zones, c->wl_upd))) return rc;
+    // the update and the ghost exchange take contiguous runs of identical
+    // patches per XCD, so that a patch's x- and y-neighbours run on its XCD
+    // (256^3 FP32: update 1.14 against 1.24 ms at the same measured HBM
+    // traffic); the sweeps keep the balanced order, which measured faster
+    if ((rc = build_tile_list(c, 0, -1, 0, -1, 32, c->upd_zones, same_shape(c), c->wl_upd))) return rc;
     if ((rc = build_sweeps(c))) return rc;
     if ((rc = dev_alloc(c, &c->d_smax, 2))) return rc;
     if ((rc = dev_alloc(c, &c->d_sc, 1))) return rc;
