@@ -1044,9 +1044,10 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     if ((rc = build_tile_list(c, -2, 2, -2, 2, 40, 256, false, c->wl_cth))) return rc;
     c->upd_zones = choose_upd_zones(c);
     // the update and the ghost exchange take contiguous runs of identical
-    // patches per XCD, so that a patch's x- and y-neighbours run on its XCD
-    // (256^3 FP32: update 1.14 against 1.24 ms at the same measured HBM
-    // traffic); the sweeps keep the balanced order, which measured faster
+    // patches per XCD, so that the update's x-ghost pushes go to a patch on
+    // the same XCD (256^3 FP32: update 1.14 against 1.24 ms at the same
+    // measured HBM traffic; runs that put x-neighbours on other XCDs measured
+    // 1.24 ms too); the sweeps keep the balanced order, which measured faster
     if ((rc = build_tile_list(c, 0, -1, 0, -1, 32, c->upd_zones, same_shape(c), c->wl_upd))) return rc;
     if ((rc = build_sweeps(c))) return rc;
     if ((rc = dev_alloc(c, &c->d_smax, 2))) return rc;
