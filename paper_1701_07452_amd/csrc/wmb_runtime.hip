@@ -144,57 +144,44 @@ int dev_alloc(wmb_ctx* c, T** ptr, size_t count) {
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin by workgroup id, and
-// each XCD has its own L2.  Reorder a work list so that all blocks of a patch
-// run on one XCD, in their original order: block id 8 j + x takes the j-th
-// item of XCD x's queue.  Patches go to XCDs by their item count in this list,
-// largest first, each to the least loaded XCD (so that neither the patch
-// numbering nor uneven patch sizes leave XCDs idle), or, where the caller
-// asks for it and every patch has as many items, in contiguous runs of the
-// list order; queues are padded with empty items (patch = -1) that exit at
-// once.
+// each XCD has its own L2.  Reorder a work list so that all blocks of a unit
+// (a patch, or a group of patches the caller names) run on one XCD, in their
+// original order: block id 8 j + x takes the j-th item of XCD x's queue.
+// Units go to XCDs by their work in this list (items, or for column tiles
+// zones x planes), largest first, each to the least loaded XCD (so that
+// neither the patch numbering nor uneven patch sizes leave XCDs idle); each
+// queue takes its units largest first.  Queues are padded with empty items
+// (patch = -1) that exit at once.
 constexpr int NXCD = 8;
-std::vector<WorkItem> xcd_order(const std::vector<WorkItem>& items, bool contiguous = false) {
-    // item count and first appearance of every patch in the list
-    std::vector<int> order;
-    std::vector<long long> count;
-    std::vector<int> slot;  // patch -> index in order
+std::vector<WorkItem> xcd_order(const std::vector<WorkItem>& items, const std::vector<int>* group = nullptr,
+                                bool tiles = false) {
+    // work and first appearance of every unit in the list
+    std::vector<int> slot;  // unit -> index in order
+    std::vector<long long> work;
+    std::vector<std::vector<WorkItem>> per;
     for (const WorkItem& w : items) {
-        if (w.patch >= (int)slot.size()) slot.resize(w.patch + 1, -1);
-        if (slot[w.patch] < 0) {
-            slot[w.patch] = (int)order.size();
-            order.push_back(w.patch);
-            count.push_back(0);
+        const int u = group ? (*group)[w.patch] : w.patch;
+        if (u >= (int)slot.size()) slot.resize(u + 1, -1);
+        if (slot[u] < 0) {
+            slot[u] = (int)per.size();
+            per.emplace_back();
+            work.push_back(0);
         }
-        count[slot[w.patch]]++;
+        const long long wt = tiles ? (long long)(w.b & 0xffff) * (w.b >> 16) * ((w.c >> 16) - (w.c & 0xffff)) : 1;
+        work[slot[u]] += wt;
+        per[slot[u]].push_back(w);
     }
-    std::vector<int> byload(order.size());
+    std::vector<int> byload(per.size());
     for (size_t i = 0; i < byload.size(); i++) byload[i] = (int)i;
-    std::stable_sort(byload.begin(), byload.end(), [&](int a, int b) { return count[a] > count[b]; });
-    std::vector<int> xcd_of(order.size(), 0);
+    std::stable_sort(byload.begin(), byload.end(), [&](int a, int b) { return work[a] > work[b]; });
     long long load[NXCD] = {0};
+    std::vector<std::vector<WorkItem>> q(NXCD);
     for (int i : byload) {
         int best = 0;
         for (int x = 1; x < NXCD; x++)
             if (load[x] < load[best]) best = x;
-        xcd_of[i] = best;
-        load[best] += count[i];
-    }
-    std::vector<std::vector<WorkItem>> q(NXCD);
-    std::vector<std::vector<WorkItem>> per(order.size());
-    for (const WorkItem& w : items) per[slot[w.patch]].push_back(w);
-    if (contiguous && !order.empty() &&
-        std::all_of(count.begin(), count.end(), [&](long long v) { return v == count[0]; })) {
-        // patches in list order (spatial, x fastest) cut into NXCD runs of
-        // near-equal length, each run's items in list order: x- and
-        // y-neighbours share an XCD and its L2.  Asked for by lists of
-        // identical patches only (equal item counts then mean equal work).
-        const long long np = (long long)order.size();
-        for (long long i = 0; i < np; i++)
-            for (const WorkItem& w : per[i]) q[(int)((2 * i + 1) * NXCD / (2 * np))].push_back(w);
-    } else {
-        // each XCD's queue: its patches largest first, items of a patch in list order
-        for (int i : byload)
-            for (const WorkItem& w : per[i]) q[xcd_of[i]].push_back(w);
+        load[best] += work[i];
+        for (const WorkItem& w : per[i]) q[best].push_back(w);
     }
     size_t len = 0;
     for (auto& v : q) len = v.size() > len ? v.size() : len;
@@ -474,17 +461,28 @@ int build_box_list(wmb_ctx* c, Box bx, DevList& out, bool xcd = true) {
 // may be negative): a = i0 | j0 << 16, b = tx | ty << 16, c = k0 | k1 << 16
 // with k1 exclusive.
 constexpr int TILE_BIAS = 16;
-// every patch has the same interior extents (then equal item counts in a
-// list mean equal work, and xcd_order may cut the patches into runs)
-bool same_shape(const wmb_ctx* c) {
-    for (int p = 1; p < c->npatch; p++)
-        for (int a = 0; a < 3; a++)
-            if (c->desc[p].n[a] != c->desc[0].n[a]) return false;
-    return true;
+// x-rows: patches linked by their x face neighbours (a periodic ring or a
+// chain between domain boundaries), numbered by their smallest patch id;
+// the unit of xcd_order for the update and the ghost exchange
+std::vector<int> x_rows(const wmb_ctx* c) {
+    std::vector<int> row(c->npatch, -1), seen(c->npatch, -1);
+    for (int p = 0; p < c->npatch; p++) {
+        if (row[p] >= 0) continue;
+        std::vector<int> members{p};
+        seen[p] = p;
+        for (int dir = 0; dir < 2; dir++)  // walk -x, then +x
+            for (int q = c->hpatch[p].nb[dir]; q >= 0 && seen[q] != p; q = c->hpatch[q].nb[dir]) {
+                seen[q] = p;
+                members.push_back(q);
+            }
+        const int id = *std::min_element(members.begin(), members.end());
+        for (int m : members) row[m] = id;
+    }
+    return row;
 }
 
-int build_tile_list(wmb_ctx* c, int lo, int hi, int zlo, int zhi, int txmax_allowed, int maxz, bool contiguous,
-                    DevList& out) {
+int build_tile_list(wmb_ctx* c, int lo, int hi, int zlo, int zhi, int txmax_allowed, int maxz,
+                    const std::vector<int>* group, DevList& out) {
     std::vector<WorkItem> items;
     for (int p = 0; p < c->npatch; p++) {
         const int* n = c->desc[p].n;
@@ -504,7 +502,7 @@ int build_tile_list(wmb_ctx* c, int lo, int hi, int zlo, int zhi, int txmax_allo
             }
         }
     }
-    items = xcd_order(items, contiguous);
+    items = xcd_order(items, group, true);
     out.n = (int)items.size();
     return upload(c, &out.d, items);
 }
@@ -535,6 +533,7 @@ int choose_upd_zones(const wmb_ctx* c) {
 
 int build_fill_lists(wmb_ctx* c) {
     const int g = c->p.ghost;
+    const std::vector<int> rows = x_rows(c);
     for (int ax = 0; ax < 3; ax++) {
         std::vector<WorkItem> items;
         for (int p = 0; p < c->npatch; p++) {
@@ -549,7 +548,7 @@ int build_fill_lists(wmb_ctx* c) {
             int nb = (int)((e + 255) / 256);
             for (int b = 0; b < nb; b++) items.push_back(WorkItem{p, b, 0, 0});
         }
-        items = xcd_order(items, same_shape(c));
+        items = xcd_order(items, &rows);
         c->wl_fill[ax].n = (int)items.size();
         int rc = upload(c, &c->wl_fill[ax].d, items);
         if (rc) return rc;
@@ -1041,14 +1040,16 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     // Steps 3-4: tiles up to 40 zones wide and 256 a plane ((tx+1)(ty+1) <= 297
     // edges); Steps 8-11: up to 32 wide and upd_tile_zones a plane (the LDS
     // planes of the kernel are sized for both)
-    if ((rc = build_tile_list(c, -2, 2, -2, 2, 40, 256, false, c->wl_cth))) return rc;
+    if ((rc = build_tile_list(c, -2, 2, -2, 2, 40, 256, nullptr, c->wl_cth))) return rc;
     c->upd_zones = choose_upd_zones(c);
-    // the update and the ghost exchange take contiguous runs of identical
-    // patches per XCD, so that the update's x-ghost pushes go to a patch on
-    // the same XCD (256^3 FP32: update 1.14 against 1.24 ms at the same
-    // measured HBM traffic; runs that put x-neighbours on other XCDs measured
-    // 1.24 ms too); the sweeps keep the balanced order, which measured faster
-    if ((rc = build_tile_list(c, 0, -1, 0, -1, 32, c->upd_zones, same_shape(c), c->wl_upd))) return rc;
+    // the update and the ghost exchange place whole x-rows of patches on an
+    // XCD, so that the update's x-ghost pushes go to a patch on the same XCD:
+    // 256^3 FP32 update 1.14 against 1.24 ms, the uneven batch 1.80 against
+    // 2.04 ms, at the same measured HBM traffic (orders that put x-neighbours
+    // on other XCDs measured 1.24 ms at 256^3).  The sweeps keep one patch a
+    // unit, which measured faster for them.
+    const std::vector<int> rows = x_rows(c);
+    if ((rc = build_tile_list(c, 0, -1, 0, -1, 32, c->upd_zones, &rows, c->wl_upd))) return rc;
     if ((rc = build_sweeps(c))) return rc;
     if ((rc = dev_alloc(c, &c->d_smax, 2))) return rc;
     if ((rc = dev_alloc(c, &c->d_sc, 1))) return rc;
