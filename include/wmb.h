@@ -205,10 +205,13 @@ int wmb_autotune(wmb_ctx *c, int32_t reps, int32_t *chosen, int32_t nchosen);
    Invalidates the captured graphs. */
 int wmb_set_tuning(wmb_ctx *c, const int32_t *quads, int32_t n);
 
-/* Freeze (active = 0) or thaw (active != 0) one patch without touching the
-   launch plan or the captured graphs (Sect. 2.1: patches may become
-   inactive, left out of the update, for load balancing and mesh refinement;
-   here its pool memory stays reserved).  A frozen
+/* Freeze (active = 0) or thaw (active != 0) one patch without rebuilding
+   the launch plan (Sect. 2.1: patches may become inactive, left out of the
+   update, for load balancing and mesh refinement; here its pool memory stays
+   reserved).  The captured graphs stay valid, except that the first freeze
+   and the last thaw of a batch whose update runs on 512-zone tiles switch it
+   to its prepared 256-zone tiles and back; the next wmb_run_steps then
+   captures the graphs again.  A frozen
    patch keeps its state: no kernel updates it, it adds nothing to the CFL
    maximum or to the floor and protection counters, and it serves its
    neighbours as fixed ghost data (its work items exit at once).  Its state

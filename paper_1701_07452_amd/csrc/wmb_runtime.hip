@@ -72,8 +72,9 @@ struct wmb_ctx {
     int cur = 0;
     PatchDev* d_patch = nullptr;
     DevList wl_fill[3];
-    DevList wl_int, wl_diag, wl_cth, wl_upd;
+    DevList wl_int, wl_diag, wl_cth, wl_upd, wl_upd256;
     int upd_zones = 256;  // zones a tile plane of Steps 8-11 (the update's block size)
+    int nfrozen = 0;      // frozen patches; while any, Steps 8-11 run on 256-zone tiles
     bool keep_edges = false;  // Steps 8-11 also store the Step-9 edges (debugging)
     bool xg_valid = false;    // the current copy's x-ghosts (interior rows) hold the neighbours' values
     bool edges_kept = false;  // the last step stored them
@@ -399,8 +400,13 @@ int run_step(wmb_ctx* c, bool split = false) {
             mark(c);
         }
     }
-    e = launch_update<R>(c->pool, c->d_patch, c->wl_upd.d, c->wl_upd.n, c->dp, coef<R>(c), cur, c->d_sc, c->d_nfloor,
-                         c->d_smax, c->keep_edges ? 1 : 0, c->upd_zones, c->stream);
+    // with frozen patches the 256-zone tiles (whose blocks of frozen patches
+    // exit at once) measured faster: 1.01 against 1.56 ms with every other
+    // patch of 256^3 FP32 frozen, against 1.19 and 1.14 ms with all active
+    const bool t256 = c->nfrozen > 0 && c->upd_zones != 256;
+    const DevList& wu = t256 ? c->wl_upd256 : c->wl_upd;
+    e = launch_update<R>(c->pool, c->d_patch, wu.d, wu.n, c->dp, coef<R>(c), cur, c->d_sc, c->d_nfloor, c->d_smax,
+                         c->keep_edges ? 1 : 0, t256 ? 256 : c->upd_zones, c->stream);
     STEPCK("update");
     mark(c);
     c->edges_kept = c->keep_edges;
@@ -1050,6 +1056,8 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     // unit, which measured faster for them.
     const std::vector<int> rows = x_rows(c);
     if ((rc = build_tile_list(c, 0, -1, 0, -1, 32, c->upd_zones, &rows, c->wl_upd))) return rc;
+    if (c->upd_zones != 256 && (rc = build_tile_list(c, 0, -1, 0, -1, 32, 256, &rows, c->wl_upd256))) return rc;
+    c->nfrozen = 0;
     if ((rc = build_sweeps(c))) return rc;
     if ((rc = dev_alloc(c, &c->d_smax, 2))) return rc;
     if ((rc = dev_alloc(c, &c->d_sc, 1))) return rc;
@@ -1234,6 +1242,10 @@ int wmb_set_active(wmb_ctx* c, int32_t patch, int32_t active) {
     P.active = on;
     CKH(hipMemcpyAsync(c->d_patch + patch, &P, sizeof(PatchDev), hipMemcpyHostToDevice, c->stream));
     CKH(hipStreamSynchronize(c->stream));
+    // the first freeze and the last thaw switch the Steps 8-11 tiles (the
+    // captured graphs hold the launch, so they are captured again)
+    c->nfrozen += on ? -1 : 1;
+    if (c->upd_zones != 256 && c->nfrozen == (on ? 0 : 1)) free_graphs(c);
     // the folded signal-speed maximum no longer covers the active set
     if (c->smax_state == SMAX_CLEAN) c->smax_state = SMAX_DIRTY;
     c->xg_valid = false;

@@ -798,6 +798,36 @@ def test_frozen_patches_fp64(wmb):
     orc.close()
 
 
+def test_frozen_patches_fp32_512_zone_tiles(wmb):
+    """FP32 on 32^3 patches, whose update runs on 512-zone tiles while every
+    patch is active and on 256-zone tiles while any is frozen (the first
+    freeze and the last thaw switch them and re-capture the graphs): two of
+    eight patches frozen for 3 steps, both thawed for 2 more.  Frozen states
+    bitwise unchanged while frozen; rho and E within 1e-5 relative L1 of the
+    FP64 oracle driven the same way."""
+    G = I.uniform_grid(64, 32)
+    q, b = I.random_smooth((64, 64, 64), 43)
+    q, b = as_f32(q), as_f32(b)
+    sim, orc, held = _frozen_run(wmb, G, q, b, 1, [1, 6], 3)
+    for f, (qf, bf) in held.items():
+        qa, ba = sim.get_state(f)
+        assert np.array_equal(qa, qf) and np.array_equal(ba, bf), f
+    for f in (1, 6):
+        sim.set_active(f, True)
+    for _ in range(2):
+        dt = sim.compute_dt()
+        sim.run_steps(1)
+        orc.fill_ghosts()
+        orc.advance(dt)
+    qg, bg = I.gather(G, [sim.get_state(i) for i in range(G.npatch)])
+    qo, bo = oracle_gather(G, orc)
+    e_rho, e_e = _rel_l1(qg[0], qo[0]), _rel_l1(qg[7], qo[7])
+    print("frozen fp32 512-zone tiles: relL1 rho %.2e E %.2e" % (e_rho, e_e))
+    assert e_rho <= 1e-5 and e_e <= 1e-5
+    sim.close()
+    orc.close()
+
+
 def test_frozen_patches_next_to_walls_fp64(wmb):
     """Frozen patches beside domain boundaries: outflow along x and y,
     periodic z, 2 x 2 x 1 patches of 8 x 8 x 10, two patches frozen for 4
