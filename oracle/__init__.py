@@ -12,6 +12,7 @@ from .oracle import (  # noqa: F401
     build_oracle,
     default_params,
     eigensystem,
+    floor_state,
     hll_flux,
     line_fluxes,
     phys_flux,

@@ -101,6 +101,9 @@ def _load():
         lib.orc_eigensystem.argtypes = [dp, dp, C.POINTER(OracleParams), dp, dp, dp]
         lib.orc_line_fluxes.argtypes = [C.POINTER(OracleParams), C.c_int, dp, dp, C.c_double, dp]
         lib.orc_hll_flux.argtypes = [dp, dp, C.POINTER(OracleParams), dp]
+        lib.orc_floor_state.restype = C.c_int
+        lib.orc_floor_state.argtypes = [C.POINTER(OracleParams), dp]
+        lib.orc_floor_added.argtypes = [C.c_void_p, dp]
         lib.orc_num_threads.restype = C.c_int
         _lib = lib
     return _lib
@@ -139,6 +142,14 @@ def hll_flux(uL, uR, params: OracleParams):
     out = np.zeros(8)
     lib.orc_hll_flux(_p(uL), _p(uR), C.byref(params), _p(out))
     return out
+
+
+def floor_state(params: OracleParams, u):
+    """The floor rule applied to one lab-ordered 8-state; returns (fired, new state)."""
+    lib = _load()
+    u = np.array(u, dtype=np.float64)
+    hit = lib.orc_floor_state(C.byref(params), _p(u))
+    return bool(hit), u
 
 
 def line_fluxes(params: OracleParams, q8: np.ndarray, bf: np.ndarray, lam: float) -> np.ndarray:
@@ -247,6 +258,12 @@ class OracleSim:
         nf = C.c_int64(0)
         self.lib.orc_diagnostics(self.h, _p(tot), _p(dn), _p(dr), C.byref(nf))
         return tot, float(dn[0]), float(dr[0]), int(nf.value)
+
+    def floor_added(self):
+        """(mass, total energy) the final-update floors added since creation, times dV."""
+        out = np.zeros(2)
+        self.lib.orc_floor_added(self.h, _p(out))
+        return float(out[0]), float(out[1])
 
     def num_threads(self) -> int:
         return int(self.lib.orc_num_threads())

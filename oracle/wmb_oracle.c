@@ -29,15 +29,19 @@
  *
  * Parity pins (tests/test_oracle_*.py): Roe property, L.R = I and the
  * eigen-relation against a finite-difference Jacobian of the printed flux,
- * consistency, the Lax-Wendroff closed form in smooth single-wave data,
- * reduction of the 3D step to an independent 1D update, exact periodic
- * conservation, div b preservation, fixed point of uniform states,
- * second-order convergence to the closed-form linear fast wave and to the
- * circularly polarised Alfven wave, ghost-width dependency cone, closed-form
- * speeds and dt, restart and patch-decomposition invariance.
- * The numeric values that depend on the corner-EMF upwinding, on the div-B
- * source vector and on the epsilon / limiter defaults are pinned only through
- * those invariants and convergence rates ("parity unpinned" beyond them).
+ * consistency, the Lax-Wendroff closed form in smooth single-wave data, the
+ * first-order flux with the entropy-fix viscosity Q(nu) where the limiter is
+ * off, the textbook flux-limiter form of the Sweby family (beta = 1 .. 2) for
+ * advected entropy waves, the floor rule through the equation of state and
+ * its mass/energy ledger inside a step, reduction of the 3D step to an
+ * independent 1D update, exact periodic conservation, div b preservation,
+ * fixed point of uniform states, second-order convergence to the closed-form
+ * linear MHD waves (beta = 1, 1.5, 2) and to the circularly polarised Alfven
+ * wave, ghost-width dependency cone, closed-form speeds and dt, restart and
+ * patch-decomposition invariance.
+ * The numeric values that depend on the corner-EMF upwinding and on the div-B
+ * source vector are pinned only through those invariants and convergence
+ * rates ("parity unpinned" beyond them).
  */
 #include <math.h>
 #include <stdint.h>
@@ -87,6 +91,8 @@ typedef struct {
     int npatch;
     orc_patch *p;
     int64_t nfloor;
+    double floor_mass;   /* mass the floors of the final update added, times the zone volume */
+    double floor_energy; /* total energy they added, times the zone volume */
     int keep_stages;
 } orc_sim;
 
@@ -783,6 +789,15 @@ static int apply_floor(double *u[8], size_t x, const orc_params *P)
 /* one CTU+CT step on one patch (Sect. 5.2, Steps 1-11)                        */
 /* ------------------------------------------------------------------------ */
 
+/* The floor rule on one 8-state u (lab order); returns 1 if it fired.
+   Exported for the pins of the floor arithmetic. */
+int orc_floor_state(const orc_params *P, double u[8])
+{
+    double *c[8];
+    for (int k = 0; k < 8; k++) c[k] = u + k;
+    return apply_floor(c, 0, P);
+}
+
 static double minmod2(double a, double b)
 {
     if (a > 0.0 && b > 0.0) return fmin(a, b);
@@ -920,7 +935,7 @@ static void ct_update(const orc_patch *pt, const orc_params *P, const double *b0
     }
 }
 
-static int64_t step_patch(orc_sim *S, int ip, double dt)
+static int64_t step_patch(orc_sim *S, int ip, double dt, double added[2])
 {
     const orc_params *P = &S->P;
     orc_patch *pt = &S->p[ip];
@@ -1030,6 +1045,7 @@ static int64_t step_patch(orc_sim *S, int ip, double dt)
        Step 11: b^{n+1} = b^n - dt curl E, zone field = face average; floors */
     ct_update(pt, P, b, ed2, dt, bn);
     int64_t nfl = 0;
+    const double dV = P->dx[0] * P->dx[1] * P->dx[2];
     double *qn = malloc(sizeof(double) * 8 * V);
     memcpy(qn, q, sizeof(double) * 8 * V);
     for (int k = g; k < g + pt->n[2]; k++)
@@ -1047,7 +1063,12 @@ static int64_t step_patch(orc_sim *S, int ip, double dt)
                 for (int d = 0; d < 3; d++) qn[(4 + d) * V + x] = 0.5 * (bn[d * V + x] + bn[d * V + xp[d]]);
                 double *u[8];
                 for (int c = 0; c < 8; c++) u[c] = qn + c * V;
-                nfl += apply_floor(u, x, P);
+                const double r0 = qn[x], e0 = qn[7 * V + x];
+                if (apply_floor(u, x, P)) {
+                    nfl++;
+                    added[0] += (qn[x] - r0) * dV;
+                    added[1] += (qn[7 * V + x] - e0) * dV;
+                }
             }
     /* write back: interior zones, own faces and the shared right boundary faces */
     for (int k = g; k < g + pt->n[2]; k++)
@@ -1088,9 +1109,25 @@ static int64_t step_patch(orc_sim *S, int ip, double dt)
 void orc_advance(orc_sim *S, double dt)
 {
     int64_t nfl = 0;
+    double *added = calloc((size_t)S->npatch * 2, sizeof(double));
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : nfl)
-    for (int ip = 0; ip < S->npatch; ip++) nfl += step_patch(S, ip, dt);
+    for (int ip = 0; ip < S->npatch; ip++) nfl += step_patch(S, ip, dt, added + 2 * (size_t)ip);
+    /* patch order, so the sums do not depend on the thread schedule */
+    for (int ip = 0; ip < S->npatch; ip++) {
+        S->floor_mass += added[2 * (size_t)ip];
+        S->floor_energy += added[2 * (size_t)ip + 1];
+    }
+    free(added);
     S->nfloor += nfl;
+}
+
+/* mass and total energy the floors of the final updates have added since
+   the simulation was created (sums of the per-zone increments times the
+   zone volume) */
+void orc_floor_added(const orc_sim *S, double out[2])
+{
+    out[0] = S->floor_mass;
+    out[1] = S->floor_energy;
 }
 
 /* copy of a stage of the last step (keep_stages must have been on):

@@ -198,3 +198,79 @@ def test_brio_wu_line_is_finite_and_conservative():
         assert np.isfinite(F[g:g + N + 1]).all()
         q = q - 0.2 * (F[g + 1:g + N + 1] - F[g:g + N])
     assert np.allclose(q.sum(0), tot0, rtol=1e-13, atol=1e-12)
+
+
+def _entropy_line(rho, v0, gam, p0=1.0):
+    """Frame 8-states of a line carrying only an entropy wave: density varies,
+    velocity (v0 along the line), pressure and B = 0 are uniform."""
+    return np.array([state(r, [v0, 0, 0], [0, 0, 0], p0, gam) for r in rho])
+
+
+@pytest.mark.parametrize("eps,v0,lam", [(0.3, 0.7, 0.45), (0.3, -0.7, 0.45), (0.45, 0.5, 0.6),
+                                        (0.2, 0.0, 0.5), (0.1, 0.7, 0.45), (0.3, 0.6, 1.0)])
+def test_P4b_entropy_fix_first_order(eps, v0, lam):
+    """Entropy-fix branch of Q (Appendix A, the numerical-viscosity coefficient
+    with epsilon_k).  An alternating density line makes g-tilde change sign at
+    every face, so every limiter value g is 0 and the scheme reduces to the
+    first-order flux 1/2 (F_L + F_R) - Q(nu) dq / (2 lam), nu = lam v0, with
+    Q(chi) = chi^2/(4 eps) + eps for |chi| < 2 eps (here |nu| < 2 eps except
+    for the (0.1, 0.7, 0.45) case, which takes |chi|, and the (0.3, 0.6, 1.0)
+    case, which sits exactly on the branch point |nu| = 2 eps, where both
+    expressions give 2 eps).  Only the entropy wave is excited (B = 0,
+    uniform v and P), so dq is a multiple of its eigenvector."""
+    gam = 5 / 3
+    P = default_params(eps=(eps,) * 7)
+    m = 16
+    rho = [1.0 + (0.1 if s % 2 else 0.0) for s in range(m)]
+    q8 = _entropy_line(rho, v0, gam)
+    F = line_fluxes(P, q8, np.zeros(m), lam)
+    nu = lam * v0
+    Q = nu * nu / (4 * eps) + eps if abs(nu) < 2 * eps else abs(nu)
+    if abs(nu) == 2 * eps:
+        assert abs(Q - 2 * eps) < 1e-15
+    for s in range(2, m - 1):
+        uL, uR = q8[s - 1], q8[s]
+        ref = 0.5 * (phys_flux(uL, gam) + phys_flux(uR, gam)) - Q * (uR - uL) / (2 * lam)
+        ref[4] = 0.0
+        assert np.allclose(F[s], ref, rtol=1e-13, atol=1e-15), (s, F[s] - ref)
+
+
+def sweby_phi(theta, beta):
+    """Sweby's limiter family in flux-limiter form (Sweby 1984; LeVeque,
+    Numerical Methods for Conservation Laws, Sect. 16.2): beta = 1 minmod,
+    beta = 2 superbee."""
+    return max(0.0, min(beta * theta, 1.0), min(theta, beta))
+
+
+@pytest.mark.parametrize("beta", [1.0, 1.25, 1.5, 2.0])
+@pytest.mark.parametrize("v0", [0.7, -0.55])
+def test_P4c_sweby_family_flux_limiter_form(beta, v0):
+    """The limiter (Appendix A, SWEBY with parameter beta) against the
+    textbook flux-limiter scheme.  For linear advection at speed a with
+    Courant number nu = lam a, eps = 0 and a Sweby limiter phi, Harten's
+    modified flux reduces to the upwind flux plus the limited anti-diffusion
+        F_{i+1/2} = F(u_up) + 1/2 |a| (1 - |nu|) phi(theta) (u_{i+1} - u_i),
+    theta = (u_up - u_up-1) / (u_{i+1} - u_i) the upwind slope ratio.  A
+    line carrying only an entropy wave (B = 0, uniform v and P) is such an
+    advection for every component, so each face of a random density line
+    must match it; beta > 1 (beyond minmod) is exercised wherever the slope
+    ratio is away from 1."""
+    gam = 5 / 3
+    P = default_params(eps=(0.0,) * 7, limiter_beta=beta)
+    rng = np.random.default_rng(int(beta * 100) + (1 if v0 > 0 else 2))
+    m, lam = 40, 0.45
+    rho = 1.0 + 0.4 * rng.random(m)
+    q8 = _entropy_line(rho, v0, gam)
+    F = line_fluxes(P, q8, np.zeros(m), lam)
+    nu = abs(lam * v0)
+    checked = 0
+    for s in range(3, m - 2):  # face s between zones s-1 and s
+        up = s - 1 if v0 > 0 else s
+        d = rho[s] - rho[s - 1]
+        dup = rho[up] - rho[up - 1] if v0 > 0 else rho[up + 1] - rho[up]
+        theta = dup / d
+        ref = phys_flux(q8[up], gam) + 0.5 * abs(v0) * (1 - nu) * sweby_phi(theta, beta) * (q8[s] - q8[s - 1])
+        ref[4] = 0.0
+        assert np.allclose(F[s], ref, rtol=1e-12, atol=1e-14), (s, theta, F[s] - ref)
+        checked += 1
+    assert checked == m - 5
