@@ -1,20 +1,32 @@
 #!/usr/bin/env python3
 """Benchmark: zone-updates/s of the patch MHD update on one MI355X.
 
-Workload: 3D periodic 256^3 box as 512 patches of 32^3 (ghost width 4, the
-stencil minimum), rho = 1, P = 1, B = (0.1, 0, 0), seeded Gaussian random
-velocity with a k^-5/3 spectrum at rms Mach 1, gamma = 5/3, CFL 0.4.
+Headline workload: 3D periodic 256^3 box as 512 patches of 32^3 (ghost width
+4, the stencil minimum), rho = 1, P = 1, B = (0.1, 0, 0), seeded Gaussian
+random velocity with a k^-5/3 spectrum at rms Mach 1, gamma = 5/3, CFL 0.4.
 One step = ghost exchange + FP64 CFL reduction + the full CTU+CT MHDTVD
 update (Steps 1-11) of all patches, replayed from a captured HIP graph, with
 the state resident in HBM.  The headline value is the FP32 batch (FP32 sweeps
-and CT, FP64 dt and floors); the FP64 batch is reported beside it.
+and CT, FP64 dt and floors); the FP64 batch of the same workload is reported
+beside it, and so are the uneven 400-patch batch, the 512^3 Orszag-Tang batch
+(patches of 64^3, 50 steps) and the 768^3 high-contrast batch (patches of
+48^3).
+
+Roofline: the algorithmic bytes of one step are those of the patch design
+(16 + 24 ((1 + 2g/n)^3 - 1) words per interior zone-update for cubic patches
+of edge n: the step reads and writes the 8 conserved words of every interior
+zone, the ghost exchange reads and writes those of every ghost zone, and the
+step reads the ghosts), over the step time measured with HIP events on the
+library's stream around the timed graph replays.
 
 Prints ONE JSON line.  --gpus > 1 is not supported (one GPU per process; the
 multi-GPU design is documented, not built).
 """
 import argparse
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -24,6 +36,8 @@ if ROOT not in sys.path:
 
 METRIC = "zone-updates/sec on 1 MI355X (FP32 batched vs FP64 plain) + % HBM roofline"
 HBM_PEAK_GBS = 8000.0
+PROFILE_JSON = os.path.join(ROOT, "profiles", "turb256_512x32_fp32_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1701_07452_amd", "csrc", "wmb_kernels.hip")
 
 
 def log(*a):
@@ -31,67 +45,102 @@ def log(*a):
 
 
 # ---------------------------------------------------------------------------
-# algorithmic bytes per launch of each kernel class (unique words each launch
-# must read or write at least once, times the word size)
+# algorithmic bytes of one step, and their attribution to the kernel classes
 # ---------------------------------------------------------------------------
 
-def alg_bytes(kclass, n, g, es, npatch):
-    """n: interior edge, g: ghost width, es: bytes per word (uniform patches)."""
-    def box(lo, hi):
-        return (n + hi - lo + 1) ** 3
-
-    N = n + 2 * g
-    if kclass == "fill":
-        # y and z passes (the step before wrote the x-ghosts): 11 words read +
-        # 11 written per ghost zone of whole y-ghost rows and z-ghost planes
-        per = 22 * (2 * g * N * n + 2 * g * N * N)
-    elif kclass == "dt":
-        per = 0                                          # finalize only: the reduction is folded into "update"
-    elif kclass.startswith("sweep1"):
-        T, P = n + 6, n + 8
-        per = 9 * P * T * T + 7 * (P - 3) * T * T        # q + b_par in; 7 flux rows out
-        if kclass == "sweep1_x":
-            per += 3 * box(-3, 2)                        # and the Step-2 reference EMF
-    elif kclass.startswith("sweep2"):
-        T, P = n + 2, n + 6
-        per = (8 + 2 * 7 + 3 + 1) * P * T * T + 7 * (P - 3) * T * T  # q, 2 transverse fluxes, b, b^{n+1/2}; flux out
-    elif kclass == "ct_half":
-        # Steps 3-4 fused: Step-1 flux rows 0, 5, 6 (3 dirs), E^r and b^n in,
-        # b^{n+1/2} out, over the box [-2, n+2]^3
-        per = (9 + 3 + 3 + 3) * box(-2, 2)
-    elif kclass == "update":
-        # Steps 8-11 fused: q^n rho, m + flux rows 0-3 + b^{n+1/2} over the E^r
-        # box [-1, n]; flux rows 5-6 over the edge box [0, n]; q^n E, flux row 4,
-        # b^n in and q^{n+1}, b^{n+1} out over the interior
-        per = (4 + 12 + 3) * box(-1, 0) + 6 * box(0, 0) + (1 + 3 + 3 + 11) * n ** 3
-        per += 11 * 2 * g * n * n                        # the x-ghosts it writes into the neighbours
-    else:
-        raise KeyError(kclass)
-    return per * es * npatch
+def alg_words(descs, g):
+    """Algorithmic words of one step over a batch of patches (8 conserved
+    words per zone; the zone-centred field is carried, the face field is not
+    counted separately), attributed to the kernel class that must move them:
+      - the ghost exchange reads and writes 8 words of every ghost zone: the
+        x-ghosts of interior rows are written by the update kernel (its push
+        to the x-neighbours), the other ghosts by the y/z exchange passes;
+      - the step reads q^n over the whole stored box (interior and ghosts):
+        charged to the three Step-1 sweeps, a third each;
+      - the step writes q^{n+1} over the interior: charged to the update.
+    The total is 16 V_int + 24 (V_stored - V_int) per patch."""
+    w = {"fill": 0, "sweep1_x": 0, "sweep1_y": 0, "sweep1_z": 0, "update": 0}
+    for n, _ in descs:
+        vi = n[0] * n[1] * n[2]
+        vs = (n[0] + 2 * g) * (n[1] + 2 * g) * (n[2] + 2 * g)
+        gx = 2 * g * n[1] * n[2]
+        w["update"] += 16 * gx + 8 * vi
+        w["fill"] += 16 * (vs - vi - gx)
+        for k in ("sweep1_x", "sweep1_y", "sweep1_z"):
+            w[k] += 8 * vs / 3.0
+    return w
 
 
-def measured_traffic(kclass):
-    """HBM bytes per launch of a kernel class from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None when the kernel
-    source has changed since the counters were taken."""
-    import hashlib
-
-    path = os.path.join(ROOT, "profiles", "turb256_512x32_fp32_hbm_traffic.json")
-    src = os.path.join(ROOT, "paper_1701_07452_amd", "csrc", "wmb_kernels.hip")
+def profile_record():
+    """The committed rocprofv3 counter summary (copy-calibrated FETCH_SIZE /
+    WRITE_SIZE bytes and VALU utilisation per kernel class of one step), or
+    None when the kernel source has changed since it was taken."""
     try:
-        rec = json.load(open(path))
-        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        rec = json.load(open(PROFILE_JSON))
+        cur = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if rec.get("kernels_source_sha256") != cur or kclass not in rec.get("per_launch_bytes", {}):
-        return None
-    return rec["per_launch_bytes"][kclass]["total"]
+    return rec if rec.get("kernels_source_sha256") == cur else None
 
 
-def cpu_baseline(q, b, G, dx, ghost, budget_s=12.0):
+def roofline(descs, g, es, zones, ms_step, kern_ms, prof=None):
+    """Step-level HBM roofline at the algorithmic bytes, with per-kernel
+    shares (each kernel's algorithmic bytes over the step time; the shares sum
+    to the step fraction) and the measured traffic and VALU utilisation from
+    the committed counter summary when it is current."""
+    words = alg_words(descs, g)
+    step_bytes = sum(words.values()) * es
+    t = ms_step * 1e-3
+    achieved = step_bytes / t / 1e9
+    per = {}
+    for k, ms in (kern_ms or {}).items():
+        ab = words.get(k, 0) * es
+        per[k] = {"alg_bytes": ab, "frac_share": round(ab / t / 1e9 / HBM_PEAK_GBS, 5), "eager_ms": round(ms, 4),
+                  "frac_own_time": round(ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else None}
+        if prof and k in prof.get("per_class", {}):
+            pc = prof["per_class"][k]
+            per[k]["design_bytes"] = pc.get("fetch_bytes", 0) + pc.get("write_bytes", 0)
+            per[k]["valu_busy"] = pc.get("valu_busy")
+    traffic = None
+    if prof and es == 4:
+        traffic = sum(v.get("fetch_bytes", 0) + v.get("write_bytes", 0) for v in prof["per_class"].values())
+    dom = max(kern_ms, key=kern_ms.get) if kern_ms else None
+    return {
+        "kernel": "step (one graph replay: exchange, dt, Steps 1-11 of every patch)",
+        "bound": "hbm",
+        "achieved": round(achieved, 2),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 5),
+        "traffic": traffic,
+        "alg_bytes_per_step": step_bytes,
+        "alg_bytes_per_zone_update": round(step_bytes / zones, 3),
+        "ms_per_step": ms_step,
+        "measured_traffic_GBs": round(traffic / t / 1e9, 1) if traffic else None,
+        "dominant_kernel": dom,
+        "per_kernel": per,
+    }
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline (the oracle as it stands)
+# ---------------------------------------------------------------------------
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(q, b, dx, ghost, budget_s=12.0):
     """The FP64 oracle as it stands, timed on this host's cores on a bounded
     sample: a 2x2xk block of the workload's 32^3 patches (periodic sample box),
-    one warm-up step then timed steps until about budget_s seconds."""
+    one warm-up step then timed steps until about budget_s seconds.  Also the
+    one-patch linear-wave case (32^3, 10 steps) in CPU seconds."""
     import numpy as np
 
     from oracle import OracleSim, default_params
@@ -114,25 +163,65 @@ def cpu_baseline(q, b, G, dx, ghost, budget_s=12.0):
         if el > budget_s or steps >= 50:
             break
     zones = sub.zones()
+    threads = orc.num_threads()
+    orc.close()
+    # one periodic 32^3 patch, linear fast wave, FP64, 10 steps (the oracle
+    # runs patches in parallel, so one patch runs on one core)
+    qw, bw, _ = I.fast_wave_diagonal(32)
+    Gw = I.uniform_grid(32, 32)
+    ow = OracleSim(default_params(dx=(1 / 32,) * 3), Gw.descs)
+    ow.set_state(0, qw, bw)
+    c0 = time.process_time()
+    w0 = time.perf_counter()
+    ow.run_steps(10)
+    c1_wall = time.perf_counter() - w0
+    c1_cpu = time.process_time() - c0
+    ow.close()
     return {
         "value": zones * steps / el,
         "unit": "zone-updates/s",
-        "cores": orc.num_threads(),
+        "cores": threads,
         "kind": "oracle",
         "sample": "%d patches of 32^3 (%d zones) cut from the workload, periodic sample box, FP64, %d steps in %.1f s"
                   % (sub.npatch, zones, steps, el),
+        "cpu_model": cpu_model(),
+        "host_cpus": os.cpu_count(),
+        "linear_wave_32cubed_10_steps": {"wall_s": round(c1_wall, 3), "cpu_s": round(c1_cpu, 3), "cores_used": 1,
+                                         "note": "one patch: the oracle parallelises over patches only"},
     }
 
 
-def run_precision(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps, tuning=None, freeze=(), **params):
+# ---------------------------------------------------------------------------
+# one batch on the GPU
+# ---------------------------------------------------------------------------
+
+def free_device_memory():
+    import gc
+
     import torch
 
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def make_sim(W, G, q, b, dx, prec, ghost, stream, **params):
     from paper_1701_07452_amd import inputs as I
 
-    stream = torch.cuda.Stream()
     sim = W.Sim(W.make_params(dx=dx, precision=prec, ghost=ghost, **params), G.descs, origins=G.origin, stream=stream)
-    for ip, (qp, bp) in enumerate(I.split(G, q, b)):
+    for ip, (qp, bp) in enumerate(I.iter_split(G, q, b)):
         sim.set_state(ip, qp, bp)
+    return sim
+
+
+def run_batch(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps, tuning=None, freeze=(), divb_at=(), **params):
+    """Time `steps` graph replays after `warmup` ones; per-kernel eager
+    durations from prof_steps profiled steps; optionally the normalised div b
+    of a fresh run after each step count in divb_at."""
+    import torch
+
+    stream = torch.cuda.Stream()
+    sim = make_sim(W, G, q, b, dx, prec, ghost, stream, **params)
     if tuning:
         sim.set_tuning(tuning)
     else:
@@ -169,9 +258,25 @@ def run_precision(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps, tuning
     tot, dn, dr, nfl = sim.diagnostics()
     nprot = sim.protected_faces()
     sim.close()
-    extra = {"freeze_ms_per_patch": freeze_ms} if freeze else {}
-    return ms, wall, kern, {"max_divb_norm": dn, "max_divb_raw": dr, "floors": nfl, "protected_faces": nprot,
-                            "tuning": W.tuning_to_str(tuning), **extra}
+    diag = {"max_divb_norm": dn, "max_divb_raw": dr, "floors": nfl, "protected_faces": nprot,
+            "tuning": W.tuning_to_str(tuning)}
+    if freeze:
+        diag["freeze_ms_per_patch"] = freeze_ms
+    if divb_at:
+        # normalised div b against the step count, from the initial state
+        sim = make_sim(W, G, q, b, dx, prec, ghost, stream, **params)
+        sim.set_tuning(tuning)
+        done, curve = 0, {}
+        for n in sorted(divb_at):
+            sim.run_steps(n - done)
+            done = n
+            _, dnn, _, _ = sim.diagnostics()
+            curve[str(n)] = dnn
+        sim.close()
+        diag["divb_norm_vs_steps"] = curve
+    del sim
+    free_device_memory()
+    return ms, wall, kern, diag
 
 
 def main():
@@ -186,6 +291,9 @@ def main():
     ap.add_argument("--tuning32", default="", help="sweep shapes for FP32 (e.g. 1x32=16,...); default: autotune")
     ap.add_argument("--tuning64", default="", help="sweep shapes for FP64; default: autotune")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven 400-patch batch (reported beside)")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 512^3 Orszag-Tang batch of 64^3 patches")
+    ap.add_argument("--c5", action="store_true",
+                    help="also time the 768^3 high-contrast batch of 48^3 patches (210 GB pool, minutes of set-up)")
     ap.add_argument("--protection", action="store_true",
                     help="also time the Mach-5 lognormal-density batch (384^3 as 512 x 48^3, FP32) with the protection "
                          "floors off and on (reported beside)")
@@ -202,7 +310,6 @@ def main():
               "(the multi-GPU sharding is a documented design, not built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1701_07452_amd import inputs as I
@@ -212,6 +319,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     W.load_library()
+    t_start = time.perf_counter()
 
     if args.calib_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -220,25 +328,29 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    prof = profile_record()
     N, n, g = 256, 32, args.ghost
     dx = (1.0 / N,) * 3
     log("bench: building the 256^3 turbulence state")
     q, b = I.turbulence(N)
     G = I.uniform_grid(N, n)
     zones = G.zones()
+    divb_at = (10, 20, 50) if args.prof_steps > 0 else ()
 
     log("bench: FP32 batch, %d warm-up + %d timed steps" % (args.warmup, args.steps))
-    ms32, wall32, kern32, diag32 = run_precision(W, G, q, b, dx, W.WMB_FP32, g, args.steps, args.warmup, args.prof_steps,
-                                                 W.tuning_from_str(args.tuning32))
+    ms32, wall32, kern32, diag32 = run_batch(W, G, q, b, dx, W.WMB_FP32, g, args.steps, args.warmup, args.prof_steps,
+                                             W.tuning_from_str(args.tuning32), divb_at=divb_at)
     value = zones * args.steps / (ms32 / 1e3)
     log("bench: FP32 %.3f ms/step, %.3e zone-updates/s" % (ms32 / args.steps, value))
     fp64 = None
     if not args.no_fp64:
         log("bench: FP64 batch")
-        ms64, wall64, kern64, diag64 = run_precision(W, G, q, b, dx, W.WMB_FP64, g, args.steps, args.warmup,
-                                                     args.prof_steps, W.tuning_from_str(args.tuning64))
-        fp64 = {"value": zones * args.steps / (ms64 / 1e3), "ms_per_step": ms64 / args.steps,
+        ms64, wall64, kern64, diag64 = run_batch(W, G, q, b, dx, W.WMB_FP64, g, args.steps, args.warmup,
+                                                 args.prof_steps, W.tuning_from_str(args.tuning64))
+        fp64 = {"value": zones * args.steps / (ms64 / 1e3), "ms_per_step": ms64 / args.steps, "dtype": "f64",
                 "kernels_ms": kern64, **diag64}
+        if kern64:
+            fp64["roofline"] = roofline(G.descs, g, 8, zones, ms64 / args.steps, kern64)
         log("bench: FP64 %.3f ms/step" % (ms64 / args.steps))
 
     uneven = None
@@ -249,14 +361,47 @@ def main():
         Nz, Ny, Nx = Gu.shape
         log("bench: uneven batch, %d patches, %d zones" % (Gu.npatch, Gu.zones()))
         qu, bu = I.turbulence(None, seed=170107454, shape=Gu.shape, box=(Nx / 256, Ny / 256, Nz / 256))
-        msu, wallu, kernu, diagu = run_precision(W, Gu, qu, bu, (1.0 / 256,) * 3, W.WMB_FP32, g, args.steps,
-                                                 args.warmup, 1)
+        msu, wallu, kernu, diagu = run_batch(W, Gu, qu, bu, (1.0 / 256,) * 3, W.WMB_FP32, g, args.steps,
+                                             args.warmup, 1)
         del qu, bu
         uneven = {"workload": "uneven batch: 400 patches, 8 x 10 x 5 slabs with edges from {16,24,32,48,64}, "
                               "turbulence, ghost %d, FP32" % g,
                   "zones": Gu.zones(), "patches": Gu.npatch, "ms_per_step": msu / args.steps,
-                  "value": Gu.zones() * args.steps / (msu / 1e3), "kernels_ms": kernu, **diagu}
+                  "value": Gu.zones() * args.steps / (msu / 1e3), "kernels_ms": kernu, **diagu,
+                  "roofline": roofline(Gu.descs, g, 4, Gu.zones(), msu / args.steps, kernu)}
         log("bench: uneven FP32 %.3f ms/step, %.3e zone-updates/s" % (msu / args.steps, uneven["value"]))
+
+    c4 = None
+    if not args.no_c4 and args.prof_steps > 0:
+        N4, n4, s4 = 512, 64, 50
+        G4 = I.uniform_grid(N4, n4)
+        log("bench: 512^3 Orszag-Tang batch, %d patches of 64^3" % G4.npatch)
+        q4, b4 = I.orszag_tang_3d(N4)
+        ms4, _, kern4, diag4 = run_batch(W, G4, q4, b4, (1.0 / N4,) * 3, W.WMB_FP32, g, s4, args.warmup, 1,
+                                         divb_at=(10, 20, 50))
+        del q4, b4
+        c4 = {"workload": "3D Orszag-Tang extension, 512^3 as 512 patches of 64^3, ghost %d, FP32, %d graph-replayed "
+                          "steps" % (g, s4),
+              "zones": G4.zones(), "patches": G4.npatch, "steps": s4, "ms_per_step": ms4 / s4,
+              "value": G4.zones() * s4 / (ms4 / 1e3), "kernels_ms": kern4, **diag4,
+              "roofline": roofline(G4.descs, g, 4, G4.zones(), ms4 / s4, kern4)}
+        log("bench: C4 FP32 %.3f ms/step, %.3e zone-updates/s" % (ms4 / s4, c4["value"]))
+
+    c5 = None
+    if args.c5:
+        N5, n5 = 768, 48
+        G5 = I.uniform_grid(N5, n5)
+        log("bench: 768^3 high-contrast batch, %d patches of 48^3" % G5.npatch)
+        q5, b5 = I.high_contrast_turbulence(N5, workers=-1)
+        ms5, _, kern5, diag5 = run_batch(W, G5, q5, b5, (1.0 / N5,) * 3, W.WMB_FP32, g, args.steps, args.warmup, 1,
+                                         rho_floor=1e-8, p_floor=1e-8)
+        del q5, b5
+        c5 = {"workload": "high-contrast turbulence (lognormal rho, sigma 1.5, Mach 5, beta 1), 768^3 as 4096 patches "
+                          "of 48^3, ghost %d, FP32, FP64 floors 1e-8" % g,
+              "zones": G5.zones(), "patches": G5.npatch, "ms_per_step": ms5 / args.steps,
+              "value": G5.zones() * args.steps / (ms5 / 1e3), "kernels_ms": kern5, **diag5,
+              "roofline": roofline(G5.descs, g, 4, G5.zones(), ms5 / args.steps, kern5)}
+        log("bench: C5 FP32 %.3f ms/step, %.3e zone-updates/s" % (ms5 / args.steps, c5["value"]))
 
     protection = None
     if args.protection:
@@ -267,8 +412,8 @@ def main():
         protection = {"workload": "Mach-5 solenoidal turbulence, lognormal rho (sigma 1.5), beta 1, %d^3 as %d "
                                   "patches of 48^3, ghost %d, FP32, floors 1e-8" % (Nh, Gh.npatch, g)}
         for tag, pf in (("off", 0.0), ("on", 1e-4)):
-            msh, _, kernh, diagh = run_precision(W, Gh, qh, bh, (1.0 / Nh,) * 3, W.WMB_FP32, g, 10, args.warmup, 1,
-                                                 rho_floor=1e-8, p_floor=1e-8, rho_protect=pf, p_protect=pf)
+            msh, _, kernh, diagh = run_batch(W, Gh, qh, bh, (1.0 / Nh,) * 3, W.WMB_FP32, g, 10, args.warmup, 1,
+                                             rho_floor=1e-8, p_floor=1e-8, rho_protect=pf, p_protect=pf)
             protection[tag] = {"protect_floor": pf, "ms_per_step": msh / 10, "value": Gh.zones() * 10 / (msh / 1e3),
                                "kernels_ms": kernh, **diagh}
             log("bench: protection %s: %.3f ms/step, %d protected faces, %d floors" %
@@ -279,8 +424,8 @@ def main():
     if args.outflow:
         Go = I.uniform_grid(N, n, periodic=(False, False, False))
         log("bench: FP32 batch with outflow on every side")
-        mso, _, kerno, diago = run_precision(W, Go, q, b, dx, W.WMB_FP32, g, args.steps, args.warmup, 1,
-                                             W.tuning_from_str(args.tuning32) or None)
+        mso, _, kerno, diago = run_batch(W, Go, q, b, dx, W.WMB_FP32, g, args.steps, args.warmup, 1,
+                                         W.tuning_from_str(args.tuning32) or None)
         outflow = {"workload": "the FP32 batch with outflow (zero-gradient) boundaries on all six sides",
                    "ms_per_step": mso / args.steps, "value": zones * args.steps / (mso / 1e3), "kernels_ms": kerno,
                    **diago}
@@ -291,8 +436,8 @@ def main():
         px, py, pz = G.nblocks
         half = [(k * py + j) * px + i for k in range(pz) for j in range(py) for i in range(px) if (i + j + k) % 2]
         log("bench: FP32 batch with %d of %d patches frozen" % (len(half), G.npatch))
-        msf, _, kernf, diagf = run_precision(W, G, q, b, dx, W.WMB_FP32, g, args.steps, args.warmup, 1,
-                                             W.tuning_from_str(args.tuning32) or None, freeze=half)
+        msf, _, kernf, diagf = run_batch(W, G, q, b, dx, W.WMB_FP32, g, args.steps, args.warmup, 1,
+                                         W.tuning_from_str(args.tuning32) or None, freeze=half)
         active = zones - len(half) * n ** 3
         frozen = {"workload": "the FP32 batch with every other patch (checkerboard) frozen after graph capture",
                   "frozen_patches": len(half), "active_zones": active, "ms_per_step": msf / args.steps,
@@ -303,30 +448,14 @@ def main():
     if not kern32:  # counter-collection runs skip the per-kernel pass
         print(json.dumps({"metric": METRIC, "value": value, "unit": "zone-updates/s", "partial": True}), flush=True)
         return
-    # roofline of the dominant kernel class (FP32 batch)
-    dom = max(kern32, key=kern32.get)
-    per_launch = alg_bytes(dom, n, g, 4, G.npatch)
-    achieved = per_launch / (kern32[dom] * 1e-3) / 1e9
-    step_bytes = sum(alg_bytes(k, n, g, 4, G.npatch) for k in kern32)
-    traffic = measured_traffic(dom)
-    roof = {
-        "kernel": dom,
-        "bound": "hbm",
-        "achieved": round(achieved, 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": traffic,
-        "traffic_GBs": round(traffic / (kern32[dom] * 1e-3) / 1e9, 1) if traffic else None,
-        "alg_bytes_per_launch": per_launch,
-        "avg_launch_ms": kern32[dom],
-        "step_alg_bytes": step_bytes,
-        "step_alg_frac": round(step_bytes / (ms32 / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-    }
+    roof = roofline(G.descs, g, 4, zones, ms32 / args.steps, kern32, prof)
+    if prof:
+        roof["valu_busy_sweeps"] = {k: v.get("valu_busy") for k, v in prof["per_class"].items() if k.startswith("sweep")}
+        roof["profile"] = os.path.relpath(PROFILE_JSON, ROOT)
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: CPU baseline (oracle)")
-        cpu = cpu_baseline(q, b, G, dx, g)
+        cpu = cpu_baseline(q, b, dx, g)
         log("bench: CPU %.3e zone-updates/s on %d threads" % (cpu["value"], cpu["cores"]))
 
     out = {
@@ -352,11 +481,14 @@ def main():
         "fp32_diag": diag32,
         "fp64": fp64,
         "uneven_fp32": uneven,
+        "c4_fp32": c4,
+        "c5_fp32": c5,
         "protection_fp32": protection,
         "frozen_half_fp32": frozen,
         "outflow_fp32": outflow,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "bench_wall_s": round(time.perf_counter() - t_start, 1),
     }
     print(json.dumps(out), flush=True)
 

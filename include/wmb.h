@@ -149,9 +149,11 @@ int wmb_compute_dt(wmb_ctx *c, double *dt_out);
 /* One CTU+CT step (Sect. 5.2, Steps 1-11) of every patch.  Ghosts must be
    current.  dt > 0: use this dt (the call checks it against the CFL limit of
    the current state and returns WMB_ECFL if it is larger by more than 1e-12
-   relative; this check synchronises).  dt <= 0: use the device-resident dt of
-   the last wmb_compute_dt.  Floors (rho_floor, p_floor) are applied in FP64
-   and counted.  The step also writes the new state of the first and last
+   relative; this check synchronises and reduces the current state afresh:
+   with dt_lag = 1 the maximum a step folds in belongs to the state before,
+   and lagged steps after this call start again from the current state).
+   dt <= 0: use the device-resident dt of the last wmb_compute_dt.  Floors
+   (rho_floor, p_floor) are applied in FP64 and counted.  The step also writes the new state of the first and last
    ghost-width zones of every interior row into the x-neighbours' ghosts (the
    x part of the next ghost exchange; at a domain boundary the patch's own
    x-ghosts by zero gradient; next to a frozen neighbour it copies that

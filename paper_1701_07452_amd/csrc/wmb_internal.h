@@ -79,6 +79,10 @@ struct WorkItem {
     int c;  // sweeps: last pencil (inclusive); tiles: k0 | k1 << 16 (biased, k1 exclusive)
 };
 
+// Diagnostics record of one work item (doubles): 9 compensated sums as (hi, lo)
+// pairs (q times the zone volume, |B|^2), the max |div b|, one pad word.
+constexpr int DIAG_REC = 20;
+
 // Column tiles of the Steps 8-11 kernel: the largest tile plane (one thread a
 // zone, the block size).  FP32 may take 512 (fewer ring zones of E^r per tile
 // zone at the same occupancy) where the patches' tiles fill such blocks; FP64

@@ -1257,44 +1257,143 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
 }
 
 // ---------------------------------------------------------------------------
-// FP64 diagnostics: per-block partial sums of q * dV (8), |B|^2 and the block
-// max of |div b|; reduced on the host in a fixed order
+// FP64 diagnostics with compensated sums.  Every running sum is an unevaluated
+// pair hi + lo: a value is added with the error-free TwoSum, and two pairs
+// are merged by adding their high parts error-free and their low parts
+// plainly, then renormalising.  The result is accurate to about one rounding
+// of the exact sum, whatever the order, and the order itself is fixed (the
+// reduction trees below do not depend on timing), so results are bitwise
+// reproducible.
+//   diag_kernel        one block per work item (a run of interior zones of one
+//                      patch): per thread TwoSum accumulation, then a fixed
+//                      butterfly across the wave and a fixed merge of the waves;
+//                      writes one record of DIAG_REC doubles per item
+//   diag_final_kernel  one wave: merges the records in item order into the
+//                      totals, B_rms, the max of |div b| and the counters
 // ---------------------------------------------------------------------------
 
+constexpr int DIAG_NSUM = 9;   // q (8) times the zone volume, |B|^2
+constexpr int DIAG_THREADS = 256;
+
+struct DSum {
+    double hi, lo;
+};
+
+__device__ __forceinline__ void two_sum_add(DSum& a, double x) {
+#pragma clang fp contract(off)
+    const double s = a.hi + x;
+    const double bb = s - a.hi;
+    const double err = (a.hi - (s - bb)) + (x - bb);
+    a.hi = s;
+    a.lo += err;
+}
+
+__device__ __forceinline__ DSum merge(DSum a, DSum b) {
+#pragma clang fp contract(off)
+    DSum r{a.hi, a.lo + b.lo};
+    two_sum_add(r, b.hi);
+    const double h = r.hi + r.lo;  // renormalise (|lo| is far below |hi|)
+    r.lo = r.lo - (h - r.hi);
+    r.hi = h;
+    return r;
+}
+
+__device__ __forceinline__ DSum shfl_xor_dsum(DSum a, int off) {
+    return DSum{__shfl_xor(a.hi, off, 64), __shfl_xor(a.lo, off, 64)};
+}
+
 template <typename R>
-__global__ void __launch_bounds__(256) diag_kernel(const R* __restrict__ pool, const PatchDev* __restrict__ patches,
-                                                   const WorkItem* __restrict__ work, DevParams prm, int cur,
-                                                   double* __restrict__ partial) {
-    __shared__ double red[10][256];
-    const WorkItem w = work[blockIdx.x];
+__global__ void __launch_bounds__(DIAG_THREADS) diag_kernel(const R* __restrict__ pool, const PatchDev* __restrict__ patches,
+                                                            const WorkItem* __restrict__ work, DevParams prm, int cur,
+                                                            double* __restrict__ rec) {
+#pragma clang fp contract(off)
+    __shared__ double red[DIAG_THREADS / 64][2 * DIAG_NSUM + 1];
+    const WorkItem w = work[blockIdx.x];  // a = first interior zone (linear, x fastest), b = zone count
     const PatchDev P = patches[w.patch];
-    BoxPos bp = box_pos(P, w.a, Box{0, -1});
-    double v[10];
+    const int g = prm.ghost;
+    const long long V = P.vol;
+    const R* q = pool + P.base + (long long)(cur ? F_ST1 : F_ST0) * V;
+    const R* b = q + 8 * V;
+    const double dV = prm.dx[0] * prm.dx[1] * prm.dx[2];
+    DSum acc[DIAG_NSUM];
 #pragma unroll
-    for (int c = 0; c < 10; c++) v[c] = 0.0;
-    if (bp.valid) {
-        const int g = prm.ghost;
-        const long long V = P.vol;
-        long long x = sidx(P, bp.i + g, bp.j + g, bp.k + g);
-        const R* q = pool + P.base + (long long)(cur ? F_ST1 : F_ST0) * V;
-        const R* b = q + 8 * V;
-        double dV = prm.dx[0] * prm.dx[1] * prm.dx[2];
-        for (int c = 0; c < 8; c++) v[c] = (double)q[(long long)c * V + x] * dV;
-        v[8] = (double)q[4 * V + x] * q[4 * V + x] + (double)q[5 * V + x] * q[5 * V + x] + (double)q[6 * V + x] * q[6 * V + x];
+    for (int c = 0; c < DIAG_NSUM; c++) acc[c] = DSum{0.0, 0.0};
+    double mx = 0.0;
+    for (int z = w.a + (int)threadIdx.x; z < w.a + w.b; z += DIAG_THREADS) {
+        const int i = z % P.n[0], t = z / P.n[0];
+        const int j = t % P.n[1], k = t / P.n[1];
+        const long long x = sidx(P, i + g, j + g, k + g);
+#pragma unroll
+        for (int c = 0; c < 8; c++) two_sum_add(acc[c], (double)q[(long long)c * V + x] * dV);
+        const double b0 = q[4 * V + x], b1 = q[5 * V + x], b2 = q[6 * V + x];
+        two_sum_add(acc[8], b0 * b0 + b1 * b1 + b2 * b2);
         double div = 0.0;
-        for (int d = 0; d < 3; d++) div += ((double)b[(long long)d * V + x + stride_of(P, d)] - (double)b[(long long)d * V + x]) / prm.dx[d];
-        v[9] = fabs(div);
+#pragma unroll
+        for (int d = 0; d < 3; d++)
+            div += ((double)b[(long long)d * V + x + stride_of(P, d)] - (double)b[(long long)d * V + x]) / prm.dx[d];
+        mx = fmax(mx, fabs(div));
     }
-    for (int c = 0; c < 10; c++) red[c][threadIdx.x] = v[c];
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            for (int c = 0; c < 9; c++) red[c][threadIdx.x] += red[c][threadIdx.x + h];
-            red[9][threadIdx.x] = fmax(red[9][threadIdx.x], red[9][threadIdx.x + h]);
+    // butterfly across the wave (every lane ends with the same merged value)
+    for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+        for (int c = 0; c < DIAG_NSUM; c++) acc[c] = merge(acc[c], shfl_xor_dsum(acc[c], off));
+        mx = fmax(mx, __shfl_xor(mx, off, 64));
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < DIAG_NSUM; c++) {
+            red[wid][2 * c] = acc[c].hi;
+            red[wid][2 * c + 1] = acc[c].lo;
         }
-        __syncthreads();
+        red[wid][2 * DIAG_NSUM] = mx;
     }
-    if (threadIdx.x < 10) partial[(long long)blockIdx.x * 10 + threadIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+    if (threadIdx.x < DIAG_NSUM) {
+        const int c = threadIdx.x;
+        DSum s{red[0][2 * c], red[0][2 * c + 1]};
+        for (int v = 1; v < DIAG_THREADS / 64; v++) s = merge(s, DSum{red[v][2 * c], red[v][2 * c + 1]});
+        rec[(long long)blockIdx.x * DIAG_REC + 2 * c] = s.hi;
+        rec[(long long)blockIdx.x * DIAG_REC + 2 * c + 1] = s.lo;
+    } else if (threadIdx.x == DIAG_NSUM) {
+        double m = red[0][2 * DIAG_NSUM];
+        for (int v = 1; v < DIAG_THREADS / 64; v++) m = fmax(m, red[v][2 * DIAG_NSUM]);
+        rec[(long long)blockIdx.x * DIAG_REC + 2 * DIAG_NSUM] = m;
+        rec[(long long)blockIdx.x * DIAG_REC + 2 * DIAG_NSUM + 1] = 0.0;
+    }
+}
+
+// out[0..7] totals, [8] max normalised div b, [9] max |div b|, [10] floor
+// activations, [11] protected faces (counts as exact doubles)
+__global__ void __launch_bounds__(64) diag_final_kernel(const double* __restrict__ rec, int nrec,
+                                                         const unsigned long long* __restrict__ counters, double nzones,
+                                                         double dmin, double* __restrict__ out) {
+    const int lane = threadIdx.x;
+    DSum acc[DIAG_NSUM];
+#pragma unroll
+    for (int c = 0; c < DIAG_NSUM; c++) acc[c] = DSum{0.0, 0.0};
+    double mx = 0.0;
+    for (int r = lane; r < nrec; r += 64) {
+        const double* p = rec + (long long)r * DIAG_REC;
+#pragma unroll
+        for (int c = 0; c < DIAG_NSUM; c++) acc[c] = merge(acc[c], DSum{p[2 * c], p[2 * c + 1]});
+        mx = fmax(mx, p[2 * DIAG_NSUM]);
+    }
+    for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+        for (int c = 0; c < DIAG_NSUM; c++) acc[c] = merge(acc[c], shfl_xor_dsum(acc[c], off));
+        mx = fmax(mx, __shfl_xor(mx, off, 64));
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < 8; c++) out[c] = acc[c].hi + acc[c].lo;
+        double brms = sqrt((acc[8].hi + acc[8].lo) / (nzones > 0.0 ? nzones : 1.0));
+        if (brms < 1e-300) brms = 1e-300;
+        out[8] = mx * dmin / brms;
+        out[9] = mx;
+        out[10] = (double)counters[0];
+        out[11] = (double)counters[1];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1384,11 +1483,14 @@ hipError_t launch_sweep(int d, int stage, void* pool, const PatchDev* pt, const 
     return hipGetLastError();
 }
 
+// diagnostics into out[12] (device memory); rec holds nblk records of DIAG_REC doubles
 template <typename R>
 hipError_t launch_diag(const void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, int cur,
-                       double* partial, hipStream_t st) {
-    if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL(diag_kernel<R>, dim3(nblk), dim3(256), 0, st, (const R*)pool, pt, wk, prm, cur, partial);
+                       double* rec, const unsigned long long* counters, double nzones, double dmin, double* out,
+                       hipStream_t st) {
+    if (nblk > 0)
+        hipLaunchKernelGGL(diag_kernel<R>, dim3(nblk), dim3(DIAG_THREADS), 0, st, (const R*)pool, pt, wk, prm, cur, rec);
+    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, st, rec, nblk, counters, nzones, dmin, out);
     return hipGetLastError();
 }
 
@@ -1407,7 +1509,7 @@ hipError_t launch_diag(const void* pool, const PatchDev* pt, const WorkItem* wk,
                                         const Coef<R>&, int, const StepConst*, int, int, int, unsigned long long*,       \
                                         hipStream_t);                                                                    \
     template hipError_t launch_diag<R>(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,        \
-                                       double*, hipStream_t);
+                                       double*, const unsigned long long*, double, double, double*, hipStream_t);
 WMB_INST(float)
 WMB_INST(double)
 #undef WMB_INST

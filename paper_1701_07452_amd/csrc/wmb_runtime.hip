@@ -21,7 +21,7 @@ hipError_t launch_set_dt(StepConst*, double, const DevParams&, hipStream_t);
 template <typename R> hipError_t launch_ct_half(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int, const StepConst*, hipStream_t);
 template <typename R> hipError_t launch_update(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, unsigned long long*, unsigned long long*, int, int, hipStream_t);
 template <typename R> hipError_t launch_sweep(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, int, int, int, unsigned long long*, hipStream_t);
-template <typename R> hipError_t launch_diag(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, double*, hipStream_t);
+template <typename R> hipError_t launch_diag(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, double*, const unsigned long long*, double, double, double*, hipStream_t);
 }  // namespace wmb
 
 using namespace wmb;
@@ -85,7 +85,8 @@ struct wmb_ctx {
     Coef<float> cf32{};
     Coef<double> cf64{};
     unsigned long long* d_nfloor = nullptr;
-    double* d_partial = nullptr;
+    double* d_partial = nullptr;   // diagnostics records, DIAG_REC doubles per item of wl_diag
+    double* d_diag_out = nullptr;  // the 12 diagnostics outputs
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
     std::string err;
@@ -142,6 +143,15 @@ int dev_alloc(wmb_ctx* c, T** ptr, size_t count) {
     c->owned.push_back(p);
     *ptr = static_cast<T*>(p);
     return WMB_OK;
+}
+
+// free a library-owned device allocation before the context ends
+void release(wmb_ctx* c, void* p) {
+    if (!p) return;
+    auto it = std::find(c->owned.begin(), c->owned.end(), p);
+    if (it == c->owned.end()) return;
+    c->owned.erase(it);
+    (void)hipFree(p);  // a list no launch uses any more: nothing to report
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin by workgroup id, and
@@ -230,16 +240,20 @@ uint64_t region_bytes(const wmb_patch_desc& d, int g, size_t es) {
     return (b + 255) & ~uint64_t(255);
 }
 
-// largest interior edge accepted (keeps the box volume arithmetic far from
-// overflow; the 4 GiB region limit below is the binding one)
-constexpr int kMaxEdge = 65536;
+// Largest interior edge the kernels take, per precision.  Every axis is a
+// transverse axis of some sweep, and a sweep work item packs its pencil
+// rectangle's first transverse coordinates as 10-bit fields biased by 512,
+// where a frame rectangle starts at the edge n itself: n <= 511.  A Step-1
+// sweep block holds whole pencils of n + 8 zones with 16 words of LDS a zone
+// (at most 1024 threads and 64 KiB): n <= 1016 in FP32, n <= 504 in FP64.
+int max_edge(size_t es) { return es == 4 ? 511 : 504; }
 
 int check_table(int32_t np, const wmb_patch_desc* d, int g, size_t es, std::string& why) {
     for (int i = 0; i < np; i++) {
         for (int a = 0; a < 3; a++)
-            if (d[i].n[a] < g || d[i].n[a] > kMaxEdge) {
+            if (d[i].n[a] < g || d[i].n[a] > max_edge(es)) {
                 why = "patch " + std::to_string(i) + ": interior edge below the ghost width or above " +
-                      std::to_string(kMaxEdge);
+                      std::to_string(max_edge(es));
                 return WMB_EINVAL;
             }
         // kernels address a patch region with 32-bit byte offsets
@@ -459,6 +473,20 @@ int build_box_list(wmb_ctx* c, Box bx, DevList& out, bool xcd = true) {
     return upload(c, &out.d, items);
 }
 
+// Diagnostics work items: runs of at most DIAG_CHUNK interior zones of one
+// patch (linear index, x fastest): a = first zone, b = count.  Patch order,
+// so that the reduction order is fixed.
+constexpr int DIAG_CHUNK = 16384;
+int build_diag_list(wmb_ctx* c) {
+    std::vector<WorkItem> items;
+    for (int p = 0; p < c->npatch; p++) {
+        const int nz = c->desc[p].n[0] * c->desc[p].n[1] * c->desc[p].n[2];
+        for (int z0 = 0; z0 < nz; z0 += DIAG_CHUNK) items.push_back(WorkItem{p, z0, std::min(DIAG_CHUNK, nz - z0), 0});
+    }
+    c->wl_diag.n = (int)items.size();
+    return upload(c, &c->wl_diag.d, items);
+}
+
 // Column tiles of the marching kernels over the in-plane box [lo, n+hi]^2
 // (x, y) and the planes [zlo, n+zhi]: each patch's box is cut into near-equal
 // parts of at most txmax zones along x (whole rows where they fit, so tile
@@ -613,6 +641,9 @@ std::vector<WorkItem> sweep_items(const wmb_ctx* c, int d, int n, int tlo, int t
         }
         for (const Rect& r : rects) {
             const int npen = r.fcnt * r.scnt;
+            if (npen <= 0) continue;
+            // the packed fields (check_table bounds the edges so that they fit)
+            if (r.flo < -512 || r.flo > 511 || r.slo < -512 || r.slo > 511 || r.fcnt > 2047) return {};
             const int code = (r.flo + 512) | ((r.slo + 512) << 10) | (r.fcnt << 20);
             for (int p0 = 0; p0 < npen; p0 += W)
                 items.push_back(WorkItem{p, p0, code, (p0 + W - 1 < npen - 1) ? p0 + W - 1 : npen - 1});
@@ -622,19 +653,24 @@ std::vector<WorkItem> sweep_items(const wmb_ctx* c, int d, int n, int tlo, int t
 }
 
 // (Re)build a group's work lists for W pencils a block.
+// (Re)build a group's work lists for W pencils a block; the lists they
+// replace are freed.
 int set_group_W(wmb_ctx* c, int d, int stage, SweepGroup& G, int W) {
-    std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, W);
-    int rc = upload(c, &G.wl.d, items);
+    auto rebuild = [&](DevList& L, SweepPart part) -> int {
+        std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, W, part);
+        if (items.empty()) return fail(c, WMB_EINVAL, "sweep work list: pencil rectangle outside the packed range");
+        WorkItem* nd = nullptr;
+        int rc = upload(c, &nd, items);
+        if (rc) return rc;
+        release(c, L.d);
+        L.d = nd;
+        L.n = (int)items.size();
+        return WMB_OK;
+    };
+    int rc = rebuild(G.wl, PART_ALL);
+    if (!rc && d == 0 && stage == 0) rc = rebuild(G.wl_in, PART_INTERIOR);
+    if (!rc && d == 0 && stage == 0) rc = rebuild(G.wl_fr, PART_FRAME);
     if (rc) return rc;
-    G.wl.n = (int)items.size();
-    if (d == 0 && stage == 0) {
-        items = sweep_items(c, d, G.n, G.tlo, G.thi, W, PART_INTERIOR);
-        if ((rc = upload(c, &G.wl_in.d, items))) return rc;
-        G.wl_in.n = (int)items.size();
-        items = sweep_items(c, d, G.n, G.tlo, G.thi, W, PART_FRAME);
-        if ((rc = upload(c, &G.wl_fr.d, items))) return rc;
-        G.wl_fr.n = (int)items.size();
-    }
     G.W = W;
     return WMB_OK;
 }
@@ -706,7 +742,11 @@ int capture_graphs(wmb_ctx* c) {
             return rc ? rc : fail(c, WMB_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
         }
         c->graph[cur0] = g;
-        CKH(hipGraphInstantiate(&c->gexec[cur0], g, nullptr, nullptr, 0));
+        e = hipGraphInstantiate(&c->gexec[cur0], g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            restore();
+            return fail(c, WMB_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
         // dispatch_step flipped cur; the second capture covers the other copy
     }
     restore();
@@ -755,12 +795,15 @@ int set_state_t(wmb_ctx* c, int ip, const double* q, const double* b) {
                                           0.5 * (u[4] * u[4] + u[5] * u[5] + u[6] * u[6]));
         if (!(pr > 0.0)) return fail(c, WMB_ESTATE, "pressure <= 0");
     }
-    std::vector<R> buf((size_t)P.vol, (R)NAN);
+    // the 11 arrays of a state copy are contiguous in the patch region: one
+    // host image (ghosts NaN until the next exchange), one copy
+    std::vector<R> img((size_t)11 * P.vol, (R)NAN);
     R* base = (R*)c->pool + P.base + (long long)(c->cur ? F_ST1 : F_ST0) * P.vol;
     if (c->smax_state != SMAX_ZERO) c->smax_state = SMAX_DIRTY;
     for (int f = 0; f < 11; f++) {
         const double* src = f < 8 ? q + f * n3 : b + (f - 8) * n3;
-        to_device_layout<R>(src, buf.data(), P, g, n3);
+        R* buf = img.data() + (size_t)f * P.vol;
+        to_device_layout<R>(src, buf, P, g, n3);
         const int a = f - 8;
         if (a >= 0 && P.nb[2 * a + 1] < 0) {
             // the patch owns its right face along an axis that ends at a domain
@@ -777,9 +820,9 @@ int set_state_t(wmb_ctx* c, int ip, const double* q, const double* b) {
                     buf[(size_t)x] = buf[(size_t)(x - st)];
                 }
         }
-        CKH(hipMemcpyAsync(base + (long long)f * P.vol, buf.data(), sizeof(R) * P.vol, hipMemcpyHostToDevice, c->stream));
-        CKH(hipStreamSynchronize(c->stream));
     }
+    CKH(hipMemcpyAsync(base, img.data(), sizeof(R) * img.size(), hipMemcpyHostToDevice, c->stream));
+    CKH(hipStreamSynchronize(c->stream));
     return WMB_OK;
 }
 
@@ -788,18 +831,19 @@ int get_state_t(wmb_ctx* c, int ip, double* q, double* b, bool stored) {
     const PatchDev& P = c->hpatch[ip];
     const int g = c->p.ghost;
     const size_t n3 = (size_t)P.n[0] * P.n[1] * P.n[2];
-    std::vector<R> buf((size_t)P.vol);
+    std::vector<R> img((size_t)11 * P.vol);
     const R* base = (const R*)c->pool + P.base + (long long)(c->cur ? F_ST1 : F_ST0) * P.vol;
+    CKH(hipMemcpyAsync(img.data(), base, sizeof(R) * img.size(), hipMemcpyDeviceToHost, c->stream));
+    CKH(hipStreamSynchronize(c->stream));
     for (int f = 0; f < 11; f++) {
         double* dst = f < 8 ? q : b;
         if (!dst) continue;
-        CKH(hipMemcpyAsync(buf.data(), base + (long long)f * P.vol, sizeof(R) * P.vol, hipMemcpyDeviceToHost, c->stream));
-        CKH(hipStreamSynchronize(c->stream));
+        const R* buf = img.data() + (size_t)f * P.vol;
         int ff = f < 8 ? f : f - 8;
         if (stored) {
             for (long long t = 0; t < P.vol; t++) dst[(size_t)ff * P.vol + t] = (double)buf[t];
         } else {
-            from_device_layout<R>(buf.data(), dst + (size_t)ff * n3, P, g);
+            from_device_layout<R>(buf, dst + (size_t)ff * n3, P, g);
         }
     }
     return WMB_OK;
@@ -840,36 +884,33 @@ int debug_stage_t(wmb_ctx* c, int ip, int stage, double* out) {
     return WMB_OK;
 }
 
+// Diagnostics on the device (compensated sums, fixed reduction order) into
+// the 12 doubles at out: totals[8], max normalised div b, max |div b|, floor
+// activations, protected faces.  rec holds wl_diag.n records.
 template <typename R>
-int diagnostics_t(wmb_ctx* c, double totals[8], double* dn, double* dr, int64_t* nfl, int64_t* npr) {
-    hipError_t e = launch_diag<R>(c->pool, c->d_patch, c->wl_diag.d, c->wl_diag.n, c->dp, c->cur, c->d_partial, c->stream);
-    if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("diag: ") + hipGetErrorString(e));
-    std::vector<double> part((size_t)c->wl_diag.n * 10);
-    CKH(hipMemcpyAsync(part.data(), c->d_partial, sizeof(double) * part.size(), hipMemcpyDeviceToHost, c->stream));
-    unsigned long long cnt[2] = {0, 0};
-    CKH(hipMemcpyAsync(cnt, c->d_nfloor, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
-    CKH(hipStreamSynchronize(c->stream));
-    double sum[9] = {0}, comp[9] = {0}, mx = 0.0;
-    for (int b = 0; b < c->wl_diag.n; b++) {
-        for (int k = 0; k < 9; k++) {
-            double y = part[(size_t)b * 10 + k] - comp[k];
-            double t = sum[k] + y;
-            comp[k] = (t - sum[k]) - y;
-            sum[k] = t;
-        }
-        mx = std::fmax(mx, part[(size_t)b * 10 + 9]);
-    }
+int enqueue_diag(wmb_ctx* c, double* rec, double* out) {
     long long nz = 0;
     for (int p = 0; p < c->npatch; p++) nz += (long long)c->desc[p].n[0] * c->desc[p].n[1] * c->desc[p].n[2];
+    const double dmin = std::fmin(c->p.dx[0], std::fmin(c->p.dx[1], c->p.dx[2]));
+    hipError_t e = launch_diag<R>(c->pool, c->d_patch, c->wl_diag.d, c->wl_diag.n, c->dp, c->cur, rec, c->d_nfloor,
+                                  (double)nz, dmin, out, c->stream);
+    if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("diag: ") + hipGetErrorString(e));
+    return WMB_OK;
+}
+
+template <typename R>
+int diagnostics_t(wmb_ctx* c, double totals[8], double* dn, double* dr, int64_t* nfl, int64_t* npr) {
+    int rc = enqueue_diag<R>(c, c->d_partial, c->d_diag_out);
+    if (rc) return rc;
+    double o[12];
+    CKH(hipMemcpyAsync(o, c->d_diag_out, sizeof(o), hipMemcpyDeviceToHost, c->stream));
+    CKH(hipStreamSynchronize(c->stream));
     if (totals)
-        for (int k = 0; k < 8; k++) totals[k] = sum[k];
-    double brms = std::sqrt(sum[8] / (double)(nz ? nz : 1));
-    if (brms < 1e-300) brms = 1e-300;
-    double dmin = std::fmin(c->p.dx[0], std::fmin(c->p.dx[1], c->p.dx[2]));
-    if (dr) *dr = mx;
-    if (dn) *dn = mx * dmin / brms;
-    if (nfl) *nfl = (int64_t)cnt[0];
-    if (npr) *npr = (int64_t)cnt[1];
+        for (int k = 0; k < 8; k++) totals[k] = o[k];
+    if (dn) *dn = o[8];
+    if (dr) *dr = o[9];
+    if (nfl) *nfl = (int64_t)o[10];
+    if (npr) *npr = (int64_t)o[11];
     return WMB_OK;
 }
 
@@ -884,9 +925,23 @@ int autotune_t(wmb_ctx* c, int reps) {
     if (!rc) rc = ensure_smax(c);
     if (!rc) rc = run_finalize(c);
     if (rc) return rc;
-    hipEvent_t e0, e1;
-    CKH(hipEventCreate(&e0));
-    CKH(hipEventCreate(&e1));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    WorkItem* dl = nullptr;  // the candidate list of one timing
+    // every exit below goes through cleanup
+    auto cleanup = [&](int code) -> int {
+        if (dl) (void)hipFree(dl);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return code;
+    };
+#define CKT(call)                                                                                       \
+    do {                                                                                                \
+        hipError_t e_ = (call);                                                                         \
+        if (e_ != hipSuccess)                                                                           \
+            return cleanup(fail(c, WMB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)));        \
+    } while (0)
+    CKT(hipEventCreate(&e0));
+    CKT(hipEventCreate(&e1));
     const size_t es = sizeof(R);
     for (int stage = 0; stage < 2; stage++) {
         if (stage == 1) {
@@ -899,7 +954,7 @@ int autotune_t(wmb_ctx* c, int reps) {
             if (e == hipSuccess)
                 e = launch_ct_half<R>(c->pool, c->d_patch, c->wl_cth.d, c->wl_cth.n, coef<R>(c), c->p.ghost, c->cur,
                                       c->d_sc, c->stream);
-            if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+            if (e != hipSuccess) return cleanup(fail(c, WMB_EHIP, std::string("autotune: ") + hipGetErrorString(e)));
         }
         for (int d = 0; d < 3; d++) {
             for (auto& G : c->sweeps[d][stage]) {
@@ -917,23 +972,25 @@ int autotune_t(wmb_ctx* c, int reps) {
                 for (int W : cand) {
                     if ((size_t)G.P * W > 1024 || es * 16 * (size_t)G.P * W > 64 * 1024 || G.P * W < 64) continue;
                     std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, W);
-                    WorkItem* dl = nullptr;
-                    CKH(hipMalloc(&dl, sizeof(WorkItem) * items.size()));
-                    CKH(hipMemcpy(dl, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
+                    if (items.empty()) continue;
+                    CKT(hipMalloc(&dl, sizeof(WorkItem) * items.size()));
+                    CKT(hipMemcpy(dl, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
                     float tot = 0.f;
                     hipError_t e = hipSuccess;
                     for (int r = 0; r <= reps && e == hipSuccess; r++) {
-                        CKH(hipEventRecord(e0, c->stream));
+                        CKT(hipEventRecord(e0, c->stream));
                         e = launch_sweep<R>(d, stage + 1, c->pool, c->d_patch, dl, (int)items.size(), c->dp, coef<R>(c),
                                             c->cur, c->d_sc, G.P, W, G.zlo, c->d_nfloor + 2, c->stream);
-                        CKH(hipEventRecord(e1, c->stream));
-                        CKH(hipEventSynchronize(e1));
+                        CKT(hipEventRecord(e1, c->stream));
+                        CKT(hipEventSynchronize(e1));
                         float t = 0.f;
-                        CKH(hipEventElapsedTime(&t, e0, e1));
+                        CKT(hipEventElapsedTime(&t, e0, e1));
                         if (r > 0) tot += t;  // first launch is a warm-up
                     }
-                    (void)hipFree(dl);  // the candidate list of one timing
-                    if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+                    (void)hipFree(dl);
+                    dl = nullptr;
+                    if (e != hipSuccess)
+                        return cleanup(fail(c, WMB_EHIP, std::string("autotune: ") + hipGetErrorString(e)));
                     if (tot < best) {
                         best = tot;
                         bestW = W;
@@ -941,15 +998,14 @@ int autotune_t(wmb_ctx* c, int reps) {
                 }
                 if (bestW != G.W) {
                     int rc2 = set_group_W(c, d, stage, G, bestW);
-                    if (rc2) return rc2;
+                    if (rc2) return cleanup(rc2);
                 }
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+#undef CKT
     free_graphs(c);  // launch plans changed
-    return WMB_OK;
+    return cleanup(WMB_OK);
 }
 
 }  // namespace
@@ -989,7 +1045,7 @@ int wmb_pool_bytes(const wmb_params* p, int32_t npatch, const wmb_patch_desc* d,
     if (check_params(p) || npatch <= 0 || !d || !bytes) return WMB_EINVAL;
     for (int i = 0; i < npatch; i++)
         for (int a = 0; a < 3; a++)
-            if (d[i].n[a] < 1 || d[i].n[a] > kMaxEdge) return WMB_EINVAL;
+            if (d[i].n[a] < 1 || d[i].n[a] > max_edge(esize_of(p))) return WMB_EINVAL;
     uint64_t tot = 0;
     for (int i = 0; i < npatch; i++) tot += region_bytes(d[i], p->ghost, esize_of(p));
     *bytes = tot;
@@ -1042,7 +1098,7 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     if ((rc = upload(c, &c->d_patch, c->hpatch))) return rc;
     if ((rc = build_fill_lists(c))) return rc;
     if ((rc = build_box_list(c, BOX_INTERIOR, c->wl_int))) return rc;
-    if ((rc = build_box_list(c, BOX_INTERIOR, c->wl_diag, false))) return rc;
+    if ((rc = build_diag_list(c))) return rc;
     // Steps 3-4: tiles up to 40 zones wide and 256 a plane ((tx+1)(ty+1) <= 297
     // edges); Steps 8-11: up to 32 wide and upd_tile_zones a plane (the LDS
     // planes of the kernel are sized for both)
@@ -1063,7 +1119,8 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     if ((rc = dev_alloc(c, &c->d_sc, 1))) return rc;
     // counters: floor activations, protected faces, and a sink for tuning runs
     if ((rc = dev_alloc(c, &c->d_nfloor, 3))) return rc;
-    if ((rc = dev_alloc(c, &c->d_partial, (size_t)c->wl_diag.n * 10))) return rc;
+    if ((rc = dev_alloc(c, &c->d_partial, (size_t)c->wl_diag.n * DIAG_REC))) return rc;
+    if ((rc = dev_alloc(c, &c->d_diag_out, 12))) return rc;
     CKH(hipMemsetAsync(c->d_smax, 0, 2 * sizeof(unsigned long long), c->stream));
     CKH(hipMemsetAsync(c->d_sc, 0, sizeof(StepConst), c->stream));
     CKH(hipMemsetAsync(c->d_nfloor, 0, 3 * sizeof(unsigned long long), c->stream));
@@ -1123,8 +1180,11 @@ int wmb_advance(wmb_ctx* c, double dt) {
     if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
     if (dt > 0.0) {
         if (!std::isfinite(dt)) return fail(c, WMB_EINVAL, "non-finite dt");
+        // the limit of the current state: an explicit reduction (the maximum
+        // the last update folded in may be the lagged one under dt_lag)
         double lim = 0.0;
-        int rc = wmb_compute_dt(c, &lim);
+        int rc = c->esize == 4 ? run_reduce<float>(c) : run_reduce<double>(c);
+        if (!rc) rc = wmb_compute_dt(c, &lim);
         if (rc) return rc;
         if (dt > lim * (1.0 + 1e-12)) return fail(c, WMB_ECFL, "dt above the CFL limit " + std::to_string(lim));
         CKH(launch_set_dt(c->d_sc, dt, c->dp, c->stream));

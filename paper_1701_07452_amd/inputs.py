@@ -111,6 +111,13 @@ def split(G: PatchGrid, q, b):
     return out
 
 
+def iter_split(G: PatchGrid, q, b):
+    """Like split, one patch at a time (no second copy of the whole box)."""
+    for (n, _), (ox, oy, oz) in zip(G.descs, G.origin):
+        sl = (slice(None), slice(oz, oz + n[2]), slice(oy, oy + n[1]), slice(ox, ox + n[0]))
+        yield np.ascontiguousarray(q[sl]), np.ascontiguousarray(b[sl])
+
+
 def gather(G: PatchGrid, parts):
     """Per-patch (q, b) -> global (8, Nz, Ny, Nx), (3, Nz, Ny, Nx)."""
     q = np.zeros((8,) + G.shape)

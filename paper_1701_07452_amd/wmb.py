@@ -176,9 +176,12 @@ class Sim:
             raise WmbError(rc, msg)
 
     def close(self):
+        """Destroy the context and drop the pool tensor (its memory returns to
+        torch's caching allocator once no other reference holds it)."""
         if getattr(self, "h", None) and self.h.value:
             self.lib.wmb_destroy(self.h)
             self.h = C.c_void_p()
+        self.pool = None
 
     def __del__(self):
         try:
@@ -305,6 +308,6 @@ def sim_from_grid(G, q=None, b=None, **params_kw):
     prm = make_params(**params_kw)
     sim = Sim(prm, G.descs, origins=G.origin)
     if q is not None:
-        for ip, (qp, bp) in enumerate(I.split(G, q, b)):
+        for ip, (qp, bp) in enumerate(I.iter_split(G, q, b)):
             sim.set_state(ip, qp, bp)
     return sim

@@ -165,3 +165,34 @@ def test_patch_table_checks_reject_malformed_tables(lib):
         assert lib.wmb_destroy(h) == 0
         cases += 1
     assert cases == 400
+
+
+@pytest.mark.parametrize("prec,edge,ok", [(1, 511, True), (1, 512, False), (0, 504, True), (0, 505, False)])
+def test_edge_limits_of_the_kernels(lib, prec, edge, ok):
+    """Interior edges beyond what the kernels take are rejected up front
+    (WMB_EINVAL from wmb_pool_bytes and wmb_init_patches), before any device
+    work: at most 511 zones along any axis (the sweeps' packed pencil
+    rectangles), and at most 504 in FP64 (a Step-1 sweep block holds a whole
+    pencil of n + 8 zones with 16 doubles of LDS a zone).  Thin patches keep
+    the region far below its 4 GiB limit, so this check is the binding one."""
+    from paper_1701_07452_amd import inputs as I
+    from paper_1701_07452_amd import wmb
+
+    for axis in range(3):
+        n = [8, 8, 8]
+        n[axis] = edge
+        G = I.uniform_grid(tuple(n), tuple(n))
+        p = wmb.make_params(ghost=4, precision=prec)
+        d = wmb.descs_to_c(G.descs, G.origin)
+        out = C.c_uint64(0)
+        rc = lib.wmb_pool_bytes(C.byref(p), 1, d, C.byref(out))
+        assert (rc == 0) == ok, (axis, rc)
+        h = C.c_void_p()
+        assert lib.wmb_create(C.byref(p), C.byref(h)) == 0
+        rc = lib.wmb_init_patches(h, 1, d, C.c_void_p(1), C.c_uint64(1 << 40), None)
+        if ok:
+            assert rc != wmb.WMB_EINVAL  # passes the checks (then needs a GPU)
+        else:
+            assert rc == wmb.WMB_EINVAL
+            assert b"above" in lib.wmb_last_error(h)
+        assert lib.wmb_destroy(h) == 0
