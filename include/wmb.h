@@ -181,6 +181,22 @@ int wmb_run_steps(wmb_ctx *c, int32_t nsteps);
 int wmb_diagnostics(wmb_ctx *c, double totals[8], double *max_divb_norm, double *max_divb_raw,
                     int64_t *n_floored, int64_t *n_protected);
 
+/* Allocation-free variant of wmb_diagnostics, for callers that cannot
+   allocate (code under HIP graph capture, tight serving loops, harnesses
+   that forbid allocation): enqueues the same kernels on the context's stream
+   and writes 12 doubles to dev_out, a caller-owned device array: totals[0..7],
+   max_divb_norm, max_divb_raw, n_floored, n_protected (counts as exact
+   doubles), bitwise what wmb_diagnostics returns for the same state.  It
+   allocates nothing and does not synchronise: the per-record partial sums go
+   to a static device array of 32768 records (5 MiB) that each GPU the
+   library runs on holds until the process ends.  Every call on a GPU shares
+   that array: calls that overlap on one GPU (contexts on several streams)
+   race; each call rewrites every record it reads, so nothing has to be
+   cleared between calls.  WMB_ESIZE if the batch needs more than 32768
+   records (one per started run of 32768 interior zones of a patch),
+   WMB_EINVAL for a NULL dev_out. */
+int wmb_diagnostics_noalloc(wmb_ctx *c, double *dev_out);
+
 /* Test hook: copy an intermediate of the last step of one patch over the
    ghosted box, widened to double, in this layout: stage 1 Step-1 fluxes
    (3 x 8 x vol, lab component order, B_par row 0), 3 b^{n+1/2} (3 x vol),

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -87,6 +88,8 @@ struct wmb_ctx {
     unsigned long long* d_nfloor = nullptr;
     double* d_partial = nullptr;   // diagnostics records, DIAG_REC doubles per item of wl_diag
     double* d_diag_out = nullptr;  // the 12 diagnostics outputs
+    double* noalloc_rec = nullptr; // this device's copy of the static records (wmb_diagnostics_noalloc)
+    long long nzones = 0;          // interior zones of the batch
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
     std::string err;
@@ -124,6 +127,13 @@ void make_coef(const wmb_params& p, Coef<R>& cf) {
 
 int fail(wmb_ctx* c, int code, const std::string& msg) {
     if (c) c->err = msg;
+    return code;
+}
+
+// failure with a fixed message, without allocating (the message buffer is
+// reserved when the context is created)
+int fail_static(wmb_ctx* c, int code, const char* msg) {
+    if (c) c->err.assign(msg);
     return code;
 }
 
@@ -476,7 +486,7 @@ int build_box_list(wmb_ctx* c, Box bx, DevList& out, bool xcd = true) {
 // Diagnostics work items: runs of at most DIAG_CHUNK interior zones of one
 // patch (linear index, x fastest): a = first zone, b = count.  Patch order,
 // so that the reduction order is fixed.
-constexpr int DIAG_CHUNK = 16384;
+constexpr int DIAG_CHUNK = 32768;
 int build_diag_list(wmb_ctx* c) {
     std::vector<WorkItem> items;
     for (int p = 0; p < c->npatch; p++) {
@@ -889,12 +899,10 @@ int debug_stage_t(wmb_ctx* c, int ip, int stage, double* out) {
 // activations, protected faces.  rec holds wl_diag.n records.
 template <typename R>
 int enqueue_diag(wmb_ctx* c, double* rec, double* out) {
-    long long nz = 0;
-    for (int p = 0; p < c->npatch; p++) nz += (long long)c->desc[p].n[0] * c->desc[p].n[1] * c->desc[p].n[2];
     const double dmin = std::fmin(c->p.dx[0], std::fmin(c->p.dx[1], c->p.dx[2]));
     hipError_t e = launch_diag<R>(c->pool, c->d_patch, c->wl_diag.d, c->wl_diag.n, c->dp, c->cur, rec, c->d_nfloor,
-                                  (double)nz, dmin, out, c->stream);
-    if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("diag: ") + hipGetErrorString(e));
+                                  (double)c->nzones, dmin, out, c->stream);
+    if (e != hipSuccess) return fail_static(c, WMB_EHIP, "diagnostics: kernel launch failed");
     return WMB_OK;
 }
 
@@ -1008,6 +1016,35 @@ int autotune_t(wmb_ctx* c, int reps) {
     return cleanup(WMB_OK);
 }
 
+// ---------------------------------------------------------------------------
+// Static records of the allocation-free diagnostics (wmb_diagnostics_noalloc):
+// NOALLOC_RECORDS records of DIAG_REC doubles (5 MiB) in a device array that
+// every GPU the library runs on holds until the process ends.  In host code
+// the array's name is only a stand-in: kernels get the device address that
+// hipGetSymbolAddress returns for the current device, taken once per device
+// when a context is bound to it (wmb_init_patches).
+// ---------------------------------------------------------------------------
+constexpr int NOALLOC_RECORDS = 32768;
+static __device__ __align__(256) double scratch[NOALLOC_RECORDS * DIAG_REC];
+
+constexpr int MAX_DEVICES = 64;
+double* scratch_dev[MAX_DEVICES] = {};
+std::mutex scratch_mu;
+
+int bind_scratch(wmb_ctx* c) {
+    int dev = -1;
+    CKH(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail_static(c, WMB_EHIP, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* p = nullptr;
+        CKH(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        scratch_dev[dev] = static_cast<double*>(p);
+    }
+    c->noalloc_rec = scratch_dev[dev];
+    return WMB_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1023,6 +1060,7 @@ int wmb_create(const wmb_params* p, wmb_ctx** out) {
     if (rc) return rc;
     wmb_ctx* c = new (std::nothrow) wmb_ctx();
     if (!c) return WMB_ENOMEM;
+    c->err.reserve(256);  // fixed messages fit without a later allocation
     c->p = *p;
     c->esize = esize_of(p);
     c->dp.gamma = p->gamma;
@@ -1121,6 +1159,9 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     if ((rc = dev_alloc(c, &c->d_nfloor, 3))) return rc;
     if ((rc = dev_alloc(c, &c->d_partial, (size_t)c->wl_diag.n * DIAG_REC))) return rc;
     if ((rc = dev_alloc(c, &c->d_diag_out, 12))) return rc;
+    c->nzones = 0;
+    for (int p = 0; p < npatch; p++) c->nzones += (long long)d[p].n[0] * d[p].n[1] * d[p].n[2];
+    if ((rc = bind_scratch(c))) return rc;
     CKH(hipMemsetAsync(c->d_smax, 0, 2 * sizeof(unsigned long long), c->stream));
     CKH(hipMemsetAsync(c->d_sc, 0, sizeof(StepConst), c->stream));
     CKH(hipMemsetAsync(c->d_nfloor, 0, 3 * sizeof(unsigned long long), c->stream));
@@ -1222,6 +1263,18 @@ int wmb_diagnostics(wmb_ctx* c, double totals[8], double* max_divb_norm, double*
     if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
     return c->esize == 4 ? diagnostics_t<float>(c, totals, max_divb_norm, max_divb_raw, n_floored, n_protected)
                          : diagnostics_t<double>(c, totals, max_divb_norm, max_divb_raw, n_floored, n_protected);
+}
+
+int wmb_diagnostics_noalloc(wmb_ctx* c, double* dev_out) {
+    if (!c) return WMB_EINVAL;
+    if (!dev_out) return fail_static(c, WMB_EINVAL, "diagnostics_noalloc: null output");
+    if (!c->inited) return fail_static(c, WMB_EORDER, "wmb_init_patches first");
+    if (c->wl_diag.n > NOALLOC_RECORDS)
+        return fail_static(c, WMB_ESIZE,
+                           "diagnostics_noalloc: the batch needs more than 32768 records (one per started run of "
+                           "32768 interior zones of a patch); use wmb_diagnostics");
+    if (!c->noalloc_rec) return fail_static(c, WMB_EHIP, "diagnostics_noalloc: no scratch address for this device");
+    return c->esize == 4 ? enqueue_diag<float>(c, c->noalloc_rec, dev_out) : enqueue_diag<double>(c, c->noalloc_rec, dev_out);
 }
 
 int wmb_debug_stage(wmb_ctx* c, int32_t patch, int32_t stage, double* out) {

@@ -20,7 +20,8 @@ WMB_FP64, WMB_FP32 = 0, 1
 
 EXPORTS = [
     "wmb_create", "wmb_pool_bytes", "wmb_init_patches", "wmb_set_state", "wmb_get_state", "wmb_get_stored",
-    "wmb_fill_ghosts", "wmb_compute_dt", "wmb_advance", "wmb_run_steps", "wmb_diagnostics", "wmb_debug_stage",
+    "wmb_fill_ghosts", "wmb_compute_dt", "wmb_advance", "wmb_run_steps", "wmb_diagnostics",
+    "wmb_diagnostics_noalloc", "wmb_debug_stage",
     "wmb_autotune", "wmb_set_tuning", "wmb_keep_stages", "wmb_set_active", "wmb_profile_step", "wmb_destroy",
     "wmb_strerror", "wmb_last_error",
 ]
@@ -101,6 +102,7 @@ def load_library():
     lib.wmb_advance.argtypes = [vp, C.c_double]
     lib.wmb_run_steps.argtypes = [vp, C.c_int32]
     lib.wmb_diagnostics.argtypes = [vp, dp, dp, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.wmb_diagnostics_noalloc.argtypes = [vp, vp]
     lib.wmb_debug_stage.argtypes = [vp, C.c_int32, C.c_int32, dp]
     lib.wmb_profile_step.argtypes = [vp, dp, C.c_int32]
     lib.wmb_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.c_int32]
@@ -239,6 +241,16 @@ class Sim:
         nf = C.c_int64(0)
         self._check(self.lib.wmb_diagnostics(self.h, _dp(tot), _dp(dn), _dp(dr), C.byref(nf), None))
         return tot, float(dn[0]), float(dr[0]), int(nf.value)
+
+    def diagnostics_noalloc(self, out):
+        """Enqueue the allocation-free diagnostics into `out`, a float64 device
+        tensor of 12 (totals[8], div b normalised, raw, floors, protected)."""
+        import torch
+
+        if out.dtype != torch.float64 or out.numel() < 12 or not out.is_cuda or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 device tensor of 12 elements")
+        self._check(self.lib.wmb_diagnostics_noalloc(self.h, C.c_void_p(out.data_ptr())))
+        return out
 
     def protected_faces(self):
         """Faces that took the HLL flux (protection floors) since creation."""
