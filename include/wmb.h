@@ -206,21 +206,33 @@ int wmb_diagnostics_noalloc(wmb_ctx *c, double *dev_out);
    overwritten by Step 9) give WMB_EINVAL.  Synchronous. */
 int wmb_debug_stage(wmb_ctx *c, int32_t patch, int32_t stage, double *out);
 
-/* Search the block shape of the directional sweeps (pencils per block) for
-   every group of patches with the same edge along the sweep axis, timing
-   each candidate `reps` times on the device, and keep the fastest.  The
-   choice never changes results (the arithmetic of a face does not depend on
-   it).  The interior state is unchanged; ghosts are refreshed and the step
+/* Search the shape of the directional sweeps for every group of patches
+   with the same edge along the sweep axis, timing each candidate `reps`
+   times on the device, and keep the fastest.  A shape W > 0 is the LDS
+   pencil form with W pencils a block (every thread one zone of a pencil);
+   W < 0, for the y and z sweeps only, is the marching form with -W pencils
+   a block (every thread walks one whole pencil, consecutive lanes on
+   consecutive x, the face data carried in registers); in FP32, W = -(w + 512)
+   selects for the corrector sweeps (Steps 6-7) the marching variant that
+   issues the next zone's loads one zone ahead (w pencils a block; more
+   registers, half the waves).  The choice never
+   changes results (both forms compute every face with the same
+   arithmetic).  The interior state is unchanged; ghosts are refreshed and the step
    intermediates overwritten.  Invalidates the captured graphs.  If chosen !=
-   NULL it receives quadruples (stage, axis, edge, pencils per block), up to
-   nchosen ints, 0-terminated when shorter.  Synchronous. */
+   NULL it receives quadruples (stage, axis, edge, shape), up to nchosen
+   ints, 0-terminated when shorter.  Synchronous. */
 int wmb_autotune(wmb_ctx *c, int32_t reps, int32_t *chosen, int32_t nchosen);
 
-/* Set the pencils per block of sweep groups directly: quads of (stage 1|2,
-   axis 0..2, edge along the axis, pencils per block), n ints in total (a
-   multiple of 4), as returned by wmb_autotune.  Groups not named keep their
-   shape.  WMB_EINVAL if a shape exceeds 1024 threads or 64 KiB of LDS.
-   Invalidates the captured graphs. */
+/* Set the shapes of sweep groups directly: quads of (stage 1|2, axis 0..2,
+   edge along the axis, shape), n ints in total (a multiple of 4), as
+   returned by wmb_autotune (shape > 0: pencil form with that many pencils a
+   block; shape < 0: marching form, y and z only, with -shape pencils a
+   block, at most 256, or -(w + 512) for the FP32 corrector with the loads
+   one zone ahead).  Groups not named keep their shape.  WMB_EINVAL if a
+   pencil shape exceeds 1024 threads or 64 KiB of LDS, or a marching shape
+   is asked for x or beyond 256.  Invalidates the captured graphs.  The
+   defaults are the marching form (64 pencils a block) for the y and z
+   sweeps in FP32 and the pencil form elsewhere. */
 int wmb_set_tuning(wmb_ctx *c, const int32_t *quads, int32_t n);
 
 /* Freeze (active = 0) or thaw (active != 0) one patch without rebuilding
@@ -262,7 +274,13 @@ int wmb_keep_stages(wmb_ctx *c, int32_t on);
 #define WMB_NCLASS 10
 int wmb_profile_step(wmb_ctx *c, double *ms, int32_t nclass);
 
-/* Free the context, its tables and graphs (not the pool, not the stream). */
+/* Free the context, its tables and graphs (not the pool, not the stream).
+   The streams the library uses besides the caller's (two for the concurrent
+   branches of the step graph, and its own main stream when the caller passed
+   NULL) are not destroyed but kept for later contexts on the same device:
+   on ROCm 7, destroying a stream that took part in a graph capture before
+   the memory its captured kernels used is freed keeps that memory from ever
+   being freed, and the caller frees its pool after this call. */
 int wmb_destroy(wmb_ctx *c);
 
 /* Static message for an error code. */

@@ -56,9 +56,15 @@ __device__ __forceinline__ double gdiv(double dg, double alpha) { return dg / al
 template <typename R>
 __device__ __forceinline__ R sgn1(R x) { return x >= R(0) ? R(1) : R(-1); }
 
+// The arithmetic helpers of the sweeps form fused multiply-adds only within
+// a source expression (contract(on)), so that the pencil and the marching
+// form of a sweep, which inline them into different code, round every face
+// identically.
+
 // coefficient of numerical viscosity Q_k(chi) (Appendix A); q4e = 1/(4 eps)
 template <typename R>
 __device__ __forceinline__ R qvisc(R chi, R eps, R q4e) {
+#pragma clang fp contract(on)
     R ac = fabs(chi);
     if (ac < R(2) * eps) return chi * chi * q4e + eps;
     return ac;
@@ -69,6 +75,7 @@ __device__ __forceinline__ R qvisc(R chi, R eps, R q4e) {
 // exactly and one branch is dropped (bitwise the same result)
 template <bool MM, typename R>
 __device__ __forceinline__ R sweby(R gp, R gm, R beta) {
+#pragma clang fp contract(on)
     R s = sgn1(gp);
     if (MM) return s * fmax(R(0), fmin(fabs(gp), s * gm));
     R t1 = fmin(beta * fabs(gp), s * gm);
@@ -78,6 +85,7 @@ __device__ __forceinline__ R sweby(R gp, R gm, R beta) {
 
 template <typename R>
 __device__ __forceinline__ R minmod2(R a, R b) {
+#pragma clang fp contract(on)
     if (a > R(0) && b > R(0)) return fmin(a, b);
     if (a < R(0) && b < R(0)) return fmax(a, b);
     return R(0);
@@ -126,6 +134,7 @@ __device__ __forceinline__ long long stride_of(const PatchDev& P, int a) {
 // raised by adding thermal energy).  Returns true if a floor fired.
 template <typename R>
 __device__ __forceinline__ bool apply_floor64(R u[8], const DevParams& p) {
+#pragma clang fp contract(on)
     bool hit = false;
     double rho = (double)u[0];
     if (rho < p.rho_floor) {
@@ -148,9 +157,11 @@ __device__ __forceinline__ bool apply_floor64(R u[8], const DevParams& p) {
 // density is above twice the floor) cannot be floored in FP64 either, so the
 // FP64 evaluation is skipped for it.
 __device__ __forceinline__ bool apply_floor(double u[8], const DevParams& p, const Coef<double>&) {
+#pragma clang fp contract(on)
     return apply_floor64(u, p);
 }
 __device__ __forceinline__ bool apply_floor(float u[8], const DevParams& p, const Coef<float>& cf) {
+#pragma clang fp contract(on)
     if (u[0] > 2.0f * cf.rho_floor) {
         float ir = frcp(u[0]);
         float ke = 0.5f * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * ir;
@@ -870,6 +881,7 @@ struct FaceEig {
 template <typename R>
 __device__ __forceinline__ bool fan_below_floor(R rl, R vxl, R vyl, R vzl, R b1l, R b2l, R pl, R bf,
                                                 const FaceEig<R>& e, R a2raw, const R alpha[7], const Coef<R>& cf) {
+#pragma clang fp contract(on)
     if (a2raw <= R(0)) return true;
     R w0 = rl, w1 = rl * vxl, w2 = rl * vyl, w3 = rl * vzl, w5 = b1l, w6 = b2l;
     R w7 = pl * cf.igm1 + R(0.5) * rl * (vxl * vxl + vyl * vyl + vzl * vzl) + R(0.5) * (bf * bf + b1l * b1l + b2l * b2l);
@@ -908,6 +920,367 @@ __device__ __forceinline__ bool fan_below_floor(R rl, R vxl, R vyl, R vzl, R b1l
     return low;
 }
 
+// ---------------------------------------------------------------------------
+// The three phases of a directional sweep as functions of values, shared by
+// the two forms of the sweep (the LDS pencil kernel and the marching kernel)
+// so that both compute every face with the same arithmetic.
+// ---------------------------------------------------------------------------
+
+// Phase A.  The zone state along the sweep frame of axis D (STAGE 2 first
+// builds the predictor state q^{n+1/2}_D from q^n, the transverse Step-1
+// fluxes and the div-B source, with FP64 floors) -> primitive record
+// (rho, v_par, v_t1, v_t2, B_t1, B_t2, P clamped at p_floor, 1/sqrt(rho)).
+// Split into the loads (zone_fetch) and the arithmetic (zone_record), so
+// that the marching form can issue a zone's loads one zone ahead.
+template <typename R, int STAGE>
+struct ZoneRaw {
+    R q[8];
+    // STAGE 2: the transverse Step-1 flux rows at the zone and one zone up
+    // along A1 (fa) and A2 (fb): rows 0-4, then B_D's rows (A1 row 6, A2 row
+    // 5), then B_A1's (A2 row 6) and B_A2's (A1 row 5); the face field at
+    // the zone's lower and upper faces along each axis
+    R fa[STAGE == 2 ? 7 : 1][2], fb[STAGE == 2 ? 7 : 1][2], b[STAGE == 2 ? 3 : 1][2];
+};
+
+template <typename R, int D, int STAGE>
+__device__ __forceinline__ void zone_fetch(__amdgpu_buffer_rsrc_t rs, unsigned xo, const unsigned st[3], unsigned qs,
+                                           unsigned VB, ZoneRaw<R, STAGE>& z) {
+    constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
+    constexpr unsigned ES = sizeof(R);
+    const R z0 = R(0);
+#pragma unroll
+    for (int c = 0; c < 8; c++) z.q[c] = bload(z0, rs, xo, qs + c * VB);
+    if (STAGE == 2) {
+        const unsigned f1 = (unsigned)(F_FL1 + 7 * A1) * VB, f2 = (unsigned)(F_FL1 + 7 * A2) * VB;
+        const unsigned s1 = st[A1] * ES, s2 = st[A2] * ES;
+#pragma unroll
+        for (int r = 0; r < 7; r++) {
+            // rows 0-4, then A1's row 6 / A2's row 5 (B_D), then A1's row 5 / A2's row 6
+            const int ra = r < 5 ? r : (r == 5 ? 6 : 5), rb = r < 5 ? r : (r == 5 ? 5 : 6);
+            z.fa[r][0] = bload(z0, rs, xo, f1 + ra * VB);
+            z.fa[r][1] = bload(z0, rs, xo, f1 + ra * VB + s1);
+            z.fb[r][0] = bload(z0, rs, xo, f2 + rb * VB);
+            z.fb[r][1] = bload(z0, rs, xo, f2 + rb * VB + s2);
+        }
+        const unsigned bs = qs + 8 * VB;
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            z.b[a][0] = bload(z0, rs, xo, bs + a * VB);
+            z.b[a][1] = bload(z0, rs, xo, bs + a * VB + st[a] * ES);
+        }
+    }
+}
+
+template <typename R, int D, int STAGE>
+__device__ __forceinline__ Rec8<R> zone_record(const ZoneRaw<R, STAGE>& z, const Coef<R>& cf, const DevParams& prm,
+                                               const StepConst& sc) {
+#pragma clang fp contract(on)
+    constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
+    R u[8];
+#pragma unroll
+    for (int c = 0; c < 8; c++) u[c] = z.q[c];
+    if (STAGE == 2) {
+        // q^n values the div-B source needs (before the update below)
+        const R q0 = u[0], q1 = u[1 + A1], q2 = u[1 + A2];
+        const R B0[3] = {u[4], u[5], u[6]};
+        const R hdt = sc_hdt(sc, R(0));
+        const R i1 = cf.idx[A1], i2 = cf.idx[A2];
+        // rho, m, E (rows 0..4 -> components 0,1,2,3,7)
+#pragma unroll
+        for (int r = 0; r < 5; r++) {
+            const int c = r < 4 ? r : 7;
+            R div = (z.fa[r][1] - z.fa[r][0]) * i1 + (z.fb[r][1] - z.fb[r][0]) * i2;
+            u[c] -= hdt * div;
+        }
+        // B_D: flux_A1 row 6 (B_{A1+2}) and flux_A2 row 5 (B_{A2+1})
+        {
+            R div = (z.fa[5][1] - z.fa[5][0]) * i1 + (z.fb[5][1] - z.fb[5][0]) * i2;
+            u[4 + D] -= hdt * div;
+        }
+        // B_A1 only from flux_A2 row 6; B_A2 only from flux_A1 row 5
+        u[4 + A1] -= hdt * ((z.fb[6][1] - z.fb[6][0]) * i2);
+        u[4 + A2] -= hdt * ((z.fa[6][1] - z.fa[6][0]) * i1);
+        // div-B source (Gardiner & Stone 2008 form): momentum B dB_D/dx_D,
+        // B_t v_t minmod(dB_D/dx_D, -dB_t'/dx_t'), energy B_t . S[B_t]
+        R dB[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) dB[a] = (z.b[a][1] - z.b[a][0]) * cf.idx[a];
+        R ir0 = frcp(q0);
+        R v1 = q1 * ir0, v2 = q2 * ir0;
+        R B1 = B0[A1], B2 = B0[A2];
+        R sB1 = v1 * minmod2(dB[D], -dB[A2]);
+        R sB2 = v2 * minmod2(dB[D], -dB[A1]);
+#pragma unroll
+        for (int c = 0; c < 3; c++) u[1 + c] += hdt * B0[c] * dB[D];
+        u[4 + A1] += hdt * sB1;
+        u[4 + A2] += hdt * sB2;
+        u[7] += hdt * (B1 * sB1 + B2 * sB2);
+        apply_floor(u, prm, cf);
+    }
+    R rho = u[0];
+    // 1/sqrt(rho) once per zone: the faces form sqrt(rho), 1/rho and the
+    // Roe density's reciprocal from it
+    R rsq = frsq(rho);
+    R ir = rsq * rsq;
+    R vpar = u[1 + D] * ir, vt1 = u[1 + A1] * ir, vt2 = u[1 + A2] * ir;
+    R b2 = u[4] * u[4] + u[5] * u[5] + u[6] * u[6];
+    R pr = cf.gm1 * (u[7] - R(0.5) * rho * (vpar * vpar + vt1 * vt1 + vt2 * vt2) - R(0.5) * b2);
+    if (pr < cf.p_floor) pr = cf.p_floor;
+    Rec8<R> rec;
+    rec.v[0] = rho;
+    rec.v[1] = vpar;
+    rec.v[2] = vt1;
+    rec.v[3] = vt2;
+    rec.v[4] = u[4 + A1];
+    rec.v[5] = u[4 + A2];
+    rec.v[6] = pr;
+    rec.v[7] = rsq;
+    return rec;
+}
+
+template <typename R, int D, int STAGE>
+__device__ __forceinline__ Rec8<R> zone_phase(__amdgpu_buffer_rsrc_t rs, unsigned xo, const unsigned st[3], unsigned qs,
+                                              unsigned VB, const Coef<R>& cf, const DevParams& prm,
+                                              const StepConst& sc) {
+    ZoneRaw<R, STAGE> z;
+    zone_fetch<R, D, STAGE>(rs, xo, st, qs, VB, z);
+    return zone_record<R, D, STAGE>(z, cf, prm, sc);
+}
+
+// Phase B.  Face between zones L and Rr with B_par = bf: Roe average,
+// eigen-speeds, characteristic jumps alpha_k, nu_k and g-tilde_k; with
+// protection floors set, the trigger (a protected face then contributes no
+// g-tilde).
+template <typename R, bool PROT>
+__device__ __forceinline__ void face_phase(const Rec8<R>& L, const Rec8<R>& Rr, R bf, R lam, const Coef<R>& cf,
+                                           FaceEig<R>& e, R alpha[7], R nu[7], Rec8<R>& gr, bool& prot) {
+#pragma clang fp contract(on)
+    R rl = L.v[0], vxl = L.v[1], vyl = L.v[2], vzl = L.v[3], b1l = L.v[4], b2l = L.v[5], pl = L.v[6];
+    R rr = Rr.v[0], vxr = Rr.v[1], vyr = Rr.v[2], vzr = Rr.v[3], b1r = Rr.v[4], b2r = Rr.v[5], prr = Rr.v[6];
+
+    R bf2 = bf * bf;
+    const R rsl = L.v[7], rsr = Rr.v[7];  // 1/sqrt(rho) of the two zones
+    R hl = (cf.ggm * pl + R(0.5) * rl * (vxl * vxl + vyl * vyl + vzl * vzl) + bf2 + b1l * b1l + b2l * b2l) * (rsl * rsl);
+    R hr = (cf.ggm * prr + R(0.5) * rr * (vxr * vxr + vyr * vyr + vzr * vzr) + bf2 + b1r * b1r + b2r * b2r) * (rsr * rsr);
+    R sl = rl * rsl, sr = rr * rsr;
+    R isum = frcp(sl + sr);
+    e.rho = sl * sr;
+    e.vx = (sl * vxl + sr * vxr) * isum;
+    e.vy = (sl * vyl + sr * vyr) * isum;
+    e.vz = (sl * vzl + sr * vzr) * isum;
+    R h = (sl * hl + sr * hr) * isum;
+    e.b1 = (sr * b1l + sl * b1r) * isum;
+    e.b2 = (sr * b2l + sl * b2r) * isum;
+    R db1 = b1r - b1l, db2 = b2r - b2l;
+    e.X = (db1 * db1 + db2 * db2) * R(0.5) * isum * isum;
+    R v2 = e.vx * e.vx + e.vy * e.vy + e.vz * e.vz;
+    R bt2 = e.b1 * e.b1 + e.b2 * e.b2;
+    R irho = rsl * rsr;  // 1 / (sqrt(rho_L) sqrt(rho_R))
+    R a2 = cf.gm1 * (h - R(0.5) * v2 - (bf2 + bt2) * irho) - cf.gm2 * e.X;
+    const R a2raw = a2;
+    R a2min = cf.gam * cf.p_floor * irho;
+    if (a2 < a2min) a2 = a2min;
+    R ca2 = bf2 * irho, bp2 = bt2 * irho;
+    R dpr = a2 - ca2 - bp2;
+    R dd = fsqrt(dpr * dpr + R(4) * a2 * bp2);
+    R cf2 = R(0.5) * (a2 + ca2 + bp2 + dd);
+    const R rcf = frsq(cf2);  // 1/cf
+    R cs2 = a2 * ca2 * (rcf * rcf);
+    if (dd <= cf.tol * (a2 + ca2 + bp2)) {
+        e.alf = R(1);
+        e.als = R(0);
+    } else {
+        R af2, as2;
+        if (dpr >= R(0)) {
+            af2 = R(0.5) * (dd + dpr);
+            as2 = a2 * bp2 * frcp(af2);
+        } else {
+            as2 = R(0.5) * (dd - dpr);
+            af2 = a2 * bp2 * frcp(as2);
+        }
+        R idd = frcp(dd);
+        e.alf = fsqrt(af2 * idd);
+        e.als = fsqrt(as2 * idd);
+    }
+    if (bt2 <= cf.tol2 * (bf2 + bt2)) {
+        e.by = R(0.70710678118654752440);
+        e.bz = R(0.70710678118654752440);
+    } else {
+        R ib = frsq(bt2);
+        e.by = e.b1 * ib;
+        e.bz = e.b2 * ib;
+    }
+    e.s = bf >= R(0) ? R(1) : R(-1);
+    const R isq = frsq(e.rho), ra = frsq(a2);  // 1/sqrt(rho), 1/a
+    e.sq = e.rho * isq;
+    e.a2 = a2;
+    e.a = a2 * ra;
+    e.cf = cf2 * rcf;
+    e.cs = fsqrt(cs2);
+    R ca = fsqrt(ca2);
+
+    // characteristic jumps: alpha_k = L_k . (d rho, d v, d B_t, dP + X d rho)
+    R drho = rr - rl;
+    R dvx = vxr - vxl, dvy = vyr - vyl, dvz = vzr - vzl;
+    R dp = (prr - pl) + e.X * drho;
+    R dvpar = e.by * dvy + e.bz * dvz, dvper = -e.bz * dvy + e.by * dvz;
+    R dbpar = e.by * db1 + e.bz * db2, dbper = -e.bz * db1 + e.by * db2;
+    R ia2 = ra * ra;
+    R i2a2 = R(0.5) * ia2;
+    R ipa = R(0.5) * isq * ra;
+    R pterm = dp * irho * i2a2;
+    R Ef = e.alf * pterm + e.als * dbpar * ipa;
+    R Of = (e.alf * e.cf * dvx - e.als * e.cs * e.s * dvpar) * i2a2;
+    R Es = e.als * pterm - e.alf * dbpar * ipa;
+    R Os = (e.als * e.cs * dvx + e.alf * e.cf * e.s * dvpar) * i2a2;
+    R Ea = R(0.5) * dvper;
+    R Oa = -R(0.5) * e.s * dbper * isq;
+    alpha[0] = Ef - Of;
+    alpha[6] = Ef + Of;
+    alpha[2] = Es - Os;
+    alpha[4] = Es + Os;
+    alpha[1] = Ea - Oa;
+    alpha[5] = Ea + Oa;
+    alpha[3] = drho - dp * ia2;
+    R ev[7] = {e.vx - e.cf, e.vx - ca, e.vx - e.cs, e.vx, e.vx + e.cs, e.vx + ca, e.vx + e.cf};
+#pragma unroll
+    for (int k = 0; k < 7; k++) {
+        nu[k] = lam * ev[k];
+        gr.v[k] = R(0.5) * (qvisc(nu[k], cf.eps[k], cf.q4e[k]) - nu[k] * nu[k]) * alpha[k];
+    }
+    gr.v[7] = R(0);
+    prot = false;
+    if (PROT) {
+        // protected face: HLL flux, no g-tilde for the limiters
+        prot = fan_below_floor(rl, vxl, vyl, vzl, b1l, b2l, pl, bf, e, a2raw, alpha, cf);
+        if (prot)
+#pragma unroll
+            for (int k = 0; k < 7; k++) gr.v[k] = R(0);
+    }
+}
+
+// Physical fluxes of the two rebuilt face states (B_par = bf), the frame's 7
+// rows (rho, m_par, m_t1, m_t2, E, B_t1, B_t2).
+template <typename R>
+__device__ __forceinline__ void face_fluxes(const Rec8<R>& Z, R bf, const Coef<R>& cf, R F[7]) {
+#pragma clang fp contract(on)
+    R r = Z.v[0], vx = Z.v[1], vy = Z.v[2], vz = Z.v[3], b1 = Z.v[4], b2 = Z.v[5], pr = Z.v[6];
+    R bb = bf * bf + b1 * b1 + b2 * b2;
+    R pt = pr + R(0.5) * bb;
+    R ept = cf.ggm * pr + R(0.5) * r * (vx * vx + vy * vy + vz * vz) + bb;  // E + P*
+    R mx = r * vx;
+    F[0] = mx;
+    F[1] = mx * vx + pt - bf * bf;
+    F[2] = mx * vy - bf * b1;
+    F[3] = mx * vz - bf * b2;
+    F[4] = ept * vx - bf * (bf * vx + b1 * vy + b2 * vz);
+    F[5] = b1 * vx - bf * vy;
+    F[6] = b2 * vx - bf * vz;
+}
+
+// The flux part that needs no limiter: half the sum of the two states'
+// physical fluxes, or for a protected face the whole HLL flux (Einfeldt
+// bounds): (b+ F_L - b- F_R + b+ b- (u_R - u_L)) / (b+ - b-).
+template <typename R, bool PROT>
+__device__ __forceinline__ void face_central(const Rec8<R>& ZL, const Rec8<R>& ZR, R bf, const FaceEig<R>& e, bool prot,
+                                             const Coef<R>& cf, R cav[7]) {
+#pragma clang fp contract(on)
+    R F[2][7];
+    face_fluxes(ZL, bf, cf, F[0]);
+    face_fluxes(ZR, bf, cf, F[1]);
+#pragma unroll
+    for (int r = 0; r < 7; r++) cav[r] = R(0.5) * (F[0][r] + F[1][r]);
+    if (PROT && prot) {
+        R U[2][7], vfs[2];
+#pragma unroll
+        for (int side = 0; side < 2; side++) {
+            const Rec8<R>& Z = side ? ZR : ZL;
+            R r = Z.v[0], vx = Z.v[1], vy = Z.v[2], vz = Z.v[3], b1 = Z.v[4], b2 = Z.v[5], pr = Z.v[6];
+            U[side][0] = r;
+            U[side][1] = r * vx;
+            U[side][2] = r * vy;
+            U[side][3] = r * vz;
+            U[side][4] = pr * cf.igm1 + R(0.5) * r * (vx * vx + vy * vy + vz * vz) + R(0.5) * (bf * bf + b1 * b1 + b2 * b2);
+            U[side][5] = b1;
+            U[side][6] = b2;
+            // fast speed of the rebuilt state along the sweep
+            R ir = frcp(r);
+            R fa2 = cf.gam * pr * ir, fca2 = bf * bf * ir, fbp2 = (b1 * b1 + b2 * b2) * ir;
+            R fdp = fa2 - fca2 - fbp2;
+            R fcf = fsqrt(R(0.5) * (fa2 + fca2 + fbp2 + fsqrt(fdp * fdp + R(4) * fa2 * fbp2)));
+            vfs[side] = side ? vx + fcf : vx - fcf;
+        }
+        const R bp = fmax(fmax(e.vx + e.cf, vfs[1]), R(0));
+        const R bm = fmin(fmin(e.vx - e.cf, vfs[0]), R(0));
+        const R iden = frcp(bp - bm);
+#pragma unroll
+        for (int r = 0; r < 7; r++) cav[r] = (bp * F[0][r] - bm * F[1][r]) * iden + bp * bm * iden * (U[1][r] - U[0][r]);
+    }
+}
+
+// Phase C.  Correction of a face from the limiter values of its two zones
+// (gL of the left zone, gR of the right one): gamma_k, beta_k and
+// sum_k beta_k R_k, assembled in (rho, v, B_t, P) and mapped to conserved
+// variables once (7 frame rows).  The modified flux is
+// cav - (dx / (2 dt)) c (face_combine).
+// glim(k, gL, gR) yields the two limiter values of wave k.
+template <typename R, typename GLim>
+__device__ __forceinline__ void face_correction(GLim glim, const FaceEig<R>& e, const R alpha[7], const R nu[7],
+                                                const Coef<R>& cf, R c[7]) {
+#pragma clang fp contract(on)
+    R bet[7];
+#pragma unroll
+    for (int k = 0; k < 7; k++) {
+        R gL, gR;
+        glim(k, gL, gR);
+        R gk = (fabs(alpha[k]) > alpha_min(alpha[k])) ? gdiv(gR - gL, alpha[k]) : R(0);
+        bet[k] = qvisc(nu[k] + gk, cf.eps[k], cf.q4e[k]) * alpha[k] - (gL + gR);
+    }
+    R bfp = bet[6] + bet[0], bfm = bet[6] - bet[0];
+    R bsp = bet[4] + bet[2], bsm = bet[4] - bet[2];
+    R bap = bet[5] + bet[1], bam = bet[5] - bet[1];
+    R wrho = e.rho * (e.alf * bfp + e.als * bsp) + bet[3];
+    R wvx = e.alf * e.cf * bfm + e.als * e.cs * bsm;
+    R wvpar = e.s * (-e.als * e.cs * bfm + e.alf * e.cf * bsm);
+    R wvy = wvpar * e.by - bap * e.bz;
+    R wvz = wvpar * e.bz + bap * e.by;
+    R wbpar = e.sq * e.a * (e.als * bfp - e.alf * bsp);
+    R wb1 = wbpar * e.by + e.s * e.sq * bam * e.bz;
+    R wb2 = wbpar * e.bz - e.s * e.sq * bam * e.by;
+    R wp = e.rho * e.a2 * (e.alf * bfp + e.als * bsp);
+    R v2 = e.vx * e.vx + e.vy * e.vy + e.vz * e.vz;
+    c[0] = wrho;
+    c[1] = e.vx * wrho + e.rho * wvx;
+    c[2] = e.vy * wrho + e.rho * wvy;
+    c[3] = e.vz * wrho + e.rho * wvz;
+    c[4] = (R(0.5) * v2 + cf.gm2 * e.X * cf.igm1) * wrho + e.rho * (e.vx * wvx + e.vy * wvy + e.vz * wvz) +
+           e.b1 * wb1 + e.b2 * wb2 + wp * cf.igm1;
+    c[5] = wb1;
+    c[6] = wb2;
+}
+
+template <typename R>
+__device__ __forceinline__ void face_combine(const R cav[7], const R c[7], R il, R out[7]) {
+#pragma clang fp contract(on)
+#pragma unroll
+    for (int r = 0; r < 7; r++) out[r] = cav[r] - il * c[r];
+}
+
+// the 7 frame rows of a face flux to the lab rows of direction D
+template <typename R, int D>
+__device__ __forceinline__ void store_flux(const R out[7], __amdgpu_buffer_rsrc_t rs, unsigned xo, unsigned fo,
+                                           unsigned VB) {
+    constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
+    // frame -> lab rows: m_par -> m_D, m_t1 -> m_A1, m_t2 -> m_A2
+    bstore(out[0], rs, xo, fo);
+    bstore(out[1], rs, xo, fo + (1 + D) * VB);
+    bstore(out[2], rs, xo, fo + (1 + A1) * VB);
+    bstore(out[3], rs, xo, fo + (1 + A2) * VB);
+    bstore(out[4], rs, xo, fo + 4 * VB);
+    bstore(out[5], rs, xo, fo + 5 * VB);
+    bstore(out[6], rs, xo, fo + 6 * VB);
+}
+
 template <typename R, int D, int STAGE, bool MM, bool PROT>
 __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
                                                      const WorkItem* __restrict__ work, DevParams prm, Coef<R> cf,
@@ -918,7 +1291,6 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
     Rec8<R>* shp = reinterpret_cast<Rec8<R>*>(smem_raw);  // zone primitives
     Rec8<R>* shg = shp + nthr;                             // face g-tilde
 
-    constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
     constexpr int FA = (D == 0) ? 1 : 0;                 // fast transverse axis
     constexpr int SA = (D == 0) ? 2 : (D == 1 ? 2 : 1);  // slow transverse axis
     constexpr unsigned ES = sizeof(R);
@@ -958,12 +1330,12 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
 
     // ---------------- phase A: zone primitives ----------------
     if (live) {
-        R u[8];
-#pragma unroll
-        for (int c = 0; c < 8; c++) u[c] = bload(z0, rs, xo, qs + c * VB);
         if (STAGE == 1 && D == 0) {
             // Step 2: reference EMF E^r = -v x B from q^n on [-3, n+2]^3
             if (zc[0] >= -3 && zc[0] <= Pt.n[0] + 2) {
+                R u[8];
+#pragma unroll
+                for (int c = 0; c < 8; c++) u[c] = bload(z0, rs, xo, qs + c * VB);
                 R ir = frcp(u[0]);
                 R vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
                 bstore(vz * u[5] - vy * u[6], rs, xo, (unsigned)F_ER * VB);
@@ -971,288 +1343,153 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
                 bstore(vy * u[4] - vx * u[5], rs, xo, (unsigned)(F_ER + 2) * VB);
             }
         }
-        if (STAGE == 2) {
-            // q^n values the div-B source needs (before the update below)
-            const R q0 = u[0], q1 = u[1 + A1], q2 = u[1 + A2];
-            const R B0[3] = {u[4], u[5], u[6]};
-            const R hdt = sc_hdt(*sc, R(0));
-            const unsigned f1 = (unsigned)(F_FL1 + 7 * A1) * VB, f2 = (unsigned)(F_FL1 + 7 * A2) * VB;
-            const unsigned s1 = st[A1] * ES, s2 = st[A2] * ES;
-            const R i1 = cf.idx[A1], i2 = cf.idx[A2];
-            // rho, m, E (rows 0..4 -> components 0,1,2,3,7)
-#pragma unroll
-            for (int r = 0; r < 5; r++) {
-                const int c = r < 4 ? r : 7;
-                R div = (bload(z0, rs, xo, f1 + r * VB + s1) - bload(z0, rs, xo, f1 + r * VB)) * i1 +
-                        (bload(z0, rs, xo, f2 + r * VB + s2) - bload(z0, rs, xo, f2 + r * VB)) * i2;
-                u[c] -= hdt * div;
-            }
-            // B_D: flux_A1 row 6 (B_{A1+2}) and flux_A2 row 5 (B_{A2+1})
-            {
-                R div = (bload(z0, rs, xo, f1 + 6 * VB + s1) - bload(z0, rs, xo, f1 + 6 * VB)) * i1 +
-                        (bload(z0, rs, xo, f2 + 5 * VB + s2) - bload(z0, rs, xo, f2 + 5 * VB)) * i2;
-                u[4 + D] -= hdt * div;
-            }
-            // B_A1 only from flux_A2 row 6; B_A2 only from flux_A1 row 5
-            u[4 + A1] -= hdt * ((bload(z0, rs, xo, f2 + 6 * VB + s2) - bload(z0, rs, xo, f2 + 6 * VB)) * i2);
-            u[4 + A2] -= hdt * ((bload(z0, rs, xo, f1 + 5 * VB + s1) - bload(z0, rs, xo, f1 + 5 * VB)) * i1);
-            // div-B source (Gardiner & Stone 2008 form): momentum B dB_D/dx_D,
-            // B_t v_t minmod(dB_D/dx_D, -dB_t'/dx_t'), energy B_t . S[B_t]
-            const unsigned bs = qs + 8 * VB;
-            R dB[3];
-#pragma unroll
-            for (int a = 0; a < 3; a++)
-                dB[a] = (bload(z0, rs, xo, bs + a * VB + st[a] * ES) - bload(z0, rs, xo, bs + a * VB)) * cf.idx[a];
-            R ir0 = frcp(q0);
-            R v1 = q1 * ir0, v2 = q2 * ir0;
-            R B1 = B0[A1], B2 = B0[A2];
-            R sB1 = v1 * minmod2(dB[D], -dB[A2]);
-            R sB2 = v2 * minmod2(dB[D], -dB[A1]);
-#pragma unroll
-            for (int c = 0; c < 3; c++) u[1 + c] += hdt * B0[c] * dB[D];
-            u[4 + A1] += hdt * sB1;
-            u[4 + A2] += hdt * sB2;
-            u[7] += hdt * (B1 * sB1 + B2 * sB2);
-            apply_floor(u, prm, cf);
-        }
-        R rho = u[0];
-        // 1/sqrt(rho) once per zone: the faces form sqrt(rho), 1/rho and the
-        // Roe density's reciprocal from it
-        R rsq = frsq(rho);
-        R ir = rsq * rsq;
-        R vpar = u[1 + D] * ir, vt1 = u[1 + A1] * ir, vt2 = u[1 + A2] * ir;
-        R b2 = u[4] * u[4] + u[5] * u[5] + u[6] * u[6];
-        R pr = cf.gm1 * (u[7] - R(0.5) * rho * (vpar * vpar + vt1 * vt1 + vt2 * vt2) - R(0.5) * b2);
-        if (pr < cf.p_floor) pr = cf.p_floor;
-        Rec8<R> rec;
-        rec.v[0] = rho;
-        rec.v[1] = vpar;
-        rec.v[2] = vt1;
-        rec.v[3] = vt2;
-        rec.v[4] = u[4 + A1];
-        rec.v[5] = u[4 + A2];
-        rec.v[6] = pr;
-        rec.v[7] = rsq;
-        shp[tid] = rec;
+        shp[tid] = zone_phase<R, D, STAGE>(rs, xo, st, qs, VB, cf, prm, *sc);
     }
     __syncthreads();
 
     // ---------------- phase B: face s between zones s-1 and s ----------------
     FaceEig<R> e;
     R alpha[7], nu[7];
-    R bf = R(0), a2raw = R(0);
+    R bf = R(0);
     bool prot = false;
     const bool face = live && s >= 1;
     if (face) {
         bf = bload(z0, rs, xo, (STAGE == 1) ? qs + (8 + D) * VB : (unsigned)(F_BH + D) * VB);
-        const int tl = tid - sstep;
-        const Rec8<R> L = shp[tl], Rr = shp[tid];
-        R rl = L.v[0], vxl = L.v[1], vyl = L.v[2], vzl = L.v[3], b1l = L.v[4], b2l = L.v[5], pl = L.v[6];
-        R rr = Rr.v[0], vxr = Rr.v[1], vyr = Rr.v[2], vzr = Rr.v[3], b1r = Rr.v[4], b2r = Rr.v[5], prr = Rr.v[6];
-
-        R bf2 = bf * bf;
-        const R rsl = L.v[7], rsr = Rr.v[7];  // 1/sqrt(rho) of the two zones
-        R hl = (cf.ggm * pl + R(0.5) * rl * (vxl * vxl + vyl * vyl + vzl * vzl) + bf2 + b1l * b1l + b2l * b2l) * (rsl * rsl);
-        R hr = (cf.ggm * prr + R(0.5) * rr * (vxr * vxr + vyr * vyr + vzr * vzr) + bf2 + b1r * b1r + b2r * b2r) * (rsr * rsr);
-        R sl = rl * rsl, sr = rr * rsr;
-        R isum = frcp(sl + sr);
-        e.rho = sl * sr;
-        e.vx = (sl * vxl + sr * vxr) * isum;
-        e.vy = (sl * vyl + sr * vyr) * isum;
-        e.vz = (sl * vzl + sr * vzr) * isum;
-        R h = (sl * hl + sr * hr) * isum;
-        e.b1 = (sr * b1l + sl * b1r) * isum;
-        e.b2 = (sr * b2l + sl * b2r) * isum;
-        R db1 = b1r - b1l, db2 = b2r - b2l;
-        e.X = (db1 * db1 + db2 * db2) * R(0.5) * isum * isum;
-        R v2 = e.vx * e.vx + e.vy * e.vy + e.vz * e.vz;
-        R bt2 = e.b1 * e.b1 + e.b2 * e.b2;
-        R irho = rsl * rsr;  // 1 / (sqrt(rho_L) sqrt(rho_R))
-        R a2 = cf.gm1 * (h - R(0.5) * v2 - (bf2 + bt2) * irho) - cf.gm2 * e.X;
-        a2raw = a2;
-        R a2min = cf.gam * cf.p_floor * irho;
-        if (a2 < a2min) a2 = a2min;
-        R ca2 = bf2 * irho, bp2 = bt2 * irho;
-        R dpr = a2 - ca2 - bp2;
-        R dd = fsqrt(dpr * dpr + R(4) * a2 * bp2);
-        R cf2 = R(0.5) * (a2 + ca2 + bp2 + dd);
-        const R rcf = frsq(cf2);  // 1/cf
-        R cs2 = a2 * ca2 * (rcf * rcf);
-        if (dd <= cf.tol * (a2 + ca2 + bp2)) {
-            e.alf = R(1);
-            e.als = R(0);
-        } else {
-            R af2, as2;
-            if (dpr >= R(0)) {
-                af2 = R(0.5) * (dd + dpr);
-                as2 = a2 * bp2 * frcp(af2);
-            } else {
-                as2 = R(0.5) * (dd - dpr);
-                af2 = a2 * bp2 * frcp(as2);
-            }
-            R idd = frcp(dd);
-            e.alf = fsqrt(af2 * idd);
-            e.als = fsqrt(as2 * idd);
-        }
-        if (bt2 <= cf.tol2 * (bf2 + bt2)) {
-            e.by = R(0.70710678118654752440);
-            e.bz = R(0.70710678118654752440);
-        } else {
-            R ib = frsq(bt2);
-            e.by = e.b1 * ib;
-            e.bz = e.b2 * ib;
-        }
-        e.s = bf >= R(0) ? R(1) : R(-1);
-        const R isq = frsq(e.rho), ra = frsq(a2);  // 1/sqrt(rho), 1/a
-        e.sq = e.rho * isq;
-        e.a2 = a2;
-        e.a = a2 * ra;
-        e.cf = cf2 * rcf;
-        e.cs = fsqrt(cs2);
-        R ca = fsqrt(ca2);
-
-        // characteristic jumps: alpha_k = L_k . (d rho, d v, d B_t, dP + X d rho)
-        R drho = rr - rl;
-        R dvx = vxr - vxl, dvy = vyr - vyl, dvz = vzr - vzl;
-        R dp = (prr - pl) + e.X * drho;
-        R dvpar = e.by * dvy + e.bz * dvz, dvper = -e.bz * dvy + e.by * dvz;
-        R dbpar = e.by * db1 + e.bz * db2, dbper = -e.bz * db1 + e.by * db2;
-        R ia2 = ra * ra;
-        R i2a2 = R(0.5) * ia2;
-        R ipa = R(0.5) * isq * ra;
-        R pterm = dp * irho * i2a2;
-        R Ef = e.alf * pterm + e.als * dbpar * ipa;
-        R Of = (e.alf * e.cf * dvx - e.als * e.cs * e.s * dvpar) * i2a2;
-        R Es = e.als * pterm - e.alf * dbpar * ipa;
-        R Os = (e.als * e.cs * dvx + e.alf * e.cf * e.s * dvpar) * i2a2;
-        R Ea = R(0.5) * dvper;
-        R Oa = -R(0.5) * e.s * dbper * isq;
-        alpha[0] = Ef - Of;
-        alpha[6] = Ef + Of;
-        alpha[2] = Es - Os;
-        alpha[4] = Es + Os;
-        alpha[1] = Ea - Oa;
-        alpha[5] = Ea + Oa;
-        alpha[3] = drho - dp * ia2;
-        R ev[7] = {e.vx - e.cf, e.vx - ca, e.vx - e.cs, e.vx, e.vx + e.cs, e.vx + ca, e.vx + e.cf};
         Rec8<R> gr;
-#pragma unroll
-        for (int k = 0; k < 7; k++) {
-            nu[k] = lam * ev[k];
-            gr.v[k] = R(0.5) * (qvisc(nu[k], cf.eps[k], cf.q4e[k]) - nu[k] * nu[k]) * alpha[k];
-        }
-        gr.v[7] = R(0);
-        if (PROT) {
-            // protected face: HLL flux in phase C, no g-tilde for the limiters
-            prot = fan_below_floor(rl, vxl, vyl, vzl, b1l, b2l, pl, bf, e, a2raw, alpha, cf);
-            if (prot)
-#pragma unroll
-                for (int k = 0; k < 7; k++) gr.v[k] = R(0);
-        }
+        face_phase<R, PROT>(shp[tid - sstep], shp[tid], bf, lam, cf, e, alpha, nu, gr, prot);
         shg[tid] = gr;
     }
     __syncthreads();
 
     // ---------------- phase C: modified flux at faces 2 .. P-2 ----------------
     if (face && s >= 2 && s <= P - 2) {
-        R bet[7];
-        const Rec8<R> Gm = shg[tid - sstep], G0 = shg[tid], Gp = shg[tid + sstep];
-#pragma unroll
-        for (int k = 0; k < 7; k++) {
-            R gm = Gm.v[k];
-            R g0 = G0.v[k];
-            R gp = Gp.v[k];
-            R gL = sweby<MM>(g0, gm, cf.beta_l);  // zone s-1: faces s-1 (left), s (right)
-            R gR = sweby<MM>(gp, g0, cf.beta_l);  // zone s: faces s, s+1
-            R gk = (fabs(alpha[k]) > alpha_min(alpha[k])) ? gdiv(gR - gL, alpha[k]) : R(0);
-            bet[k] = qvisc(nu[k] + gk, cf.eps[k], cf.q4e[k]) * alpha[k] - (gL + gR);
-        }
-        // correction sum_k beta_k R_k in (rho, v, B_t, P), then mapped to conserved
-        R bfp = bet[6] + bet[0], bfm = bet[6] - bet[0];
-        R bsp = bet[4] + bet[2], bsm = bet[4] - bet[2];
-        R bap = bet[5] + bet[1], bam = bet[5] - bet[1];
-        R wrho = e.rho * (e.alf * bfp + e.als * bsp) + bet[3];
-        R wvx = e.alf * e.cf * bfm + e.als * e.cs * bsm;
-        R wvpar = e.s * (-e.als * e.cs * bfm + e.alf * e.cf * bsm);
-        R wvy = wvpar * e.by - bap * e.bz;
-        R wvz = wvpar * e.bz + bap * e.by;
-        R wbpar = e.sq * e.a * (e.als * bfp - e.alf * bsp);
-        R wb1 = wbpar * e.by + e.s * e.sq * bam * e.bz;
-        R wb2 = wbpar * e.bz - e.s * e.sq * bam * e.by;
-        R wp = e.rho * e.a2 * (e.alf * bfp + e.als * bsp);
-        R v2 = e.vx * e.vx + e.vy * e.vy + e.vz * e.vz;
-        R c0 = wrho;
-        R c1 = e.vx * wrho + e.rho * wvx;
-        R c2 = e.vy * wrho + e.rho * wvy;
-        R c3 = e.vz * wrho + e.rho * wvz;
-        R c7 = (R(0.5) * v2 + cf.gm2 * e.X * cf.igm1) * wrho + e.rho * (e.vx * wvx + e.vy * wvy + e.vz * wvz) +
-               e.b1 * wb1 + e.b2 * wb2 + wp * cf.igm1;
-        // physical fluxes of the two rebuilt face states
-        R F[2][7];
-#pragma unroll
-        for (int side = 0; side < 2; side++) {
-            const Rec8<R> Z = shp[side ? tid : tid - sstep];
-            R r = Z.v[0], vx = Z.v[1], vy = Z.v[2], vz = Z.v[3], b1 = Z.v[4], b2 = Z.v[5], pr = Z.v[6];
-            R bb = bf * bf + b1 * b1 + b2 * b2;
-            R pt = pr + R(0.5) * bb;
-            R ept = cf.ggm * pr + R(0.5) * r * (vx * vx + vy * vy + vz * vz) + bb;  // E + P*
-            R mx = r * vx;
-            F[side][0] = mx;
-            F[side][1] = mx * vx + pt - bf * bf;
-            F[side][2] = mx * vy - bf * b1;
-            F[side][3] = mx * vz - bf * b2;
-            F[side][4] = ept * vx - bf * (bf * vx + b1 * vy + b2 * vz);
-            F[side][5] = b1 * vx - bf * vy;
-            F[side][6] = b2 * vx - bf * vz;
-        }
-        const R il = sc_il(*sc, D, R(0));  // 1 / (2 lambda)
-        R out[7];
-        out[0] = R(0.5) * (F[0][0] + F[1][0]) - il * c0;
-        out[1] = R(0.5) * (F[0][1] + F[1][1]) - il * c1;
-        out[2] = R(0.5) * (F[0][2] + F[1][2]) - il * c2;
-        out[3] = R(0.5) * (F[0][3] + F[1][3]) - il * c3;
-        out[4] = R(0.5) * (F[0][4] + F[1][4]) - il * c7;
-        out[5] = R(0.5) * (F[0][5] + F[1][5]) - il * wb1;
-        out[6] = R(0.5) * (F[0][6] + F[1][6]) - il * wb2;
+        R cav[7], out[7];
         if (PROT && prot) {
-            // HLL (Einfeldt bounds): (b+ F_L - b- F_R + b+ b- (u_R - u_L)) / (b+ - b-)
-            R U[2][7], vfs[2];
-#pragma unroll
-            for (int side = 0; side < 2; side++) {
-                const Rec8<R> Z = shp[side ? tid : tid - sstep];
-                R r = Z.v[0], vx = Z.v[1], vy = Z.v[2], vz = Z.v[3], b1 = Z.v[4], b2 = Z.v[5], pr = Z.v[6];
-                U[side][0] = r;
-                U[side][1] = r * vx;
-                U[side][2] = r * vy;
-                U[side][3] = r * vz;
-                U[side][4] = pr * cf.igm1 + R(0.5) * r * (vx * vx + vy * vy + vz * vz) +
-                             R(0.5) * (bf * bf + b1 * b1 + b2 * b2);
-                U[side][5] = b1;
-                U[side][6] = b2;
-                // fast speed of the rebuilt state along the sweep
-                R ir = frcp(r);
-                R fa2 = cf.gam * pr * ir, fca2 = bf * bf * ir, fbp2 = (b1 * b1 + b2 * b2) * ir;
-                R fdp = fa2 - fca2 - fbp2;
-                R fcf = fsqrt(R(0.5) * (fa2 + fca2 + fbp2 + fsqrt(fdp * fdp + R(4) * fa2 * fbp2)));
-                vfs[side] = side ? vx + fcf : vx - fcf;
-            }
-            const R bp = fmax(fmax(e.vx + e.cf, vfs[1]), R(0));
-            const R bm = fmin(fmin(e.vx - e.cf, vfs[0]), R(0));
-            const R iden = frcp(bp - bm);
-#pragma unroll
-            for (int r = 0; r < 7; r++)
-                out[r] = (bp * F[0][r] - bm * F[1][r]) * iden + bp * bm * iden * (U[1][r] - U[0][r]);
+            face_central<R, PROT>(shp[tid - sstep], shp[tid], bf, e, prot, cf, out);
             atomicAdd(nprot, 1ULL);
+        } else {
+            const Rec8<R> Gm = shg[tid - sstep], G0 = shg[tid], Gp = shg[tid + sstep];
+            R c[7];
+            auto glim = [&](int k, R& gL, R& gR) {
+                gL = sweby<MM>(G0.v[k], Gm.v[k], cf.beta_l);  // zone s-1: faces s-1 (left), s (right)
+                gR = sweby<MM>(Gp.v[k], G0.v[k], cf.beta_l);  // zone s: faces s, s+1
+            };
+            face_correction<R>(glim, e, alpha, nu, cf, c);
+            face_central<R, PROT>(shp[tid - sstep], shp[tid], bf, e, prot, cf, cav);
+            face_combine(cav, c, sc_il(*sc, D, R(0)), out);
         }
-        const unsigned fo = (unsigned)((STAGE == 1 ? F_FL1 : F_FL2) + 7 * D) * VB;
-        // frame -> lab rows: m_par -> m_D, m_t1 -> m_A1, m_t2 -> m_A2
-        bstore(out[0], rs, xo, fo);
-        bstore(out[1], rs, xo, fo + (1 + D) * VB);
-        bstore(out[2], rs, xo, fo + (1 + A1) * VB);
-        bstore(out[3], rs, xo, fo + (1 + A2) * VB);
-        bstore(out[4], rs, xo, fo + 4 * VB);
-        bstore(out[5], rs, xo, fo + 5 * VB);
-        bstore(out[6], rs, xo, fo + 6 * VB);
+        store_flux<R, D>(out, rs, xo, (unsigned)((STAGE == 1 ? F_FL1 : F_FL2) + 7 * D) * VB, VB);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Marching form of the y and z sweeps.  One thread owns one whole pencil
+// along D and walks it zone by zone; the lanes of a wave hold consecutive
+// pencils of the item's rectangle, numbered x fastest, so every load and
+// store of a wave covers consecutive x.  The face and limiter data a later
+// face needs are carried in registers from one zone to the next: zone s
+// gives face s (phase B), whose g-tilde completes the limiter value of zone
+// s-1 and with it the modified flux of face s-1 (phase C).  No LDS, no
+// barrier; the same arithmetic as the pencil kernel, face by face.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+struct MarchFace {
+    Rec8<R> rec;      // zone s
+    FaceEig<R> e;     // face s (between zones s-1 and s)
+    R alpha[7], nu[7], cav[7];
+    Rec8<R> gt;       // g-tilde of face s
+    R gz[7];          // limiter value of zone s-1
+    bool prot;
+};
+
+template <typename R, int D, int STAGE, bool MM, bool PROT, bool PF2>
+__global__ void __launch_bounds__(256) march_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
+                                                    const WorkItem* __restrict__ work, DevParams prm, Coef<R> cf,
+                                                    int cur, const StepConst* __restrict__ sc, int P, int zlo,
+                                                    unsigned long long* __restrict__ nprot) {
+    static_assert(D == 1 || D == 2, "the marching form serves the y and z sweeps");
+    constexpr int SA = (D == 1) ? 2 : 1;  // slow transverse axis (x is the fast one)
+    constexpr unsigned ES = sizeof(R);
+    const WorkItem wi = work[blockIdx.x];
+    if (wi.patch < 0) return;  // padding item
+    const PatchDev Pt = patches[wi.patch];
+    if (!Pt.active) return;  // frozen patch
+    const int pen = wi.a + (int)threadIdx.x;
+    if (pen > wi.c) return;  // past the item's last pencil (no barrier follows)
+    const int flo = (wi.b & 1023) - 512, slo = ((wi.b >> 10) & 1023) - 512, tf = wi.b >> 20;
+    const int g = prm.ghost;
+    const int slow = (int)(((float)pen + 0.5f) * __builtin_amdgcn_rcpf((float)tf));
+    int zc[3];
+    zc[D] = zlo;
+    zc[0] = flo + (pen - slow * tf);
+    zc[SA] = slo + slow;
+    const unsigned st[3] = {1u, (unsigned)Pt.N[0], (unsigned)(Pt.N[0] * Pt.N[1])};
+    unsigned xo = ((unsigned)(zc[0] + g) + st[1] * (unsigned)(zc[1] + g) + st[2] * (unsigned)(zc[2] + g)) * ES;
+    const unsigned sD = st[D] * ES;
+    const unsigned VB = (unsigned)Pt.vol * ES;
+    const StepConst scv = *sc;
+    const R lam = sc_lam(scv, D, R(0)), il = sc_il(scv, D, R(0));
+    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + Pt.base, (unsigned)F_TOTAL * VB);
+    const unsigned qs = (unsigned)(cur ? F_ST1 : F_ST0) * VB;
+    const unsigned bfo = (STAGE == 1) ? qs + (8 + D) * VB : (unsigned)(F_BH + D) * VB;
+    const unsigned fo = (unsigned)((STAGE == 1 ? F_FL1 : F_FL2) + 7 * D) * VB;
+    const R z0 = R(0);
+
+    // Zone s's loads and face field requested one iteration ahead, so that
+    // their latency overlaps the previous face's arithmetic: always in FP32
+    // Step 1 (9 loads a zone); in the FP32 corrector (43 loads a zone) as
+    // the variant PF2, which takes 2 waves a SIMD instead of 4; never in
+    // FP64, whose marching kernels already use 256 VGPRs.
+    constexpr bool PF = sizeof(R) == 4 && (STAGE == 1 || PF2);
+    MarchFace<R> pv;  // zone s-1 and face s-1
+    pv.rec = zone_phase<R, D, STAGE>(rs, xo, st, qs, VB, cf, prm, scv);
+    ZoneRaw<R, STAGE> nx;
+    R bfn = R(0);
+    if constexpr (PF) {
+        zone_fetch<R, D, STAGE>(rs, xo + sD, st, qs, VB, nx);
+        bfn = bload(z0, rs, xo + sD, bfo);
+    }
+    for (int s = 1; s < P; s++) {
+        xo += sD;
+        MarchFace<R> cu;
+        R bf;
+        if constexpr (PF) {
+            cu.rec = zone_record<R, D, STAGE>(nx, cf, prm, scv);
+            bf = bfn;
+            if (s + 1 < P) {
+                zone_fetch<R, D, STAGE>(rs, xo + sD, st, qs, VB, nx);
+                bfn = bload(z0, rs, xo + sD, bfo);
+            }
+        } else {
+            cu.rec = zone_phase<R, D, STAGE>(rs, xo, st, qs, VB, cf, prm, scv);
+            bf = bload(z0, rs, xo, bfo);
+        }
+        face_phase<R, PROT>(pv.rec, cu.rec, bf, lam, cf, cu.e, cu.alpha, cu.nu, cu.gt, cu.prot);
+        if (s >= 2 && s <= P - 2) face_central<R, PROT>(pv.rec, cu.rec, bf, cu.e, cu.prot, cf, cu.cav);
+        if (s >= 2) {
+#pragma unroll
+            for (int k = 0; k < 7; k++) cu.gz[k] = sweby<MM>(cu.gt.v[k], pv.gt.v[k], cf.beta_l);  // zone s-1
+        }
+        if (s >= 3) {
+            // face s-1 (2 <= s-1 <= P-2): limiter values of zones s-2 and s-1
+            R out[7];
+            if (PROT && pv.prot) {
+#pragma unroll
+                for (int r = 0; r < 7; r++) out[r] = pv.cav[r];
+                atomicAdd(nprot, 1ULL);
+            } else {
+                R c[7];
+                auto glim = [&](int k, R& gL, R& gR) {
+                    gL = pv.gz[k];
+                    gR = cu.gz[k];
+                };
+                face_correction<R>(glim, pv.e, pv.alpha, pv.nu, cf, c);
+                face_combine(pv.cav, c, il, out);
+            }
+            store_flux<R, D>(out, rs, xo - sD, fo, VB);
+        }
+        pv = cu;
     }
 }
 
@@ -1484,6 +1721,46 @@ hipError_t launch_sweep(int d, int stage, void* pool, const PatchDev* pt, const 
 }
 
 // diagnostics into out[12] (device memory); rec holds nblk records of DIAG_REC doubles
+// the marching y/z sweeps: W threads (pencils) a block
+template <typename R>
+hipError_t launch_march(int d, int stage, void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm,
+                        const Coef<R>& cf, int cur, const StepConst* sc, int P, int W, int zlo,
+                        unsigned long long* nprot, hipStream_t st) {
+    if (nblk <= 0) return hipSuccess;
+    // W > 512: the corrector with the one-zone-ahead loads (FP32), W - 512 pencils a block
+    const bool pf = W > 512 && sizeof(R) == 4 && stage == 2;
+    if (W > 512) W -= 512;
+    if (d < 1 || d > 2 || W < 1 || W > 256) return hipErrorInvalidValue;
+    const bool mm = cf.beta_l == R(1);
+    const bool pr = cf.rho_prot > R(0) || cf.p_prot > R(0);
+#define WMB_MA1(DD, SS, MM, PR)                                                                                     \
+    do {                                                                                                            \
+        if (pf)                                                                                                     \
+            hipLaunchKernelGGL((march_kernel<R, DD, SS, MM, PR, true>), dim3(nblk), dim3(W), 0, st, (R*)pool, pt, wk, \
+                               prm, cf, cur, sc, P, zlo, nprot);                                                    \
+        else                                                                                                        \
+            hipLaunchKernelGGL((march_kernel<R, DD, SS, MM, PR, false>), dim3(nblk), dim3(W), 0, st, (R*)pool, pt,    \
+                               wk, prm, cf, cur, sc, P, zlo, nprot);                                                \
+    } while (0)
+#define WMB_MA(DD, SS)                                                                                              \
+    do {                                                                                                            \
+        if (mm && !pr) WMB_MA1(DD, SS, true, false);                                                                \
+        else if (mm) WMB_MA1(DD, SS, true, true);                                                                   \
+        else if (!pr) WMB_MA1(DD, SS, false, false);                                                                \
+        else WMB_MA1(DD, SS, false, true);                                                                          \
+    } while (0)
+    if (stage == 1) {
+        if (d == 1) WMB_MA(1, 1);
+        else WMB_MA(2, 1);
+    } else {
+        if (d == 1) WMB_MA(1, 2);
+        else WMB_MA(2, 2);
+    }
+#undef WMB_MA1
+#undef WMB_MA
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_diag(const void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, int cur,
                        double* rec, const unsigned long long* counters, double nzones, double dmin, double* out,
@@ -1506,6 +1783,9 @@ hipError_t launch_diag(const void* pool, const PatchDev* pt, const WorkItem* wk,
                                          int, const StepConst*, unsigned long long*, unsigned long long*, int, int,     \
                                          hipStream_t);                                                                   \
     template hipError_t launch_sweep<R>(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&,        \
+                                        const Coef<R>&, int, const StepConst*, int, int, int, unsigned long long*,       \
+                                        hipStream_t);                                                                    \
+    template hipError_t launch_march<R>(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&,        \
                                         const Coef<R>&, int, const StepConst*, int, int, int, unsigned long long*,       \
                                         hipStream_t);                                                                    \
     template hipError_t launch_diag<R>(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,        \

@@ -22,6 +22,7 @@ hipError_t launch_set_dt(StepConst*, double, const DevParams&, hipStream_t);
 template <typename R> hipError_t launch_ct_half(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int, const StepConst*, hipStream_t);
 template <typename R> hipError_t launch_update(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, unsigned long long*, unsigned long long*, int, int, hipStream_t);
 template <typename R> hipError_t launch_sweep(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, int, int, int, unsigned long long*, hipStream_t);
+template <typename R> hipError_t launch_march(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, int, int, int, unsigned long long*, hipStream_t);
 template <typename R> hipError_t launch_diag(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, double*, const unsigned long long*, double, double, double*, hipStream_t);
 }  // namespace wmb
 
@@ -34,8 +35,12 @@ struct DevList {
     int n = 0;
 };
 
+// Sweep shapes: W > 0 is the LDS pencil form with W pencils a block; W < 0
+// (y and z sweeps only) the marching form with -W pencils a block, one a
+// thread.  Both forms compute every face with the same arithmetic.
 struct SweepGroup {
     int P, W, zlo, tlo, thi, n;
+    int Wp = 0, Wm = 0;    // autotune: the fastest pencil and marching shapes alone
     DevList wl;            // every pencil of the transverse range [tlo, n+thi]^2
     DevList wl_in, wl_fr;  // Step-1 x sweep only: the pencils with both transverse
                            // coords interior, and the frame around them
@@ -67,7 +72,8 @@ struct wmb_ctx {
     bool own_stream = false;
     // second stream and fork/join events of the captured step: the y/z ghost
     // exchange runs beside the interior part of the Step-1 x sweep
-    hipStream_t side = nullptr, side2 = nullptr;
+    hipStream_t side = nullptr, side2 = nullptr;  // borrowed from the device's spare streams
+    int device = -1;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipEvent_t ev_br[6] = {};  // fork/join of the three sweep branches of a stage
     int cur = 0;
@@ -321,6 +327,27 @@ void mark(wmb_ctx* c) {
 }
 
 template <typename R>
+hipError_t launch_group(wmb_ctx* c, int d, int stage, const SweepGroup& G, const DevList& L, int cur,
+                        unsigned long long* nprot, hipStream_t st) {
+    if (G.W < 0)
+        return launch_march<R>(d, stage, c->pool, c->d_patch, L.d, L.n, c->dp, coef<R>(c), cur, c->d_sc, G.P, -G.W,
+                               G.zlo, nprot, st);
+    return launch_sweep<R>(d, stage, c->pool, c->d_patch, L.d, L.n, c->dp, coef<R>(c), cur, c->d_sc, G.P, G.W, G.zlo,
+                           nprot, st);
+}
+
+// whether a sweep shape is valid for axis d and pencils of P zones (marching
+// shapes -W with W in [1, 256], or W + 512 in FP32 for the corrector with
+// the next zone's loads issued one zone ahead)
+bool shape_ok(int d, int P, size_t es, int W, int stage) {
+    if (W < 0) {
+        const int w = -W;
+        return d != 0 && ((w >= 1 && w <= 256) || (es == 4 && stage == 2 && w >= 513 && w <= 768));
+    }
+    return W >= 1 && (size_t)P * W <= 1024 && es * 16 * (size_t)P * W <= 64 * 1024;
+}
+
+template <typename R>
 int run_fill(wmb_ctx* c, int mask) {
     const WorkItem* wl[3] = {c->wl_fill[0].d, c->wl_fill[1].d, c->wl_fill[2].d};
     const int nw[3] = {c->wl_fill[0].n, c->wl_fill[1].n, c->wl_fill[2].n};
@@ -349,6 +376,11 @@ int run_finalize(wmb_ctx* c) {
     return WMB_OK;
 }
 
+// one sweep group's launch in its form
+template <typename R>
+hipError_t launch_group(wmb_ctx* c, int d, int stage, const SweepGroup& G, const DevList& L, int cur,
+                        unsigned long long* nprot, hipStream_t st);
+
 // One step.  split (the captured graph): the y/z ghost exchange was forked
 // onto the side stream (ev_join marks its end).  The three sweeps of a stage
 // are independent (each writes its own flux array), so they run as three
@@ -366,8 +398,7 @@ int run_step(wmb_ctx* c, bool split = false) {
     auto sweeps = [&](int d, int stage, const DevList SweepGroup::*wl, hipStream_t st) -> hipError_t {
         for (auto& G : c->sweeps[d][stage - 1]) {
             const DevList& L = G.*wl;
-            hipError_t r = launch_sweep<R>(d, stage, c->pool, c->d_patch, L.d, L.n, c->dp, coef<R>(c), cur, c->d_sc, G.P,
-                                           G.W, G.zlo, c->d_nfloor + 1, st);
+            hipError_t r = launch_group<R>(c, d, stage, G, L, cur, c->d_nfloor + 1, st);
             if (r != hipSuccess) return r;
         }
         return hipSuccess;
@@ -601,6 +632,10 @@ int build_fill_lists(wmb_ctx* c) {
 }
 
 int choose_W(int d, int P, size_t es) {
+    // y and z in FP32: the marching form (coalesced, no barrier; about 120
+    // VGPRs, 4 waves a SIMD); in FP64 it needs 256 VGPRs and the pencil form
+    // is kept
+    if (d != 0 && es == 4) return -64;
     if (d == 0) {
         // about 256 threads a block, packed into whole 64-lane waves: the
         // pencil count whose P * W wastes the fewest lanes, nearest to 256
@@ -667,7 +702,7 @@ std::vector<WorkItem> sweep_items(const wmb_ctx* c, int d, int n, int tlo, int t
 // replace are freed.
 int set_group_W(wmb_ctx* c, int d, int stage, SweepGroup& G, int W) {
     auto rebuild = [&](DevList& L, SweepPart part) -> int {
-        std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, W, part);
+        std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, W < 0 ? (-W) % 512 : W, part);
         if (items.empty()) return fail(c, WMB_EINVAL, "sweep work list: pencil rectangle outside the packed range");
         WorkItem* nd = nullptr;
         int rc = upload(c, &nd, items);
@@ -716,6 +751,12 @@ int build_sweeps(wmb_ctx* c) {
 }
 
 void free_graphs(wmb_ctx* c) {
+    // the launch stream's completion does not mean every parallel branch of
+    // a replayed graph has retired: destroying the executable before the
+    // whole device is idle keeps the memory its kernels used from ever being
+    // freed (measured on ROCm 7: a pool freed after wmb_destroy stayed
+    // allocated unless the device was synchronised first)
+    if (c->gexec[0] || c->gexec[1]) (void)hipDeviceSynchronize();  // teardown: nothing to report
     for (int i = 0; i < 2; i++) {
         if (c->gexec[i]) (void)hipGraphExecDestroy(c->gexec[i]);  // teardown: nothing to report
         if (c->graph[i]) (void)hipGraphDestroy(c->graph[i]);
@@ -957,8 +998,7 @@ int autotune_t(wmb_ctx* c, int reps) {
             hipError_t e = hipSuccess;
             for (int d = 0; d < 3 && e == hipSuccess; d++)
                 for (auto& G : c->sweeps[d][0])
-                    e = launch_sweep<R>(d, 1, c->pool, c->d_patch, G.wl.d, G.wl.n, c->dp, coef<R>(c), c->cur, c->d_sc, G.P,
-                                        G.W, G.zlo, c->d_nfloor + 2, c->stream);
+                    e = launch_group<R>(c, d, 1, G, G.wl, c->cur, c->d_nfloor + 2, c->stream);
             if (e == hipSuccess)
                 e = launch_ct_half<R>(c->pool, c->d_patch, c->wl_cth.d, c->wl_cth.n, coef<R>(c), c->p.ghost, c->cur,
                                       c->d_sc, c->stream);
@@ -970,16 +1010,17 @@ int autotune_t(wmb_ctx* c, int reps) {
                 // pencil counts around the 64-lane wave: 5, 10 and 20 pencils
                 // of 38 zones fill whole waves to 99%
                 const int opts_x[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24};
-                const int opts_t[] = {2, 4, 8, 16, 32};
+                // negative: the marching form (beyond -512: loads one zone ahead)
+                const int opts_t[] = {2, 4, 8, 16, 32, -64, -128, -256, -576, -640, -768};
                 if (d == 0)
                     for (int W : opts_x) cand.push_back(W);
                 else
                     for (int W : opts_t) cand.push_back(W);
-                float best = 1e30f;
+                float best = 1e30f, bestp = 1e30f, bestm = 1e30f;
                 int bestW = G.W;
                 for (int W : cand) {
-                    if ((size_t)G.P * W > 1024 || es * 16 * (size_t)G.P * W > 64 * 1024 || G.P * W < 64) continue;
-                    std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, W);
+                    if (!shape_ok(d, G.P, es, W, stage + 1) || (W > 0 && G.P * W < 64)) continue;
+                    std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, W < 0 ? (-W) % 512 : W);
                     if (items.empty()) continue;
                     CKT(hipMalloc(&dl, sizeof(WorkItem) * items.size()));
                     CKT(hipMemcpy(dl, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
@@ -987,8 +1028,10 @@ int autotune_t(wmb_ctx* c, int reps) {
                     hipError_t e = hipSuccess;
                     for (int r = 0; r <= reps && e == hipSuccess; r++) {
                         CKT(hipEventRecord(e0, c->stream));
-                        e = launch_sweep<R>(d, stage + 1, c->pool, c->d_patch, dl, (int)items.size(), c->dp, coef<R>(c),
-                                            c->cur, c->d_sc, G.P, W, G.zlo, c->d_nfloor + 2, c->stream);
+                        SweepGroup T = G;
+                        T.W = W;
+                        e = launch_group<R>(c, d, stage + 1, T, DevList{dl, (int)items.size()}, c->cur, c->d_nfloor + 2,
+                                            c->stream);
                         CKT(hipEventRecord(e1, c->stream));
                         CKT(hipEventSynchronize(e1));
                         float t = 0.f;
@@ -1003,6 +1046,8 @@ int autotune_t(wmb_ctx* c, int reps) {
                         best = tot;
                         bestW = W;
                     }
+                    if (W > 0 && tot < bestp) bestp = tot, G.Wp = W;
+                    if (W < 0 && tot < bestm) bestm = tot, G.Wm = W;
                 }
                 if (bestW != G.W) {
                     int rc2 = set_group_W(c, d, stage, G, bestW);
@@ -1010,6 +1055,77 @@ int autotune_t(wmb_ctx* c, int reps) {
                 }
             }
         }
+    }
+    // The graph runs the three sweeps of a stage concurrently, so the shapes
+    // that are fastest alone need not be the fastest together: time whole
+    // stages (x on the main stream, y and z on the side streams, joined) for
+    // the shapes picked alone, for the best pencil shapes and for the best
+    // marching shapes of the y and z groups, and keep the fastest.
+    for (int stage = 0; stage < 2; stage++) {
+        auto time_stage = [&](float* ms) -> int {
+            hipError_t e = hipSuccess;
+            float tot = 0.f;
+            for (int r = 0; r <= reps && e == hipSuccess; r++) {
+                CKT(hipEventRecord(e0, c->stream));
+                CKT(hipEventRecord(c->ev_br[5], c->stream));
+                CKT(hipStreamWaitEvent(c->side, c->ev_br[5], 0));
+                CKT(hipStreamWaitEvent(c->side2, c->ev_br[5], 0));
+                hipStream_t sts[3] = {c->stream, c->side, c->side2};
+                for (int d = 0; d < 3 && e == hipSuccess; d++)
+                    for (auto& G : c->sweeps[d][stage])
+                        if (e == hipSuccess) e = launch_group<R>(c, d, stage + 1, G, G.wl, c->cur, c->d_nfloor + 2, sts[d]);
+                CKT(hipEventRecord(c->ev_br[3], c->side));
+                CKT(hipEventRecord(c->ev_br[4], c->side2));
+                CKT(hipStreamWaitEvent(c->stream, c->ev_br[3], 0));
+                CKT(hipStreamWaitEvent(c->stream, c->ev_br[4], 0));
+                CKT(hipEventRecord(e1, c->stream));
+                CKT(hipEventSynchronize(e1));
+                float t = 0.f;
+                CKT(hipEventElapsedTime(&t, e0, e1));
+                if (r > 0) tot += t;
+            }
+            if (e != hipSuccess) return cleanup(fail(c, WMB_EHIP, std::string("autotune: ") + hipGetErrorString(e)));
+            *ms = tot;
+            return WMB_OK;
+        };
+        std::vector<int> alone;
+        for (int d = 1; d < 3; d++)
+            for (auto& G : c->sweeps[d][stage]) alone.push_back(G.W);
+        float best = 0.f;
+        int rc2 = time_stage(&best);
+        if (rc2) return rc2;
+        int choice = 0;  // 0: alone, 1: all pencil, 2: all marching
+        for (int alt = 1; alt <= 2; alt++) {
+            bool differs = false, valid = true;
+            for (int d = 1; d < 3; d++)
+                for (auto& G : c->sweeps[d][stage]) {
+                    const int W = alt == 1 ? G.Wp : G.Wm;
+                    valid = valid && W != 0;
+                    differs = differs || W != G.W;
+                }
+            if (!valid || !differs) continue;
+            for (int d = 1; d < 3 && !rc2; d++)
+                for (auto& G : c->sweeps[d][stage])
+                    if (!rc2) rc2 = set_group_W(c, d, stage, G, alt == 1 ? G.Wp : G.Wm);
+            if (rc2) return cleanup(rc2);
+            float t = 0.f;
+            if ((rc2 = time_stage(&t))) return rc2;
+            if (t < best) {
+                best = t;
+                choice = alt;
+            }
+            // back to the alone shapes before the next alternative
+            size_t k = 0;
+            for (int d = 1; d < 3 && !rc2; d++)
+                for (auto& G : c->sweeps[d][stage])
+                    if (!rc2) rc2 = set_group_W(c, d, stage, G, alone[k++]);
+            if (rc2) return cleanup(rc2);
+        }
+        if (choice)
+            for (int d = 1; d < 3 && !rc2; d++)
+                for (auto& G : c->sweeps[d][stage])
+                    if (!rc2) rc2 = set_group_W(c, d, stage, G, choice == 1 ? G.Wp : G.Wm);
+        if (rc2) return cleanup(rc2);
     }
 #undef CKT
     free_graphs(c);  // launch plans changed
@@ -1030,6 +1146,38 @@ static __device__ __align__(256) double scratch[NOALLOC_RECORDS * DIAG_REC];
 constexpr int MAX_DEVICES = 64;
 double* scratch_dev[MAX_DEVICES] = {};
 std::mutex scratch_mu;
+
+// Side streams of the step graphs, borrowed from a per-device pool and given
+// back (never destroyed) when a context ends.  On ROCm 7, destroying a stream
+// that took part in a graph capture before the memory its captured kernels
+// used is freed keeps that memory from ever being freed, and the caller
+// frees its pool only after wmb_destroy.
+std::vector<hipStream_t> spare_streams[MAX_DEVICES];
+std::mutex stream_mu;
+
+int borrow_stream(wmb_ctx* c, hipStream_t* out) {
+    int dev = -1;
+    CKH(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail_static(c, WMB_EHIP, "device index beyond the stream table");
+    {
+        std::lock_guard<std::mutex> lk(stream_mu);
+        if (!spare_streams[dev].empty()) {
+            *out = spare_streams[dev].back();
+            spare_streams[dev].pop_back();
+            return WMB_OK;
+        }
+    }
+    CKH(hipStreamCreateWithFlags(out, hipStreamNonBlocking));
+    return WMB_OK;
+}
+
+void return_stream(int dev, hipStream_t s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s);  // teardown: nothing to report
+    if (dev < 0 || dev >= MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lk(stream_mu);
+    spare_streams[dev].push_back(s);
+}
 
 int bind_scratch(wmb_ctx* c) {
     int dev = -1;
@@ -1105,14 +1253,17 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     c->desc.assign(d, d + npatch);
     c->pool = dev_pool;
     c->pool_bytes = pool_bytes;
+    CKH(hipGetDevice(&c->device));
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
     } else {
-        CKH(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        int rco = borrow_stream(c, &c->stream);
+        if (rco) return rco;
         c->own_stream = true;
     }
-    CKH(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-    CKH(hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking));
+    int rcs = borrow_stream(c, &c->side);
+    if (!rcs) rcs = borrow_stream(c, &c->side2);
+    if (rcs) return rcs;
     CKH(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     CKH(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     for (auto& ev : c->ev_br) CKH(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -1311,11 +1462,12 @@ int wmb_set_tuning(wmb_ctx* c, const int32_t* quads, int32_t n) {
     if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
     for (int k = 0; k + 4 <= n; k += 4) {
         const int stage = quads[k], d = quads[k + 1], edge = quads[k + 2], W = quads[k + 3];
-        if (stage < 1 || stage > 2 || d < 0 || d > 2 || W < 1) return fail(c, WMB_EINVAL, "bad tuning entry");
+        if (stage < 1 || stage > 2 || d < 0 || d > 2 || W == 0) return fail(c, WMB_EINVAL, "bad tuning entry");
         for (auto& G : c->sweeps[d][stage - 1]) {
             if (G.n != edge) continue;
-            if ((size_t)G.P * W > 1024 || c->esize * 16 * (size_t)G.P * W > 64 * 1024)
-                return fail(c, WMB_EINVAL, "tuning entry exceeds the block or LDS limit");
+            if (!shape_ok(d, G.P, c->esize, W, stage))
+                return fail(c, WMB_EINVAL, "tuning entry: the marching form serves y and z with at most 256 pencils "
+                                           "a block; the pencil form must fit 1024 threads and 64 KiB of LDS");
             int rc = set_group_W(c, d, stage - 1, G, W);
             if (rc) return rc;
         }
@@ -1406,16 +1558,12 @@ int wmb_destroy(wmb_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);  // teardown: nothing to report
     free_graphs(c);
     for (void* p : c->owned) (void)hipFree(p);
-    for (hipStream_t sd : {c->side, c->side2})
-        if (sd) {
-            (void)hipStreamSynchronize(sd);
-            (void)hipStreamDestroy(sd);
-        }
+    for (hipStream_t sd : {c->side, c->side2}) return_stream(c->device, sd);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     for (hipEvent_t ev : c->ev_br)
         if (ev) (void)hipEventDestroy(ev);
-    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    if (c->own_stream) return_stream(c->device, c->stream);
     delete c;
     return WMB_OK;
 }
