@@ -214,6 +214,29 @@ def make_sim(W, G, q, b, dx, prec, ghost, stream, **params):
     return sim
 
 
+SCHEDULE = 0  # captured-step schedule: 0 picks 1, 2 or 3 patch groups by timing during the warm-up
+
+
+def pick_schedule(sim, stream, reps=3):
+    """Time `reps` graph replays under 1, 2 and 3 patch groups (warm-up steps:
+    the state advances) and keep the fastest; returns {groups: ms per step}."""
+    import torch
+
+    times = {}
+    for groups in (1, 2, 3):
+        sim.set_schedule(groups)
+        sim.run_steps(1)  # captures the graphs of this schedule
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.run_steps(reps)
+        e1.record(stream)
+        stream.synchronize()
+        times[groups] = e0.elapsed_time(e1) / reps
+    best = min(times, key=times.get)
+    sim.set_schedule(best)
+    return best, times
+
+
 def run_batch(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps, tuning=None, freeze=(), divb_at=(), **params):
     """Time `steps` graph replays after `warmup` ones; per-kernel eager
     durations from prof_steps profiled steps; optionally the normalised div b
@@ -227,6 +250,13 @@ def run_batch(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps, tuning=Non
     else:
         tuning = sim.autotune(reps=3)
     log("bench: pencils per block %s" % W.tuning_to_str(tuning))
+    if SCHEDULE:
+        groups, sched_ms = SCHEDULE, None
+        sim.set_schedule(groups)
+    else:
+        groups, sched_ms = pick_schedule(sim, stream)
+    log("bench: schedule %d patch group(s) %s" % (groups, "" if sched_ms is None else
+                                                   {g: round(t, 3) for g, t in sched_ms.items()}))
     sim.run_steps(max(warmup, 1))  # captures the graphs
     stream.synchronize()
     freeze_ms = None
@@ -259,13 +289,14 @@ def run_batch(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps, tuning=Non
     nprot = sim.protected_faces()
     sim.close()
     diag = {"max_divb_norm": dn, "max_divb_raw": dr, "floors": nfl, "protected_faces": nprot,
-            "tuning": W.tuning_to_str(tuning)}
+            "tuning": W.tuning_to_str(tuning), "schedule_groups": groups, "schedule_ms": sched_ms}
     if freeze:
         diag["freeze_ms_per_patch"] = freeze_ms
     if divb_at:
         # normalised div b against the step count, from the initial state
         sim = make_sim(W, G, q, b, dx, prec, ghost, stream, **params)
         sim.set_tuning(tuning)
+        sim.set_schedule(groups)
         done, curve = 0, {}
         for n in sorted(divb_at):
             sim.run_steps(n - done)
@@ -292,8 +323,8 @@ def main():
     ap.add_argument("--tuning64", default="", help="sweep shapes for FP64; default: autotune")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven 400-patch batch (reported beside)")
     ap.add_argument("--no-c4", action="store_true", help="skip the 512^3 Orszag-Tang batch of 64^3 patches")
-    ap.add_argument("--c5", action="store_true",
-                    help="also time the 768^3 high-contrast batch of 48^3 patches (210 GB pool, minutes of set-up)")
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the 768^3 high-contrast batch of 48^3 patches (210 GB pool, about a minute of set-up)")
     ap.add_argument("--protection", action="store_true",
                     help="also time the Mach-5 lognormal-density batch (384^3 as 512 x 48^3, FP32) with the protection "
                          "floors off and on (reported beside)")
@@ -301,6 +332,8 @@ def main():
                     help="also time the FP32 batch with outflow boundaries on every side of the domain")
     ap.add_argument("--frozen", action="store_true",
                     help="also time the FP32 batch with every other patch frozen (checkerboard), graphs reused")
+    ap.add_argument("--schedule", type=int, default=0,
+                    help="captured-step schedule: 1 (concurrent sweep branches), 2 or 3 patch groups; 0 picks by timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -319,6 +352,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     W.load_library()
+    global SCHEDULE
+    SCHEDULE = args.schedule
     t_start = time.perf_counter()
 
     if args.calib_copy:
@@ -388,7 +423,7 @@ def main():
         log("bench: C4 FP32 %.3f ms/step, %.3e zone-updates/s" % (ms4 / s4, c4["value"]))
 
     c5 = None
-    if args.c5:
+    if not args.no_c5 and args.prof_steps > 0:
         N5, n5 = 768, 48
         G5 = I.uniform_grid(N5, n5)
         log("bench: 768^3 high-contrast batch, %d patches of 48^3" % G5.npatch)

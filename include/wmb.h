@@ -235,6 +235,19 @@ int wmb_autotune(wmb_ctx *c, int32_t reps, int32_t *chosen, int32_t nchosen);
    sweeps in FP32 and the pencil form elsewhere. */
 int wmb_set_tuning(wmb_ctx *c, const int32_t *quads, int32_t n);
 
+/* Schedule of the captured step (wmb_run_steps).  groups = 1 (the default):
+   the three sweeps of each stage run as concurrent branches and the y/z
+   ghost exchange beside the interior part of the Step-1 x sweep.  groups =
+   2..4: the patches are dealt, whole x-rows at a time, to that many groups,
+   and each group runs its whole step (Steps 1-11) on a stream of its own
+   after the exchange and dt, so that the memory-bound stages of one group
+   overlap the sweeps of another (the paper's update engine works on
+   patches in different stages at once, Sect. 4.1).  Results are bitwise
+   the same under every schedule; wmb_advance and wmb_profile_step always
+   run the stages one after another.  Invalidates the captured graphs.
+   WMB_EINVAL outside 1..4. */
+int wmb_set_schedule(wmb_ctx *c, int32_t groups);
+
 /* Freeze (active = 0) or thaw (active != 0) one patch without rebuilding
    the launch plan (Sect. 2.1: patches may become inactive, left out of the
    update, for load balancing and mesh refinement; here its pool memory stays

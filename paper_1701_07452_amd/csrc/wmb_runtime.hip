@@ -42,6 +42,7 @@ struct SweepGroup {
     int P, W, zlo, tlo, thi, n;
     int Wp = 0, Wm = 0;    // autotune: the fastest pencil and marching shapes alone
     DevList wl;            // every pencil of the transverse range [tlo, n+thi]^2
+    DevList wlg[4];        // the same for the patches of each step group (grouped schedule)
     DevList wl_in, wl_fr;  // Step-1 x sweep only: the pencils with both transverse
                            // coords interior, and the frame around them
 };
@@ -80,6 +81,13 @@ struct wmb_ctx {
     PatchDev* d_patch = nullptr;
     DevList wl_fill[3];
     DevList wl_int, wl_diag, wl_cth, wl_upd, wl_upd256;
+    // grouped schedule (wmb_set_schedule): ngroups > 1 patch groups (whole
+    // x-rows), each running its whole step on its own stream in the graph
+    int ngroups = 1;
+    std::vector<int> pgroup;  // patch -> step group
+    DevList wl_cth_g[4], wl_upd_g[4], wl_upd256_g[4];
+    hipStream_t gstream[4] = {};  // group streams 1..3 (group 0 runs on the main stream), borrowed
+    hipEvent_t ev_g[4] = {};
     int upd_zones = 256;  // zones a tile plane of Steps 8-11 (the update's block size)
     int nfrozen = 0;      // frozen patches; while any, Steps 8-11 run on 256-zone tiles
     bool keep_edges = false;  // Steps 8-11 also store the Step-9 edges (debugging)
@@ -473,6 +481,45 @@ int run_step(wmb_ctx* c, bool split = false) {
     return WMB_OK;
 }
 
+// The grouped schedule of the captured step: the patch groups (whole x-rows)
+// run their whole step (Step-1 sweeps, Steps 3-4, Steps 5-7, Steps 8-11) each
+// on its own stream, forked after dt and joined before the next exchange, so
+// that one group's memory-bound stages overlap another's sweeps.  Within a
+// step a patch's kernels touch only its own region, apart from the update's
+// x-ghost pushes, which write the neighbours' other state copy (read only
+// after the join), so the groups share no data inside the step.
+template <typename R>
+int run_step_grouped(wmb_ctx* c) {
+    const int cur = c->cur;
+    CKH(hipEventRecord(c->ev_fork, c->stream));
+    for (int g = 1; g < c->ngroups; g++) CKH(hipStreamWaitEvent(c->gstream[g], c->ev_fork, 0));
+    const bool t256 = c->nfrozen > 0 && c->upd_zones != 256;
+    for (int g = 0; g < c->ngroups; g++) {
+        hipStream_t st = g == 0 ? c->stream : c->gstream[g];
+        hipError_t e = hipSuccess;
+        for (int stage = 1; stage <= 2 && e == hipSuccess; stage++) {
+            for (int d = 0; d < 3 && e == hipSuccess; d++)
+                for (auto& SG : c->sweeps[d][stage - 1])
+                    if (e == hipSuccess) e = launch_group<R>(c, d, stage, SG, SG.wlg[g], cur, c->d_nfloor + 1, st);
+            if (stage == 1 && e == hipSuccess)
+                e = launch_ct_half<R>(c->pool, c->d_patch, c->wl_cth_g[g].d, c->wl_cth_g[g].n, coef<R>(c), c->p.ghost,
+                                      cur, c->d_sc, st);
+        }
+        const DevList& wu = t256 ? c->wl_upd256_g[g] : c->wl_upd_g[g];
+        if (e == hipSuccess)
+            e = launch_update<R>(c->pool, c->d_patch, wu.d, wu.n, c->dp, coef<R>(c), cur, c->d_sc, c->d_nfloor, c->d_smax,
+                                 c->keep_edges ? 1 : 0, t256 ? 256 : c->upd_zones, st);
+        if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("grouped step: ") + hipGetErrorString(e));
+        if (g > 0) CKH(hipEventRecord(c->ev_g[g], st));
+    }
+    for (int g = 1; g < c->ngroups; g++) CKH(hipStreamWaitEvent(c->stream, c->ev_g[g], 0));
+    c->edges_kept = c->keep_edges;
+    c->xg_valid = true;
+    c->cur ^= 1;
+    c->smax_state = (c->smax_state == SMAX_ZERO) ? SMAX_CLEAN : SMAX_DIRTY;
+    return WMB_OK;
+}
+
 int dispatch_fill(wmb_ctx* c, int mask = FILL_ALL) {
     return c->esize == 4 ? run_fill<float>(c, mask) : run_fill<double>(c, mask);
 }
@@ -485,6 +532,7 @@ int dispatch_dt(wmb_ctx* c) {
     return rc ? rc : run_finalize(c);
 }
 int dispatch_step(wmb_ctx* c, bool split = false) {
+    if (split && c->ngroups > 1) return c->esize == 4 ? run_step_grouped<float>(c) : run_step_grouped<double>(c);
     return c->esize == 4 ? run_step<float>(c, split) : run_step<double>(c, split);
 }
 // the y/z ghost exchange on the side stream, forked from and joined (by the
@@ -557,9 +605,10 @@ std::vector<int> x_rows(const wmb_ctx* c) {
 }
 
 int build_tile_list(wmb_ctx* c, int lo, int hi, int zlo, int zhi, int txmax_allowed, int maxz,
-                    const std::vector<int>* group, DevList& out) {
+                    const std::vector<int>* group, DevList& out, int sgroup = -1) {
     std::vector<WorkItem> items;
     for (int p = 0; p < c->npatch; p++) {
+        if (sgroup >= 0 && c->pgroup[p] != sgroup) continue;
         const int* n = c->desc[p].n;
         const int ex = n[0] + hi - lo + 1, ey = n[1] + hi - lo + 1;
         const int mx = (ex + txmax_allowed - 1) / txmax_allowed;
@@ -664,7 +713,8 @@ enum SweepPart { PART_ALL, PART_INTERIOR, PART_FRAME };
 
 // pencils of every patch whose edge along d is n, W consecutive pencils of one
 // rectangle a block
-std::vector<WorkItem> sweep_items(const wmb_ctx* c, int d, int n, int tlo, int thi, int W, SweepPart part = PART_ALL) {
+std::vector<WorkItem> sweep_items(const wmb_ctx* c, int d, int n, int tlo, int thi, int W, SweepPart part = PART_ALL,
+                                  int group = -1) {
     const int FA = (d == 0) ? 1 : 0;
     const int SA = (d == 0) ? 2 : (d == 1 ? 2 : 1);
     struct Rect {
@@ -673,6 +723,7 @@ std::vector<WorkItem> sweep_items(const wmb_ctx* c, int d, int n, int tlo, int t
     std::vector<WorkItem> items;
     for (int p = 0; p < c->npatch; p++) {
         if (c->desc[p].n[d] != n) continue;
+        if (group >= 0 && c->pgroup[p] != group) continue;
         const int nf = c->desc[p].n[FA], ns = c->desc[p].n[SA];
         const int tf = nf + thi - tlo + 1;
         std::vector<Rect> rects;
@@ -713,6 +764,14 @@ int set_group_W(wmb_ctx* c, int d, int stage, SweepGroup& G, int W) {
         return WMB_OK;
     };
     int rc = rebuild(G.wl, PART_ALL);
+    for (int g = 0; g < c->ngroups && c->ngroups > 1 && !rc; g++) {
+        std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, W < 0 ? (-W) % 512 : W, PART_ALL, g);
+        WorkItem* nd = nullptr;
+        if (!items.empty() && (rc = upload(c, &nd, items))) break;
+        release(c, G.wlg[g].d);
+        G.wlg[g].d = nd;
+        G.wlg[g].n = (int)items.size();
+    }
     if (!rc && d == 0 && stage == 0) rc = rebuild(G.wl_in, PART_INTERIOR);
     if (!rc && d == 0 && stage == 0) rc = rebuild(G.wl_fr, PART_FRAME);
     if (rc) return rc;
@@ -782,7 +841,9 @@ int capture_graphs(wmb_ctx* c) {
     for (int k = 0; k < 2; k++) {
         const int cur0 = c->cur;
         CKH(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
-        int rc = fork_fill_yz(c);
+        // grouped schedule: the exchange first, on the main stream; else the
+        // exchange on its own branch beside the interior x sweep
+        int rc = c->ngroups > 1 ? dispatch_fill(c, FILL_YZ) : fork_fill_yz(c);
         if (!rc) rc = run_finalize(c);
         if (!rc) rc = dispatch_step(c, true);
         hipGraph_t g = nullptr;
@@ -1476,6 +1537,53 @@ int wmb_set_tuning(wmb_ctx* c, const int32_t* quads, int32_t n) {
     return WMB_OK;
 }
 
+int wmb_set_schedule(wmb_ctx* c, int32_t groups) {
+    if (!c) return WMB_EINVAL;
+    if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
+    if (groups < 1 || groups > 4) return fail(c, WMB_EINVAL, "schedule: 1 to 4 patch groups");
+    if (groups == c->ngroups) return WMB_OK;
+    free_graphs(c);
+    if (groups > 1) {
+        // whole x-rows (the update's x-pushes stay inside a row), dealt to the
+        // groups in turn in the order of their first patch
+        const std::vector<int> rows = x_rows(c);
+        std::vector<int> ord(c->npatch, -1);
+        int next = 0;
+        c->pgroup.assign(c->npatch, 0);
+        for (int p = 0; p < c->npatch; p++) {
+            if (ord[rows[p]] < 0) ord[rows[p]] = next++;
+            c->pgroup[p] = ord[rows[p]] % groups;
+        }
+        for (int g = 1; g < groups; g++) {
+            if (!c->gstream[g]) {
+                int rc = borrow_stream(c, &c->gstream[g]);
+                if (rc) return rc;
+            }
+            if (!c->ev_g[g]) CKH(hipEventCreateWithFlags(&c->ev_g[g], hipEventDisableTiming));
+        }
+    }
+    c->ngroups = groups;
+    if (groups == 1) return WMB_OK;
+    for (int d = 0; d < 3; d++)
+        for (int stage = 0; stage < 2; stage++)
+            for (auto& SG : c->sweeps[d][stage]) {
+                int rc = set_group_W(c, d, stage, SG, SG.W);
+                if (rc) return rc;
+            }
+    const std::vector<int> rows = x_rows(c);
+    for (int g = 0; g < groups; g++) {
+        for (DevList* L : {&c->wl_cth_g[g], &c->wl_upd_g[g], &c->wl_upd256_g[g]}) {
+            release(c, L->d);
+            *L = DevList{};
+        }
+        int rc = build_tile_list(c, -2, 2, -2, 2, 40, 256, nullptr, c->wl_cth_g[g], g);
+        if (!rc) rc = build_tile_list(c, 0, -1, 0, -1, 32, c->upd_zones, &rows, c->wl_upd_g[g], g);
+        if (!rc && c->upd_zones != 256) rc = build_tile_list(c, 0, -1, 0, -1, 32, 256, &rows, c->wl_upd256_g[g], g);
+        if (rc) return rc;
+    }
+    return WMB_OK;
+}
+
 // A frozen patch reads the same in both state copies, ghosts included, so
 // that its neighbours can pull from it whichever copy is current: refresh
 // every ghost of the current copy, then copy the patch's whole stored box
@@ -1559,6 +1667,10 @@ int wmb_destroy(wmb_ctx* c) {
     free_graphs(c);
     for (void* p : c->owned) (void)hipFree(p);
     for (hipStream_t sd : {c->side, c->side2}) return_stream(c->device, sd);
+    for (int g = 1; g < 4; g++) {
+        return_stream(c->device, c->gstream[g]);
+        if (c->ev_g[g]) (void)hipEventDestroy(c->ev_g[g]);
+    }
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     for (hipEvent_t ev : c->ev_br)

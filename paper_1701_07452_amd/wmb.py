@@ -22,7 +22,7 @@ EXPORTS = [
     "wmb_create", "wmb_pool_bytes", "wmb_init_patches", "wmb_set_state", "wmb_get_state", "wmb_get_stored",
     "wmb_fill_ghosts", "wmb_compute_dt", "wmb_advance", "wmb_run_steps", "wmb_diagnostics",
     "wmb_diagnostics_noalloc", "wmb_debug_stage",
-    "wmb_autotune", "wmb_set_tuning", "wmb_keep_stages", "wmb_set_active", "wmb_profile_step", "wmb_destroy",
+    "wmb_autotune", "wmb_set_tuning", "wmb_set_schedule", "wmb_keep_stages", "wmb_set_active", "wmb_profile_step", "wmb_destroy",
     "wmb_strerror", "wmb_last_error",
 ]
 KERNEL_CLASSES = ["fill", "dt", "sweep1_x", "sweep1_y", "sweep1_z", "ct_half",
@@ -107,6 +107,7 @@ def load_library():
     lib.wmb_profile_step.argtypes = [vp, dp, C.c_int32]
     lib.wmb_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.c_int32]
     lib.wmb_set_tuning.argtypes = [vp, C.POINTER(C.c_int32), C.c_int32]
+    lib.wmb_set_schedule.argtypes = [vp, C.c_int32]
     lib.wmb_keep_stages.argtypes = [vp, C.c_int32]
     lib.wmb_set_active.argtypes = [vp, C.c_int32, C.c_int32]
     lib.wmb_destroy.argtypes = [vp]
@@ -280,6 +281,10 @@ class Sim:
         flat = [v for (st, ax, e), W in sorted(tuning.items()) for v in (st, ax, e, W)]
         buf = (C.c_int32 * max(len(flat), 1))(*flat)
         self._check(self.lib.wmb_set_tuning(self.h, buf, len(flat)))
+
+    def set_schedule(self, groups):
+        """Captured-step schedule: 1 (concurrent sweep branches) or 2..4 patch groups."""
+        self._check(self.lib.wmb_set_schedule(self.h, int(groups)))
 
     def set_active(self, ip, on=True):
         """Freeze (on=False) or thaw a patch; the captured graphs stay valid."""

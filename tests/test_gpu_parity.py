@@ -244,9 +244,10 @@ def test_steps_fp32_tolerance(wmb, setup):
 
 @pytest.mark.parametrize("grid", ["uneven", "cube32"])
 def test_run_steps_graph_equals_eager_and_determinism(wmb, grid):
-    """Graph replay (concurrent branches) equals eager launches, and two
-    graph runs agree, bitwise.  FP32; the 32^3 patches of cube32 run the
-    Steps 8-11 kernel on 512-zone tiles."""
+    """Graph replay (concurrent branches; and the grouped schedules with 2
+    and 3 patch groups) equals eager launches, and graph runs agree,
+    bitwise.  FP32; the 32^3 patches of cube32 run the Steps 8-11 kernel on
+    512-zone tiles."""
     if grid == "uneven":
         G, (q, b) = CASES["uneven"]()
     else:
@@ -254,9 +255,11 @@ def test_run_steps_graph_equals_eager_and_determinism(wmb, grid):
     N = G.shape
     dx = (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
     outs = []
-    for mode in ("graph", "eager", "graph"):
+    for mode in ("graph", "eager", "graph", "graph2", "graph3"):
         sim = gpu_sim(wmb, G, q, b, 1, dx=dx)
-        if mode == "graph":
+        if mode.startswith("graph"):
+            if mode != "graph":
+                sim.set_schedule(int(mode[-1]))
             sim.run_steps(3)
             sim.run_steps(2)
         else:
