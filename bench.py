@@ -123,6 +123,226 @@ def roofline(descs, g, es, zones, ms_step, kern_ms, prof=None):
 
 
 # ---------------------------------------------------------------------------
+# rocprofv3 counter summary (written into profiles/, read back by roofline())
+# ---------------------------------------------------------------------------
+
+TUNING32_PROF = "1x32=12,1y32=16,1z32=16,2x32=2,2y32=16,2z32=16"
+TUNING64_PROF = "1x32=6,1y32=-256,1z32=-256,2x32=3,2y32=-64,2z32=-64"
+COUNTER_ARGS = ("--steps 2 --warmup 1 --prof-steps 0 --no-fp64 --no-cpu-baseline --schedule 1 --calib-copy "
+                "--tuning32 " + TUNING32_PROF)
+SQ_COUNTERS = "SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES GRBM_GUI_ACTIVE"
+TRACE_ARGS = ("--steps 5 --warmup 1 --prof-steps 3 --no-cpu-baseline --no-uneven --no-c4 --no-c5 --no-divb --schedule 1 "
+              "--tuning32 " + TUNING32_PROF + " --tuning64 " + TUNING64_PROF)
+
+
+def kernel_class(name):
+    """Kernel class of a dispatch name (as in kernels_ms), or None outside the step."""
+    import re
+
+    m = re.search(r"(?:sweep|march)_kernel<(?:float|double), (\d), (\d)", name)
+    if m:
+        return "sweep%s_%s" % (m.group(2), "xyz"[int(m.group(1))])
+    for key, cls in (("fill_pass_kernel", "fill"), ("ct_half_kernel", "ct_half"), ("update_kernel", "update"),
+                     ("dt_finalize_kernel", "dt")):
+        if key in name:
+            return cls
+    return None
+
+
+def short_name(name):
+    name = name.replace("void ", "").replace("wmb::", "")
+    depth = 0
+    for i, ch in enumerate(name):
+        depth += ch == "<"
+        depth -= ch == ">"
+        if ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
+def read_counter_csv(path):
+    """Dispatches of a rocprofv3 counter_collection.csv, in dispatch order:
+    [{"name", "ns", counter: value, ...}]."""
+    import csv
+
+    disp = {}
+    for r in csv.DictReader(open(path)):
+        d = disp.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"],
+                                                    "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"]),
+                                                    "vgpr": r.get("VGPR_Count")})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return [disp[k] for k in sorted(disp)]
+
+
+def last_step(disp):
+    """The dispatches of the last step before the trailing diagnostics: back
+    from the last update launch to the previous step's update."""
+    cls = [kernel_class(d["name"]) for d in disp]
+    last = max(i for i, c in enumerate(cls) if c == "update")
+    j = last
+    while j > 0 and cls[j - 1] == "update":
+        j -= 1
+    k = j - 1
+    while k >= 0 and cls[k] != "update":
+        k -= 1
+    return disp[k + 1:last + 1]
+
+
+def find_one(root, pattern):
+    import glob
+
+    hits = sorted(glob.glob(os.path.join(root, "**", pattern), recursive=True))
+    if not hits:
+        raise SystemExit("no %s under %s" % (pattern, root))
+    return hits[-1]
+
+
+def summarize_counters(root):
+    """Turn the rocprofv3 runs under `root` (fetch/, write/, sq/: one counter
+    pass each of COUNTER_ARGS; trace/: --kernel-trace --stats of TRACE_ARGS,
+    with its bench line in trace/bench.json; kernels.sha256: the kernel
+    source the runs were built from) into the committed summaries."""
+    sha = open(os.path.join(root, "kernels.sha256")).read().split()[0]
+    cur = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if sha != cur:
+        log("summarize: the runs were made from another kernel source (%s, now %s)" % (sha[:12], cur[:12]))
+    fetch = read_counter_csv(find_one(os.path.join(root, "fetch"), "*counter_collection.csv"))
+    write = read_counter_csv(find_one(os.path.join(root, "write"), "*counter_collection.csv"))
+    sq = read_counter_csv(find_one(os.path.join(root, "sq"), "*counter_collection.csv"))
+    copy_bytes = 1 << 30
+
+    def calib(disp, counter):
+        copies = [d for d in disp if "copyBuffer" in d["name"]]
+        return max(d.get(counter, 0.0) for d in copies)
+
+    fetch_kib, write_kib = calib(fetch, "FETCH_SIZE"), calib(write, "WRITE_SIZE")
+    fs, ws = copy_bytes / 1024 / fetch_kib, copy_bytes / 1024 / write_kib
+    steps = {"fetch": last_step(fetch), "write": last_step(write), "sq": last_step(sq)}
+    names = [d["name"] for d in steps["fetch"]]
+    for k in ("write", "sq"):
+        if [d["name"] for d in steps[k]] != names:
+            raise SystemExit("the three passes launched different kernels in their last step")
+    rows, per_class = [], {}
+    for i, nm in enumerate(names):
+        f = steps["fetch"][i].get("FETCH_SIZE", 0.0) * 1024 * fs
+        w = steps["write"][i].get("WRITE_SIZE", 0.0) * 1024 * ws
+        s = steps["sq"][i]
+        cyc = s.get("GRBM_GUI_ACTIVE", 0.0) / 8
+        rows.append({"kernel": short_name(nm), "class": kernel_class(nm), "fetch": f, "write": w,
+                     "ms": steps["fetch"][i]["ns"] / 1e6, "waves": s.get("SQ_WAVES", 0.0),
+                     "valu": s.get("SQ_INSTS_VALU", 0.0), "active_valu": s.get("SQ_ACTIVE_INST_VALU", 0.0),
+                     "cyc": cyc, "vgpr": s.get("vgpr")})
+    for r in rows:
+        pc = per_class.setdefault(r["class"], {"launches": 0, "fetch_bytes": 0.0, "write_bytes": 0.0, "ms": 0.0,
+                                               "waves": 0.0, "valu": 0.0, "active_valu": 0.0, "cyc": 0.0})
+        pc["launches"] += 1
+        for a, b in (("fetch_bytes", "fetch"), ("write_bytes", "write"), ("ms", "ms"), ("waves", "waves"),
+                     ("valu", "valu"), ("active_valu", "active_valu"), ("cyc", "cyc")):
+            pc[a] += r[b]
+    for pc in per_class.values():
+        pc["valu_busy"] = round(pc["active_valu"] * 4 / (1024 * pc["cyc"]), 4) if pc["cyc"] else None
+        pc["valu_insts_per_wave"] = round(pc["valu"] / pc["waves"], 1) if pc["waves"] else None
+        pc["fetch_bytes"], pc["write_bytes"] = round(pc["fetch_bytes"]), round(pc["write_bytes"])
+        pc["ms"] = round(pc["ms"], 4)
+        for k in ("waves", "valu", "active_valu", "cyc"):
+            del pc[k]
+    tot_f = sum(r["fetch"] for r in rows)
+    tot_w = sum(r["write"] for r in rows)
+    tot_ms = sum(r["ms"] for r in rows)
+    rec = {
+        "workload": "turbulence 256^3 as 512 x 32^3, ghost 4, FP32, one step (the last of the run)",
+        "kernels_source_sha256": sha,
+        "commands": {"fetch": "rocprofv3 --pmc FETCH_SIZE -- python3 bench.py " + COUNTER_ARGS,
+                     "write": "rocprofv3 --pmc WRITE_SIZE -- python3 bench.py " + COUNTER_ARGS,
+                     "sq": "rocprofv3 --pmc " + SQ_COUNTERS + " -- python3 bench.py " + COUNTER_ARGS},
+        "calibration": {"copy_bytes": copy_bytes, "fetch_kib": fetch_kib, "write_kib": write_kib,
+                        "fetch_scale": fs, "write_scale": ws},
+        "per_class": per_class,
+        "whole_step": {"fetch_bytes": round(tot_f), "write_bytes": round(tot_w), "kernel_ms": round(tot_ms, 4)},
+    }
+    with open(PROFILE_JSON, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    md = ["# HBM traffic and VALU issue per kernel: 256^3 turbulence as 512 x 32^3, FP32 batch", "",
+          "Commands (TMPDIR=/tmp, run from /tmp, `<repo>` the repository root, one pass each, "
+          "`--output-format csv -d <out>/{fetch,write,sq} -o run`):", "```"]
+    for k in ("fetch", "write", "sq"):
+        md.append(rec["commands"][k].replace("python3 bench.py", "python3 <repo>/bench.py"))
+    md += ["```", "Summarised by `python bench.py --summarize-counters <out>`, which writes this file and "
+           "`%s` (read by `bench.py`'s roofline while the kernel source's sha256 matches)." %
+           os.path.basename(PROFILE_JSON), "",
+           "Calibration: each run first copies 1 GiB device to device (`--calib-copy`). For that copy "
+           "`FETCH_SIZE` reads %.0f KiB and `WRITE_SIZE` %.0f KiB against 1048576 KiB moved each way, so fetch "
+           "values are scaled by %.3f and write values by %.3f." % (fetch_kib, write_kib, fs, ws), "",
+           "Values are those of the dispatches of the run's last step (the profiler serialises the "
+           "kernels; durations are those of the FETCH_SIZE pass). VALU busy = SQ_ACTIVE_INST_VALU x 4 / "
+           "(1024 SIMDs x GRBM_GUI_ACTIVE / 8): GRBM_GUI_ACTIVE reads the busy cycles of the 8 XCDs summed, "
+           "and a wave64 FP32 VALU instruction holds a 16-lane SIMD for 4 cycles.", "",
+           "| Kernel | Fetch (GB) | Write (GB) | Duration (ms) | Measured TB/s | VALU instr. per wave | VALU busy |",
+           "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        busy = r["active_valu"] * 4 / (1024 * r["cyc"]) if r["cyc"] else 0.0
+        md.append("| `%s` | %.3f | %.3f | %.3f | %.2f | %.0f | %.0f%% |" % (
+            r["kernel"], r["fetch"] / 1e9, r["write"] / 1e9, r["ms"], (r["fetch"] + r["write"]) / (r["ms"] * 1e9),
+            r["valu"] / r["waves"] if r["waves"] else 0, 100 * busy))
+    md.append("| **whole step** | %.3f | %.3f | %.3f | %.2f | | |" % (tot_f / 1e9, tot_w / 1e9, tot_ms,
+                                                                       (tot_f + tot_w) / (tot_ms * 1e9)))
+    md += ["", "The step moves %.2f GB of measured traffic in %.3f ms of serialised kernel time (%.2f TB/s); "
+           "its algorithmic bytes are 2.609 GB (155.5 B per zone-update)." % ((tot_f + tot_w) / 1e9, tot_ms,
+                                                                             (tot_f + tot_w) / (tot_ms * 1e9))]
+    base = PROFILE_JSON[:-len(".json")]
+    with open(base + ".md", "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    summarize_trace(os.path.join(root, "trace"), sha)
+    log("summarize: wrote %s(.json, .md)" % base)
+
+
+def summarize_trace(root, sha):
+    """profiles/turb256_512x32_kernel_stats.md from a --kernel-trace --stats run of TRACE_ARGS."""
+    import csv
+
+    stats = list(csv.DictReader(open(find_one(root, "*kernel_stats.csv"))))
+    trace = list(csv.DictReader(open(find_one(root, "*kernel_trace.csv"))))
+    bench = json.loads(open(os.path.join(root, "bench.json")).read().strip().splitlines()[-1])
+    durs = {}
+    for r in sorted(trace, key=lambda r: int(r["Start_Timestamp"])):
+        durs.setdefault(short_name(r["Kernel_Name"]), []).append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+    md = ["# rocprofv3 kernel statistics: 256^3 turbulence as 512 patches of 32^3 (FP32 and FP64 batches)", "",
+          "Command (TMPDIR=/tmp, run from /tmp; `<repo>` is the repository root):", "```",
+          "rocprofv3 --kernel-trace --stats --output-format csv -d <out>/trace -o run -- \\",
+          "  python3 <repo>/bench.py " + TRACE_ARGS, "```",
+          "Kernel source sha256 %s. Per precision the run does 1 warm-up step, 5 graph-replayed timed steps "
+          "and 3 eager profiled steps (`wmb_profile_step`: the same launches, one kernel at a time), plus "
+          "set-up and diagnostics kernels. `Avg` is rocprofv3's `AverageNs` over all calls: in the replayed "
+          "steps the three sweeps of a stage run concurrently and share the GPU, so their average lies above "
+          "the one-at-a-time time. `Eager` is the mean of each kernel's last 3 dispatches (the profiled "
+          "steps). The last column is `bench.py`'s own HIP-event time for the kernel class in the same run "
+          "(`kernels_ms`; FP32 `%s` ms/step, FP64 `%s` ms/step in the graph)." % (
+              sha[:16], "%.3f" % bench["ms_per_step"], "%.3f" % bench["fp64"]["ms_per_step"]), "",
+          "| Kernel | Calls | Avg (ms) | Min (ms) | Max (ms) | Eager (ms) | bench.py HIP-event (ms) |",
+          "|---|---:|---:|---:|---:|---:|---:|"]
+    km = {"float": bench.get("kernels_ms") or {}, "double": (bench.get("fp64") or {}).get("kernels_ms") or {}}
+    seen = set()
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        nm = short_name(r["Name"])
+        cls = kernel_class(nm)
+        prec = "double" if "<double" in nm else "float"
+        eager = durs.get(nm, [])[-3:]
+        hip = ""
+        if cls and (prec, cls) not in seen and cls in km[prec]:
+            hip = "%.3f" % km[prec][cls]
+            seen.add((prec, cls))
+        md.append("| `%s` | %s | %.4f | %.4f | %.4f | %s | %s |" % (
+            nm, r["Calls"], float(r["AverageNs"]) / 1e6, float(r["MinNs"]) / 1e6, float(r["MaxNs"]) / 1e6,
+            "%.4f" % (sum(eager) / len(eager)) if eager else "", hip))
+    md += ["", "`bench.py`'s class times sum the launches of a class in a step (the fill's y and z passes; the "
+           "Step-1 x sweep's launches); its column sits on the class's first row."]
+    with open(os.path.join(ROOT, "profiles", "turb256_512x32_kernel_stats.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+
+
+# ---------------------------------------------------------------------------
 # CPU baseline (the oracle as it stands)
 # ---------------------------------------------------------------------------
 
@@ -332,11 +552,19 @@ def main():
                     help="also time the FP32 batch with outflow boundaries on every side of the domain")
     ap.add_argument("--frozen", action="store_true",
                     help="also time the FP32 batch with every other patch frozen (checkerboard), graphs reused")
+    ap.add_argument("--no-divb", action="store_true", help="skip the div b against step count runs")
+    ap.add_argument("--planar", action="store_true",
+                    help="also time the planar Orszag-Tang vortex (192^2 and 2048^2) run as one-patch-thin 3D boxes")
     ap.add_argument("--schedule", type=int, default=0,
                     help="captured-step schedule: 1 (concurrent sweep branches), 2 or 3 patch groups; 0 picks by timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
+    ap.add_argument("--summarize-counters", metavar="DIR", default="",
+                    help="no run: summarise the rocprofv3 passes under DIR into profiles/")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: the library runs on one GPU only; --gpus %d is not supported "
@@ -370,7 +598,7 @@ def main():
     q, b = I.turbulence(N)
     G = I.uniform_grid(N, n)
     zones = G.zones()
-    divb_at = (10, 20, 50) if args.prof_steps > 0 else ()
+    divb_at = (10, 20, 50) if args.prof_steps > 0 and not args.no_divb else ()
 
     log("bench: FP32 batch, %d warm-up + %d timed steps" % (args.warmup, args.steps))
     ms32, wall32, kern32, diag32 = run_batch(W, G, q, b, dx, W.WMB_FP32, g, args.steps, args.warmup, args.prof_steps,
@@ -480,6 +708,25 @@ def main():
         log("bench: frozen half: %.3f ms/step, %.3e active zone-updates/s, %.2f ms per set_active" %
             (msf / args.steps, frozen["value"], diagf["freeze_ms_per_patch"]))
 
+    planar = None
+    if args.planar:
+        # planar problems run as 3D boxes one patch thin (5 zones, periodic) across z
+        planar = {"workload": "planar Orszag-Tang vortex as an N x N x 5 box of 32 x 32 x 5 patches, ghost %d, "
+                              "FP32; per planar zone-update and per stored 3D zone-update" % g}
+        for N2 in (192, 2048):
+            G2 = I.patch_grid([32] * (N2 // 32), [32] * (N2 // 32), [5])
+            q2, b2 = I.orszag_tang_2d(N2)
+            log("bench: planar Orszag-Tang %d^2 as %d patches of 32 x 32 x 5" % (N2, G2.npatch))
+            ms2, _, kern2, diag2 = run_batch(W, G2, q2, b2, (1.0 / N2,) * 3, W.WMB_FP32, g, args.steps, args.warmup,
+                                             1)
+            del q2, b2
+            planar[str(N2)] = {"ms_per_step": ms2 / args.steps, "patches": G2.npatch,
+                               "planar_zone_updates_per_s": N2 * N2 * args.steps / (ms2 / 1e3),
+                               "zone_updates_per_s_3d": G2.zones() * args.steps / (ms2 / 1e3),
+                               "kernels_ms": kern2, **diag2}
+            log("bench: planar %d^2: %.3f ms/step, %.3e planar zone-updates/s" %
+                (N2, ms2 / args.steps, planar[str(N2)]["planar_zone_updates_per_s"]))
+
     if not kern32:  # counter-collection runs skip the per-kernel pass
         print(json.dumps({"metric": METRIC, "value": value, "unit": "zone-updates/s", "partial": True}), flush=True)
         return
@@ -521,6 +768,7 @@ def main():
         "protection_fp32": protection,
         "frozen_half_fp32": frozen,
         "outflow_fp32": outflow,
+        "planar_fp32": planar,
         "roofline": roof,
         "cpu_baseline": cpu,
         "bench_wall_s": round(time.perf_counter() - t_start, 1),
