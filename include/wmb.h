@@ -217,10 +217,20 @@ int wmb_debug_stage(wmb_ctx *c, int32_t patch, int32_t stage, double *out);
    issues the next zone's loads one zone ahead (w pencils a block; more
    registers, half the waves).  The choice never
    changes results (both forms compute every face with the same
-   arithmetic).  The interior state is unchanged; ghosts are refreshed and the step
-   intermediates overwritten.  Invalidates the captured graphs.  If chosen !=
-   NULL it receives quadruples (stage, axis, edge, shape), up to nchosen
-   ints, 0-terminated when shorter.  Synchronous. */
+   arithmetic).  It then times the tiles of Steps 3-4 (the widest tile along
+   x: 40, 20 or 13 zones, 256 zones a plane) and of Steps 8-11 (256 or, in
+   FP32, 512 zones a plane), which do not change results either.  The
+   interior state is unchanged; ghosts are refreshed and the step
+   intermediates overwritten.  Invalidates the captured graphs.  The choice
+   is kept for the life of the process under a key of the device
+   architecture, the precision, the ghost width, the limiter and protection
+   variants and the patch extents with their counts: a later call with the
+   same key (on any context) applies it without timing.  reps < 0 times
+   anyway, with -reps repetitions, and replaces the kept choice.  If chosen
+   != NULL it receives quadruples (stage, axis, edge, shape) -- the sweep
+   groups, then (3, 0, 0, Steps 3-4 tile width) and (4, 0, 0, Steps 8-11
+   tile zones) -- up to nchosen ints, 0-terminated when shorter.
+   Synchronous. */
 int wmb_autotune(wmb_ctx *c, int32_t reps, int32_t *chosen, int32_t nchosen);
 
 /* Set the shapes of sweep groups directly: quads of (stage 1|2, axis 0..2,
@@ -232,7 +242,11 @@ int wmb_autotune(wmb_ctx *c, int32_t reps, int32_t *chosen, int32_t nchosen);
    pencil shape exceeds 1024 threads or 64 KiB of LDS, or a marching shape
    is asked for x or beyond 256.  Invalidates the captured graphs.  The
    defaults are the marching form (64 pencils a block) for the y and z
-   sweeps in FP32 and the pencil form elsewhere. */
+   sweeps in FP32 and the pencil form elsewhere.  Tile entries: (3, 0, 0, w)
+   sets the widest Steps 3-4 tile along x to w zones (4..40, default 40);
+   (4, 0, 0, z) the zones of a Steps 8-11 tile plane (256, or 512 in FP32;
+   the default is the one that leaves fewer threads idle).  Every entry is
+   checked before any is applied. */
 int wmb_set_tuning(wmb_ctx *c, const int32_t *quads, int32_t n);
 
 /* Schedule of the captured step (wmb_run_steps).  groups = 1 (the default):
@@ -249,23 +263,48 @@ int wmb_set_tuning(wmb_ctx *c, const int32_t *quads, int32_t n);
 int wmb_set_schedule(wmb_ctx *c, int32_t groups);
 
 /* Freeze (active = 0) or thaw (active != 0) one patch without rebuilding
-   the launch plan (Sect. 2.1: patches may become inactive, left out of the
-   update, for load balancing and mesh refinement; here its pool memory stays
-   reserved).  The captured graphs stay valid, except that the first freeze
-   and the last thaw of a batch whose update runs on 512-zone tiles switch it
-   to its prepared 256-zone tiles and back; the next wmb_run_steps then
-   captures the graphs again.  A frozen
-   patch keeps its state: no kernel updates it, it adds nothing to the CFL
-   maximum or to the floor and protection counters, and it serves its
-   neighbours as fixed ghost data (its work items exit at once).  Its state
-   then reads the same in both internal state copies, which freezing
-   establishes by refreshing every ghost and copying the patch's stored box;
-   wmb_set_state on a frozen patch does the same.  The face it shares with an
-   active neighbour stays the frozen patch's.  Diagnostics still cover every
-   patch.  With every patch frozen the CFL maximum is empty: dt comes out
-   +inf and steps change nothing.  All patches start active.  WMB_EINVAL for
-   a patch index out of range.  Synchronous. */
+   the launch plan or the captured graphs (Sect. 2.1: patches may become
+   inactive, left out of the update, for load balancing and mesh
+   refinement; here its pool memory stays reserved).  A frozen patch keeps
+   its state: no kernel updates it, it adds nothing to the CFL maximum or to
+   the floor and protection counters, and it serves its neighbours as fixed
+   ghost data (its work items exit at once).  Its state then reads the same
+   in both internal state copies, which freezing establishes by refreshing
+   every ghost and copying the patch's stored box; wmb_set_state on a frozen
+   patch does the same.  The face it shares with an active neighbour stays
+   the frozen patch's.  Diagnostics still cover every present patch.  With
+   every patch frozen the CFL maximum is empty: dt comes out +inf and steps
+   change nothing.  All patches start active.  Asynchronous: the work (the
+   ghost refresh, the copy and the patch-table entry) is enqueued on the
+   library's stream, ordered before the next step.  The next call that
+   steps (wmb_advance, wmb_run_steps, wmb_profile_step, wmb_autotune) plans
+   the stage work lists again without the frozen patches, in place (it
+   waits for the stream once): the graphs keep their buffers and grid sizes
+   and stay valid.  WMB_EINVAL for a patch index out of range, WMB_EORDER
+   for an absent patch. */
 int wmb_set_active(wmb_ctx *c, int32_t patch, int32_t active);
+
+/* Remove (present = 0) or add back (present != 0) one patch slot of the
+   table given to wmb_init_patches, without rebuilding the launch plan or
+   the captured graphs (Sect. 2.1: a domain allocates and frees patches, for
+   load balancing and mesh refinement; here the slot's pool memory stays
+   reserved, so the slots are the patches the domain may ever hold).  A
+   removed slot leaves the domain: no kernel reads or writes it, the
+   diagnostics leave it out, and its face neighbours see a domain boundary
+   there (zero-gradient ghosts; edge and corner ghosts still arrive through
+   the x, y, z order of the exchange).  Removal first refreshes every ghost,
+   so the faces the slot shared with its neighbours keep their last values
+   and become those neighbours' own boundary faces.  Adding a slot back links
+   it to its face neighbours of the init table that are present, active;
+   it brings the state the slot holds (set it with wmb_set_state before or
+   after, before the next step).  Each patch owns the faces on its low sides
+   (-x, -y, -z): the added slot's low faces replace its present neighbours'
+   copies at the next exchange and its high faces take theirs, so div b is
+   kept on the shared faces when the given state matches them.
+   Asynchronous (the table entries are enqueued on the library's stream);
+   the work lists are planned again as after wmb_set_active.  All slots
+   start present.  WMB_EINVAL for a patch index out of range. */
+int wmb_set_present(wmb_ctx *c, int32_t patch, int32_t present);
 
 /* Debugging: with on != 0, later steps also store the Step-9 edge EMFs in
    device memory for wmb_debug_stage (the fused Steps 8-11 otherwise keep

@@ -50,6 +50,8 @@ struct PatchDev {
     int N[3];
     int nb[6];   // face neighbours: -x, +x, -y, +y, -z, +z (-1: domain boundary)
     int active;  // 0: frozen (no kernel updates it; its state is the same in both copies)
+    int present; // 0: the slot is absent from the domain (removed: no neighbour links to it,
+                 //    no kernel reads or writes it; also inactive)
     long long base;
     long long vol;
 };

@@ -217,6 +217,7 @@ __global__ void __launch_bounds__(256) fill_pass_kernel(R* __restrict__ pool, co
     const WorkItem w = work[blockIdx.x];
     if (w.patch < 0) return;  // padding item (whole block)
     const PatchDev D = patches[w.patch];
+    if (!D.present) return;  // absent slot
     // along a later pass's axis that ends at a domain boundary on the right,
     // the rows reach the boundary face n the patch owns: that later pass
     // copies the normal face there onto itself, so it must be in place
@@ -1556,7 +1557,8 @@ __global__ void __launch_bounds__(DIAG_THREADS) diag_kernel(const R* __restrict_
 #pragma unroll
     for (int c = 0; c < DIAG_NSUM; c++) acc[c] = DSum{0.0, 0.0};
     double mx = 0.0;
-    for (int z = w.a + (int)threadIdx.x; z < w.a + w.b; z += DIAG_THREADS) {
+    const int zend = P.present ? w.a + w.b : w.a;  // an absent slot adds nothing
+    for (int z = w.a + (int)threadIdx.x; z < zend; z += DIAG_THREADS) {
         const int i = z % P.n[0], t = z / P.n[0];
         const int j = t % P.n[1], k = t / P.n[1];
         const long long x = sidx(P, i + g, j + g, k + g);
@@ -1660,6 +1662,17 @@ hipError_t launch_dt_reduce(void* pool, const PatchDev* pt, const WorkItem* wk, 
 
 hipError_t launch_dt_finalize(unsigned long long* smax, StepConst* sc, const DevParams& prm, hipStream_t st) {
     hipLaunchKernelGGL(dt_finalize_kernel, dim3(1), dim3(1), 0, st, smax, sc, prm);
+    return hipGetLastError();
+}
+
+// one entry of the device patch table, ordered on the stream (freeze, thaw,
+// removal and addition of patches between steps)
+__global__ void set_patch_kernel(PatchDev* __restrict__ table, int idx, PatchDev v) {
+    if (threadIdx.x == 0) table[idx] = v;
+}
+
+hipError_t launch_set_patch(PatchDev* table, int idx, const PatchDev& v, hipStream_t st) {
+    hipLaunchKernelGGL(set_patch_kernel, dim3(1), dim3(64), 0, st, table, idx, v);
     return hipGetLastError();
 }
 

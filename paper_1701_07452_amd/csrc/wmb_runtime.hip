@@ -19,6 +19,7 @@ template <typename R> hipError_t launch_fill(void*, const PatchDev*, const WorkI
 template <typename R> hipError_t launch_dt_reduce(void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, unsigned long long*, hipStream_t);
 hipError_t launch_dt_finalize(unsigned long long*, StepConst*, const DevParams&, hipStream_t);
 hipError_t launch_set_dt(StepConst*, double, const DevParams&, hipStream_t);
+hipError_t launch_set_patch(PatchDev*, int, const PatchDev&, hipStream_t);
 template <typename R> hipError_t launch_ct_half(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int, const StepConst*, hipStream_t);
 template <typename R> hipError_t launch_update(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, unsigned long long*, unsigned long long*, int, int, hipStream_t);
 template <typename R> hipError_t launch_sweep(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, int, int, int, unsigned long long*, hipStream_t);
@@ -80,16 +81,18 @@ struct wmb_ctx {
     int cur = 0;
     PatchDev* d_patch = nullptr;
     DevList wl_fill[3];
-    DevList wl_int, wl_diag, wl_cth, wl_upd, wl_upd256;
+    DevList wl_int, wl_diag, wl_cth, wl_upd;
     // grouped schedule (wmb_set_schedule): ngroups > 1 patch groups (whole
     // x-rows), each running its whole step on its own stream in the graph
     int ngroups = 1;
     std::vector<int> pgroup;  // patch -> step group
-    DevList wl_cth_g[4], wl_upd_g[4], wl_upd256_g[4];
+    DevList wl_cth_g[4], wl_upd_g[4];
     hipStream_t gstream[4] = {};  // group streams 1..3 (group 0 runs on the main stream), borrowed
     hipEvent_t ev_g[4] = {};
     int upd_zones = 256;  // zones a tile plane of Steps 8-11 (the update's block size)
-    int nfrozen = 0;      // frozen patches; while any, Steps 8-11 run on 256-zone tiles
+    int cth_tx = 40;      // widest tile of Steps 3-4 along x (zones; 256 a tile plane)
+    int nfrozen = 0;      // frozen patches
+    bool plan_dirty = false;  // the active set changed since the stage work lists were planned
     bool keep_edges = false;  // Steps 8-11 also store the Step-9 edges (debugging)
     bool xg_valid = false;    // the current copy's x-ghosts (interior rows) hold the neighbours' values
     bool edges_kept = false;  // the last step stored them
@@ -463,13 +466,8 @@ int run_step(wmb_ctx* c, bool split = false) {
             mark(c);
         }
     }
-    // with frozen patches the 256-zone tiles (whose blocks of frozen patches
-    // exit at once) measured faster: 1.01 against 1.56 ms with every other
-    // patch of 256^3 FP32 frozen, against 1.19 and 1.14 ms with all active
-    const bool t256 = c->nfrozen > 0 && c->upd_zones != 256;
-    const DevList& wu = t256 ? c->wl_upd256 : c->wl_upd;
-    e = launch_update<R>(c->pool, c->d_patch, wu.d, wu.n, c->dp, coef<R>(c), cur, c->d_sc, c->d_nfloor, c->d_smax,
-                         c->keep_edges ? 1 : 0, t256 ? 256 : c->upd_zones, c->stream);
+    e = launch_update<R>(c->pool, c->d_patch, c->wl_upd.d, c->wl_upd.n, c->dp, coef<R>(c), cur, c->d_sc, c->d_nfloor,
+                         c->d_smax, c->keep_edges ? 1 : 0, c->upd_zones, c->stream);
     STEPCK("update");
     mark(c);
     c->edges_kept = c->keep_edges;
@@ -493,7 +491,6 @@ int run_step_grouped(wmb_ctx* c) {
     const int cur = c->cur;
     CKH(hipEventRecord(c->ev_fork, c->stream));
     for (int g = 1; g < c->ngroups; g++) CKH(hipStreamWaitEvent(c->gstream[g], c->ev_fork, 0));
-    const bool t256 = c->nfrozen > 0 && c->upd_zones != 256;
     for (int g = 0; g < c->ngroups; g++) {
         hipStream_t st = g == 0 ? c->stream : c->gstream[g];
         hipError_t e = hipSuccess;
@@ -505,10 +502,10 @@ int run_step_grouped(wmb_ctx* c) {
                 e = launch_ct_half<R>(c->pool, c->d_patch, c->wl_cth_g[g].d, c->wl_cth_g[g].n, coef<R>(c), c->p.ghost,
                                       cur, c->d_sc, st);
         }
-        const DevList& wu = t256 ? c->wl_upd256_g[g] : c->wl_upd_g[g];
+        const DevList& wu = c->wl_upd_g[g];
         if (e == hipSuccess)
             e = launch_update<R>(c->pool, c->d_patch, wu.d, wu.n, c->dp, coef<R>(c), cur, c->d_sc, c->d_nfloor, c->d_smax,
-                                 c->keep_edges ? 1 : 0, t256 ? 256 : c->upd_zones, st);
+                                 c->keep_edges ? 1 : 0, c->upd_zones, st);
         if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("grouped step: ") + hipGetErrorString(e));
         if (g > 0) CKH(hipEventRecord(c->ev_g[g], st));
     }
@@ -593,8 +590,11 @@ std::vector<int> x_rows(const wmb_ctx* c) {
         if (row[p] >= 0) continue;
         std::vector<int> members{p};
         seen[p] = p;
-        for (int dir = 0; dir < 2; dir++)  // walk -x, then +x
-            for (int q = c->hpatch[p].nb[dir]; q >= 0 && seen[q] != p; q = c->hpatch[q].nb[dir]) {
+        // walk -x, then +x, along the init table's links (a row stays one
+        // unit while patches of it are removed and added again)
+        const int fx[2] = {12, 14};
+        for (int dir = 0; dir < 2; dir++)
+            for (int q = c->desc[p].nbr[fx[dir]]; q >= 0 && seen[q] != p; q = c->desc[q].nbr[fx[dir]]) {
                 seen[q] = p;
                 members.push_back(q);
             }
@@ -604,11 +604,16 @@ std::vector<int> x_rows(const wmb_ctx* c) {
     return row;
 }
 
-int build_tile_list(wmb_ctx* c, int lo, int hi, int zlo, int zhi, int txmax_allowed, int maxz,
-                    const std::vector<int>* group, DevList& out, int sgroup = -1) {
+// The stage work lists (sweeps, Steps 3-4, Steps 8-11) cover the present,
+// active patches; frozen and absent ones are left out when the lists are
+// planned again (replan), so their blocks are not launched at all.
+bool in_plan(const wmb_ctx* c, int p) { return c->hpatch[p].present && c->hpatch[p].active; }
+
+std::vector<WorkItem> tile_items(const wmb_ctx* c, int lo, int hi, int zlo, int zhi, int txmax_allowed, int maxz,
+                                 const std::vector<int>* group, int sgroup = -1) {
     std::vector<WorkItem> items;
     for (int p = 0; p < c->npatch; p++) {
-        if (sgroup >= 0 && c->pgroup[p] != sgroup) continue;
+        if (!in_plan(c, p) || (sgroup >= 0 && c->pgroup[p] != sgroup)) continue;
         const int* n = c->desc[p].n;
         const int ex = n[0] + hi - lo + 1, ey = n[1] + hi - lo + 1;
         const int mx = (ex + txmax_allowed - 1) / txmax_allowed;
@@ -626,7 +631,12 @@ int build_tile_list(wmb_ctx* c, int lo, int hi, int zlo, int zhi, int txmax_allo
             }
         }
     }
-    items = xcd_order(items, group, true);
+    return xcd_order(items, group, true);
+}
+
+int build_tile_list(wmb_ctx* c, int lo, int hi, int zlo, int zhi, int txmax_allowed, int maxz,
+                    const std::vector<int>* group, DevList& out, int sgroup = -1) {
+    std::vector<WorkItem> items = tile_items(c, lo, hi, zlo, zhi, txmax_allowed, maxz, group, sgroup);
     out.n = (int)items.size();
     return upload(c, &out.d, items);
 }
@@ -655,6 +665,37 @@ int choose_upd_zones(const wmb_ctx* c) {
     return fill[1] >= fill[0] ? zmax : 256;
 }
 
+// The tile lists of Steps 3-4 and 8-11 for the current cth_tx and
+// upd_zones: Steps 3-4 tiles up to cth_tx zones wide and 256 a plane
+// ((tx+1)(ty+1) <= 297 edges for any tx <= 40); Steps 8-11 tiles up to 32
+// wide and upd_zones a plane (the LDS planes of the kernel are sized for
+// the largest).  The update
+// and the ghost exchange place whole x-rows of patches on an XCD, so that
+// the update's x-ghost pushes go to a patch on the same XCD: 256^3 FP32
+// update 1.14 against 1.24 ms, the uneven batch 1.80 against 2.04 ms, at the
+// same measured HBM traffic (orders that put x-neighbours on other XCDs
+// measured 1.24 ms at 256^3).  The sweeps keep one patch a unit, which
+// measured faster for them.  With a grouped schedule, the lists of every
+// group as well.
+int build_ct_update_lists(wmb_ctx* c) {
+    for (DevList* L : {&c->wl_cth, &c->wl_upd}) {
+        release(c, L->d);
+        *L = DevList{};
+    }
+    const std::vector<int> rows = x_rows(c);
+    int rc = build_tile_list(c, -2, 2, -2, 2, c->cth_tx, 256, nullptr, c->wl_cth);
+    if (!rc) rc = build_tile_list(c, 0, -1, 0, -1, 32, c->upd_zones, &rows, c->wl_upd);
+    for (int g = 0; g < c->ngroups && c->ngroups > 1 && !rc; g++) {
+        for (DevList* L : {&c->wl_cth_g[g], &c->wl_upd_g[g]}) {
+            release(c, L->d);
+            *L = DevList{};
+        }
+        rc = build_tile_list(c, -2, 2, -2, 2, c->cth_tx, 256, nullptr, c->wl_cth_g[g], g);
+        if (!rc) rc = build_tile_list(c, 0, -1, 0, -1, 32, c->upd_zones, &rows, c->wl_upd_g[g], g);
+    }
+    return rc;
+}
+
 int build_fill_lists(wmb_ctx* c) {
     const int g = c->p.ghost;
     const std::vector<int> rows = x_rows(c);
@@ -663,8 +704,10 @@ int build_fill_lists(wmb_ctx* c) {
         for (int p = 0; p < c->npatch; p++) {
             const int* n = c->desc[p].n;
             // rows reach the owned boundary face along a later axis that ends
-            // at a domain boundary on the right (the kernel's extents)
-            const int wy = c->hpatch[p].nb[3] < 0, wz = c->hpatch[p].nb[5] < 0;
+            // at a domain boundary on the right; the kernel takes its extents
+            // from the patch table, so the list covers the longer rows always
+            // (removing or adding a neighbour then needs no new list)
+            const int wy = 1, wz = 1;
             long long e;
             if (ax == 0) e = 2LL * g * (n[1] + wy) * (n[2] + wz);
             else if (ax == 1) e = 2LL * g * (n[0] + 2 * g) * (n[2] + wz);
@@ -713,8 +756,9 @@ enum SweepPart { PART_ALL, PART_INTERIOR, PART_FRAME };
 
 // pencils of every patch whose edge along d is n, W consecutive pencils of one
 // rectangle a block
+// *bad is set when a pencil rectangle does not fit the packed fields
 std::vector<WorkItem> sweep_items(const wmb_ctx* c, int d, int n, int tlo, int thi, int W, SweepPart part = PART_ALL,
-                                  int group = -1) {
+                                  int group = -1, bool* bad = nullptr) {
     const int FA = (d == 0) ? 1 : 0;
     const int SA = (d == 0) ? 2 : (d == 1 ? 2 : 1);
     struct Rect {
@@ -722,7 +766,7 @@ std::vector<WorkItem> sweep_items(const wmb_ctx* c, int d, int n, int tlo, int t
     };
     std::vector<WorkItem> items;
     for (int p = 0; p < c->npatch; p++) {
-        if (c->desc[p].n[d] != n) continue;
+        if (c->desc[p].n[d] != n || !in_plan(c, p)) continue;
         if (group >= 0 && c->pgroup[p] != group) continue;
         const int nf = c->desc[p].n[FA], ns = c->desc[p].n[SA];
         const int tf = nf + thi - tlo + 1;
@@ -739,7 +783,10 @@ std::vector<WorkItem> sweep_items(const wmb_ctx* c, int d, int n, int tlo, int t
             const int npen = r.fcnt * r.scnt;
             if (npen <= 0) continue;
             // the packed fields (check_table bounds the edges so that they fit)
-            if (r.flo < -512 || r.flo > 511 || r.slo < -512 || r.slo > 511 || r.fcnt > 2047) return {};
+            if (r.flo < -512 || r.flo > 511 || r.slo < -512 || r.slo > 511 || r.fcnt > 2047) {
+                if (bad) *bad = true;
+                return {};
+            }
             const int code = (r.flo + 512) | ((r.slo + 512) << 10) | (r.fcnt << 20);
             for (int p0 = 0; p0 < npen; p0 += W)
                 items.push_back(WorkItem{p, p0, code, (p0 + W - 1 < npen - 1) ? p0 + W - 1 : npen - 1});
@@ -753,8 +800,9 @@ std::vector<WorkItem> sweep_items(const wmb_ctx* c, int d, int n, int tlo, int t
 // replace are freed.
 int set_group_W(wmb_ctx* c, int d, int stage, SweepGroup& G, int W) {
     auto rebuild = [&](DevList& L, SweepPart part) -> int {
-        std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, W < 0 ? (-W) % 512 : W, part);
-        if (items.empty()) return fail(c, WMB_EINVAL, "sweep work list: pencil rectangle outside the packed range");
+        bool bad = false;
+        std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, W < 0 ? (-W) % 512 : W, part, -1, &bad);
+        if (bad) return fail(c, WMB_EINVAL, "sweep work list: pencil rectangle outside the packed range");
         WorkItem* nd = nullptr;
         int rc = upload(c, &nd, items);
         if (rc) return rc;
@@ -823,6 +871,56 @@ void free_graphs(wmb_ctx* c) {
         c->graph[i] = nullptr;
     }
 }
+
+// Plan the stage work lists again for the current active set (after a
+// freeze, thaw, removal or addition), in place: a list whose items still fit
+// its buffer keeps the buffer and its length (the rest padded with empty
+// items, whose blocks exit at once), so the captured graphs, which hold the
+// buffers and the grid sizes, stay valid.  Only a list that outgrows its
+// buffer (a thaw after the tiles were re-planned smaller) is reallocated,
+// and then the graphs are captured again.  Dropping the inactive patches'
+// items keeps the blocks that run spread over the CUs: where a launch's
+// blocks are all resident at once (the 512-zone Steps 8-11 tiles at 32^3),
+// a checkerboard of frozen patches otherwise left every fourth pair of
+// block ids, and with them whole CUs, without work.
+int replan(wmb_ctx* c) {
+    c->plan_dirty = false;
+    CKH(hipStreamSynchronize(c->stream));  // no launch in flight reads the lists
+    bool regrid = false;
+    auto put = [&](DevList& L, std::vector<WorkItem> items) -> int {
+        if (L.d && items.size() <= (size_t)L.n) {
+            items.resize((size_t)L.n, WorkItem{-1, 0, 0, 0});
+            if (L.n > 0) CKH(hipMemcpy(L.d, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
+            return WMB_OK;
+        }
+        release(c, L.d);
+        L = DevList{};
+        regrid = true;
+        L.n = (int)items.size();
+        return upload(c, &L.d, items);
+    };
+    int rc = WMB_OK;
+    for (int d = 0; d < 3 && !rc; d++)
+        for (int stage = 0; stage < 2 && !rc; stage++)
+            for (auto& G : c->sweeps[d][stage]) {
+                const int W = G.W < 0 ? (-G.W) % 512 : G.W;
+                if (!rc) rc = put(G.wl, sweep_items(c, d, G.n, G.tlo, G.thi, W, PART_ALL));
+                for (int g = 0; g < c->ngroups && c->ngroups > 1 && !rc; g++)
+                    rc = put(G.wlg[g], sweep_items(c, d, G.n, G.tlo, G.thi, W, PART_ALL, g));
+                if (!rc && d == 0 && stage == 0) rc = put(G.wl_in, sweep_items(c, d, G.n, G.tlo, G.thi, W, PART_INTERIOR));
+                if (!rc && d == 0 && stage == 0) rc = put(G.wl_fr, sweep_items(c, d, G.n, G.tlo, G.thi, W, PART_FRAME));
+            }
+    const std::vector<int> rows = x_rows(c);
+    if (!rc) rc = put(c->wl_cth, tile_items(c, -2, 2, -2, 2, c->cth_tx, 256, nullptr));
+    if (!rc) rc = put(c->wl_upd, tile_items(c, 0, -1, 0, -1, 32, c->upd_zones, &rows));
+    for (int g = 0; g < c->ngroups && c->ngroups > 1 && !rc; g++) {
+        rc = put(c->wl_cth_g[g], tile_items(c, -2, 2, -2, 2, c->cth_tx, 256, nullptr, g));
+        if (!rc) rc = put(c->wl_upd_g[g], tile_items(c, 0, -1, 0, -1, 32, c->upd_zones, &rows, g));
+    }
+    if (regrid) free_graphs(c);
+    return rc;
+}
+
 
 // One graph per state copy: fill ghosts, dt = cfl / smax, step (whose final
 // update refills smax for the next replay).  Replays require smax to hold the
@@ -1037,9 +1135,11 @@ int autotune_t(wmb_ctx* c, int reps) {
     if (rc) return rc;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     WorkItem* dl = nullptr;  // the candidate list of one timing
+    WorkItem* tl = nullptr;  // a candidate tile list (library-owned)
     // every exit below goes through cleanup
     auto cleanup = [&](int code) -> int {
         if (dl) (void)hipFree(dl);
+        if (tl) release(c, tl);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         return code;
@@ -1085,7 +1185,7 @@ int autotune_t(wmb_ctx* c, int reps) {
                     if (items.empty()) continue;
                     CKT(hipMalloc(&dl, sizeof(WorkItem) * items.size()));
                     CKT(hipMemcpy(dl, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
-                    float tot = 0.f;
+                    float tot = 1e30f;  // the fastest of the timed launches
                     hipError_t e = hipSuccess;
                     for (int r = 0; r <= reps && e == hipSuccess; r++) {
                         CKT(hipEventRecord(e0, c->stream));
@@ -1097,7 +1197,7 @@ int autotune_t(wmb_ctx* c, int reps) {
                         CKT(hipEventSynchronize(e1));
                         float t = 0.f;
                         CKT(hipEventElapsedTime(&t, e0, e1));
-                        if (r > 0) tot += t;  // first launch is a warm-up
+                        if (r > 0) tot = std::min(tot, t);  // first launch is a warm-up
                     }
                     (void)hipFree(dl);
                     dl = nullptr;
@@ -1125,7 +1225,7 @@ int autotune_t(wmb_ctx* c, int reps) {
     for (int stage = 0; stage < 2; stage++) {
         auto time_stage = [&](float* ms) -> int {
             hipError_t e = hipSuccess;
-            float tot = 0.f;
+            float tot = 1e30f;
             for (int r = 0; r <= reps && e == hipSuccess; r++) {
                 CKT(hipEventRecord(e0, c->stream));
                 CKT(hipEventRecord(c->ev_br[5], c->stream));
@@ -1143,7 +1243,7 @@ int autotune_t(wmb_ctx* c, int reps) {
                 CKT(hipEventSynchronize(e1));
                 float t = 0.f;
                 CKT(hipEventElapsedTime(&t, e0, e1));
-                if (r > 0) tot += t;
+                if (r > 0) tot = std::min(tot, t);
             }
             if (e != hipSuccess) return cleanup(fail(c, WMB_EHIP, std::string("autotune: ") + hipGetErrorString(e)));
             *ms = tot;
@@ -1188,9 +1288,103 @@ int autotune_t(wmb_ctx* c, int reps) {
                     if (!rc2) rc2 = set_group_W(c, d, stage, G, choice == 1 ? G.Wp : G.Wm);
         if (rc2) return cleanup(rc2);
     }
+    // The tiles of Steps 3-4 (widest tile along x) and of Steps 8-11 (zones
+    // a tile plane): time each candidate's whole launch.  The intermediates
+    // they read are those the stage-2 timings left; the update writes only
+    // the other state copy (and the x-ghosts there), its floor count and
+    // signal-speed maximum go to the sinks, so nothing the next step reads
+    // changes.
+    {
+        const std::vector<int> rows = x_rows(c);
+        auto time_tiles = [&](int kind, int v, float* ms) -> int {
+            DevList L;
+            int rc3 = kind == 0 ? build_tile_list(c, -2, 2, -2, 2, v, 256, nullptr, L)
+                                : build_tile_list(c, 0, -1, 0, -1, 32, v, &rows, L);
+            if (rc3) return cleanup(rc3);
+            tl = L.d;  // released by cleanup on an error exit
+            hipError_t e = hipSuccess;
+            float tot = 1e30f;
+            for (int r = 0; r <= reps && e == hipSuccess; r++) {
+                CKT(hipEventRecord(e0, c->stream));
+                e = kind == 0 ? launch_ct_half<R>(c->pool, c->d_patch, L.d, L.n, coef<R>(c), c->p.ghost, c->cur, c->d_sc,
+                                                  c->stream)
+                              : launch_update<R>(c->pool, c->d_patch, L.d, L.n, c->dp, coef<R>(c), c->cur, c->d_sc,
+                                                 c->d_nfloor + 2, c->d_smax + 2, 0, v, c->stream);
+                CKT(hipEventRecord(e1, c->stream));
+                CKT(hipEventSynchronize(e1));
+                float t = 0.f;
+                CKT(hipEventElapsedTime(&t, e0, e1));
+                if (r > 0) tot = std::min(tot, t);
+            }
+            if (e != hipSuccess) return cleanup(fail(c, WMB_EHIP, std::string("autotune: ") + hipGetErrorString(e)));
+            tl = nullptr;
+            release(c, L.d);
+            *ms = tot;
+            return WMB_OK;
+        };
+        const int cth_opts[] = {40, 20, 13};
+        const int upd_opts[] = {256, upd_tile_zones_max((int)es)};
+        int best_tx = c->cth_tx, best_z = c->upd_zones;
+        float bt = 1e30f, bz = 1e30f;
+        for (int v : cth_opts) {
+            float t = 0.f;
+            int rc3 = time_tiles(0, v, &t);
+            if (rc3) return rc3;
+            if (t < bt) bt = t, best_tx = v;
+        }
+        for (int k = 0; k < 2; k++) {
+            if (k == 1 && upd_opts[1] == upd_opts[0]) break;
+            float t = 0.f;
+            int rc3 = time_tiles(1, upd_opts[k], &t);
+            if (rc3) return rc3;
+            if (t < bz) bz = t, best_z = upd_opts[k];
+        }
+        if (best_tx != c->cth_tx || best_z != c->upd_zones) {
+            c->cth_tx = best_tx;
+            c->upd_zones = best_z;
+            int rc3 = build_ct_update_lists(c);
+            if (rc3) return cleanup(rc3);
+        }
+    }
 #undef CKT
     free_graphs(c);  // launch plans changed
     return cleanup(WMB_OK);
+}
+
+// Autotune choices kept for the life of the process, keyed by what decides
+// the timings: the device architecture, the precision, the ghost width, the
+// limiter and protection variants of the sweeps, and the patch extents with
+// their counts.  A value is the quadruples wmb_autotune reports.
+std::mutex tune_mu;
+std::vector<std::pair<std::string, std::vector<int32_t>>> tune_cache;
+
+std::string tune_key(const wmb_ctx* c) {
+    hipDeviceProp_t prop;
+    std::string arch = hipGetDeviceProperties(&prop, c->device) == hipSuccess ? prop.gcnArchName : "?";
+    std::vector<std::string> ext;
+    for (const auto& d : c->desc)
+        ext.push_back(std::to_string(d.n[0]) + "x" + std::to_string(d.n[1]) + "x" + std::to_string(d.n[2]));
+    std::sort(ext.begin(), ext.end());
+    std::string key = arch + "|" + std::to_string(c->esize) + "|" + std::to_string(c->p.ghost) + "|" +
+                      (c->p.limiter_beta == 1.0 ? "mm" : "sweby") + "|" +
+                      ((c->p.rho_protect > 0.0 || c->p.p_protect > 0.0) ? "prot" : "plain");
+    for (size_t i = 0; i < ext.size();) {
+        size_t j = i;
+        while (j < ext.size() && ext[j] == ext[i]) j++;
+        key += "|" + ext[i] + "*" + std::to_string(j - i);
+        i = j;
+    }
+    return key;
+}
+
+std::vector<int32_t> tuning_quads(const wmb_ctx* c) {
+    std::vector<int32_t> q;
+    for (int stage = 0; stage < 2; stage++)
+        for (int d = 0; d < 3; d++)
+            for (const auto& G : c->sweeps[d][stage]) q.insert(q.end(), {stage + 1, d, G.n, G.W});
+    q.insert(q.end(), {3, 0, 0, c->cth_tx});
+    q.insert(q.end(), {4, 0, 0, c->upd_zones});
+    return q;
 }
 
 // ---------------------------------------------------------------------------
@@ -1342,6 +1536,7 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
         const int faces[6] = {12, 14, 10, 16, 4, 22};
         for (int t = 0; t < 6; t++) P.nb[t] = d[i].nbr[faces[t]];
         P.active = 1;
+        P.present = 1;
         off += region_bytes(d[i], g, c->esize);
     }
     int rc;
@@ -1349,23 +1544,14 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     if ((rc = build_fill_lists(c))) return rc;
     if ((rc = build_box_list(c, BOX_INTERIOR, c->wl_int))) return rc;
     if ((rc = build_diag_list(c))) return rc;
-    // Steps 3-4: tiles up to 40 zones wide and 256 a plane ((tx+1)(ty+1) <= 297
-    // edges); Steps 8-11: up to 32 wide and upd_tile_zones a plane (the LDS
-    // planes of the kernel are sized for both)
-    if ((rc = build_tile_list(c, -2, 2, -2, 2, 40, 256, nullptr, c->wl_cth))) return rc;
+    c->cth_tx = 40;
     c->upd_zones = choose_upd_zones(c);
-    // the update and the ghost exchange place whole x-rows of patches on an
-    // XCD, so that the update's x-ghost pushes go to a patch on the same XCD:
-    // 256^3 FP32 update 1.14 against 1.24 ms, the uneven batch 1.80 against
-    // 2.04 ms, at the same measured HBM traffic (orders that put x-neighbours
-    // on other XCDs measured 1.24 ms at 256^3).  The sweeps keep one patch a
-    // unit, which measured faster for them.
-    const std::vector<int> rows = x_rows(c);
-    if ((rc = build_tile_list(c, 0, -1, 0, -1, 32, c->upd_zones, &rows, c->wl_upd))) return rc;
-    if (c->upd_zones != 256 && (rc = build_tile_list(c, 0, -1, 0, -1, 32, 256, &rows, c->wl_upd256))) return rc;
+    if ((rc = build_ct_update_lists(c))) return rc;
     c->nfrozen = 0;
     if ((rc = build_sweeps(c))) return rc;
-    if ((rc = dev_alloc(c, &c->d_smax, 2))) return rc;
+    // the signal-speed maxima of the current and the previous state, and a
+    // sink for tuning runs
+    if ((rc = dev_alloc(c, &c->d_smax, 3))) return rc;
     if ((rc = dev_alloc(c, &c->d_sc, 1))) return rc;
     // counters: floor activations, protected faces, and a sink for tuning runs
     if ((rc = dev_alloc(c, &c->d_nfloor, 3))) return rc;
@@ -1374,7 +1560,7 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     c->nzones = 0;
     for (int p = 0; p < npatch; p++) c->nzones += (long long)d[p].n[0] * d[p].n[1] * d[p].n[2];
     if ((rc = bind_scratch(c))) return rc;
-    CKH(hipMemsetAsync(c->d_smax, 0, 2 * sizeof(unsigned long long), c->stream));
+    CKH(hipMemsetAsync(c->d_smax, 0, 3 * sizeof(unsigned long long), c->stream));
     CKH(hipMemsetAsync(c->d_sc, 0, sizeof(StepConst), c->stream));
     CKH(hipMemsetAsync(c->d_nfloor, 0, 3 * sizeof(unsigned long long), c->stream));
     CKH(hipStreamSynchronize(c->stream));
@@ -1392,7 +1578,7 @@ int wmb_set_state(wmb_ctx* c, int32_t patch, const double* q, const double* b) {
     if (patch < 0 || patch >= c->npatch || !q || !b) return fail(c, WMB_EINVAL, "bad patch or null array");
     c->xg_valid = false;  // the neighbours' x-ghosts of this patch are stale
     int rc = c->esize == 4 ? set_state_t<float>(c, patch, q, b) : set_state_t<double>(c, patch, q, b);
-    if (!rc && !c->hpatch[patch].active) rc = freeze_sync(c, patch);
+    if (!rc && c->hpatch[patch].present && !c->hpatch[patch].active) rc = freeze_sync(c, patch);
     return rc;
 }
 
@@ -1431,6 +1617,10 @@ int wmb_compute_dt(wmb_ctx* c, double* dt_out) {
 int wmb_advance(wmb_ctx* c, double dt) {
     if (!c) return WMB_EINVAL;
     if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
+    if (c->plan_dirty) {
+        int rc = replan(c);
+        if (rc) return rc;
+    }
     if (dt > 0.0) {
         if (!std::isfinite(dt)) return fail(c, WMB_EINVAL, "non-finite dt");
         // the limit of the current state: an explicit reduction (the maximum
@@ -1450,6 +1640,10 @@ int wmb_run_steps(wmb_ctx* c, int32_t nsteps) {
     if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
     if (nsteps < 0) return fail(c, WMB_EINVAL, "nsteps < 0");
     if (nsteps == 0) return WMB_OK;
+    if (c->plan_dirty) {
+        int rc = replan(c);
+        if (rc) return rc;
+    }
     if (!c->gexec[0]) {
         int rc = capture_graphs(c);
         if (rc) {
@@ -1499,20 +1693,37 @@ int wmb_debug_stage(wmb_ctx* c, int32_t patch, int32_t stage, double* out) {
 int wmb_autotune(wmb_ctx* c, int32_t reps, int32_t* chosen, int32_t nchosen) {
     if (!c) return WMB_EINVAL;
     if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
-    if (reps < 1) reps = 1;
-    int rc = c->esize == 4 ? autotune_t<float>(c, reps) : autotune_t<double>(c, reps);
-    if (rc) return rc;
+    if (c->plan_dirty) {
+        int rc = replan(c);
+        if (rc) return rc;
+    }
+    const std::string key = tune_key(c);
+    std::vector<int32_t> q;
+    if (reps >= 0) {
+        std::lock_guard<std::mutex> lk(tune_mu);
+        for (const auto& kv : tune_cache)
+            if (kv.first == key) q = kv.second;
+    }
+    if (!q.empty()) {
+        int rc = wmb_set_tuning(c, q.data(), (int32_t)q.size());
+        if (rc) return rc;
+    } else {
+        int r = reps < 0 ? -reps : reps;
+        int rc = c->esize == 4 ? autotune_t<float>(c, r < 1 ? 1 : r) : autotune_t<double>(c, r < 1 ? 1 : r);
+        if (rc) return rc;
+        q = tuning_quads(c);
+        std::lock_guard<std::mutex> lk(tune_mu);
+        bool found = false;
+        for (auto& kv : tune_cache)
+            if (kv.first == key) kv.second = q, found = true;
+        if (!found) tune_cache.emplace_back(key, q);
+    }
     if (chosen) {
         int k = 0;
-        for (int stage = 0; stage < 2; stage++)
-            for (int d = 0; d < 3; d++)
-                for (auto& G : c->sweeps[d][stage]) {
-                    if (k + 4 > nchosen) return WMB_OK;
-                    chosen[k++] = stage + 1;
-                    chosen[k++] = d;
-                    chosen[k++] = G.n;
-                    chosen[k++] = G.W;
-                }
+        for (int32_t v : q) {
+            if (k >= nchosen) return WMB_OK;
+            chosen[k++] = v;
+        }
         if (k < nchosen) chosen[k] = 0;
     }
     return WMB_OK;
@@ -1521,17 +1732,41 @@ int wmb_autotune(wmb_ctx* c, int32_t reps, int32_t* chosen, int32_t nchosen) {
 int wmb_set_tuning(wmb_ctx* c, const int32_t* quads, int32_t n) {
     if (!c || (!quads && n > 0) || n < 0 || n % 4) return WMB_EINVAL;
     if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
+    // check every entry before applying any
     for (int k = 0; k + 4 <= n; k += 4) {
         const int stage = quads[k], d = quads[k + 1], edge = quads[k + 2], W = quads[k + 3];
+        if (stage == 3 || stage == 4) {
+            if (d != 0 || edge != 0) return fail(c, WMB_EINVAL, "tuning entry: tile entries have axis 0 and edge 0");
+            if (stage == 3 && (W < 4 || W > 40))
+                return fail(c, WMB_EINVAL, "tuning entry: Steps 3-4 tiles are 4 to 40 zones wide");
+            if (stage == 4 && W != 256 && W != upd_tile_zones_max((int)c->esize))
+                return fail(c, WMB_EINVAL, "tuning entry: Steps 8-11 tiles hold 256 zones a plane (512 in FP32)");
+            continue;
+        }
         if (stage < 1 || stage > 2 || d < 0 || d > 2 || W == 0) return fail(c, WMB_EINVAL, "bad tuning entry");
-        for (auto& G : c->sweeps[d][stage - 1]) {
-            if (G.n != edge) continue;
-            if (!shape_ok(d, G.P, c->esize, W, stage))
+        for (auto& G : c->sweeps[d][stage - 1])
+            if (G.n == edge && !shape_ok(d, G.P, c->esize, W, stage))
                 return fail(c, WMB_EINVAL, "tuning entry: the marching form serves y and z with at most 256 pencils "
                                            "a block; the pencil form must fit 1024 threads and 64 KiB of LDS");
+    }
+    bool tiles = false;
+    for (int k = 0; k + 4 <= n; k += 4) {
+        const int stage = quads[k], d = quads[k + 1], edge = quads[k + 2], W = quads[k + 3];
+        if (stage == 3 || stage == 4) {
+            int& v = stage == 3 ? c->cth_tx : c->upd_zones;
+            tiles = tiles || v != W;
+            v = W;
+            continue;
+        }
+        for (auto& G : c->sweeps[d][stage - 1]) {
+            if (G.n != edge) continue;
             int rc = set_group_W(c, d, stage - 1, G, W);
             if (rc) return rc;
         }
+    }
+    if (tiles) {
+        int rc = build_ct_update_lists(c);
+        if (rc) return rc;
     }
     free_graphs(c);
     return WMB_OK;
@@ -1570,18 +1805,7 @@ int wmb_set_schedule(wmb_ctx* c, int32_t groups) {
                 int rc = set_group_W(c, d, stage, SG, SG.W);
                 if (rc) return rc;
             }
-    const std::vector<int> rows = x_rows(c);
-    for (int g = 0; g < groups; g++) {
-        for (DevList* L : {&c->wl_cth_g[g], &c->wl_upd_g[g], &c->wl_upd256_g[g]}) {
-            release(c, L->d);
-            *L = DevList{};
-        }
-        int rc = build_tile_list(c, -2, 2, -2, 2, 40, 256, nullptr, c->wl_cth_g[g], g);
-        if (!rc) rc = build_tile_list(c, 0, -1, 0, -1, 32, c->upd_zones, &rows, c->wl_upd_g[g], g);
-        if (!rc && c->upd_zones != 256) rc = build_tile_list(c, 0, -1, 0, -1, 32, 256, &rows, c->wl_upd256_g[g], g);
-        if (rc) return rc;
-    }
-    return WMB_OK;
+    return build_ct_update_lists(c);
 }
 
 // A frozen patch reads the same in both state copies, ghosts included, so
@@ -1597,7 +1821,12 @@ int freeze_sync(wmb_ctx* c, int patch) {
     const long long cur0 = (long long)(c->cur ? F_ST1 : F_ST0), oth0 = (long long)(c->cur ? F_ST0 : F_ST1);
     CKH(hipMemcpyAsync(pool + (P.base + oth0 * P.vol) * c->esize, pool + (P.base + cur0 * P.vol) * c->esize, bytes,
                        hipMemcpyDeviceToDevice, c->stream));
-    CKH(hipStreamSynchronize(c->stream));
+    return WMB_OK;
+}
+
+// the device copy of one patch-table entry, ordered on the library stream
+int push_patch(wmb_ctx* c, int patch) {
+    CKH(launch_set_patch(c->d_patch, patch, c->hpatch[patch], c->stream));
     return WMB_OK;
 }
 
@@ -1606,6 +1835,7 @@ int wmb_set_active(wmb_ctx* c, int32_t patch, int32_t active) {
     if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
     if (patch < 0 || patch >= c->npatch) return fail(c, WMB_EINVAL, "bad patch");
     PatchDev& P = c->hpatch[patch];
+    if (!P.present) return fail(c, WMB_EORDER, "patch is absent (wmb_set_present)");
     const int on = active != 0;
     if (P.active == on) return WMB_OK;
     if (!on) {
@@ -1613,15 +1843,71 @@ int wmb_set_active(wmb_ctx* c, int32_t patch, int32_t active) {
         if (rc) return rc;
     }
     P.active = on;
-    CKH(hipMemcpyAsync(c->d_patch + patch, &P, sizeof(PatchDev), hipMemcpyHostToDevice, c->stream));
-    CKH(hipStreamSynchronize(c->stream));
-    // the first freeze and the last thaw switch the Steps 8-11 tiles (the
-    // captured graphs hold the launch, so they are captured again)
+    int rc = push_patch(c, patch);
+    if (rc) return rc;
     c->nfrozen += on ? -1 : 1;
-    if (c->upd_zones != 256 && c->nfrozen == (on ? 0 : 1)) free_graphs(c);
+    c->plan_dirty = true;
     // the folded signal-speed maximum no longer covers the active set
     if (c->smax_state == SMAX_CLEAN) c->smax_state = SMAX_DIRTY;
     c->xg_valid = false;
+    return WMB_OK;
+}
+
+// Face t of the patch table (-x, +x, -y, +y, -z, +z) in the init table's 27
+// entries.
+constexpr int kFaceEntry[6] = {12, 14, 10, 16, 4, 22};
+
+int wmb_set_present(wmb_ctx* c, int32_t patch, int32_t present) {
+    if (!c) return WMB_EINVAL;
+    if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
+    if (patch < 0 || patch >= c->npatch) return fail(c, WMB_EINVAL, "bad patch");
+    PatchDev& P = c->hpatch[patch];
+    const int on = present != 0;
+    if (P.present == on) return WMB_OK;
+    std::vector<int> touched{patch};
+    if (!on) {
+        // bring every ghost and shared face up to date first (the faces the
+        // slot shares with its neighbours keep these values and become the
+        // neighbours' own boundary faces), and give both state copies the
+        // slot's state, which it keeps while absent
+        int rc = freeze_sync(c, patch);
+        if (rc) return rc;
+        if (!P.active) c->nfrozen--;
+        for (int t = 0; t < 6; t++) {
+            const int q = P.nb[t];
+            if (q < 0) continue;
+            PatchDev& Q = c->hpatch[q];
+            if (Q.nb[t ^ 1] == patch) Q.nb[t ^ 1] = -1;
+            touched.push_back(q);
+            P.nb[t] = -1;
+        }
+        P.present = 0;
+        P.active = 0;
+    } else {
+        // link to the init table's face neighbours that are present
+        for (int t = 0; t < 6; t++) {
+            const int q = c->desc[patch].nbr[kFaceEntry[t]];
+            if (q < 0 || q == patch || !c->hpatch[q].present) continue;
+            P.nb[t] = q;
+            c->hpatch[q].nb[t ^ 1] = patch;
+            touched.push_back(q);
+        }
+        // periodic with itself along an axis (one patch across): its own neighbour
+        for (int t = 0; t < 6; t++)
+            if (c->desc[patch].nbr[kFaceEntry[t]] == patch) P.nb[t] = patch;
+        P.present = 1;
+        P.active = 1;
+    }
+    for (int q : touched) {
+        int rc = push_patch(c, q);
+        if (rc) return rc;
+    }
+    c->nzones = 0;
+    for (int p = 0; p < c->npatch; p++)
+        if (c->hpatch[p].present) c->nzones += (long long)c->desc[p].n[0] * c->desc[p].n[1] * c->desc[p].n[2];
+    if (c->smax_state == SMAX_CLEAN) c->smax_state = SMAX_DIRTY;
+    c->xg_valid = false;
+    c->plan_dirty = true;
     return WMB_OK;
 }
 
@@ -1636,7 +1922,8 @@ int wmb_profile_step(wmb_ctx* c, double* ms, int32_t nclass) {
     if (!c || !ms) return WMB_EINVAL;
     if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
     if (nclass < WMB_NCLASS) return fail(c, WMB_EINVAL, "ms must hold WMB_NCLASS entries");
-    int rc = ensure_smax(c);
+    int rc = c->plan_dirty ? replan(c) : WMB_OK;
+    if (!rc) rc = ensure_smax(c);
     if (!rc && !c->xg_valid) rc = dispatch_fill(c, FILL_X);  // as before a graph replay
     if (rc) return rc;
     hipEvent_t ev[WMB_NCLASS + 1];

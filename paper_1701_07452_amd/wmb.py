@@ -22,7 +22,8 @@ EXPORTS = [
     "wmb_create", "wmb_pool_bytes", "wmb_init_patches", "wmb_set_state", "wmb_get_state", "wmb_get_stored",
     "wmb_fill_ghosts", "wmb_compute_dt", "wmb_advance", "wmb_run_steps", "wmb_diagnostics",
     "wmb_diagnostics_noalloc", "wmb_debug_stage",
-    "wmb_autotune", "wmb_set_tuning", "wmb_set_schedule", "wmb_keep_stages", "wmb_set_active", "wmb_profile_step", "wmb_destroy",
+    "wmb_autotune", "wmb_set_tuning", "wmb_set_schedule", "wmb_keep_stages", "wmb_set_active", "wmb_set_present",
+    "wmb_profile_step", "wmb_destroy",
     "wmb_strerror", "wmb_last_error",
 ]
 KERNEL_CLASSES = ["fill", "dt", "sweep1_x", "sweep1_y", "sweep1_z", "ct_half",
@@ -110,6 +111,7 @@ def load_library():
     lib.wmb_set_schedule.argtypes = [vp, C.c_int32]
     lib.wmb_keep_stages.argtypes = [vp, C.c_int32]
     lib.wmb_set_active.argtypes = [vp, C.c_int32, C.c_int32]
+    lib.wmb_set_present.argtypes = [vp, C.c_int32, C.c_int32]
     lib.wmb_destroy.argtypes = [vp]
     lib.wmb_strerror.argtypes = [C.c_int]
     lib.wmb_strerror.restype = C.c_char_p
@@ -267,7 +269,9 @@ class Sim:
         return out.reshape((3, 8) + sh) if nw == 24 else out
 
     def autotune(self, reps=3):
-        """Pick the sweep block shapes by timing; returns {(stage, axis, edge): pencils per block}."""
+        """Pick the sweep block shapes and the Steps 3-4 / 8-11 tiles by timing (or from the
+        per-process cache; reps < 0 forces timing); returns {(stage, axis, edge): shape}, with
+        (3, 0, 0) the Steps 3-4 tile width and (4, 0, 0) the Steps 8-11 tile zones."""
         buf = (C.c_int32 * 256)()
         self._check(self.lib.wmb_autotune(self.h, int(reps), buf, 256))
         out, k = {}, 0
@@ -277,7 +281,7 @@ class Sim:
         return out
 
     def set_tuning(self, tuning):
-        """Apply {(stage, axis, edge): pencils per block} without timing."""
+        """Apply {(stage, axis, edge): shape} (as autotune returns it) without timing."""
         flat = [v for (st, ax, e), W in sorted(tuning.items()) for v in (st, ax, e, W)]
         buf = (C.c_int32 * max(len(flat), 1))(*flat)
         self._check(self.lib.wmb_set_tuning(self.h, buf, len(flat)))
@@ -289,6 +293,10 @@ class Sim:
     def set_active(self, ip, on=True):
         """Freeze (on=False) or thaw a patch; the captured graphs stay valid."""
         self._check(self.lib.wmb_set_active(self.h, int(ip), 1 if on else 0))
+
+    def set_present(self, ip, on=True):
+        """Remove (on=False) or add back a patch slot of the init table; the captured graphs stay valid."""
+        self._check(self.lib.wmb_set_present(self.h, int(ip), 1 if on else 0))
 
     def keep_stages(self, on=True):
         """Let later steps store the Step-9 edges for debug_stage(6)."""

@@ -509,22 +509,44 @@ def test_full_size_uneven_400_fp64_sampled(wmb):
 
 
 def test_autotune_does_not_change_results(wmb):
-    """The sweep block shape is a scheduling choice only: results bitwise equal."""
+    """Block shapes and tiles are scheduling choices only: the sweep shapes,
+    the Steps 3-4 tile width and the Steps 8-11 tile size (as autotuned, and
+    forced to each other value) give bitwise the same state after 3 steps.
+    A second autotune of the same batch returns the cached choice."""
     G, (q, b) = CASES["uneven"]()
     N = G.shape
     dx = (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
-    outs = []
-    for tune in (False, True):
-        for prec in (1, 0):
+    for prec in (1, 0):
+        tiles = [None, "auto", {(3, 0, 0): 13, (4, 0, 0): 256}, {(3, 0, 0): 20}]
+        if prec == 1:
+            tiles.append({(3, 0, 0): 40, (4, 0, 0): 512})
+        outs, chosen = [], None
+        for t in tiles:
             sim = gpu_sim(wmb, G, q, b, prec, dx=dx)
-            if tune:
+            if t == "auto":
                 chosen = sim.autotune(reps=1)
                 assert chosen, "autotune returned no groups"
+                assert (3, 0, 0) in chosen and (4, 0, 0) in chosen, chosen
+                assert sim.autotune(reps=1) == chosen  # the cached choice
+            elif t:
+                sim.set_tuning(t)
             sim.run_steps(3)
             outs.append(I.gather(G, [sim.get_state(i) for i in range(G.npatch)]))
             sim.close()
-    for a, b2 in ((outs[0], outs[2]), (outs[1], outs[3])):
-        assert np.array_equal(a[0], b2[0]) and np.array_equal(a[1], b2[1])
+        print("prec %d autotune %s" % (prec, wmb.tuning_to_str(chosen)))
+        for o in outs[1:]:
+            assert np.array_equal(outs[0][0], o[0]) and np.array_equal(outs[0][1], o[1])
+
+
+def test_tile_tuning_entries_are_checked(wmb):
+    """wmb_set_tuning rejects tile entries outside what the kernels take."""
+    G, (q, b) = CASES["uneven"]()
+    for prec, bad in ((1, {(3, 0, 0): 41}), (1, {(3, 0, 0): 3}), (1, {(4, 0, 0): 384}), (0, {(4, 0, 0): 512}),
+                      (1, {(3, 0, 5): 20})):
+        sim = gpu_sim(wmb, G, q, b, prec, dx=(1 / 64,) * 3)
+        with pytest.raises(RuntimeError):
+            sim.set_tuning(bad)
+        sim.close()
 
 
 FORMS = {
@@ -944,12 +966,11 @@ def test_frozen_patches_fp64(wmb):
 
 
 def test_frozen_patches_fp32_512_zone_tiles(wmb):
-    """FP32 on 32^3 patches, whose update runs on 512-zone tiles while every
-    patch is active and on 256-zone tiles while any is frozen (the first
-    freeze and the last thaw switch them and re-capture the graphs): two of
-    eight patches frozen for 3 steps, both thawed for 2 more.  Frozen states
-    bitwise unchanged while frozen; rho and E within 1e-5 relative L1 of the
-    FP64 oracle driven the same way."""
+    """FP32 on 32^3 patches, whose update runs on 512-zone tiles (the frozen
+    patches' blocks exit at once; the graphs captured before the freeze are
+    replayed throughout): two of eight patches frozen for 3 steps, both
+    thawed for 2 more.  Frozen states bitwise unchanged while frozen; rho and
+    E within 1e-5 relative L1 of the FP64 oracle driven the same way."""
     G = I.uniform_grid(64, 32)
     q, b = I.random_smooth((64, 64, 64), 43)
     q, b = as_f32(q), as_f32(b)
@@ -1011,6 +1032,96 @@ def test_frozen_patches_uneven_fp32(wmb):
         assert _rel_l1(qg[c], qo[c]) <= 1e-5, c
     sim.close()
     orc.close()
+
+
+# ---------------------------------------------------------------------------
+# patch slots removed from and added back to the domain (wmb_set_present)
+# ---------------------------------------------------------------------------
+
+def _sub_oracle(G_sub, index_map, src, params_kw):
+    """An oracle over G_sub whose patch p takes the stored box (state,
+    ghosts, owned faces) of patch index_map[p] of the oracle `src`."""
+    from oracle import OracleSim, default_params
+
+    orc = OracleSim(default_params(**params_kw), G_sub.descs)
+    for p, ps in enumerate(index_map):
+        orc.set_stored(p, *src.get_stored(ps))
+    return orc
+
+
+def test_removed_and_added_patch_slots_fp64(wmb):
+    """A 4 x 2 x 2 batch of 12^3 patches (outflow along x, periodic y, z):
+    the last x-column (4 slots) is removed before the first step, the rest
+    runs 3 graph-replayed steps, then the column is added back with a given
+    state and the whole batch runs 2 more.  Reference: the oracle on the
+    3 x 2 x 2 box (its patches' stored boxes, owned faces included, taken
+    from the full oracle after a ghost exchange), then on the 4 x 2 x 2 box
+    (the first three columns from it, the last from the given state), on the
+    GPU's dt.  FP64 within 1e-11; the removed slots' states untouched while
+    removed; diagnostics of the smaller domain within 1e-11; the graphs
+    captured before the removal are replayed after it and after the
+    addition (the library keeps them)."""
+    G4 = I.patch_grid([12] * 4, [12, 12], [12, 12], periodic=(False, True, True))
+    G3 = I.patch_grid([12] * 3, [12, 12], [12, 12], periodic=(False, True, True))
+    q, b = I.random_smooth(G4.shape, 47)
+    dx = (1.0 / 48, 1.0 / 24, 1.0 / 24)
+    idx4 = lambda i, j, k: (k * 2 + j) * 4 + i  # noqa: E731
+    keep = [idx4(i, j, k) for k in range(2) for j in range(2) for i in range(3)]
+    last = [idx4(3, j, k) for k in range(2) for j in range(2)]
+    sim = gpu_sim(wmb, G4, q, b, 0, dx=dx)
+    full = oracle_sim(G4, q, b, dx=dx)
+    full.fill_ghosts()
+    orc = _sub_oracle(G3, keep, full, dict(dx=dx))
+    full.close()
+    init = {p: sim.get_state(p) for p in last}
+    for p in last:
+        sim.set_present(p, False)
+    sim.set_present(last[0], False)  # no change
+    with pytest.raises(wmb.WmbError):
+        sim.set_active(last[0], True)  # absent: neither frozen nor active
+    for _ in range(3):
+        dt = sim.compute_dt()
+        sim.run_steps(1)
+        orc.fill_ghosts()
+        orc.advance(dt)
+    for p3, p4 in enumerate(keep):
+        qg, bg = sim.get_state(p4)
+        qo, bo = orc.get_state(p3)
+        for c in range(8):
+            assert rel_max(qg[c], qo[c]) <= 1e-11, (p4, c)
+        assert rel_max(bg, bo) <= 1e-11, p4
+    for p in last:
+        qa, ba = sim.get_state(p)
+        assert np.array_equal(qa, init[p][0]) and np.array_equal(ba, init[p][1]), p
+    tot_g, _, _, _ = sim.diagnostics()
+    tot_o = orc.diagnostics()[0]
+    for c in range(8):
+        assert abs(tot_g[c] - tot_o[c]) <= 1e-11 * (1.0 + abs(tot_o[c])), c
+    # add the column back with a given state (its own initial state)
+    parts = I.split(G4, q, b)
+    for p in last:
+        sim.set_state(p, *parts[p])
+        sim.set_present(p, True)
+    from oracle import OracleSim, default_params
+
+    orc4 = OracleSim(default_params(dx=dx), G4.descs)
+    for p3, p4 in enumerate(keep):
+        orc4.set_stored(p4, *orc.get_stored(p3))
+    for p in last:
+        orc4.set_state(p, *parts[p])
+    orc.close()
+    for _ in range(2):
+        dt = sim.compute_dt()
+        sim.run_steps(1)
+        orc4.fill_ghosts()
+        orc4.advance(dt)
+    qg, bg = I.gather(G4, [sim.get_state(i) for i in range(G4.npatch)])
+    qo, bo = oracle_gather(G4, orc4)
+    for c in range(8):
+        assert rel_max(qg[c], qo[c]) <= 1e-11, c
+    assert rel_max(bg, bo) <= 1e-11
+    sim.close()
+    orc4.close()
 
 
 # ---------------------------------------------------------------------------
