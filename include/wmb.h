@@ -219,7 +219,8 @@ int wmb_debug_stage(wmb_ctx *c, int32_t patch, int32_t stage, double *out);
    changes results (both forms compute every face with the same
    arithmetic).  It then times the tiles of Steps 3-4 (the widest tile along
    x: 40, 20 or 13 zones, 256 zones a plane) and of Steps 8-11 (256 or, in
-   FP32, 512 zones a plane), which do not change results either.  The
+   FP32, 512 zones a plane) with either Steps 8-11 launch, which do not
+   change results either.  The
    interior state is unchanged; ghosts are refreshed and the step
    intermediates overwritten.  Invalidates the captured graphs.  The choice
    is kept for the life of the process under a key of the device
@@ -228,8 +229,9 @@ int wmb_debug_stage(wmb_ctx *c, int32_t patch, int32_t stage, double *out);
    same key (on any context) applies it without timing.  reps < 0 times
    anyway, with -reps repetitions, and replaces the kept choice.  If chosen
    != NULL it receives quadruples (stage, axis, edge, shape) -- the sweep
-   groups, then (3, 0, 0, Steps 3-4 tile width) and (4, 0, 0, Steps 8-11
-   tile zones) -- up to nchosen ints, 0-terminated when shorter.
+   groups, then (3, 0, 0, Steps 3-4 tile width), (4, 0, 0, Steps 8-11
+   tile zones) and (5, 0, 0, Steps 8-11 launch) -- up to nchosen ints,
+   0-terminated when shorter.
    Synchronous. */
 int wmb_autotune(wmb_ctx *c, int32_t reps, int32_t *chosen, int32_t nchosen);
 
@@ -245,8 +247,10 @@ int wmb_autotune(wmb_ctx *c, int32_t reps, int32_t *chosen, int32_t nchosen);
    sweeps in FP32 and the pencil form elsewhere.  Tile entries: (3, 0, 0, w)
    sets the widest Steps 3-4 tile along x to w zones (4..40, default 40);
    (4, 0, 0, z) the zones of a Steps 8-11 tile plane (256, or 512 in FP32;
-   the default is the one that leaves fewer threads idle).  Every entry is
-   checked before any is applied. */
+   the default is the one that leaves fewer threads idle); (5, 0, 0, m) the
+   Steps 8-11 launch: m = 0 one block a tile (the default), m = 1 a
+   persistent grid whose blocks take the tiles of their XCD's queue from an
+   atomic counter.  Every entry is checked before any is applied. */
 int wmb_set_tuning(wmb_ctx *c, const int32_t *quads, int32_t n);
 
 /* Schedule of the captured step (wmb_run_steps).  groups = 1 (the default):

@@ -569,19 +569,18 @@ __global__ void __launch_bounds__(TILE_THREADS) ct_half_kernel(R* __restrict__ p
 // and z passes.
 // ---------------------------------------------------------------------------
 
+// One tile of Steps 8-11 (all threads of the block); returns the block's
+// part of the signal-speed maximum of the new state (per thread).
 template <typename R>
-__global__ void __launch_bounds__(UpdTile<R>::threads) update_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
-                                                              const WorkItem* __restrict__ work, DevParams prm, Coef<R> cf,
-                                                              int cur, const StepConst* __restrict__ sc,
-                                                              unsigned long long* __restrict__ nfloor,
-                                                              unsigned long long* __restrict__ smax_bits, int keep_edges) {
+__device__ __forceinline__ double update_tile(const WorkItem w, R* __restrict__ pool,
+                                              const PatchDev* __restrict__ patches, const DevParams& prm,
+                                              const Coef<R>& cf, int cur, const StepConst* __restrict__ sc,
+                                              unsigned long long* __restrict__ nfloor, int keep_edges,
+                                              R* __restrict__ s_er, R* __restrict__ s_ed) {
     constexpr int UPD_ERMAX = UpdTile<R>::er, UPD_EDMAX = UpdTile<R>::ed;
-    __shared__ R s_er[2 * 3 * UPD_ERMAX];  // [plane & 1][component][(ey+1)(tx+2) + ex+1]
-    __shared__ R s_ed[2 * 3 * UPD_EDMAX];  // [plane & 1][component][j (tx+1) + i]
-    const WorkItem w = work[blockIdx.x];
-    if (w.patch < 0) return;  // padding item (whole block)
+    if (w.patch < 0) return 0.0;  // padding item (whole block)
     const PatchDev P = patches[w.patch];
-    if (!P.active) return;  // frozen patch (whole block, before any barrier)
+    if (!P.active) return 0.0;  // frozen patch (whole block, before any barrier)
     const int i0 = (w.a & 0xffff) - TILE_BIAS, j0 = (w.a >> 16) - TILE_BIAS;
     const int tx = w.b & 0xffff, ty = w.b >> 16;
     const int k0 = (w.c & 0xffff) - TILE_BIAS, k1 = (w.c >> 16) - TILE_BIAS;
@@ -832,6 +831,46 @@ __global__ void __launch_bounds__(UpdTile<R>::threads) update_kernel(R* __restri
             sp = fmax(sp, signal_speed(ud, prm));
 #pragma unroll
             for (int c = 0; c < 4; c++) ufc[c] = ufn[c];
+        }
+    }
+    return sp;
+}
+
+// QUEUE = false: block b takes item b of the list.  QUEUE = true: a
+// persistent grid whose block b, on XCD b mod 8 (blocks go to the XCDs
+// round-robin), takes the items of that XCD's queue in the list (positions
+// 8 j + x, the order xcd_order gives) one after another from an atomic
+// counter; the last block to finish sets the counters back to zero, so the
+// launch needs no reset of its own (and none inside a captured graph).
+template <typename R, bool QUEUE>
+__global__ void __launch_bounds__(UpdTile<R>::threads) update_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
+                                                              const WorkItem* __restrict__ work, int nitems,
+                                                              unsigned int* __restrict__ queue, DevParams prm, Coef<R> cf,
+                                                              int cur, const StepConst* __restrict__ sc,
+                                                              unsigned long long* __restrict__ nfloor,
+                                                              unsigned long long* __restrict__ smax_bits, int keep_edges) {
+    constexpr int UPD_ERMAX = UpdTile<R>::er, UPD_EDMAX = UpdTile<R>::ed;
+    __shared__ R s_er[2 * 3 * UPD_ERMAX];  // [plane & 1][component][(ey+1)(tx+2) + ex+1]
+    __shared__ R s_ed[2 * 3 * UPD_EDMAX];  // [plane & 1][component][j (tx+1) + i]
+    double sp = 0.0;
+    if (!QUEUE) {
+        sp = update_tile<R>(work[blockIdx.x], pool, patches, prm, cf, cur, sc, nfloor, keep_edges, s_er, s_ed);
+    } else {
+        __shared__ int s_item;
+        const int x = (int)(blockIdx.x & 7u), nq = nitems / 8;
+        for (;;) {
+            if (threadIdx.x == 0) s_item = (int)atomicAdd(queue + x, 1u);
+            __syncthreads();
+            const int j = s_item;
+            __syncthreads();  // every thread has read s_item (and left the last tile's LDS)
+            if (j >= nq) break;
+            sp = fmax(sp, update_tile<R>(work[8 * j + x], pool, patches, prm, cf, cur, sc, nfloor, keep_edges, s_er,
+                                         s_ed));
+        }
+        __threadfence();
+        if (threadIdx.x == 0 && atomicAdd(queue + 8, 1u) == gridDim.x - 1) {
+            // the last block: every block has made its last take
+            for (int q = 0; q < 9; q++) atomicExch(queue + q, 0u);
         }
     }
     block_max_atomic(sp, smax_bits);
@@ -1689,14 +1728,33 @@ hipError_t launch_ct_half(void* pool, const PatchDev* pt, const WorkItem* wk, in
     return hipGetLastError();
 }
 
+// queue != nullptr: the persistent form, with as many blocks as are
+// resident at once (a multiple of 8), over a list of nblk items (a multiple
+// of 8, as xcd_order pads it); queue holds 9 counters, zero between launches
 template <typename R>
 hipError_t launch_update(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm,
                          const Coef<R>& cf, int cur, const StepConst* sc, unsigned long long* nfl, unsigned long long* smax,
-                         int keep_edges, int threads, hipStream_t st) {
+                         int keep_edges, int threads, unsigned int* queue, hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
     if (threads < 64 || threads > UpdTile<R>::threads || threads % 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(update_kernel<R>, dim3(nblk), dim3(threads), 0, st, (R*)pool, pt, wk, prm, cf, cur, sc, nfl,
-                       smax, keep_edges);
+    if (!queue) {
+        hipLaunchKernelGGL((update_kernel<R, false>), dim3(nblk), dim3(threads), 0, st, (R*)pool, pt, wk, nblk, queue,
+                           prm, cf, cur, sc, nfl, smax, keep_edges);
+        return hipGetLastError();
+    }
+    if (nblk % 8) return hipErrorInvalidValue;
+    int dev = 0, per_cu = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)update_kernel<R, true>, threads, 0);
+    if (e != hipSuccess) return e;
+    int grid = per_cu * cus;
+    grid -= grid % 8;
+    if (grid < 8) grid = 8;
+    if (grid > nblk) grid = nblk;
+    hipLaunchKernelGGL((update_kernel<R, true>), dim3(grid), dim3(threads), 0, st, (R*)pool, pt, wk, nblk, queue, prm,
+                       cf, cur, sc, nfl, smax, keep_edges);
     return hipGetLastError();
 }
 
@@ -1794,7 +1852,7 @@ hipError_t launch_diag(const void* pool, const PatchDev* pt, const WorkItem* wk,
                                           const StepConst*, hipStream_t);                                                \
     template hipError_t launch_update<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, \
                                          int, const StepConst*, unsigned long long*, unsigned long long*, int, int,     \
-                                         hipStream_t);                                                                   \
+                                         unsigned int*, hipStream_t);                                                    \
     template hipError_t launch_sweep<R>(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&,        \
                                         const Coef<R>&, int, const StepConst*, int, int, int, unsigned long long*,       \
                                         hipStream_t);                                                                    \

@@ -21,7 +21,7 @@ hipError_t launch_dt_finalize(unsigned long long*, StepConst*, const DevParams&,
 hipError_t launch_set_dt(StepConst*, double, const DevParams&, hipStream_t);
 hipError_t launch_set_patch(PatchDev*, int, const PatchDev&, hipStream_t);
 template <typename R> hipError_t launch_ct_half(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int, const StepConst*, hipStream_t);
-template <typename R> hipError_t launch_update(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, unsigned long long*, unsigned long long*, int, int, hipStream_t);
+template <typename R> hipError_t launch_update(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, unsigned long long*, unsigned long long*, int, int, unsigned int*, hipStream_t);
 template <typename R> hipError_t launch_sweep(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, int, int, int, unsigned long long*, hipStream_t);
 template <typename R> hipError_t launch_march(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, int, int, int, unsigned long long*, hipStream_t);
 template <typename R> hipError_t launch_diag(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, double*, const unsigned long long*, double, double, double*, hipStream_t);
@@ -42,6 +42,7 @@ struct DevList {
 struct SweepGroup {
     int P, W, zlo, tlo, thi, n;
     int Wp = 0, Wm = 0;    // autotune: the fastest pencil and marching shapes alone
+    int Wx[2] = {0, 0};    // autotune, x sweeps: the second and third fastest shapes alone
     DevList wl;            // every pencil of the transverse range [tlo, n+thi]^2
     DevList wlg[4];        // the same for the patches of each step group (grouped schedule)
     DevList wl_in, wl_fr;  // Step-1 x sweep only: the pencils with both transverse
@@ -91,6 +92,8 @@ struct wmb_ctx {
     hipEvent_t ev_g[4] = {};
     int upd_zones = 256;  // zones a tile plane of Steps 8-11 (the update's block size)
     int cth_tx = 40;      // widest tile of Steps 3-4 along x (zones; 256 a tile plane)
+    int upd_queue = 0;    // Steps 8-11 launch: 0 one block a tile, 1 persistent blocks on per-XCD queues
+    unsigned int* d_queue = nullptr;  // the queues' counters, 16 per step group
     int nfrozen = 0;      // frozen patches
     bool plan_dirty = false;  // the active set changed since the stage work lists were planned
     bool keep_edges = false;  // Steps 8-11 also store the Step-9 edges (debugging)
@@ -467,7 +470,8 @@ int run_step(wmb_ctx* c, bool split = false) {
         }
     }
     e = launch_update<R>(c->pool, c->d_patch, c->wl_upd.d, c->wl_upd.n, c->dp, coef<R>(c), cur, c->d_sc, c->d_nfloor,
-                         c->d_smax, c->keep_edges ? 1 : 0, c->upd_zones, c->stream);
+                         c->d_smax, c->keep_edges ? 1 : 0, c->upd_zones, c->upd_queue ? c->d_queue : nullptr,
+                         c->stream);
     STEPCK("update");
     mark(c);
     c->edges_kept = c->keep_edges;
@@ -505,7 +509,7 @@ int run_step_grouped(wmb_ctx* c) {
         const DevList& wu = c->wl_upd_g[g];
         if (e == hipSuccess)
             e = launch_update<R>(c->pool, c->d_patch, wu.d, wu.n, c->dp, coef<R>(c), cur, c->d_sc, c->d_nfloor, c->d_smax,
-                                 c->keep_edges ? 1 : 0, c->upd_zones, st);
+                                 c->keep_edges ? 1 : 0, c->upd_zones, c->upd_queue ? c->d_queue + 16 * g : nullptr, st);
         if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("grouped step: ") + hipGetErrorString(e));
         if (g > 0) CKH(hipEventRecord(c->ev_g[g], st));
     }
@@ -1179,6 +1183,7 @@ int autotune_t(wmb_ctx* c, int reps) {
                     for (int W : opts_t) cand.push_back(W);
                 float best = 1e30f, bestp = 1e30f, bestm = 1e30f;
                 int bestW = G.W;
+                std::vector<std::pair<float, int>> timed;  // (ms, shape) of every candidate
                 for (int W : cand) {
                     if (!shape_ok(d, G.P, es, W, stage + 1) || (W > 0 && G.P * W < 64)) continue;
                     std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, W < 0 ? (-W) % 512 : W);
@@ -1209,7 +1214,11 @@ int autotune_t(wmb_ctx* c, int reps) {
                     }
                     if (W > 0 && tot < bestp) bestp = tot, G.Wp = W;
                     if (W < 0 && tot < bestm) bestm = tot, G.Wm = W;
+                    timed.emplace_back(tot, W);
                 }
+                std::sort(timed.begin(), timed.end());
+                G.Wx[0] = timed.size() > 1 ? timed[1].second : 0;
+                G.Wx[1] = timed.size() > 2 ? timed[2].second : 0;
                 if (bestW != G.W) {
                     int rc2 = set_group_W(c, d, stage, G, bestW);
                     if (rc2) return cleanup(rc2);
@@ -1219,42 +1228,79 @@ int autotune_t(wmb_ctx* c, int reps) {
     }
     // The graph runs the three sweeps of a stage concurrently, so the shapes
     // that are fastest alone need not be the fastest together: time whole
-    // stages (x on the main stream, y and z on the side streams, joined) for
-    // the shapes picked alone, for the best pencil shapes and for the best
-    // marching shapes of the y and z groups, and keep the fastest.
+    // steps replayed from a captured graph for the shapes picked alone, then,
+    // stage by stage, for each x group its second and third shapes alone,
+    // then for the best pencil shapes and for the best marching shapes of
+    // the y and z groups, keeping the fastest each time.
     for (int stage = 0; stage < 2; stage++) {
+        // a whole step captured and replayed as a graph, as wmb_run_steps
+        // runs it (the sweeps of a stage as branches), its results going
+        // nowhere the next step reads: the update writes the other state
+        // copy, floors, protected faces and the signal-speed maximum go to
+        // the sinks, and the current copy and the flags are restored
         auto time_stage = [&](float* ms) -> int {
-            hipError_t e = hipSuccess;
+            unsigned long long *smax0 = c->d_smax, *nfl0 = c->d_nfloor;
+            const int cur0 = c->cur, ss0 = c->smax_state;
+            const bool xg0 = c->xg_valid, ek0 = c->edges_kept;
+            c->d_smax = smax0 + 2;
+            c->d_nfloor = nfl0 + 2;
+            hipGraph_t gr = nullptr;
+            hipGraphExec_t ge = nullptr;
+            int rc4 = WMB_OK;
+            hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
+            if (e == hipSuccess) {
+                e = hipEventRecord(c->ev_join, c->stream);  // the exchange is done
+                if (e == hipSuccess) rc4 = run_step<R>(c, true);
+                hipError_t e2 = hipStreamEndCapture(c->stream, &gr);
+                if (e == hipSuccess) e = e2;
+            }
+            c->d_smax = smax0;
+            c->d_nfloor = nfl0;
+            c->cur = cur0;
+            c->smax_state = ss0;
+            c->xg_valid = xg0;
+            c->edges_kept = ek0;
+            if (!rc4 && e == hipSuccess) e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
             float tot = 1e30f;
-            for (int r = 0; r <= reps && e == hipSuccess; r++) {
-                CKT(hipEventRecord(e0, c->stream));
-                CKT(hipEventRecord(c->ev_br[5], c->stream));
-                CKT(hipStreamWaitEvent(c->side, c->ev_br[5], 0));
-                CKT(hipStreamWaitEvent(c->side2, c->ev_br[5], 0));
-                hipStream_t sts[3] = {c->stream, c->side, c->side2};
-                for (int d = 0; d < 3 && e == hipSuccess; d++)
-                    for (auto& G : c->sweeps[d][stage])
-                        if (e == hipSuccess) e = launch_group<R>(c, d, stage + 1, G, G.wl, c->cur, c->d_nfloor + 2, sts[d]);
-                CKT(hipEventRecord(c->ev_br[3], c->side));
-                CKT(hipEventRecord(c->ev_br[4], c->side2));
-                CKT(hipStreamWaitEvent(c->stream, c->ev_br[3], 0));
-                CKT(hipStreamWaitEvent(c->stream, c->ev_br[4], 0));
-                CKT(hipEventRecord(e1, c->stream));
-                CKT(hipEventSynchronize(e1));
+            for (int r = 0; r <= reps && !rc4 && e == hipSuccess; r++) {
+                e = hipEventRecord(e0, c->stream);
+                if (e == hipSuccess) e = hipGraphLaunch(ge, c->stream);
+                if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float t = 0.f;
-                CKT(hipEventElapsedTime(&t, e0, e1));
+                if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
                 if (r > 0) tot = std::min(tot, t);
             }
+            // a graph executable is destroyed only on an idle device (ROCm 7
+            // otherwise keeps the memory its kernels used from being freed)
+            (void)hipDeviceSynchronize();
+            if (ge) (void)hipGraphExecDestroy(ge);
+            if (gr) (void)hipGraphDestroy(gr);
+            if (rc4) return cleanup(rc4);
             if (e != hipSuccess) return cleanup(fail(c, WMB_EHIP, std::string("autotune: ") + hipGetErrorString(e)));
             *ms = tot;
             return WMB_OK;
         };
-        std::vector<int> alone;
-        for (int d = 1; d < 3; d++)
-            for (auto& G : c->sweeps[d][stage]) alone.push_back(G.W);
         float best = 0.f;
         int rc2 = time_stage(&best);
         if (rc2) return rc2;
+        // the x sweeps: the second and third shapes alone, one group at a time
+        for (auto& G : c->sweeps[0][stage])
+            for (int a = 0; a < 2; a++) {
+                const int W0 = G.W, W1 = G.Wx[a];
+                if (W1 == 0 || W1 == W0) continue;
+                if ((rc2 = set_group_W(c, 0, stage, G, W1))) return cleanup(rc2);
+                float t = 0.f;
+                if ((rc2 = time_stage(&t))) return rc2;
+                if (t < best) {
+                    best = t;
+                } else if ((rc2 = set_group_W(c, 0, stage, G, W0))) {
+                    return cleanup(rc2);
+                }
+            }
+        std::vector<int> alone;
+        for (int d = 1; d < 3; d++)
+            for (auto& G : c->sweeps[d][stage]) alone.push_back(G.W);
         int choice = 0;  // 0: alone, 1: all pencil, 2: all marching
         for (int alt = 1; alt <= 2; alt++) {
             bool differs = false, valid = true;
@@ -1298,6 +1344,7 @@ int autotune_t(wmb_ctx* c, int reps) {
         const std::vector<int> rows = x_rows(c);
         auto time_tiles = [&](int kind, int v, float* ms) -> int {
             DevList L;
+            // kind 0: Steps 3-4; 1: Steps 8-11, one block a tile; 2: the same on the queues
             int rc3 = kind == 0 ? build_tile_list(c, -2, 2, -2, 2, v, 256, nullptr, L)
                                 : build_tile_list(c, 0, -1, 0, -1, 32, v, &rows, L);
             if (rc3) return cleanup(rc3);
@@ -1309,7 +1356,8 @@ int autotune_t(wmb_ctx* c, int reps) {
                 e = kind == 0 ? launch_ct_half<R>(c->pool, c->d_patch, L.d, L.n, coef<R>(c), c->p.ghost, c->cur, c->d_sc,
                                                   c->stream)
                               : launch_update<R>(c->pool, c->d_patch, L.d, L.n, c->dp, coef<R>(c), c->cur, c->d_sc,
-                                                 c->d_nfloor + 2, c->d_smax + 2, 0, v, c->stream);
+                                                 c->d_nfloor + 2, c->d_smax + 2, 0, v, kind == 2 ? c->d_queue : nullptr,
+                                                 c->stream);
                 CKT(hipEventRecord(e1, c->stream));
                 CKT(hipEventSynchronize(e1));
                 float t = 0.f;
@@ -1324,7 +1372,7 @@ int autotune_t(wmb_ctx* c, int reps) {
         };
         const int cth_opts[] = {40, 20, 13};
         const int upd_opts[] = {256, upd_tile_zones_max((int)es)};
-        int best_tx = c->cth_tx, best_z = c->upd_zones;
+        int best_tx = c->cth_tx, best_z = c->upd_zones, best_q = c->upd_queue;
         float bt = 1e30f, bz = 1e30f;
         for (int v : cth_opts) {
             float t = 0.f;
@@ -1332,13 +1380,15 @@ int autotune_t(wmb_ctx* c, int reps) {
             if (rc3) return rc3;
             if (t < bt) bt = t, best_tx = v;
         }
-        for (int k = 0; k < 2; k++) {
-            if (k == 1 && upd_opts[1] == upd_opts[0]) break;
-            float t = 0.f;
-            int rc3 = time_tiles(1, upd_opts[k], &t);
-            if (rc3) return rc3;
-            if (t < bz) bz = t, best_z = upd_opts[k];
-        }
+        for (int q = 0; q < 2; q++)
+            for (int k = 0; k < 2; k++) {
+                if (k == 1 && upd_opts[1] == upd_opts[0]) break;
+                float t = 0.f;
+                int rc3 = time_tiles(1 + q, upd_opts[k], &t);
+                if (rc3) return rc3;
+                if (t < bz) bz = t, best_z = upd_opts[k], best_q = q;
+            }
+        c->upd_queue = best_q;
         if (best_tx != c->cth_tx || best_z != c->upd_zones) {
             c->cth_tx = best_tx;
             c->upd_zones = best_z;
@@ -1384,6 +1434,7 @@ std::vector<int32_t> tuning_quads(const wmb_ctx* c) {
             for (const auto& G : c->sweeps[d][stage]) q.insert(q.end(), {stage + 1, d, G.n, G.W});
     q.insert(q.end(), {3, 0, 0, c->cth_tx});
     q.insert(q.end(), {4, 0, 0, c->upd_zones});
+    q.insert(q.end(), {5, 0, 0, c->upd_queue});
     return q;
 }
 
@@ -1553,8 +1604,9 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     // sink for tuning runs
     if ((rc = dev_alloc(c, &c->d_smax, 3))) return rc;
     if ((rc = dev_alloc(c, &c->d_sc, 1))) return rc;
-    // counters: floor activations, protected faces, and a sink for tuning runs
-    if ((rc = dev_alloc(c, &c->d_nfloor, 3))) return rc;
+    // counters: floor activations, protected faces, and two sinks for tuning runs
+    if ((rc = dev_alloc(c, &c->d_nfloor, 4))) return rc;
+    if ((rc = dev_alloc(c, &c->d_queue, 64))) return rc;
     if ((rc = dev_alloc(c, &c->d_partial, (size_t)c->wl_diag.n * DIAG_REC))) return rc;
     if ((rc = dev_alloc(c, &c->d_diag_out, 12))) return rc;
     c->nzones = 0;
@@ -1562,7 +1614,8 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     if ((rc = bind_scratch(c))) return rc;
     CKH(hipMemsetAsync(c->d_smax, 0, 3 * sizeof(unsigned long long), c->stream));
     CKH(hipMemsetAsync(c->d_sc, 0, sizeof(StepConst), c->stream));
-    CKH(hipMemsetAsync(c->d_nfloor, 0, 3 * sizeof(unsigned long long), c->stream));
+    CKH(hipMemsetAsync(c->d_nfloor, 0, 4 * sizeof(unsigned long long), c->stream));
+    CKH(hipMemsetAsync(c->d_queue, 0, 64 * sizeof(unsigned int), c->stream));
     CKH(hipStreamSynchronize(c->stream));
     c->cur = 0;
     c->smax_state = SMAX_ZERO;
@@ -1735,6 +1788,11 @@ int wmb_set_tuning(wmb_ctx* c, const int32_t* quads, int32_t n) {
     // check every entry before applying any
     for (int k = 0; k + 4 <= n; k += 4) {
         const int stage = quads[k], d = quads[k + 1], edge = quads[k + 2], W = quads[k + 3];
+        if (stage == 5) {
+            if (d != 0 || edge != 0 || (W != 0 && W != 1))
+                return fail(c, WMB_EINVAL, "tuning entry: (5, 0, 0, 0 or 1) picks the Steps 8-11 launch");
+            continue;
+        }
         if (stage == 3 || stage == 4) {
             if (d != 0 || edge != 0) return fail(c, WMB_EINVAL, "tuning entry: tile entries have axis 0 and edge 0");
             if (stage == 3 && (W < 4 || W > 40))
@@ -1752,6 +1810,10 @@ int wmb_set_tuning(wmb_ctx* c, const int32_t* quads, int32_t n) {
     bool tiles = false;
     for (int k = 0; k + 4 <= n; k += 4) {
         const int stage = quads[k], d = quads[k + 1], edge = quads[k + 2], W = quads[k + 3];
+        if (stage == 5) {
+            c->upd_queue = W;
+            continue;
+        }
         if (stage == 3 || stage == 4) {
             int& v = stage == 3 ? c->cth_tx : c->upd_zones;
             tiles = tiles || v != W;

@@ -62,7 +62,7 @@ def test_pool_bytes(lib):
     b32, b64 = wmb.pool_bytes(p32, G.descs), wmb.pool_bytes(p64, G.descs)
     vol = 42 ** 3
     assert b32 >= 8 * 73 * vol * 4 and b64 >= 8 * 73 * vol * 8
-    assert b64 == 2 * b32
+    assert abs(b64 - 2 * b32) <= 256 * len(G.descs)  # regions are 256-byte aligned
 
 
 C_PROGRAM = r"""

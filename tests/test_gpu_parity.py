@@ -510,23 +510,24 @@ def test_full_size_uneven_400_fp64_sampled(wmb):
 
 def test_autotune_does_not_change_results(wmb):
     """Block shapes and tiles are scheduling choices only: the sweep shapes,
-    the Steps 3-4 tile width and the Steps 8-11 tile size (as autotuned, and
-    forced to each other value) give bitwise the same state after 3 steps.
-    A second autotune of the same batch returns the cached choice."""
+    the Steps 3-4 tile width, the Steps 8-11 tile size and launch (one block
+    a tile, or persistent blocks on per-XCD queues), as autotuned and forced
+    to each other value, give bitwise the same state after 3 graph-replayed
+    steps.  A second autotune of the same batch returns the cached choice."""
     G, (q, b) = CASES["uneven"]()
     N = G.shape
     dx = (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
     for prec in (1, 0):
-        tiles = [None, "auto", {(3, 0, 0): 13, (4, 0, 0): 256}, {(3, 0, 0): 20}]
+        tiles = [None, "auto", {(3, 0, 0): 13, (4, 0, 0): 256}, {(3, 0, 0): 20, (5, 0, 0): 1}]
         if prec == 1:
-            tiles.append({(3, 0, 0): 40, (4, 0, 0): 512})
+            tiles += [{(3, 0, 0): 40, (4, 0, 0): 512}, {(4, 0, 0): 512, (5, 0, 0): 1}]
         outs, chosen = [], None
         for t in tiles:
             sim = gpu_sim(wmb, G, q, b, prec, dx=dx)
             if t == "auto":
                 chosen = sim.autotune(reps=1)
                 assert chosen, "autotune returned no groups"
-                assert (3, 0, 0) in chosen and (4, 0, 0) in chosen, chosen
+                assert (3, 0, 0) in chosen and (4, 0, 0) in chosen and (5, 0, 0) in chosen, chosen
                 assert sim.autotune(reps=1) == chosen  # the cached choice
             elif t:
                 sim.set_tuning(t)
@@ -542,7 +543,7 @@ def test_tile_tuning_entries_are_checked(wmb):
     """wmb_set_tuning rejects tile entries outside what the kernels take."""
     G, (q, b) = CASES["uneven"]()
     for prec, bad in ((1, {(3, 0, 0): 41}), (1, {(3, 0, 0): 3}), (1, {(4, 0, 0): 384}), (0, {(4, 0, 0): 512}),
-                      (1, {(3, 0, 5): 20})):
+                      (1, {(3, 0, 5): 20}), (1, {(5, 0, 0): 2})):
         sim = gpu_sim(wmb, G, q, b, prec, dx=(1 / 64,) * 3)
         with pytest.raises(RuntimeError):
             sim.set_tuning(bad)
