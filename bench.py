@@ -397,6 +397,18 @@ def cpu_baseline(q, b, dx, ghost, budget_s=12.0):
     c1_wall = time.perf_counter() - w0
     c1_cpu = time.process_time() - c0
     ow.close()
+    # the same 32^3 box as 8 patches of 16^3 on all the oracle's threads
+    G8 = I.uniform_grid(32, 16)
+    o8 = OracleSim(default_params(dx=(1 / 32,) * 3), G8.descs)
+    for ip, (qp, bp) in enumerate(I.split(G8, qw, bw)):
+        o8.set_state(ip, qp, bp)
+    c0 = time.process_time()
+    w0 = time.perf_counter()
+    o8.run_steps(10)
+    c8_wall = time.perf_counter() - w0
+    c8_cpu = time.process_time() - c0
+    c8_threads = min(o8.num_threads(), G8.npatch)
+    o8.close()
     return {
         "value": zones * steps / el,
         "unit": "zone-updates/s",
@@ -408,6 +420,9 @@ def cpu_baseline(q, b, dx, ghost, budget_s=12.0):
         "host_cpus": os.cpu_count(),
         "linear_wave_32cubed_10_steps": {"wall_s": round(c1_wall, 3), "cpu_s": round(c1_cpu, 3), "cores_used": 1,
                                          "note": "one patch: the oracle parallelises over patches only"},
+        "linear_wave_32cubed_10_steps_8x16cubed": {"wall_s": round(c8_wall, 3), "cpu_s": round(c8_cpu, 3),
+                                                   "cores_used": c8_threads,
+                                                   "note": "the same box as 8 patches of 16^3, one a thread"},
     }
 
 

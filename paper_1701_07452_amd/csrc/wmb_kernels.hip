@@ -283,21 +283,26 @@ __global__ void __launch_bounds__(256) fill_pass_kernel(R* __restrict__ pool, co
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ double signal_speed(const double u[8], const DevParams& p) {
-    double ir = 1.0 / u[0];
-    double v[3] = {u[1] * ir, u[2] * ir, u[3] * ir};
-    double b2 = u[4] * u[4] + u[5] * u[5] + u[6] * u[6];
-    double pr = (p.gamma - 1.0) * (u[7] - 0.5 * u[0] * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - 0.5 * b2);
+    // the plain formula, operation for operation and without contraction,
+    // so that the maximum (and dt) is the one the plain evaluation gives
+#pragma clang fp contract(off)
+    const double rho = u[0];
+    const double v[3] = {u[1] / rho, u[2] / rho, u[3] / rho};
+    const double b2 = u[4] * u[4] + u[5] * u[5] + u[6] * u[6];
+    double pr = (p.gamma - 1.0) * (u[7] - 0.5 * rho * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - 0.5 * b2);
     if (pr < p.p_floor) pr = p.p_floor;
-    double a2 = p.gamma * pr * ir;
+    const double a2 = p.gamma * pr / rho;
     double s = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        double ca2 = u[4 + d] * u[4 + d] * ir;
-        double bp2 = (b2 - u[4 + d] * u[4 + d]) * ir;
-        double dpr = a2 - ca2 - bp2;
-        double dd = sqrt(dpr * dpr + 4.0 * a2 * bp2);
-        double cf = sqrt(0.5 * (a2 + ca2 + bp2 + dd));
-        s = fmax(s, (fabs(v[d]) + cf) / p.dx[d]);
+        const double bd = u[4 + d];
+        const double ca2 = bd * bd / rho;
+        const double bp2 = (b2 - bd * bd) / rho;
+        const double dpr = a2 - ca2 - bp2;
+        const double dd = sqrt(dpr * dpr + 4.0 * a2 * bp2);
+        const double cf = sqrt(0.5 * (a2 + ca2 + bp2 + dd));
+        const double sd = (fabs(v[d]) + cf) / p.dx[d];
+        if (sd > s) s = sd;
     }
     return s;
 }
@@ -624,8 +629,10 @@ __device__ __forceinline__ double update_tile(const WorkItem w, R* __restrict__ 
     // Step 8 at tile-local zone (ex, ey) of plane p.  fz, bz: flux_z rows 0-3 and
     // b^{n+1/2}_z on the lower z-face (carried from plane p-1, loaded when
     // fresh); replaced by those of the upper face.  uf, if given, receives
-    // q - dt div F of rows 0-3 for the final update of the zone.
-    auto er_item = [&](int ex, int ey, int p, R(&fz)[4], R& bz, bool fresh, R* uf) {
+    // q - dt div F of rows 0-3 for the final update of the zone; r0, if
+    // given, the rho rows of flux_x, flux_y and flux_z on the zone's lower
+    // faces, which the zone's edges of Step 9 use again.
+    auto er_item = [&](int ex, int ey, int p, R(&fz)[4], R& bz, bool fresh, R* uf, R* r0) {
         const unsigned xo = zoff(ex, ey, p);
         R u[4];
 #pragma unroll
@@ -633,9 +640,11 @@ __device__ __forceinline__ double update_tile(const WorkItem w, R* __restrict__ 
             const unsigned cf0 = FX + c * VB, cf1 = FY + c * VB, cf2 = FZ + c * VB;
             if (fresh) fz[c] = ld(xo, cf2);
             const R fzn = ld(xo + s2, cf2);
+            const R fx = ld(xo, cf0), fy = ld(xo, cf1);
+            if (c == 0 && r0) r0[0] = fx, r0[1] = fy, r0[2] = fz[0];
             R div = R(0);
-            div += (ld(xo + s0, cf0) - ld(xo, cf0)) * ix;
-            div += (ld(xo + s1, cf1) - ld(xo, cf1)) * iy;
+            div += (ld(xo + s0, cf0) - fx) * ix;
+            div += (ld(xo + s1, cf1) - fy) * iy;
             div += (fzn - fz[c]) * iz;
             const R q = ld(xo, qs + c * VB);
             u[c] = q - hdt * div;
@@ -659,16 +668,18 @@ __device__ __forceinline__ double update_tile(const WorkItem w, R* __restrict__ 
     // Step 9 at tile-local edge position (i, j) of plane p, components in mask
     // (bit c).  cx: flux_y rows 0 and 5, cy: flux_x rows 0 and 6, both at (i, j)
     // of plane p-1 (carried, loaded when fresh); replaced by those of plane p.
-    auto ed_item = [&](int i, int j, int p, int mask, R(&cx)[2], R(&cy)[2], bool fresh) {
+    auto ed_item = [&](int i, int j, int p, int mask, R(&cx)[2], R(&cy)[2], bool fresh, const R* r0) {
         const unsigned xo = zoff(i, j, p);
+        // the rho rows on the position's lower faces (from Step 8 when given)
+        const R fx0 = r0 ? r0[0] : ld(xo, FX), fy0 = r0 ? r0[1] : ld(xo, FY), fz0 = r0 ? r0[2] : ld(xo, FZ);
         const int ri = (j + 1) * TXP + (i + 1), e = j * TXE + i;
         const R* ec = s_er + (p & 1) * 3 * UPD_ERMAX + ri;        // E^r of plane p at the edge's zone
         const R* ep = s_er + ((p - 1) & 1) * 3 * UPD_ERMAX + ri;  // plane p-1
         R* dst = s_ed + (p & 1) * 3 * UPD_EDMAX + e;
         if (mask & 1) {  // E_x: a = y, b = z
             if (fresh) cx[0] = ld(xo - s2, FY), cx[1] = ld(xo - s2, FY + 5 * VB);
-            const R ma = ld(xo, FY), fa5 = ld(xo, FY + 5 * VB);
-            const R mb = ld(xo, FZ), fb6 = ld(xo, FZ + 6 * VB), mba = ld(xo - s1, FZ), fb6a = ld(xo - s1, FZ + 6 * VB);
+            const R ma = fy0, fa5 = ld(xo, FY + 5 * VB);
+            const R mb = fz0, fb6 = ld(xo, FZ + 6 * VB), mba = ld(xo - s1, FZ), fb6a = ld(xo - s1, FZ + 6 * VB);
             const R E = edge_combine(-fa5, -cx[1], fb6, fb6a, ma, cx[0], mb, mba, ec[0], ec[-TXP], ep[0], ep[-TXP]);
             dst[0] = E;
             if (keep_edges) bstore(E, rs, xo, (unsigned)F_ED * VB);
@@ -676,8 +687,8 @@ __device__ __forceinline__ double update_tile(const WorkItem w, R* __restrict__ 
         }
         if (mask & 2) {  // E_y: a = z, b = x
             if (fresh) cy[0] = ld(xo - s2, FX), cy[1] = ld(xo - s2, FX + 6 * VB);
-            const R ma = ld(xo, FZ), fa5 = ld(xo, FZ + 5 * VB), mab = ld(xo - s0, FZ), fa5b = ld(xo - s0, FZ + 5 * VB);
-            const R mb = ld(xo, FX), fb6 = ld(xo, FX + 6 * VB);
+            const R ma = fz0, fa5 = ld(xo, FZ + 5 * VB), mab = ld(xo - s0, FZ), fa5b = ld(xo - s0, FZ + 5 * VB);
+            const R mb = fx0, fb6 = ld(xo, FX + 6 * VB);
             const R* c1 = ec + UPD_ERMAX;
             const R* p1 = ep + UPD_ERMAX;
             const R E = edge_combine(-fa5, -fa5b, fb6, cy[1], ma, mab, mb, cy[0], c1[0], p1[0], c1[-1], p1[-1]);
@@ -686,8 +697,8 @@ __device__ __forceinline__ double update_tile(const WorkItem w, R* __restrict__ 
             cy[0] = mb, cy[1] = fb6;
         }
         if (mask & 4) {  // E_z: a = x, b = y
-            const R ma = ld(xo, FX), fa5 = ld(xo, FX + 5 * VB), mab = ld(xo - s1, FX), fa5b = ld(xo - s1, FX + 5 * VB);
-            const R mb = ld(xo, FY), fb6 = ld(xo, FY + 6 * VB), mba = ld(xo - s0, FY), fb6a = ld(xo - s0, FY + 6 * VB);
+            const R ma = fx0, fa5 = ld(xo, FX + 5 * VB), mab = ld(xo - s1, FX), fa5b = ld(xo - s1, FX + 5 * VB);
+            const R mb = fy0, fb6 = ld(xo, FY + 6 * VB), mba = ld(xo - s0, FY), fb6a = ld(xo - s0, FY + 6 * VB);
             const R* c2 = ec + 2 * UPD_ERMAX;
             const R E = edge_combine(-fa5, -fa5b, fb6, fb6a, ma, mab, mb, mba, c2[0], c2[-1], c2[-TXP], c2[-1 - TXP]);
             dst[2 * UPD_EDMAX] = E;
@@ -699,24 +710,25 @@ __device__ __forceinline__ double update_tile(const WorkItem w, R* __restrict__ 
     R fz_o[4], fz_r[4], bz_o = R(0), bz_r = R(0);
     R cx_o[2], cy_o[2], cx_x[2], cy_x[2];
     R ufc[4], ufn[4];  // q - dt div F (rows 0-3) of the own zone on planes k and k+1
+    R r0o[3];          // rho rows of the own zone's lower-face fluxes (Step 8 -> Step 9)
     R fz4 = R(0), bzc = R(0);  // flux_z row 4 and b^{n+1}_z on the lower face of plane k
     double sp = 0.0;
 
     // prologue: E^r of planes k0-1 and k0, edges of plane k0
-    if (owner) er_item(zi, zj, k0 - 1, fz_o, bz_o, true, nullptr);
-    if (ring) er_item(rx, ry, k0 - 1, fz_r, bz_r, true, nullptr);
-    if (owner) er_item(zi, zj, k0, fz_o, bz_o, false, ufc);
-    if (ring) er_item(rx, ry, k0, fz_r, bz_r, false, nullptr);
+    if (owner) er_item(zi, zj, k0 - 1, fz_o, bz_o, true, nullptr, nullptr);
+    if (ring) er_item(rx, ry, k0 - 1, fz_r, bz_r, true, nullptr, nullptr);
+    if (owner) er_item(zi, zj, k0, fz_o, bz_o, false, ufc, r0o);
+    if (ring) er_item(rx, ry, k0, fz_r, bz_r, false, nullptr, nullptr);
     __syncthreads();
-    if (owner) ed_item(zi, zj, k0, 7, cx_o, cy_o, true);
-    if (extra) ed_item(xi, xj, k0, xmask, cx_x, cy_x, true);
+    if (owner) ed_item(zi, zj, k0, 7, cx_o, cy_o, true, r0o);
+    if (extra) ed_item(xi, xj, k0, xmask, cx_x, cy_x, true, nullptr);
     __syncthreads();
     for (int k = k0; k < k1; k++) {
-        if (owner) er_item(zi, zj, k + 1, fz_o, bz_o, false, ufn);
-        if (ring) er_item(rx, ry, k + 1, fz_r, bz_r, false, nullptr);
+        if (owner) er_item(zi, zj, k + 1, fz_o, bz_o, false, ufn, r0o);
+        if (ring) er_item(rx, ry, k + 1, fz_r, bz_r, false, nullptr, nullptr);
         __syncthreads();
-        if (owner) ed_item(zi, zj, k + 1, 7, cx_o, cy_o, false);
-        if (extra) ed_item(xi, xj, k + 1, xmask, cx_x, cy_x, false);
+        if (owner) ed_item(zi, zj, k + 1, 7, cx_o, cy_o, false, r0o);
+        if (extra) ed_item(xi, xj, k + 1, xmask, cx_x, cy_x, false, nullptr);
         __syncthreads();
         if (owner) {
             const unsigned xo = zoff(zi, zj, k);
