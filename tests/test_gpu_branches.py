@@ -123,8 +123,8 @@ def test_floors_einfeldt_line(wmb, prec):
     pressure floors fire every step (128 zones a step).  FP64 on the oracle's
     dt: every field within 1e-10 of its group's scale and the same number of
     floor activations after 5 steps.  FP32 (floors still decided in FP64):
-    relative L1 of rho and E within 1e-4, floors fired, no zone below a
-    floor."""
+    relative L1 of rho and E within 1e-6 (measured 3e-8), floors fired, no
+    zone below a floor."""
     G, q, b, kw = _einfeldt()
     qs, bs = (as_f32(q), as_f32(b)) if prec else (q, b)
     sim = gpu_sim(wmb, G, qs, bs, prec, **kw)
@@ -152,7 +152,8 @@ def test_floors_einfeldt_line(wmb, prec):
         assert np.abs(bg - bo).max() <= 1e-10 * np.abs(bo).max()
     else:
         assert nfl > 0
-        assert _rel_l1(qg[0], qo[0]) <= 1e-4 and _rel_l1(qg[7], qo[7]) <= 1e-4
+        print("floors fp32: relL1 rho %.2e E %.2e" % (_rel_l1(qg[0], qo[0]), _rel_l1(qg[7], qo[7])))
+        assert _rel_l1(qg[0], qo[0]) <= 1e-6 and _rel_l1(qg[7], qo[7]) <= 1e-6
     rho = qg[0]
     p = 0.4 * (qg[7] - 0.5 * (qg[1] ** 2 + qg[2] ** 2 + qg[3] ** 2) / rho - 0.5 * (qg[4:7] ** 2).sum(0))
     assert rho.min() >= 0.3 * (1 - 1e-6) and p.min() >= 1e-3 * (1 - 1e-3)

@@ -768,8 +768,8 @@ def _run_pair(wmb, G, q, b, prec, nsteps, **kw):
 def test_protection_strong_rarefaction(wmb, prec):
     """Einfeldt-type line (rho = 1, P = 0.4, v = -/+3, gamma = 1.4, B_x = 0.1)
     along x: a strong rarefaction and a strong shock.  Protection floors 1e-3:
-    FP64 matches the oracle to 1e-10 of each field's scale, FP32 to 1e-4 in
-    relative L1; faces were protected, the state stays positive and no floor
+    FP64 matches the oracle to 1e-10 of each field's scale, FP32 to 1e-6 in
+    relative L1 (measured 2e-8, 3e-8); faces were protected, the state stays positive and no floor
     fired.  Without protection the oracle needs its floors here."""
     G = I.patch_grid([32, 32], [8], [8])
     q, b = I.shock_tube_x(G.shape, gamma=1.4, left=(1.0, -3.0, 0.0, 0.0, 0.0, 0.0, 0.4),
@@ -790,7 +790,8 @@ def test_protection_strong_rarefaction(wmb, prec):
             scale = max(np.abs(qo[c]).max(), np.abs(qo[1:4]).max() if 1 <= c <= 3 else 0.0, 1e-300)
             assert np.abs(qg[c] - qo[c]).max() <= 1e-10 * scale, c
     else:
-        assert _rel_l1(qg[0], qo[0]) <= 1e-4 and _rel_l1(qg[7], qo[7]) <= 1e-4
+        print("protection fp32: relL1 rho %.2e E %.2e" % (_rel_l1(qg[0], qo[0]), _rel_l1(qg[7], qo[7])))
+        assert _rel_l1(qg[0], qo[0]) <= 1e-6 and _rel_l1(qg[7], qo[7]) <= 1e-6
     sim.close()
     orc.close()
     # the same line without protection: the floors are needed
@@ -1176,8 +1177,8 @@ def test_protection_with_outflow_ends(wmb, prec):
     """The Einfeldt-type line (v = -/+3 out of the middle, gamma 1.4) with
     outflow at both x ends and protection floors 1e-3: the rarefaction
     empties the middle while material leaves through the ends.  FP64 within
-    1e-10 of each field group's scale, FP32 within 1e-4 relative L1;
-    positive density, no floor fired."""
+    1e-10 of each field group's scale, FP32 within 1e-6 relative L1
+    (measured 2e-8); positive density, no floor fired."""
     G = I.patch_grid([32, 32], [8], [8], periodic=(False, True, True))
     q, b = I.shock_tube_x(G.shape, gamma=1.4, left=(1.0, -3.0, 0.0, 0.0, 0.0, 0.0, 0.4),
                           right=(1.0, 3.0, 0.0, 0.0, 0.0, 0.0, 0.4), bx=0.1)
@@ -1195,8 +1196,9 @@ def test_protection_with_outflow_ends(wmb, prec):
             scale = np.abs(qo[1:4]).max() if 1 <= c <= 3 else (np.abs(qo[4:7]).max() if 4 <= c <= 6 else np.abs(qo[c]).max())
             assert np.abs(qg[c] - qo[c]).max() <= 1e-10 * max(scale, 1e-300), c
     else:
+        print("protection+outflow fp32: relL1 rho %.2e E %.2e" % (_rel_l1(qg[0], qo[0]), _rel_l1(qg[7], qo[7])))
         for c in (0, 7):
-            assert _rel_l1(qg[c], qo[c]) <= 1e-4, c
+            assert _rel_l1(qg[c], qo[c]) <= 1e-6, c
     sim.close()
     orc.close()
 

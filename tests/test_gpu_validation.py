@@ -83,8 +83,9 @@ def _rel_l1(a, ref):
 @pytest.mark.parametrize("name", sorted(TUBES))
 def test_gpu_shock_tube(wmb, name, prec):
     """FP64: within 1e-10 of each field group's scale at the printed time.
-    FP32: relative L1 of rho and E within 1e-4 (shocks and the limiter's
-    branch points amplify FP32 rounding locally), positivity, no floor."""
+    FP32: relative L1 of rho and E within 1e-6 (measured 3e-8 to 9e-8;
+    shocks and the limiter's branch points amplify FP32 rounding locally, so
+    the per-zone maximum is larger), positivity, no floor."""
     left, right, bx, gamma, t_end = TUBES[name]
     G, q, b, dx = _tube_state(left, right, bx, gamma, 128)
     qg, bg, qo, bo, diag, steps = _run_both(wmb, G, q, b, prec, t_end, dx=dx, gamma=gamma, cfl=0.4)
@@ -95,7 +96,7 @@ def test_gpu_shock_tube(wmb, name, prec):
         assert _scaled_max(qg, qo).max() <= 1e-10
         assert np.abs(bg - bo).max() <= 1e-10 * np.abs(bo).max()
     else:
-        assert _rel_l1(qg[0], qo[0]) <= 1e-4 and _rel_l1(qg[7], qo[7]) <= 1e-4
+        assert _rel_l1(qg[0], qo[0]) <= 1e-6 and _rel_l1(qg[7], qo[7]) <= 1e-6
         assert qg[0].min() > 0
 
 
