@@ -131,7 +131,8 @@ TUNING64_PROF = "1x32=6,1y32=-256,1z32=-256,2x32=3,2y32=-64,2z32=-64"
 COUNTER_ARGS = ("--steps 2 --warmup 1 --prof-steps 0 --no-fp64 --no-cpu-baseline --schedule 1 --calib-copy "
                 "--tuning32 " + TUNING32_PROF)
 SQ_COUNTERS = "SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES GRBM_GUI_ACTIVE"
-TRACE_ARGS = ("--steps 5 --warmup 1 --prof-steps 3 --no-cpu-baseline --no-uneven --no-c4 --no-c5 --no-divb --schedule 1 "
+TRACE_ARGS = ("--steps 5 --warmup 1 --prof-steps 3 --no-cpu-baseline --no-uneven --no-c4 --no-c5 --no-divb "
+              "--no-scratch-groups --schedule 1 "
               "--tuning32 " + TUNING32_PROF + " --tuning64 " + TUNING64_PROF)
 
 
@@ -485,7 +486,9 @@ def run_batch(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps, tuning=Non
     else:
         tuning = sim.autotune(reps=3)
     log("bench: pencils per block %s" % W.tuning_to_str(tuning))
-    if SCHEDULE:
+    if params.get("scratch_groups", 0) > 1:  # the schedule is the scratch groups, one after another
+        groups, sched_ms = params["scratch_groups"], None
+    elif SCHEDULE:
         groups, sched_ms = SCHEDULE, None
         sim.set_schedule(groups)
     else:
@@ -531,7 +534,8 @@ def run_batch(W, G, q, b, dx, prec, ghost, steps, warmup, prof_steps, tuning=Non
         # normalised div b against the step count, from the initial state
         sim = make_sim(W, G, q, b, dx, prec, ghost, stream, **params)
         sim.set_tuning(tuning)
-        sim.set_schedule(groups)
+        if params.get("scratch_groups", 0) <= 1:
+            sim.set_schedule(groups)
         done, curve = 0, {}
         for n in sorted(divb_at):
             sim.run_steps(n - done)
@@ -568,6 +572,8 @@ def main():
     ap.add_argument("--frozen", action="store_true",
                     help="also time the FP32 batch with every other patch frozen (checkerboard), graphs reused")
     ap.add_argument("--no-divb", action="store_true", help="skip the div b against step count runs")
+    ap.add_argument("--no-scratch-groups", action="store_true",
+                    help="skip the FP32 batch with the step intermediates shared by 4 patch groups (reported beside)")
     ap.add_argument("--planar", action="store_true",
                     help="also time the planar Orszag-Tang vortex (192^2 and 2048^2) run as one-patch-thin 3D boxes")
     ap.add_argument("--schedule", type=int, default=0,
@@ -648,6 +654,21 @@ def main():
                   "value": Gu.zones() * args.steps / (msu / 1e3), "kernels_ms": kernu, **diagu,
                   "roofline": roofline(Gu.descs, g, 4, Gu.zones(), msu / args.steps, kernu)}
         log("bench: uneven FP32 %.3f ms/step, %.3e zone-updates/s" % (msu / args.steps, uneven["value"]))
+
+    shared = None
+    if not args.no_scratch_groups and args.prof_steps > 0:
+        # the same batch with the step intermediates shared by 4 patch groups
+        # whose steps run one after another: a smaller pool for a slower step
+        log("bench: FP32 batch with 4 scratch groups")
+        mss, _, kerns, diags = run_batch(W, G, q, b, dx, W.WMB_FP32, g, args.steps, args.warmup, 1,
+                                         W.tuning_from_str(args.tuning32), scratch_groups=4)
+        p1 = W.pool_bytes(W.make_params(dx=dx, precision=W.WMB_FP32, ghost=g), G.descs)
+        p4 = W.pool_bytes(W.make_params(dx=dx, precision=W.WMB_FP32, ghost=g, scratch_groups=4), G.descs)
+        shared = {"workload": "the FP32 batch with scratch_groups = 4 (22 + 51/4 words a ghosted zone)",
+                  "pool_bytes": p4, "pool_bytes_default": p1, "ms_per_step": mss / args.steps,
+                  "value": zones * args.steps / (mss / 1e3), "kernels_ms": kerns, **diags}
+        log("bench: scratch groups 4: %.3f ms/step, pool %.2f GB against %.2f GB" % (mss / args.steps, p4 / 1e9,
+                                                                                    p1 / 1e9))
 
     c4 = None
     if not args.no_c4 and args.prof_steps > 0:
@@ -778,6 +799,7 @@ def main():
         "fp32_diag": diag32,
         "fp64": fp64,
         "uneven_fp32": uneven,
+        "scratch_groups_fp32": shared,
         "c4_fp32": c4,
         "c5_fp32": c5,
         "protection_fp32": protection,

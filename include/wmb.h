@@ -75,6 +75,15 @@ typedef struct wmb_params {
                             q^(n-1), the state one step earlier (the first step of
                             a run from q^0): the paper delays the dt reduction by
                             one step to overlap it with work (Sect. 4.1.1) */
+    int32_t scratch_groups; /* 0 or 1 (default): every patch has its own space for
+                            the step's intermediates (51 words a ghosted zone
+                            beside its 22 words of state).  G = 2..64: the
+                            patches are dealt, whole x-rows at a time, to G
+                            groups whose steps run one after another and share
+                            one space for the intermediates, sized for the
+                            largest group: the pool takes 22 + 51/G words a
+                            zone (at G = 4, 34.75).  The step schedule is then
+                            fixed to those groups (wmb_set_schedule) */
 } wmb_params;
 
 typedef struct wmb_patch_desc {
@@ -91,18 +100,20 @@ typedef struct wmb_patch_desc {
 typedef struct wmb_ctx wmb_ctx;
 
 /* Create a context.  Validates p (gamma > 1, cfl in (0,1], ghost >= 4,
-   dx > 0, precision known, protection floors >= 0, dt_lag 0 or 1).  *out
-   receives the context. */
+   dx > 0, precision known, protection floors >= 0, dt_lag 0 or 1,
+   scratch_groups 0..64).  *out receives the context. */
 int wmb_create(const wmb_params *p, wmb_ctx **out);
 
-/* Device bytes the caller must provide for npatch patches: two state copies
-   (11 words per stored zone each) plus the step's intermediates. */
+/* Device bytes the caller must provide for npatch patches: each patch's
+   state region (two state copies, 11 words per stored zone each), then the
+   space for the step's intermediates (51 words per stored zone: a slot per
+   patch, or with scratch groups a slot per patch of the largest group). */
 int wmb_pool_bytes(const wmb_params *p, int32_t npatch, const wmb_patch_desc *d, uint64_t *bytes);
 
 /* Bind the patches to the caller's device pool and stream (hipStream_t, NULL
    = default stream).  Checks the neighbour table (face extents agree, the
    neighbour of my neighbour is me; every interior edge at least the ghost
-   width; a patch region, 73 words per ghosted zone, at most 4 GiB) and
+   width; a patch's intermediates, 51 words per ghosted zone, at most 4 GiB) and
    builds the launch plans.  The pool's
    contents are undefined until wmb_set_state has been called for every
    patch.  WMB_ESIZE if pool_bytes < wmb_pool_bytes. */
@@ -202,7 +213,8 @@ int wmb_diagnostics_noalloc(wmb_ctx *c, double *dev_out);
    (3 x 8 x vol, lab component order, B_par row 0), 3 b^{n+1/2} (3 x vol),
    5 Step-6/7 fluxes (3 x 8 x vol), 6 Step-9 edge EMFs (3 x vol; only after
    a step run with wmb_keep_stages on, else WMB_ESTATE).  Values outside the
-   ranges the step needs are unspecified.  Other stages (the Step-3 edges are
+   ranges the step needs are unspecified; with scratch groups only the
+   patches of the last group hold their own.  Other stages (the Step-3 edges are
    overwritten by Step 9) give WMB_EINVAL.  Synchronous. */
 int wmb_debug_stage(wmb_ctx *c, int32_t patch, int32_t stage, double *out);
 

@@ -52,20 +52,27 @@ struct PatchDev {
     int active;  // 0: frozen (no kernel updates it; its state is the same in both copies)
     int present; // 0: the slot is absent from the domain (removed: no neighbour links to it,
                  //    no kernel reads or writes it; also inactive)
-    long long base;
+    long long base;   // the patch's state region in the pool (words)
+    long long sbase;  // its step intermediates (words; shared with the patches of
+                      // other scratch groups, whose steps run at other times)
     long long vol;
 };
 
-// Field slots of a patch, in units of vol.
+// Field slots of a patch, in units of vol: the state region (kept between
+// steps) ...
 enum : int {
     F_ST0 = 0,   // state copy 0: q (8) then b (3)
     F_ST1 = 11,  // state copy 1
-    F_FL1 = 22,  // Step-1 fluxes, 3 directions x 7 rows
-    F_FL2 = 43,  // Step-6/7 fluxes, 3 directions x 7 rows
-    F_ED = 64,   // edge EMFs (3), reused by Steps 3 and 9
-    F_BH = 67,   // b^{n+1/2} (3)
-    F_ER = 70,   // zone-centred reference EMF (3), reused by Steps 2 and 8
-    F_TOTAL = 73
+    F_STATE = 22
+};
+// ... and the step's intermediates (written and read within one step).
+enum : int {
+    F_FL1 = 0,   // Step-1 fluxes, 3 directions x 7 rows
+    F_FL2 = 21,  // Step-6/7 fluxes, 3 directions x 7 rows
+    F_ED = 42,   // edge EMFs (3), reused by Steps 3 and 9
+    F_BH = 45,   // b^{n+1/2} (3)
+    F_ER = 48,   // zone-centred reference EMF (3), reused by Steps 2 and 8
+    F_SCRATCH = 51
 };
 // Row order of a flux array of direction d: rho, mx, my, mz, E, B_{d+1}, B_{d+2}
 // (the B_d row of the 1D flux is identically zero and is not stored).

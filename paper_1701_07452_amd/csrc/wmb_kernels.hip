@@ -459,7 +459,8 @@ __global__ void __launch_bounds__(TILE_THREADS) ct_half_kernel(R* __restrict__ p
     const int g = ghost;
     const unsigned VB = (unsigned)P.vol * ES;
     const unsigned s0 = ES, s1 = (unsigned)P.N[0] * ES, s2 = (unsigned)(P.N[0] * P.N[1]) * ES;
-    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + P.base, (unsigned)F_TOTAL * VB);
+    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + P.base, (unsigned)F_STATE * VB);     // state
+    const __amdgpu_buffer_rsrc_t rw = patch_rsrc(pool + P.sbase, (unsigned)F_SCRATCH * VB);  // step intermediates
     const unsigned bs = (unsigned)((cur ? F_ST1 : F_ST0) + 8) * VB;
     const unsigned FX = (unsigned)F_FL1 * VB, FY = FX + 7 * VB, FZ = FY + 7 * VB, ER = (unsigned)F_ER * VB;
     const R tau = sc_hdt(*sc, R(0));
@@ -470,7 +471,7 @@ __global__ void __launch_bounds__(TILE_THREADS) ct_half_kernel(R* __restrict__ p
     auto zoff = [&](int i, int j, int k) -> unsigned {
         return (unsigned)sidx(P, i0 + i + g, j0 + j + g, k + g) * ES;
     };
-    auto ld = [&](unsigned voff, unsigned soff) -> R { return bload(z0, rs, voff, soff); };
+    auto ld = [&](unsigned voff, unsigned soff) -> R { return bload(z0, rw, voff, soff); };
 
     const bool owner = t < tx * ty;
     const int zj = owner ? small_div(t, 65536 / tx + 1) : 0, zi = owner ? t - zj * tx : 0;
@@ -537,15 +538,15 @@ __global__ void __launch_bounds__(TILE_THREADS) ct_half_kernel(R* __restrict__ p
             const R* ey1 = ex1 + CTH_EDMAX;
             if (jy_in && kz_in) {
                 R curl = (ez0[e + TXE] - ez0[e]) * iy - (ey1[e] - ey0[e]) * iz;
-                bstore(ld(xo, bs) - tau * curl, rs, xo, (unsigned)F_BH * VB);
+                bstore(bload(z0, rs, xo, bs) - tau * curl, rw, xo, (unsigned)F_BH * VB);
             }
             if (ix_in && kz_in) {
                 R curl = (ex1[e] - ex0[e]) * iz - (ez0[e + 1] - ez0[e]) * ix;
-                bstore(ld(xo, bs + VB) - tau * curl, rs, xo, (unsigned)(F_BH + 1) * VB);
+                bstore(bload(z0, rs, xo, bs + VB) - tau * curl, rw, xo, (unsigned)(F_BH + 1) * VB);
             }
             if (ix_in && jy_in) {
                 R curl = (ey0[e + 1] - ey0[e]) * ix - (ex0[e + TXE] - ex0[e]) * iy;
-                bstore(ld(xo, bs + 2 * VB) - tau * curl, rs, xo, (unsigned)(F_BH + 2) * VB);
+                bstore(bload(z0, rs, xo, bs + 2 * VB) - tau * curl, rw, xo, (unsigned)(F_BH + 2) * VB);
             }
         }
     }
@@ -593,7 +594,8 @@ __device__ __forceinline__ double update_tile(const WorkItem w, R* __restrict__ 
     const int g = prm.ghost;
     const unsigned VB = (unsigned)P.vol * ES;
     const unsigned s0 = ES, s1 = (unsigned)P.N[0] * ES, s2 = (unsigned)(P.N[0] * P.N[1]) * ES;
-    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + P.base, (unsigned)F_TOTAL * VB);
+    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + P.base, (unsigned)F_STATE * VB);     // state
+    const __amdgpu_buffer_rsrc_t rw = patch_rsrc(pool + P.sbase, (unsigned)F_SCRATCH * VB);  // step intermediates
     const unsigned qs = (unsigned)(cur ? F_ST1 : F_ST0) * VB, bs = qs + 8 * VB;
     const unsigned qn = (unsigned)(cur ? F_ST0 : F_ST1) * VB, bn = qn + 8 * VB;
     const unsigned FX = (unsigned)F_FL2 * VB, FY = FX + 7 * VB, FZ = FY + 7 * VB, BH = (unsigned)F_BH * VB;
@@ -605,7 +607,8 @@ __device__ __forceinline__ double update_tile(const WorkItem w, R* __restrict__ 
     auto zoff = [&](int i, int j, int k) -> unsigned {
         return (unsigned)sidx(P, i0 + i + g, j0 + j + g, k + g) * ES;
     };
-    auto ld = [&](unsigned voff, unsigned soff) -> R { return bload(z0, rs, voff, soff); };
+    auto ld = [&](unsigned voff, unsigned soff) -> R { return bload(z0, rw, voff, soff); };
+    auto lds = [&](unsigned voff, unsigned soff) -> R { return bload(z0, rs, voff, soff); };
 
     // own zone (every thread of a full tile), ring zone of E^r, extra edge position
     const bool owner = t < tx * ty;
@@ -646,7 +649,7 @@ __device__ __forceinline__ double update_tile(const WorkItem w, R* __restrict__ 
             div += (ld(xo + s0, cf0) - fx) * ix;
             div += (ld(xo + s1, cf1) - fy) * iy;
             div += (fzn - fz[c]) * iz;
-            const R q = ld(xo, qs + c * VB);
+            const R q = lds(xo, qs + c * VB);
             u[c] = q - hdt * div;
             if (uf) uf[c] = q - dt * div;
             fz[c] = fzn;
@@ -682,7 +685,7 @@ __device__ __forceinline__ double update_tile(const WorkItem w, R* __restrict__ 
             const R mb = fz0, fb6 = ld(xo, FZ + 6 * VB), mba = ld(xo - s1, FZ), fb6a = ld(xo - s1, FZ + 6 * VB);
             const R E = edge_combine(-fa5, -cx[1], fb6, fb6a, ma, cx[0], mb, mba, ec[0], ec[-TXP], ep[0], ep[-TXP]);
             dst[0] = E;
-            if (keep_edges) bstore(E, rs, xo, (unsigned)F_ED * VB);
+            if (keep_edges) bstore(E, rw, xo, (unsigned)F_ED * VB);
             cx[0] = ma, cx[1] = fa5;
         }
         if (mask & 2) {  // E_y: a = z, b = x
@@ -693,7 +696,7 @@ __device__ __forceinline__ double update_tile(const WorkItem w, R* __restrict__ 
             const R* p1 = ep + UPD_ERMAX;
             const R E = edge_combine(-fa5, -fa5b, fb6, cy[1], ma, mab, mb, cy[0], c1[0], p1[0], c1[-1], p1[-1]);
             dst[UPD_EDMAX] = E;
-            if (keep_edges) bstore(E, rs, xo, (unsigned)(F_ED + 1) * VB);
+            if (keep_edges) bstore(E, rw, xo, (unsigned)(F_ED + 1) * VB);
             cy[0] = mb, cy[1] = fb6;
         }
         if (mask & 4) {  // E_z: a = x, b = y
@@ -702,7 +705,7 @@ __device__ __forceinline__ double update_tile(const WorkItem w, R* __restrict__ 
             const R* c2 = ec + 2 * UPD_ERMAX;
             const R E = edge_combine(-fa5, -fa5b, fb6, fb6a, ma, mab, mb, mba, c2[0], c2[-1], c2[-TXP], c2[-1 - TXP]);
             dst[2 * UPD_EDMAX] = E;
-            if (keep_edges) bstore(E, rs, xo, (unsigned)(F_ED + 2) * VB);
+            if (keep_edges) bstore(E, rw, xo, (unsigned)(F_ED + 2) * VB);
         }
     };
 
@@ -743,7 +746,7 @@ __device__ __forceinline__ double update_tile(const WorkItem w, R* __restrict__ 
                 div += (ld(xo + s0, FX + 4 * VB) - ld(xo, FX + 4 * VB)) * ix;
                 div += (ld(xo + s1, FY + 4 * VB) - ld(xo, FY + 4 * VB)) * iy;
                 div += (fz4n - fz4) * iz;
-                u[7] = ld(xo, qs + 7 * VB) - dt * div;
+                u[7] = lds(xo, qs + 7 * VB) - dt * div;
                 fz4 = fz4n;
             }
             const R* ex0 = s_ed + (k & 1) * 3 * UPD_EDMAX;  // E_x, plane k
@@ -754,14 +757,14 @@ __device__ __forceinline__ double update_tile(const WorkItem w, R* __restrict__ 
             const int e = zj * TXE + zi;
             // Step 11 on the two faces of the zone along each axis (the lower
             // z-face is the upper one of the plane below)
-            R bxl = ld(xo, bs) - dt * ((ez0[e + TXE] - ez0[e]) * iy - (ey1[e] - ey0[e]) * iz);
-            R bxr = ld(xo + s0, bs) - dt * ((ez0[e + 1 + TXE] - ez0[e + 1]) * iy - (ey1[e + 1] - ey0[e + 1]) * iz);
-            R byl = ld(xo, bs + VB) - dt * ((ex1[e] - ex0[e]) * iz - (ez0[e + 1] - ez0[e]) * ix);
-            R byr = ld(xo + s1, bs + VB) -
+            R bxl = lds(xo, bs) - dt * ((ez0[e + TXE] - ez0[e]) * iy - (ey1[e] - ey0[e]) * iz);
+            R bxr = lds(xo + s0, bs) - dt * ((ez0[e + 1 + TXE] - ez0[e + 1]) * iy - (ey1[e + 1] - ey0[e + 1]) * iz);
+            R byl = lds(xo, bs + VB) - dt * ((ex1[e] - ex0[e]) * iz - (ez0[e + 1] - ez0[e]) * ix);
+            R byr = lds(xo + s1, bs + VB) -
                     dt * ((ex1[e + TXE] - ex0[e + TXE]) * iz - (ez0[e + 1 + TXE] - ez0[e + TXE]) * ix);
-            if (k == k0) bzc = ld(xo, bs + 2 * VB) - dt * ((ey0[e + 1] - ey0[e]) * ix - (ex0[e + TXE] - ex0[e]) * iy);
+            if (k == k0) bzc = lds(xo, bs + 2 * VB) - dt * ((ey0[e + 1] - ey0[e]) * ix - (ex0[e + TXE] - ex0[e]) * iy);
             R bzl = bzc;
-            R bzr = ld(xo + s2, bs + 2 * VB) - dt * ((ey1[e + 1] - ey1[e]) * ix - (ex1[e + TXE] - ex1[e]) * iy);
+            R bzr = lds(xo + s2, bs + 2 * VB) - dt * ((ey1[e + 1] - ey1[e]) * ix - (ex1[e + TXE] - ex1[e]) * iy);
             bzc = bzr;
             bstore(bxl, rs, xo, bn);
             bstore(byl, rs, xo, bn + VB);
@@ -793,7 +796,7 @@ __device__ __forceinline__ double update_tile(const WorkItem w, R* __restrict__ 
                     const PatchDev Q = patches[nbq];
                     const int qi = side == 0 ? Q.n[0] + gi : gi - P.n[0];
                     const unsigned QB = (unsigned)Q.vol * ES;
-                    const __amdgpu_buffer_rsrc_t rq = patch_rsrc(pool + Q.base, (unsigned)F_TOTAL * QB);
+                    const __amdgpu_buffer_rsrc_t rq = patch_rsrc(pool + Q.base, (unsigned)F_STATE * QB);
                     const unsigned yo = (unsigned)sidx(Q, qi + g, j0 + zj + g, k + g) * ES;
                     const unsigned qq = (unsigned)(cur ? F_ST0 : F_ST1) * QB;
 #pragma unroll
@@ -994,9 +997,10 @@ struct ZoneRaw {
     R fa[STAGE == 2 ? 7 : 1][2], fb[STAGE == 2 ? 7 : 1][2], b[STAGE == 2 ? 3 : 1][2];
 };
 
+// rs: the patch's state, rw: its step intermediates (the Step-1 fluxes)
 template <typename R, int D, int STAGE>
-__device__ __forceinline__ void zone_fetch(__amdgpu_buffer_rsrc_t rs, unsigned xo, const unsigned st[3], unsigned qs,
-                                           unsigned VB, ZoneRaw<R, STAGE>& z) {
+__device__ __forceinline__ void zone_fetch(__amdgpu_buffer_rsrc_t rs, __amdgpu_buffer_rsrc_t rw, unsigned xo,
+                                           const unsigned st[3], unsigned qs, unsigned VB, ZoneRaw<R, STAGE>& z) {
     constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
     constexpr unsigned ES = sizeof(R);
     const R z0 = R(0);
@@ -1009,10 +1013,10 @@ __device__ __forceinline__ void zone_fetch(__amdgpu_buffer_rsrc_t rs, unsigned x
         for (int r = 0; r < 7; r++) {
             // rows 0-4, then A1's row 6 / A2's row 5 (B_D), then A1's row 5 / A2's row 6
             const int ra = r < 5 ? r : (r == 5 ? 6 : 5), rb = r < 5 ? r : (r == 5 ? 5 : 6);
-            z.fa[r][0] = bload(z0, rs, xo, f1 + ra * VB);
-            z.fa[r][1] = bload(z0, rs, xo, f1 + ra * VB + s1);
-            z.fb[r][0] = bload(z0, rs, xo, f2 + rb * VB);
-            z.fb[r][1] = bload(z0, rs, xo, f2 + rb * VB + s2);
+            z.fa[r][0] = bload(z0, rw, xo, f1 + ra * VB);
+            z.fa[r][1] = bload(z0, rw, xo, f1 + ra * VB + s1);
+            z.fb[r][0] = bload(z0, rw, xo, f2 + rb * VB);
+            z.fb[r][1] = bload(z0, rw, xo, f2 + rb * VB + s2);
         }
         const unsigned bs = qs + 8 * VB;
 #pragma unroll
@@ -1091,11 +1095,11 @@ __device__ __forceinline__ Rec8<R> zone_record(const ZoneRaw<R, STAGE>& z, const
 }
 
 template <typename R, int D, int STAGE>
-__device__ __forceinline__ Rec8<R> zone_phase(__amdgpu_buffer_rsrc_t rs, unsigned xo, const unsigned st[3], unsigned qs,
-                                              unsigned VB, const Coef<R>& cf, const DevParams& prm,
-                                              const StepConst& sc) {
+__device__ __forceinline__ Rec8<R> zone_phase(__amdgpu_buffer_rsrc_t rs, __amdgpu_buffer_rsrc_t rw, unsigned xo,
+                                              const unsigned st[3], unsigned qs, unsigned VB, const Coef<R>& cf,
+                                              const DevParams& prm, const StepConst& sc) {
     ZoneRaw<R, STAGE> z;
-    zone_fetch<R, D, STAGE>(rs, xo, st, qs, VB, z);
+    zone_fetch<R, D, STAGE>(rs, rw, xo, st, qs, VB, z);
     return zone_record<R, D, STAGE>(z, cf, prm, sc);
 }
 
@@ -1376,7 +1380,8 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
     const unsigned xo = x * ES;  // zone byte offset (VGPR)
     const unsigned VB = V * ES;  // field byte stride (SGPR)
     const R lam = sc_lam(*sc, D, R(0));
-    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + Pt.base, (unsigned)F_TOTAL * VB);
+    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + Pt.base, (unsigned)F_STATE * VB);     // state
+    const __amdgpu_buffer_rsrc_t rw = patch_rsrc(pool + Pt.sbase, (unsigned)F_SCRATCH * VB);  // step intermediates
     const unsigned qs = (unsigned)(cur ? F_ST1 : F_ST0) * VB;  // state copy
     const R z0 = R(0);
 
@@ -1390,12 +1395,12 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
                 for (int c = 0; c < 8; c++) u[c] = bload(z0, rs, xo, qs + c * VB);
                 R ir = frcp(u[0]);
                 R vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
-                bstore(vz * u[5] - vy * u[6], rs, xo, (unsigned)F_ER * VB);
-                bstore(vx * u[6] - vz * u[4], rs, xo, (unsigned)(F_ER + 1) * VB);
-                bstore(vy * u[4] - vx * u[5], rs, xo, (unsigned)(F_ER + 2) * VB);
+                bstore(vz * u[5] - vy * u[6], rw, xo, (unsigned)F_ER * VB);
+                bstore(vx * u[6] - vz * u[4], rw, xo, (unsigned)(F_ER + 1) * VB);
+                bstore(vy * u[4] - vx * u[5], rw, xo, (unsigned)(F_ER + 2) * VB);
             }
         }
-        shp[tid] = zone_phase<R, D, STAGE>(rs, xo, st, qs, VB, cf, prm, *sc);
+        shp[tid] = zone_phase<R, D, STAGE>(rs, rw, xo, st, qs, VB, cf, prm, *sc);
     }
     __syncthreads();
 
@@ -1406,7 +1411,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
     bool prot = false;
     const bool face = live && s >= 1;
     if (face) {
-        bf = bload(z0, rs, xo, (STAGE == 1) ? qs + (8 + D) * VB : (unsigned)(F_BH + D) * VB);
+        bf = (STAGE == 1) ? bload(z0, rs, xo, qs + (8 + D) * VB) : bload(z0, rw, xo, (unsigned)(F_BH + D) * VB);
         Rec8<R> gr;
         face_phase<R, PROT>(shp[tid - sstep], shp[tid], bf, lam, cf, e, alpha, nu, gr, prot);
         shg[tid] = gr;
@@ -1430,7 +1435,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(R* __restrict__ pool, const
             face_central<R, PROT>(shp[tid - sstep], shp[tid], bf, e, prot, cf, cav);
             face_combine(cav, c, sc_il(*sc, D, R(0)), out);
         }
-        store_flux<R, D>(out, rs, xo, (unsigned)((STAGE == 1 ? F_FL1 : F_FL2) + 7 * D) * VB, VB);
+        store_flux<R, D>(out, rw, xo, (unsigned)((STAGE == 1 ? F_FL1 : F_FL2) + 7 * D) * VB, VB);
     }
 }
 
@@ -1482,7 +1487,9 @@ __global__ void __launch_bounds__(256) march_kernel(R* __restrict__ pool, const 
     const unsigned VB = (unsigned)Pt.vol * ES;
     const StepConst scv = *sc;
     const R lam = sc_lam(scv, D, R(0)), il = sc_il(scv, D, R(0));
-    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + Pt.base, (unsigned)F_TOTAL * VB);
+    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + Pt.base, (unsigned)F_STATE * VB);     // state
+    const __amdgpu_buffer_rsrc_t rw = patch_rsrc(pool + Pt.sbase, (unsigned)F_SCRATCH * VB);  // step intermediates
+    const __amdgpu_buffer_rsrc_t rb = (STAGE == 1) ? rs : rw;  // the face field B_D: b^n or b^{n+1/2}
     const unsigned qs = (unsigned)(cur ? F_ST1 : F_ST0) * VB;
     const unsigned bfo = (STAGE == 1) ? qs + (8 + D) * VB : (unsigned)(F_BH + D) * VB;
     const unsigned fo = (unsigned)((STAGE == 1 ? F_FL1 : F_FL2) + 7 * D) * VB;
@@ -1495,12 +1502,12 @@ __global__ void __launch_bounds__(256) march_kernel(R* __restrict__ pool, const 
     // FP64, whose marching kernels already use 256 VGPRs.
     constexpr bool PF = sizeof(R) == 4 && (STAGE == 1 || PF2);
     MarchFace<R> pv;  // zone s-1 and face s-1
-    pv.rec = zone_phase<R, D, STAGE>(rs, xo, st, qs, VB, cf, prm, scv);
+    pv.rec = zone_phase<R, D, STAGE>(rs, rw, xo, st, qs, VB, cf, prm, scv);
     ZoneRaw<R, STAGE> nx;
     R bfn = R(0);
     if constexpr (PF) {
-        zone_fetch<R, D, STAGE>(rs, xo + sD, st, qs, VB, nx);
-        bfn = bload(z0, rs, xo + sD, bfo);
+        zone_fetch<R, D, STAGE>(rs, rw, xo + sD, st, qs, VB, nx);
+        bfn = bload(z0, rb, xo + sD, bfo);
     }
     for (int s = 1; s < P; s++) {
         xo += sD;
@@ -1510,12 +1517,12 @@ __global__ void __launch_bounds__(256) march_kernel(R* __restrict__ pool, const 
             cu.rec = zone_record<R, D, STAGE>(nx, cf, prm, scv);
             bf = bfn;
             if (s + 1 < P) {
-                zone_fetch<R, D, STAGE>(rs, xo + sD, st, qs, VB, nx);
-                bfn = bload(z0, rs, xo + sD, bfo);
+                zone_fetch<R, D, STAGE>(rs, rw, xo + sD, st, qs, VB, nx);
+                bfn = bload(z0, rb, xo + sD, bfo);
             }
         } else {
-            cu.rec = zone_phase<R, D, STAGE>(rs, xo, st, qs, VB, cf, prm, scv);
-            bf = bload(z0, rs, xo, bfo);
+            cu.rec = zone_phase<R, D, STAGE>(rs, rw, xo, st, qs, VB, cf, prm, scv);
+            bf = bload(z0, rb, xo, bfo);
         }
         face_phase<R, PROT>(pv.rec, cu.rec, bf, lam, cf, cu.e, cu.alpha, cu.nu, cu.gt, cu.prot);
         if (s >= 2 && s <= P - 2) face_central<R, PROT>(pv.rec, cu.rec, bf, cu.e, cu.prot, cf, cu.cav);
@@ -1539,7 +1546,7 @@ __global__ void __launch_bounds__(256) march_kernel(R* __restrict__ pool, const 
                 face_correction<R>(glim, pv.e, pv.alpha, pv.nu, cf, c);
                 face_combine(pv.cav, c, il, out);
             }
-            store_flux<R, D>(out, rs, xo - sD, fo, VB);
+            store_flux<R, D>(out, rw, xo - sD, fo, VB);
         }
         pv = cu;
     }

@@ -44,7 +44,7 @@ struct SweepGroup {
     int Wp = 0, Wm = 0;    // autotune: the fastest pencil and marching shapes alone
     int Wx[2] = {0, 0};    // autotune, x sweeps: the second and third fastest shapes alone
     DevList wl;            // every pencil of the transverse range [tlo, n+thi]^2
-    DevList wlg[4];        // the same for the patches of each step group (grouped schedule)
+    std::vector<DevList> wlg;  // the same for the patches of each step group (grouped schedule)
     DevList wl_in, wl_fr;  // Step-1 x sweep only: the pencils with both transverse
                            // coords interior, and the frame around them
 };
@@ -87,7 +87,8 @@ struct wmb_ctx {
     // x-rows), each running its whole step on its own stream in the graph
     int ngroups = 1;
     std::vector<int> pgroup;  // patch -> step group
-    DevList wl_cth_g[4], wl_upd_g[4];
+    std::vector<DevList> wl_cth_g, wl_upd_g;  // per step group (sized for ngroups)
+    bool serial = false;  // scratch groups: the groups' steps run one after another on the main stream
     hipStream_t gstream[4] = {};  // group streams 1..3 (group 0 runs on the main stream), borrowed
     hipEvent_t ev_g[4] = {};
     int upd_zones = 256;  // zones a tile plane of Steps 8-11 (the update's block size)
@@ -115,6 +116,7 @@ struct wmb_ctx {
     std::string err;
     std::vector<void*> owned;  // library-owned device allocations
     hipEvent_t* marks = nullptr;  // when set, an event is recorded after every kernel class
+    int mark_cap = 0;             // events at marks
     int nmark = 0;
 };
 
@@ -255,6 +257,7 @@ int check_params(const wmb_params* p) {
     if (p->precision != WMB_FP64 && p->precision != WMB_FP32) return WMB_EINVAL;
     if (!(p->rho_protect >= 0.0) || !(p->p_protect >= 0.0)) return WMB_EINVAL;
     if (p->dt_lag != 0 && p->dt_lag != 1) return WMB_EINVAL;
+    if (p->scratch_groups < 0 || p->scratch_groups > 64) return WMB_EINVAL;
     return WMB_OK;
 }
 
@@ -264,10 +267,89 @@ long long vol_of(const wmb_patch_desc& d, int g) {
     return (long long)(d.n[0] + 2 * g) * (d.n[1] + 2 * g) * (d.n[2] + 2 * g);
 }
 
-// per-patch region size in bytes, rounded to 256 B
-uint64_t region_bytes(const wmb_patch_desc& d, int g, size_t es) {
-    uint64_t b = (uint64_t)F_TOTAL * (uint64_t)vol_of(d, g) * es;
-    return (b + 255) & ~uint64_t(255);
+// a patch's state region and its space for the step's intermediates, in
+// bytes, rounded to 256 B
+uint64_t align256(uint64_t b) { return (b + 255) & ~uint64_t(255); }
+uint64_t state_bytes(const wmb_patch_desc& d, int g, size_t es) {
+    return align256((uint64_t)F_STATE * (uint64_t)vol_of(d, g) * es);
+}
+uint64_t scratch_bytes(const wmb_patch_desc& d, int g, size_t es) {
+    return align256((uint64_t)F_SCRATCH * (uint64_t)vol_of(d, g) * es);
+}
+
+// x-rows: patches linked by their x face neighbours in the init table (a
+// periodic ring or a chain between domain boundaries), named by their
+// lowest member
+std::vector<int> rows_of(int np, const wmb_patch_desc* d) {
+    std::vector<int> row(np, -1), seen(np, -1);
+    const int fx[2] = {12, 14};
+    for (int p = 0; p < np; p++) {
+        if (row[p] >= 0) continue;
+        std::vector<int> members{p};
+        seen[p] = p;
+        for (int dir = 0; dir < 2; dir++)  // walk -x, then +x
+            for (int q = d[p].nbr[fx[dir]]; q >= 0 && q < np && seen[q] != p; q = d[q].nbr[fx[dir]]) {
+                seen[q] = p;
+                members.push_back(q);
+            }
+        const int id = *std::min_element(members.begin(), members.end());
+        for (int m : members) row[m] = id;
+    }
+    return row;
+}
+
+// whole x-rows dealt to `groups` groups in turn, in the order of their first patch
+std::vector<int> deal_rows(int np, const wmb_patch_desc* d, int groups) {
+    const std::vector<int> rows = rows_of(np, d);
+    std::vector<int> ord(np, -1), grp(np, 0);
+    int next = 0;
+    for (int p = 0; p < np; p++) {
+        if (ord[rows[p]] < 0) ord[rows[p]] = next++;
+        grp[p] = groups > 1 ? ord[rows[p]] % groups : 0;
+    }
+    return grp;
+}
+
+// The pool.  Without scratch groups every patch has one region: its state,
+// then its intermediates (a patch's arrays stay close together in memory:
+// with all intermediates after all states, Steps 3-4 and 8-11 measured 1-2%
+// slower at 256^3 FP32).  With scratch groups the patches' state regions come one
+// after another, then one set of intermediate slots per group, all groups at
+// the same addresses (their steps run one after another), as large as the
+// largest group's.  Byte offsets.
+struct PoolLayout {
+    std::vector<uint64_t> base, sbase;
+    uint64_t total = 0;
+};
+PoolLayout plan_pool(int np, const wmb_patch_desc* d, int g, size_t es, int groups) {
+    PoolLayout L;
+    L.base.resize(np);
+    L.sbase.resize(np);
+    uint64_t off = 0;
+    if (groups <= 1) {
+        for (int p = 0; p < np; p++) {
+            L.base[p] = off;
+            off += state_bytes(d[p], g, es);
+            L.sbase[p] = off;
+            off += scratch_bytes(d[p], g, es);
+        }
+        L.total = off;
+        return L;
+    }
+    for (int p = 0; p < np; p++) {
+        L.base[p] = off;
+        off += state_bytes(d[p], g, es);
+    }
+    const std::vector<int> grp = deal_rows(np, d, groups);
+    std::vector<uint64_t> fill(groups, 0);
+    uint64_t top = 0;
+    for (int p = 0; p < np; p++) {
+        L.sbase[p] = off + fill[grp[p]];
+        fill[grp[p]] += scratch_bytes(d[p], g, es);
+        top = std::max(top, fill[grp[p]]);
+    }
+    L.total = off + top;
+    return L;
 }
 
 // Largest interior edge the kernels take, per precision.  Every axis is a
@@ -286,8 +368,8 @@ int check_table(int32_t np, const wmb_patch_desc* d, int g, size_t es, std::stri
                       std::to_string(max_edge(es));
                 return WMB_EINVAL;
             }
-        // kernels address a patch region with 32-bit byte offsets
-        if (region_bytes(d[i], g, es) > 0xFFFFFFFFull) {
+        // kernels address a patch's regions with 32-bit byte offsets
+        if (scratch_bytes(d[i], g, es) > 0xFFFFFFFFull) {
             why = "patch " + std::to_string(i) + ": region above 4 GiB (32-bit offsets)";
             return WMB_EINVAL;
         }
@@ -337,7 +419,8 @@ int check_table(int32_t np, const wmb_patch_desc* d, int g, size_t es, std::stri
 
 // profiling marks only (wmb_profile_step checks the events it reads)
 void mark(wmb_ctx* c) {
-    if (c->marks) (void)hipEventRecord(c->marks[c->nmark++], c->stream);
+    if (c->marks && c->nmark < c->mark_cap) (void)hipEventRecord(c->marks[c->nmark], c->stream);
+    if (c->marks) c->nmark++;
 }
 
 template <typename R>
@@ -483,37 +566,49 @@ int run_step(wmb_ctx* c, bool split = false) {
     return WMB_OK;
 }
 
-// The grouped schedule of the captured step: the patch groups (whole x-rows)
-// run their whole step (Step-1 sweeps, Steps 3-4, Steps 5-7, Steps 8-11) each
-// on its own stream, forked after dt and joined before the next exchange, so
+// The grouped schedule of the step: the patch groups (whole x-rows) run
+// their whole step (Step-1 sweeps, Steps 3-4, Steps 5-7, Steps 8-11) each on
+// its own stream, forked after dt and joined before the next exchange, so
 // that one group's memory-bound stages overlap another's sweeps.  Within a
 // step a patch's kernels touch only its own region, apart from the update's
 // x-ghost pushes, which write the neighbours' other state copy (read only
-// after the join), so the groups share no data inside the step.
+// after the join), so the groups share no data inside the step.  With
+// scratch groups (serial) the groups share the space for the intermediates,
+// so they run one after another on the main stream.
 template <typename R>
 int run_step_grouped(wmb_ctx* c) {
     const int cur = c->cur;
-    CKH(hipEventRecord(c->ev_fork, c->stream));
-    for (int g = 1; g < c->ngroups; g++) CKH(hipStreamWaitEvent(c->gstream[g], c->ev_fork, 0));
+    const bool par = !c->serial;
+    if (par) {
+        CKH(hipEventRecord(c->ev_fork, c->stream));
+        for (int g = 1; g < c->ngroups; g++) CKH(hipStreamWaitEvent(c->gstream[g], c->ev_fork, 0));
+    }
     for (int g = 0; g < c->ngroups; g++) {
-        hipStream_t st = g == 0 ? c->stream : c->gstream[g];
+        hipStream_t st = (g == 0 || !par) ? c->stream : c->gstream[g];
         hipError_t e = hipSuccess;
         for (int stage = 1; stage <= 2 && e == hipSuccess; stage++) {
-            for (int d = 0; d < 3 && e == hipSuccess; d++)
+            for (int d = 0; d < 3 && e == hipSuccess; d++) {
                 for (auto& SG : c->sweeps[d][stage - 1])
                     if (e == hipSuccess) e = launch_group<R>(c, d, stage, SG, SG.wlg[g], cur, c->d_nfloor + 1, st);
-            if (stage == 1 && e == hipSuccess)
+                if (!par) mark(c);
+            }
+            if (stage == 1 && e == hipSuccess) {
                 e = launch_ct_half<R>(c->pool, c->d_patch, c->wl_cth_g[g].d, c->wl_cth_g[g].n, coef<R>(c), c->p.ghost,
                                       cur, c->d_sc, st);
+                if (!par) mark(c);
+            }
         }
         const DevList& wu = c->wl_upd_g[g];
         if (e == hipSuccess)
             e = launch_update<R>(c->pool, c->d_patch, wu.d, wu.n, c->dp, coef<R>(c), cur, c->d_sc, c->d_nfloor, c->d_smax,
-                                 c->keep_edges ? 1 : 0, c->upd_zones, c->upd_queue ? c->d_queue + 16 * g : nullptr, st);
+                                 c->keep_edges ? 1 : 0, c->upd_zones,
+                                 c->upd_queue ? c->d_queue + 16 * (par ? g : 0) : nullptr, st);
+        if (!par) mark(c);
         if (e != hipSuccess) return fail(c, WMB_EHIP, std::string("grouped step: ") + hipGetErrorString(e));
-        if (g > 0) CKH(hipEventRecord(c->ev_g[g], st));
+        if (g > 0 && par) CKH(hipEventRecord(c->ev_g[g], st));
     }
-    for (int g = 1; g < c->ngroups; g++) CKH(hipStreamWaitEvent(c->stream, c->ev_g[g], 0));
+    if (par)
+        for (int g = 1; g < c->ngroups; g++) CKH(hipStreamWaitEvent(c->stream, c->ev_g[g], 0));
     c->edges_kept = c->keep_edges;
     c->xg_valid = true;
     c->cur ^= 1;
@@ -533,7 +628,8 @@ int dispatch_dt(wmb_ctx* c) {
     return rc ? rc : run_finalize(c);
 }
 int dispatch_step(wmb_ctx* c, bool split = false) {
-    if (split && c->ngroups > 1) return c->esize == 4 ? run_step_grouped<float>(c) : run_step_grouped<double>(c);
+    if ((split || c->serial) && c->ngroups > 1)
+        return c->esize == 4 ? run_step_grouped<float>(c) : run_step_grouped<double>(c);
     return c->esize == 4 ? run_step<float>(c, split) : run_step<double>(c, split);
 }
 // the y/z ghost exchange on the side stream, forked from and joined (by the
@@ -588,25 +684,7 @@ constexpr int TILE_BIAS = 16;
 // x-rows: patches linked by their x face neighbours (a periodic ring or a
 // chain between domain boundaries), numbered by their smallest patch id;
 // the unit of xcd_order for the update and the ghost exchange
-std::vector<int> x_rows(const wmb_ctx* c) {
-    std::vector<int> row(c->npatch, -1), seen(c->npatch, -1);
-    for (int p = 0; p < c->npatch; p++) {
-        if (row[p] >= 0) continue;
-        std::vector<int> members{p};
-        seen[p] = p;
-        // walk -x, then +x, along the init table's links (a row stays one
-        // unit while patches of it are removed and added again)
-        const int fx[2] = {12, 14};
-        for (int dir = 0; dir < 2; dir++)
-            for (int q = c->desc[p].nbr[fx[dir]]; q >= 0 && seen[q] != p; q = c->desc[q].nbr[fx[dir]]) {
-                seen[q] = p;
-                members.push_back(q);
-            }
-        const int id = *std::min_element(members.begin(), members.end());
-        for (int m : members) row[m] = id;
-    }
-    return row;
-}
+std::vector<int> x_rows(const wmb_ctx* c) { return rows_of(c->npatch, c->desc.data()); }
 
 // The stage work lists (sweeps, Steps 3-4, Steps 8-11) cover the present,
 // active patches; frozen and absent ones are left out when the lists are
@@ -689,6 +767,10 @@ int build_ct_update_lists(wmb_ctx* c) {
     const std::vector<int> rows = x_rows(c);
     int rc = build_tile_list(c, -2, 2, -2, 2, c->cth_tx, 256, nullptr, c->wl_cth);
     if (!rc) rc = build_tile_list(c, 0, -1, 0, -1, 32, c->upd_zones, &rows, c->wl_upd);
+    if (c->ngroups > 1 && c->wl_cth_g.size() < (size_t)c->ngroups) {
+        c->wl_cth_g.resize(c->ngroups);
+        c->wl_upd_g.resize(c->ngroups);
+    }
     for (int g = 0; g < c->ngroups && c->ngroups > 1 && !rc; g++) {
         for (DevList* L : {&c->wl_cth_g[g], &c->wl_upd_g[g]}) {
             release(c, L->d);
@@ -816,6 +898,7 @@ int set_group_W(wmb_ctx* c, int d, int stage, SweepGroup& G, int W) {
         return WMB_OK;
     };
     int rc = rebuild(G.wl, PART_ALL);
+    if (c->ngroups > 1 && G.wlg.size() < (size_t)c->ngroups) G.wlg.resize(c->ngroups);
     for (int g = 0; g < c->ngroups && c->ngroups > 1 && !rc; g++) {
         std::vector<WorkItem> items = sweep_items(c, d, G.n, G.tlo, G.thi, W < 0 ? (-W) % 512 : W, PART_ALL, g);
         WorkItem* nd = nullptr;
@@ -1068,8 +1151,8 @@ int debug_stage_t(wmb_ctx* c, int ip, int stage, double* out) {
     const PatchDev& P = c->hpatch[ip];
     const long long V = P.vol;
     std::vector<R> buf((size_t)V);
-    auto fetch = [&](int slot) -> int {
-        CKH(hipMemcpyAsync(buf.data(), (const R*)c->pool + P.base + (long long)slot * V, sizeof(R) * V,
+    auto fetch = [&](int slot) -> int {  // a slot of the step's intermediates
+        CKH(hipMemcpyAsync(buf.data(), (const R*)c->pool + P.sbase + (long long)slot * V, sizeof(R) * V,
                            hipMemcpyDeviceToHost, c->stream));
         CKH(hipStreamSynchronize(c->stream));
         return WMB_OK;
@@ -1505,6 +1588,31 @@ int bind_scratch(wmb_ctx* c) {
 // C ABI
 // ===========================================================================
 
+// Patch groups of the step: pgroup from deal_rows, the group lists, and for
+// concurrent groups (not serial) a stream and an event per group
+int apply_groups(wmb_ctx* c, int groups) {
+    free_graphs(c);
+    if (groups > 1) {
+        c->pgroup = deal_rows(c->npatch, c->desc.data(), groups);
+        for (int g = 1; g < groups && !c->serial; g++) {
+            if (!c->gstream[g]) {
+                int rc = borrow_stream(c, &c->gstream[g]);
+                if (rc) return rc;
+            }
+            if (!c->ev_g[g]) CKH(hipEventCreateWithFlags(&c->ev_g[g], hipEventDisableTiming));
+        }
+    }
+    c->ngroups = groups;
+    if (groups == 1) return WMB_OK;
+    for (int d = 0; d < 3; d++)
+        for (int stage = 0; stage < 2; stage++)
+            for (auto& SG : c->sweeps[d][stage]) {
+                int rc = set_group_W(c, d, stage, SG, SG.W);
+                if (rc) return rc;
+            }
+    return build_ct_update_lists(c);
+}
+
 extern "C" {
 
 int wmb_create(const wmb_params* p, wmb_ctx** out) {
@@ -1538,9 +1646,7 @@ int wmb_pool_bytes(const wmb_params* p, int32_t npatch, const wmb_patch_desc* d,
     for (int i = 0; i < npatch; i++)
         for (int a = 0; a < 3; a++)
             if (d[i].n[a] < 1 || d[i].n[a] > max_edge(esize_of(p))) return WMB_EINVAL;
-    uint64_t tot = 0;
-    for (int i = 0; i < npatch; i++) tot += region_bytes(d[i], p->ghost, esize_of(p));
-    *bytes = tot;
+    *bytes = plan_pool(npatch, d, p->ghost, esize_of(p), p->scratch_groups).total;
     return WMB_OK;
 }
 
@@ -1574,7 +1680,7 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     CKH(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     for (auto& ev : c->ev_br) CKH(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     const int g = c->p.ghost;
-    uint64_t off = 0;
+    const PoolLayout lay = plan_pool(npatch, d, g, c->esize, c->p.scratch_groups);
     c->hpatch.resize(npatch);
     for (int i = 0; i < npatch; i++) {
         PatchDev& P = c->hpatch[i];
@@ -1583,12 +1689,12 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
             P.N[a] = d[i].n[a] + 2 * g;
         }
         P.vol = vol_of(d[i], g);
-        P.base = (long long)(off / c->esize);
+        P.base = (long long)(lay.base[i] / c->esize);
+        P.sbase = (long long)(lay.sbase[i] / c->esize);
         const int faces[6] = {12, 14, 10, 16, 4, 22};
         for (int t = 0; t < 6; t++) P.nb[t] = d[i].nbr[faces[t]];
         P.active = 1;
         P.present = 1;
-        off += region_bytes(d[i], g, c->esize);
     }
     int rc;
     if ((rc = upload(c, &c->d_patch, c->hpatch))) return rc;
@@ -1600,6 +1706,10 @@ int wmb_init_patches(wmb_ctx* c, int32_t npatch, const wmb_patch_desc* d, void* 
     if ((rc = build_ct_update_lists(c))) return rc;
     c->nfrozen = 0;
     if ((rc = build_sweeps(c))) return rc;
+    if (c->p.scratch_groups > 1) {
+        c->serial = true;
+        if ((rc = apply_groups(c, c->p.scratch_groups))) return rc;
+    }
     // the signal-speed maxima of the current and the previous state, and a
     // sink for tuning runs
     if ((rc = dev_alloc(c, &c->d_smax, 3))) return rc;
@@ -1837,37 +1947,12 @@ int wmb_set_tuning(wmb_ctx* c, const int32_t* quads, int32_t n) {
 int wmb_set_schedule(wmb_ctx* c, int32_t groups) {
     if (!c) return WMB_EINVAL;
     if (!c->inited) return fail(c, WMB_EORDER, "wmb_init_patches first");
+    if (c->serial)
+        return groups == c->ngroups ? WMB_OK
+                                    : fail(c, WMB_EINVAL, "schedule: fixed to the scratch groups of the pool layout");
     if (groups < 1 || groups > 4) return fail(c, WMB_EINVAL, "schedule: 1 to 4 patch groups");
     if (groups == c->ngroups) return WMB_OK;
-    free_graphs(c);
-    if (groups > 1) {
-        // whole x-rows (the update's x-pushes stay inside a row), dealt to the
-        // groups in turn in the order of their first patch
-        const std::vector<int> rows = x_rows(c);
-        std::vector<int> ord(c->npatch, -1);
-        int next = 0;
-        c->pgroup.assign(c->npatch, 0);
-        for (int p = 0; p < c->npatch; p++) {
-            if (ord[rows[p]] < 0) ord[rows[p]] = next++;
-            c->pgroup[p] = ord[rows[p]] % groups;
-        }
-        for (int g = 1; g < groups; g++) {
-            if (!c->gstream[g]) {
-                int rc = borrow_stream(c, &c->gstream[g]);
-                if (rc) return rc;
-            }
-            if (!c->ev_g[g]) CKH(hipEventCreateWithFlags(&c->ev_g[g], hipEventDisableTiming));
-        }
-    }
-    c->ngroups = groups;
-    if (groups == 1) return WMB_OK;
-    for (int d = 0; d < 3; d++)
-        for (int stage = 0; stage < 2; stage++)
-            for (auto& SG : c->sweeps[d][stage]) {
-                int rc = set_group_W(c, d, stage, SG, SG.W);
-                if (rc) return rc;
-            }
-    return build_ct_update_lists(c);
+    return apply_groups(c, groups);
 }
 
 // A frozen patch reads the same in both state copies, ghosts included, so
@@ -1988,25 +2073,31 @@ int wmb_profile_step(wmb_ctx* c, double* ms, int32_t nclass) {
     if (!rc) rc = ensure_smax(c);
     if (!rc && !c->xg_valid) rc = dispatch_fill(c, FILL_X);  // as before a graph replay
     if (rc) return rc;
-    hipEvent_t ev[WMB_NCLASS + 1];
-    for (int i = 0; i <= WMB_NCLASS; i++) CKH(hipEventCreate(&ev[i]));
+    // one event after every kernel class; with serial groups after every
+    // class of every group (the fill and dt once), summed per class
+    const int groups = (c->serial && c->ngroups > 1) ? c->ngroups : 1;
+    const int nev = 2 + (WMB_NCLASS - 2) * groups;
+    std::vector<hipEvent_t> ev(nev + 1, nullptr);
+    for (auto& e : ev) CKH(hipEventCreate(&e));
     CKH(hipEventRecord(ev[0], c->stream));
-    c->marks = ev + 1;
+    c->marks = ev.data() + 1;
+    c->mark_cap = nev;
     c->nmark = 0;
     rc = dispatch_fill(c, FILL_YZ);
     if (!rc) rc = run_finalize(c);
     if (!rc) rc = dispatch_step(c);
     c->marks = nullptr;
-    if (!rc && c->nmark != WMB_NCLASS) rc = fail(c, WMB_EHIP, "profile: unexpected kernel count");
+    if (!rc && c->nmark != nev) rc = fail(c, WMB_EHIP, "profile: unexpected kernel count");
     if (!rc) {
-        CKH(hipEventSynchronize(ev[WMB_NCLASS]));
-        for (int i = 0; i < WMB_NCLASS; i++) {
+        CKH(hipEventSynchronize(ev[nev]));
+        for (int i = 0; i < WMB_NCLASS; i++) ms[i] = 0.0;
+        for (int i = 0; i < nev; i++) {
             float t = 0.f;
             CKH(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
-            ms[i] = t;
+            ms[i < 2 ? i : 2 + (i - 2) % (WMB_NCLASS - 2)] += t;
         }
     }
-    for (int i = 0; i <= WMB_NCLASS; i++) (void)hipEventDestroy(ev[i]);
+    for (auto& e : ev) (void)hipEventDestroy(e);
     return rc;
 }
 

@@ -51,6 +51,7 @@ class Params(C.Structure):
         ("rho_protect", C.c_double),
         ("p_protect", C.c_double),
         ("dt_lag", C.c_int32),
+        ("scratch_groups", C.c_int32),
     ]
 
 
@@ -60,7 +61,7 @@ class PatchDesc(C.Structure):
 
 def make_params(dx=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, cfl=0.4, ghost=5, precision=WMB_FP64,
                 eps=(0.1, 0.0, 0.1, 0.0, 0.1, 0.0, 0.1), limiter_beta=1.0, rho_floor=1e-10, p_floor=1e-10,
-                degen_tol=1e-12, rho_protect=0.0, p_protect=0.0, dt_lag=0) -> Params:
+                degen_tol=1e-12, rho_protect=0.0, p_protect=0.0, dt_lag=0, scratch_groups=0) -> Params:
     p = Params()
     p.gamma = gamma
     p.cfl = cfl
@@ -77,6 +78,7 @@ def make_params(dx=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, cfl=0.4, ghost=5, precision
     p.rho_protect = rho_protect
     p.p_protect = p_protect
     p.dt_lag = dt_lag
+    p.scratch_groups = scratch_groups
     return p
 
 

@@ -65,6 +65,33 @@ def test_pool_bytes(lib):
     assert abs(b64 - 2 * b32) <= 256 * len(G.descs)  # regions are 256-byte aligned
 
 
+def test_pool_bytes_with_scratch_groups(lib):
+    """With scratch groups the patches keep 22 words of state a ghosted zone
+    and share the 51 words of step intermediates group by group (whole
+    x-rows dealt in turn): 2 x 2 x 2 patches of 32^3 have 4 x-rows, so 4
+    groups hold one row (2 patches) each and the pool is 8 states and 2
+    scratch slots; 2 groups hold 2 rows each (4 slots)."""
+    from paper_1701_07452_amd import inputs as I
+    from paper_1701_07452_amd import wmb
+
+    G = I.uniform_grid(64, 32)
+    g = 4
+    vol = (32 + 2 * g) ** 3
+    for prec, es in ((wmb.WMB_FP32, 4), (wmb.WMB_FP64, 8)):
+        def align(b):
+            return (b + 255) // 256 * 256
+        st, sc = align(22 * vol * es), align(51 * vol * es)
+        sizes = {k: wmb.pool_bytes(wmb.make_params(precision=prec, ghost=g, scratch_groups=k), G.descs)
+                 for k in (0, 1, 2, 4, 8)}
+        assert sizes[0] == sizes[1] == 8 * (st + sc)
+        assert sizes[2] == 8 * st + 4 * sc
+        assert sizes[4] == 8 * st + 2 * sc
+        assert sizes[8] == 8 * st + 2 * sc  # only 4 rows: groups beyond them stay empty
+    p = wmb.make_params(scratch_groups=65)
+    h = C.c_void_p()
+    assert lib.wmb_create(C.byref(p), C.byref(h)) == wmb.WMB_EINVAL
+
+
 C_PROGRAM = r"""
 #include <stdio.h>
 #include <string.h>

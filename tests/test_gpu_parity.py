@@ -551,6 +551,43 @@ def test_tile_tuning_entries_are_checked(wmb):
         sim.close()
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+def test_scratch_groups_bitwise(wmb, prec):
+    """Scratch groups (the step intermediates shared group by group, the
+    groups' steps one after another on the main stream) give bitwise the
+    state of the default layout after 3 graph-replayed steps and one eager
+    profiled step: 2 and 3 groups (one of them empty) on the uneven 2 x 2 x 1
+    tiling, 4 groups on 2 x 2 x 2 patches of 32^3 (FP32: 512-zone update
+    tiles).  The schedule stays fixed to the groups; the pool shrinks."""
+    cases = [("uneven", (0, 2, 3))]
+    if prec == 1:
+        cases.append(("cube64", (0, 4)))
+    for name, groups in cases:
+        if name == "cube64":
+            G = I.uniform_grid(64, 32)
+            q, b = I.random_smooth((64, 64, 64), 44)
+        else:
+            G, (q, b) = CASES[name]()
+        N = G.shape
+        dx = (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
+        outs, sizes = [], []
+        for sg in groups:
+            sim = gpu_sim(wmb, G, q, b, prec, dx=dx, scratch_groups=sg)
+            sizes.append(wmb.pool_bytes(sim.params, G.descs))
+            if sg > 1:
+                sim.set_schedule(sg)  # the groups' own schedule: accepted
+                with pytest.raises(wmb.WmbError):
+                    sim.set_schedule(1)
+            sim.run_steps(3)
+            ms = sim.profile_step()
+            assert ms["update"] > 0 and ms["sweep2_y"] > 0, ms
+            outs.append(I.gather(G, [sim.get_state(i) for i in range(G.npatch)]))
+            sim.close()
+        for k in range(1, len(outs)):
+            assert np.array_equal(outs[0][0], outs[k][0]) and np.array_equal(outs[0][1], outs[k][1]), (name, k)
+            assert sizes[k] < sizes[0]
+
+
 FORMS = {
     # (precision, extra params, grid): the minmod, general-limiter and
     # protected instantiations of both sweep forms, and one 64^3 patch
