@@ -588,6 +588,33 @@ def test_scratch_groups_bitwise(wmb, prec):
             assert sizes[k] < sizes[0]
 
 
+def test_scratch_groups_with_frozen_and_removed_patches(wmb):
+    """Scratch groups with the pool's other verbs: on the 4 x 2 x 2 batch of
+    12^3 patches (outflow along x), one patch frozen and the last x-column
+    removed after a graph-replayed step, 3 more steps, then the column
+    added back and the patch thawed for 2 more: FP64 bitwise equal to the
+    same sequence on the default layout."""
+    G = I.patch_grid([12] * 4, [12, 12], [12, 12], periodic=(False, True, True))
+    q, b = I.random_smooth(G.shape, 48)
+    dx = (1.0 / 48, 1.0 / 24, 1.0 / 24)
+    last = [(k * 2 + j) * 4 + 3 for k in range(2) for j in range(2)]
+    outs = []
+    for sg in (0, 3):
+        sim = gpu_sim(wmb, G, q, b, 0, dx=dx, scratch_groups=sg)
+        sim.run_steps(1)
+        sim.set_active(5, False)
+        for p in last:
+            sim.set_present(p, False)
+        sim.run_steps(3)
+        for p in last:
+            sim.set_present(p, True)
+        sim.set_active(5, True)
+        sim.run_steps(2)
+        outs.append(I.gather(G, [sim.get_state(i) for i in range(G.npatch)]))
+        sim.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
 FORMS = {
     # (precision, extra params, grid): the minmod, general-limiter and
     # protected instantiations of both sweep forms, and one 64^3 patch
