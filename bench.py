@@ -143,6 +143,8 @@ def kernel_class(name):
     m = re.search(r"(?:sweep|march)_kernel<(?:float|double), (\d), (\d)", name)
     if m:
         return "sweep%s_%s" % (m.group(2), "xyz"[int(m.group(1))])
+    if "corr_xy_kernel" in name:  # the fused x/y corrector: counted in the x class
+        return "sweep2_x"
     for key, cls in (("fill_pass_kernel", "fill"), ("ct_half_kernel", "ct_half"), ("update_kernel", "update"),
                      ("dt_finalize_kernel", "dt")):
         if key in name:

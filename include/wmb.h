@@ -229,10 +229,12 @@ int wmb_debug_stage(wmb_ctx *c, int32_t patch, int32_t stage, double *out);
    issues the next zone's loads one zone ahead (w pencils a block; more
    registers, half the waves).  The choice never
    changes results (both forms compute every face with the same
-   arithmetic).  It then times the tiles of Steps 3-4 (the widest tile along
-   x: 40, 20 or 13 zones, 256 zones a plane) and of Steps 8-11 (256 or, in
-   FP32, 512 zones a plane) with either Steps 8-11 launch, which do not
-   change results either.  The
+   arithmetic).  It then times whole graph-replayed steps with the x and y
+   correctors fused into one launch (bands of 6, 9, 12 or 18 rows, where
+   the blocks fit) against the separate sweeps, and the tiles of Steps 3-4
+   (the widest tile along x: 40, 20 or 13 zones, 256 zones a plane) and of
+   Steps 8-11 (256 or, in FP32, 512 zones a plane) with either Steps 8-11
+   launch; none of these changes results either.  The
    interior state is unchanged; ghosts are refreshed and the step
    intermediates overwritten.  Invalidates the captured graphs.  The choice
    is kept for the life of the process under a key of the device
@@ -242,7 +244,8 @@ int wmb_debug_stage(wmb_ctx *c, int32_t patch, int32_t stage, double *out);
    anyway, with -reps repetitions, and replaces the kept choice.  If chosen
    != NULL it receives quadruples (stage, axis, edge, shape) -- the sweep
    groups, then (3, 0, 0, Steps 3-4 tile width), (4, 0, 0, Steps 8-11
-   tile zones) and (5, 0, 0, Steps 8-11 launch) -- up to nchosen ints,
+   tile zones), (5, 0, 0, Steps 8-11 launch) and (6, 0, 0, fused x/y
+   corrector band rows, 0 for separate sweeps) -- up to nchosen ints,
    0-terminated when shorter.
    Synchronous. */
 int wmb_autotune(wmb_ctx *c, int32_t reps, int32_t *chosen, int32_t nchosen);
@@ -262,7 +265,14 @@ int wmb_autotune(wmb_ctx *c, int32_t reps, int32_t *chosen, int32_t nchosen);
    the default is the one that leaves fewer threads idle); (5, 0, 0, m) the
    Steps 8-11 launch: m = 0 one block a tile (the default), m = 1 a
    persistent grid whose blocks take the tiles of their XCD's queue from an
-   atomic counter.  Every entry is checked before any is applied. */
+   atomic counter; (6, 0, 0, r) the corrector (Steps 5-7) along x and y:
+   r = 0 two separate sweeps (the default), r > 0 one fused launch whose
+   blocks each take one z-plane of a patch and a band of at most r rows
+   along y, load each zone's data once and build both predictor states from
+   it (bitwise the same fluxes; the y sweep groups' shapes are then unused).
+   WMB_EINVAL if a block of (n_x + 6) x (r + 3) threads, for any x edge,
+   exceeds 1024 threads or 64 KiB of LDS (16 words a thread).  Every entry
+   is checked before any is applied. */
 int wmb_set_tuning(wmb_ctx *c, const int32_t *quads, int32_t n);
 
 /* Schedule of the captured step (wmb_run_steps).  groups = 1 (the default):

@@ -88,6 +88,11 @@ struct WorkItem {
     int c;  // sweeps: last pencil (inclusive); tiles: k0 | k1 << 16 (biased, k1 exclusive)
 };
 
+// Fused x/y corrector items (one z-plane band of a patch): a = k + XY_BIAS,
+// b = (y0 + XY_BIAS) | (y1 + XY_BIAS) << 16 for the band's y-face rows
+// [y0, y1) (plane k and rows may be -1).
+constexpr int XY_BIAS = 16;
+
 // Diagnostics record of one work item (doubles): 9 compensated sums as (hi, lo)
 // pairs (q times the zone volume, |B|^2), the max |div b|, one pad word.
 constexpr int DIAG_REC = 20;

@@ -1553,6 +1553,166 @@ __global__ void __launch_bounds__(256) march_kernel(R* __restrict__ pool, const 
 }
 
 // ---------------------------------------------------------------------------
+// Fused x and y correctors (Steps 5-7 along x and y in one launch).  A block
+// covers one z-plane k of a patch and a band of rows along y; every thread
+// owns one zone (x fastest, so loads cover consecutive x), loads the zone's
+// data once (q^n, b^n at the zone's lower and upper faces, the three Step-1
+// flux arrays at the zone and one zone up along their own axes) and builds
+// from it both predictor states q^{n+1/2}_x and q^{n+1/2}_y (Step 5), which
+// the separate sweeps each load and build on their own.  The x faces of the
+// band's rows, then the y faces of the band, are formed as in the pencil
+// kernel through the same LDS (zone records, then face g-tilde), with the
+// same phase functions, so the fluxes are bitwise those of the separate
+// sweeps.
+//   block (P, RT): P = n_x + 6 zones [-3, n_x + 3) along x; RT rows along y,
+//   the band's y-face rows [y0, y1) with two rows below and one above (the
+//   limiter stencil); item a = k + XY_BIAS, b = (y0 + XY_BIAS) | (y1 +
+//   XY_BIAS) << 16.
+// x faces are formed on the band's rows within [-1, n_y], y faces on the
+// band's rows at x in [-1, n_x]: the ranges of the separate sweeps.
+// ---------------------------------------------------------------------------
+
+// rows of a transverse Step-1 flux in ZoneRaw's order (rows 0-4, then the
+// row of B_D, then the other B row): for the first transverse axis A1 the
+// B_D row is 6, for the second A2 it is 5
+__device__ __forceinline__ constexpr int row_a1(int r) { return r < 5 ? r : (r == 5 ? 6 : 5); }
+__device__ __forceinline__ constexpr int row_a2(int r) { return r < 5 ? r : (r == 5 ? 5 : 6); }
+
+template <typename R, int D, bool MM, bool PROT>
+__device__ __forceinline__ void xy_flux(const Rec8<R>* shp, const Rec8<R>* shg, int tid, int step, R bf,
+                                        const FaceEig<R>& e, const R alpha[7], const R nu[7], bool prot,
+                                        const Coef<R>& cf, R il, __amdgpu_buffer_rsrc_t rw, unsigned xo, unsigned VB,
+                                        unsigned long long* nprot) {
+    R out[7];
+    if (PROT && prot) {
+        face_central<R, PROT>(shp[tid - step], shp[tid], bf, e, prot, cf, out);
+        atomicAdd(nprot, 1ULL);
+    } else {
+        const Rec8<R> Gm = shg[tid - step], G0 = shg[tid], Gp = shg[tid + step];
+        R c[7], cav[7];
+        auto glim = [&](int k, R& gL, R& gR) {
+            gL = sweby<MM>(G0.v[k], Gm.v[k], cf.beta_l);
+            gR = sweby<MM>(Gp.v[k], G0.v[k], cf.beta_l);
+        };
+        face_correction<R>(glim, e, alpha, nu, cf, c);
+        face_central<R, PROT>(shp[tid - step], shp[tid], bf, e, prot, cf, cav);
+        face_combine(cav, c, il, out);
+    }
+    store_flux<R, D>(out, rw, xo, (unsigned)(F_FL2 + 7 * D) * VB, VB);
+}
+
+template <typename R, bool MM, bool PROT>
+__global__ void __launch_bounds__(sizeof(R) == 4 ? 1024 : 512) corr_xy_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
+                                                       const WorkItem* __restrict__ work, DevParams prm, Coef<R> cf,
+                                                       int cur, const StepConst* __restrict__ sc,
+                                                       unsigned long long* __restrict__ nprot) {
+    extern __shared__ unsigned char smem_raw[];
+    const int P = (int)blockDim.x, RT = (int)blockDim.y;
+    Rec8<R>* shp = reinterpret_cast<Rec8<R>*>(smem_raw);  // zone records: x, then y
+    Rec8<R>* shg = shp + P * RT;                          // face g-tilde: x, then y
+    constexpr unsigned ES = sizeof(R);
+
+    const WorkItem wi = work[blockIdx.x];
+    if (wi.patch < 0) return;  // padding item (whole block, before any barrier)
+    const PatchDev Pt = patches[wi.patch];
+    if (!Pt.active) return;  // frozen patch (whole block, before any barrier)
+    const int tx = (int)threadIdx.x, ty = (int)threadIdx.y, tid = tx + P * ty;
+    const int k = wi.a - XY_BIAS;
+    const int y0 = (wi.b & 0xffff) - XY_BIAS, y1 = (wi.b >> 16) - XY_BIAS;
+    const int rows = y1 - y0 + 3;  // the band's rows, [y0 - 2, y1]
+    const int x = tx - 3, y = y0 - 2 + ty;
+    const bool live = ty < rows;
+    const bool needX = live && y >= y0 && y < y1 && y <= Pt.n[1];  // x faces of this row
+    const bool needY = live && x >= -1 && x <= Pt.n[0];            // y faces of this column
+    const int g = prm.ghost;
+    const unsigned st[3] = {1u, (unsigned)Pt.N[0], (unsigned)(Pt.N[0] * Pt.N[1])};
+    const unsigned xo = live ? ((unsigned)(x + g) + st[1] * (unsigned)(y + g) + st[2] * (unsigned)(k + g)) * ES : 0u;
+    const unsigned VB = (unsigned)Pt.vol * ES;
+    const StepConst scv = *sc;
+    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(pool + Pt.base, (unsigned)F_STATE * VB);     // state
+    const __amdgpu_buffer_rsrc_t rw = patch_rsrc(pool + Pt.sbase, (unsigned)F_SCRATCH * VB);  // step intermediates
+    const unsigned qs = (unsigned)(cur ? F_ST1 : F_ST0) * VB;
+    const R z0 = R(0);
+
+    // ---------------- phase A: one load of the zone, two predictor records ----------------
+    Rec8<R> ry;
+    if (live) {
+        ZoneRaw<R, 2> zx, zy;
+#pragma unroll
+        for (int c = 0; c < 8; c++) zx.q[c] = zy.q[c] = bload(z0, rs, xo, qs + c * VB);
+        const unsigned bs = qs + 8 * VB;
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            zx.b[a][0] = zy.b[a][0] = bload(z0, rs, xo, bs + a * VB);
+            zx.b[a][1] = zy.b[a][1] = bload(z0, rs, xo, bs + a * VB + st[a] * ES);
+        }
+        R F[3][7][2];  // Step-1 fluxes along x, y, z at the zone and one zone up along their axis
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int r = 0; r < 7; r++) {
+                const unsigned fo = (unsigned)(F_FL1 + 7 * a + r) * VB;
+                F[a][r][0] = bload(z0, rw, xo, fo);
+                F[a][r][1] = bload(z0, rw, xo, fo + st[a] * ES);
+            }
+        // x predictor: transverse axes y (A1) and z (A2); y predictor: z (A1) and x (A2)
+#pragma unroll
+        for (int r = 0; r < 7; r++)
+#pragma unroll
+            for (int s = 0; s < 2; s++) {
+                zx.fa[r][s] = F[1][row_a1(r)][s];
+                zx.fb[r][s] = F[2][row_a2(r)][s];
+                zy.fa[r][s] = F[2][row_a1(r)][s];
+                zy.fb[r][s] = F[0][row_a2(r)][s];
+            }
+        if (needX) shp[tid] = zone_record<R, 0, 2>(zx, cf, prm, scv);
+        if (needY) ry = zone_record<R, 1, 2>(zy, cf, prm, scv);
+    }
+    __syncthreads();
+
+    // ---------------- x faces: tx - 3 between zones tx - 4 and tx - 3 ----------------
+    {
+        FaceEig<R> e;
+        R alpha[7], nu[7];
+        R bf = R(0);
+        bool prot = false;
+        const bool face = needX && tx >= 1;
+        if (face) {
+            bf = bload(z0, rw, xo, (unsigned)F_BH * VB);
+            Rec8<R> gr;
+            face_phase<R, PROT>(shp[tid - 1], shp[tid], bf, sc_lam(scv, 0, R(0)), cf, e, alpha, nu, gr, prot);
+            shg[tid] = gr;
+        }
+        __syncthreads();
+        if (face && tx >= 2 && tx <= P - 2)
+            xy_flux<R, 0, MM, PROT>(shp, shg, tid, 1, bf, e, alpha, nu, prot, cf, sc_il(scv, 0, R(0)), rw, xo, VB,
+                                    nprot);
+    }
+    __syncthreads();  // the x records and g-tilde are read
+    if (needY) shp[tid] = ry;
+    __syncthreads();
+
+    // ---------------- y faces: y between rows ty - 1 and ty ----------------
+    {
+        FaceEig<R> e;
+        R alpha[7], nu[7];
+        R bf = R(0);
+        bool prot = false;
+        const bool face = needY && ty >= 1;
+        if (face) {
+            bf = bload(z0, rw, xo, (unsigned)(F_BH + 1) * VB);
+            Rec8<R> gr;
+            face_phase<R, PROT>(shp[tid - P], shp[tid], bf, sc_lam(scv, 1, R(0)), cf, e, alpha, nu, gr, prot);
+            shg[tid] = gr;
+        }
+        __syncthreads();
+        if (face && ty >= 2 && ty <= rows - 2)
+            xy_flux<R, 1, MM, PROT>(shp, shg, tid, P, bf, e, alpha, nu, prot, cf, sc_il(scv, 1, R(0)), rw, xo, VB,
+                                    nprot);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // FP64 diagnostics with compensated sums.  Every running sum is an unevaluated
 // pair hi + lo: a value is added with the error-free TwoSum, and two pairs
 // are merged by adding their high parts error-free and their low parts
@@ -1851,6 +2011,28 @@ hipError_t launch_march(int d, int stage, void* pool, const PatchDev* pt, const 
     return hipGetLastError();
 }
 
+// the fused x and y correctors: blocks of P = n_x + 6 by RT rows (one z-plane band each)
+template <typename R>
+hipError_t launch_corr_xy(void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm,
+                          const Coef<R>& cf, int cur, const StepConst* sc, int P, int RT, unsigned long long* nprot,
+                          hipStream_t st) {
+    if (nblk <= 0) return hipSuccess;
+    // FP64 blocks stay within 512 threads (the kernel's launch bound), which the LDS bound implies
+    if (P < 1 || RT < 4 || P * RT > 1024 || sizeof(R) * 16 * (size_t)P * RT > 64 * 1024) return hipErrorInvalidValue;
+    const size_t shmem = sizeof(R) * 16 * (size_t)P * RT;
+    const bool mm = cf.beta_l == R(1);
+    const bool pr = cf.rho_prot > R(0) || cf.p_prot > R(0);
+#define WMB_XY(MM, PR)                                                                                              \
+    hipLaunchKernelGGL((corr_xy_kernel<R, MM, PR>), dim3(nblk), dim3(P, RT), shmem, st, (R*)pool, pt, wk, prm, cf, \
+                       cur, sc, nprot)
+    if (mm && !pr) WMB_XY(true, false);
+    else if (mm) WMB_XY(true, true);
+    else if (!pr) WMB_XY(false, false);
+    else WMB_XY(false, true);
+#undef WMB_XY
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_diag(const void* pool, const PatchDev* pt, const WorkItem* wk, int nblk, const DevParams& prm, int cur,
                        double* rec, const unsigned long long* counters, double nzones, double dmin, double* out,
@@ -1878,6 +2060,9 @@ hipError_t launch_diag(const void* pool, const PatchDev* pt, const WorkItem* wk,
     template hipError_t launch_march<R>(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&,        \
                                         const Coef<R>&, int, const StepConst*, int, int, int, unsigned long long*,       \
                                         hipStream_t);                                                                    \
+    template hipError_t launch_corr_xy<R>(void*, const PatchDev*, const WorkItem*, int, const DevParams&,           \
+                                          const Coef<R>&, int, const StepConst*, int, int, unsigned long long*,         \
+                                          hipStream_t);                                                                  \
     template hipError_t launch_diag<R>(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int,        \
                                        double*, const unsigned long long*, double, double, double*, hipStream_t);
 WMB_INST(float)

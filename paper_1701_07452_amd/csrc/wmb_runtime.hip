@@ -23,6 +23,7 @@ hipError_t launch_set_patch(PatchDev*, int, const PatchDev&, hipStream_t);
 template <typename R> hipError_t launch_ct_half(void*, const PatchDev*, const WorkItem*, int, const Coef<R>&, int, int, const StepConst*, hipStream_t);
 template <typename R> hipError_t launch_update(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, unsigned long long*, unsigned long long*, int, int, unsigned int*, hipStream_t);
 template <typename R> hipError_t launch_sweep(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, int, int, int, unsigned long long*, hipStream_t);
+template <typename R> hipError_t launch_corr_xy(void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, int, int, unsigned long long*, hipStream_t);
 template <typename R> hipError_t launch_march(int, int, void*, const PatchDev*, const WorkItem*, int, const DevParams&, const Coef<R>&, int, const StepConst*, int, int, int, unsigned long long*, hipStream_t);
 template <typename R> hipError_t launch_diag(const void*, const PatchDev*, const WorkItem*, int, const DevParams&, int, double*, const unsigned long long*, double, double, double*, hipStream_t);
 }  // namespace wmb
@@ -47,6 +48,11 @@ struct SweepGroup {
     std::vector<DevList> wlg;  // the same for the patches of each step group (grouped schedule)
     DevList wl_in, wl_fr;  // Step-1 x sweep only: the pencils with both transverse
                            // coords interior, and the frame around them
+    // corrector x groups, with the fused x/y corrector on: its z-plane bands
+    // (all patches, and per step group) and the block's rows
+    int RT = 0;
+    DevList wxy;
+    std::vector<DevList> wxyg;
 };
 
 // What the device signal-speed maximum (smax) holds relative to the current state.
@@ -94,6 +100,7 @@ struct wmb_ctx {
     int upd_zones = 256;  // zones a tile plane of Steps 8-11 (the update's block size)
     int cth_tx = 40;      // widest tile of Steps 3-4 along x (zones; 256 a tile plane)
     int upd_queue = 0;    // Steps 8-11 launch: 0 one block a tile, 1 persistent blocks on per-XCD queues
+    int xy_rows = 0;      // fused x/y corrector: 0 off (separate x and y sweeps), else the most y-face rows a band
     unsigned int* d_queue = nullptr;  // the queues' counters, 16 per step group
     int nfrozen = 0;      // frozen patches
     bool plan_dirty = false;  // the active set changed since the stage work lists were planned
@@ -433,6 +440,24 @@ hipError_t launch_group(wmb_ctx* c, int d, int stage, const SweepGroup& G, const
                            nprot, st);
 }
 
+// the corrector's x sweeps of one group's list (wl: all patches; g >= 0: step
+// group g), as the fused x/y kernel when xy_rows > 0
+template <typename R>
+hipError_t launch_corr_x(wmb_ctx* c, int g, int cur, unsigned long long* nprot, hipStream_t st) {
+    for (auto& G : c->sweeps[0][1]) {
+        hipError_t r;
+        if (c->xy_rows > 0) {
+            const DevList& L = g < 0 ? G.wxy : G.wxyg[g];
+            r = launch_corr_xy<R>(c->pool, c->d_patch, L.d, L.n, c->dp, coef<R>(c), cur, c->d_sc, G.P, G.RT, nprot,
+                                  st);
+        } else {
+            r = launch_group<R>(c, 0, 2, G, g < 0 ? G.wl : G.wlg[g], cur, nprot, st);
+        }
+        if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+}
+
 // whether a sweep shape is valid for axis d and pencils of P zones (marching
 // shapes -W with W in [1, 256], or W + 512 in FP32 for the corrector with
 // the next zone's loads issued one zone ahead)
@@ -535,19 +560,23 @@ int run_step(wmb_ctx* c, bool split = false) {
         CKH(hipEventRecord(c->ev_br[2], c->stream));
         CKH(hipStreamWaitEvent(c->side, c->ev_br[2], 0));
         CKH(hipStreamWaitEvent(c->side2, c->ev_br[2], 0));
-        e = sweeps(1, 2, &SweepGroup::wl, c->side);
-        STEPCK("sweep2");
+        // with the fused x/y corrector the y branch is empty
+        if (!c->xy_rows) {
+            e = sweeps(1, 2, &SweepGroup::wl, c->side);
+            STEPCK("sweep2");
+        }
         e = sweeps(2, 2, &SweepGroup::wl, c->side2);
         STEPCK("sweep2");
         CKH(hipEventRecord(c->ev_br[3], c->side));
         CKH(hipEventRecord(c->ev_br[4], c->side2));
-        e = sweeps(0, 2, &SweepGroup::wl, c->stream);
+        e = launch_corr_x<R>(c, -1, cur, c->d_nfloor + 1, c->stream);
         STEPCK("sweep2");
         CKH(hipStreamWaitEvent(c->stream, c->ev_br[3], 0));
         CKH(hipStreamWaitEvent(c->stream, c->ev_br[4], 0));
     } else {
         for (int d = 0; d < 3; d++) {
-            e = sweeps(d, 2, &SweepGroup::wl, c->stream);
+            if (d == 0) e = launch_corr_x<R>(c, -1, cur, c->d_nfloor + 1, c->stream);
+            else if (d == 2 || !c->xy_rows) e = sweeps(d, 2, &SweepGroup::wl, c->stream);
             STEPCK("sweep2");
             mark(c);
         }
@@ -588,8 +617,12 @@ int run_step_grouped(wmb_ctx* c) {
         hipError_t e = hipSuccess;
         for (int stage = 1; stage <= 2 && e == hipSuccess; stage++) {
             for (int d = 0; d < 3 && e == hipSuccess; d++) {
-                for (auto& SG : c->sweeps[d][stage - 1])
-                    if (e == hipSuccess) e = launch_group<R>(c, d, stage, SG, SG.wlg[g], cur, c->d_nfloor + 1, st);
+                if (stage == 2 && d == 0) {
+                    e = launch_corr_x<R>(c, g, cur, c->d_nfloor + 1, st);
+                } else if (!(stage == 2 && d == 1 && c->xy_rows)) {
+                    for (auto& SG : c->sweeps[d][stage - 1])
+                        if (e == hipSuccess) e = launch_group<R>(c, d, stage, SG, SG.wlg[g], cur, c->d_nfloor + 1, st);
+                }
                 if (!par) mark(c);
             }
             if (stage == 1 && e == hipSuccess) {
@@ -914,6 +947,78 @@ int set_group_W(wmb_ctx* c, int d, int stage, SweepGroup& G, int W) {
     return WMB_OK;
 }
 
+// The fused x/y corrector (xy_rows > 0): for the patches whose x edge is n,
+// one item a z-plane k in [-1, n_z] and band of y-face rows, the rows [-1,
+// n_y + 2) cut into near-equal bands of at most rb rows.  Planes outermost,
+// so that consecutive blocks of a patch share the z-flux plane between them.
+std::vector<WorkItem> xy_items(const wmb_ctx* c, int n, int rb, int group = -1) {
+    std::vector<WorkItem> items;
+    for (int p = 0; p < c->npatch; p++) {
+        if (c->desc[p].n[0] != n || !in_plan(c, p)) continue;
+        if (group >= 0 && c->pgroup[p] != group) continue;
+        const int* e = c->desc[p].n;
+        const int E = e[1] + 3, nb = (E + rb - 1) / rb;
+        for (int k = -1; k <= e[2]; k++)
+            for (int b = 0; b < nb; b++) {
+                const int y0 = -1 + E * b / nb, y1 = -1 + E * (b + 1) / nb;
+                items.push_back(WorkItem{p, k + XY_BIAS, (y0 + XY_BIAS) | ((y1 + XY_BIAS) << 16), 0});
+            }
+    }
+    return xcd_order(items);
+}
+
+// rows of the fused corrector's block for x edge n: the largest band of any
+// patch of that edge (frozen or absent ones too, so that the launch shape
+// does not change when the plan does) plus the limiter's three halo rows
+int xy_rt(const wmb_ctx* c, int n, int rb) {
+    int rt = 0;
+    for (int p = 0; p < c->npatch; p++) {
+        if (c->desc[p].n[0] != n) continue;
+        const int E = c->desc[p].n[1] + 3, nb = (E + rb - 1) / rb;
+        rt = std::max(rt, (E + nb - 1) / nb + 3);
+    }
+    return rt;
+}
+
+// whether bands of at most rb rows fit the fused corrector's blocks for
+// every x edge (1024 threads, 64 KiB of LDS)
+bool xy_ok(const wmb_ctx* c, int rb) {
+    if (rb < 1 || rb > 64) return false;
+    for (const auto& G : c->sweeps[0][1]) {
+        const long long t = (long long)G.P * xy_rt(c, G.n, rb);
+        if (t > 1024 || (long long)c->esize * 16 * t > 64 * 1024) return false;
+    }
+    return true;
+}
+
+// Switch the fused x/y corrector off (rb = 0) or on with bands of at most rb
+// rows: (re)build its lists, freeing the ones they replace.
+int set_xy(wmb_ctx* c, int rb) {
+    for (auto& G : c->sweeps[0][1]) {
+        release(c, G.wxy.d);
+        G.wxy = DevList{};
+        for (auto& L : G.wxyg) {
+            release(c, L.d);
+            L = DevList{};
+        }
+        G.RT = 0;
+        if (rb <= 0) continue;
+        std::vector<WorkItem> items = xy_items(c, G.n, rb);
+        G.wxy.n = (int)items.size();
+        int rc = upload(c, &G.wxy.d, items);
+        if (rc) return rc;
+        if (c->ngroups > 1 && G.wxyg.size() < (size_t)c->ngroups) G.wxyg.resize(c->ngroups);
+        for (int g = 0; g < c->ngroups && c->ngroups > 1; g++) {
+            std::vector<WorkItem> gi = xy_items(c, G.n, rb, g);
+            G.wxyg[g].n = (int)gi.size();
+            if (!gi.empty() && (rc = upload(c, &G.wxyg[g].d, gi))) return rc;
+        }
+        G.RT = xy_rt(c, G.n, rb);
+    }
+    c->xy_rows = rb > 0 ? rb : 0;
+    return WMB_OK;
+}
+
 int build_sweeps(wmb_ctx* c) {
     for (int d = 0; d < 3; d++) {
         for (int stage = 0; stage < 2; stage++) {
@@ -997,6 +1102,12 @@ int replan(wmb_ctx* c) {
                 if (!rc && d == 0 && stage == 0) rc = put(G.wl_in, sweep_items(c, d, G.n, G.tlo, G.thi, W, PART_INTERIOR));
                 if (!rc && d == 0 && stage == 0) rc = put(G.wl_fr, sweep_items(c, d, G.n, G.tlo, G.thi, W, PART_FRAME));
             }
+    for (auto& G : c->sweeps[0][1]) {
+        if (c->xy_rows <= 0) break;
+        if (!rc) rc = put(G.wxy, xy_items(c, G.n, c->xy_rows));
+        for (int g = 0; g < c->ngroups && c->ngroups > 1 && !rc; g++)
+            rc = put(G.wxyg[g], xy_items(c, G.n, c->xy_rows, g));
+    }
     const std::vector<int> rows = x_rows(c);
     if (!rc) rc = put(c->wl_cth, tile_items(c, -2, 2, -2, 2, c->cth_tx, 256, nullptr));
     if (!rc) rc = put(c->wl_upd, tile_items(c, 0, -1, 0, -1, 32, c->upd_zones, &rows));
@@ -1240,6 +1351,11 @@ int autotune_t(wmb_ctx* c, int reps) {
     CKT(hipEventCreate(&e0));
     CKT(hipEventCreate(&e1));
     const size_t es = sizeof(R);
+    // the separate sweeps are timed first; the fused x/y corrector after them
+    if (c->xy_rows > 0) {
+        int rc0 = set_xy(c, 0);
+        if (rc0) return cleanup(rc0);
+    }
     for (int stage = 0; stage < 2; stage++) {
         if (stage == 1) {
             // intermediates the corrector sweeps read: Step-1 fluxes, edges, b^{n+1/2}
@@ -1314,56 +1430,56 @@ int autotune_t(wmb_ctx* c, int reps) {
     // steps replayed from a captured graph for the shapes picked alone, then,
     // stage by stage, for each x group its second and third shapes alone,
     // then for the best pencil shapes and for the best marching shapes of
-    // the y and z groups, keeping the fastest each time.
+    // the y and z groups, keeping the fastest each time.  time_stage: a
+    // whole step captured and replayed as a graph, as wmb_run_steps runs it
+    // (the sweeps of a stage as branches), its results going nowhere the
+    // next step reads: the update writes the other state copy, floors,
+    // protected faces and the signal-speed maximum go to the sinks, and the
+    // current copy and the flags are restored
+    auto time_stage = [&](float* ms) -> int {
+        unsigned long long *smax0 = c->d_smax, *nfl0 = c->d_nfloor;
+        const int cur0 = c->cur, ss0 = c->smax_state;
+        const bool xg0 = c->xg_valid, ek0 = c->edges_kept;
+        c->d_smax = smax0 + 2;
+        c->d_nfloor = nfl0 + 2;
+        hipGraph_t gr = nullptr;
+        hipGraphExec_t ge = nullptr;
+        int rc4 = WMB_OK;
+        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
+        if (e == hipSuccess) {
+            e = hipEventRecord(c->ev_join, c->stream);  // the exchange is done
+            if (e == hipSuccess) rc4 = run_step<R>(c, true);
+            hipError_t e2 = hipStreamEndCapture(c->stream, &gr);
+            if (e == hipSuccess) e = e2;
+        }
+        c->d_smax = smax0;
+        c->d_nfloor = nfl0;
+        c->cur = cur0;
+        c->smax_state = ss0;
+        c->xg_valid = xg0;
+        c->edges_kept = ek0;
+        if (!rc4 && e == hipSuccess) e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+        float tot = 1e30f;
+        for (int r = 0; r <= reps && !rc4 && e == hipSuccess; r++) {
+            e = hipEventRecord(e0, c->stream);
+            if (e == hipSuccess) e = hipGraphLaunch(ge, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            if (r > 0) tot = std::min(tot, t);
+        }
+        // a graph executable is destroyed only on an idle device (ROCm 7
+        // otherwise keeps the memory its kernels used from being freed)
+        (void)hipDeviceSynchronize();
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (gr) (void)hipGraphDestroy(gr);
+        if (rc4) return cleanup(rc4);
+        if (e != hipSuccess) return cleanup(fail(c, WMB_EHIP, std::string("autotune: ") + hipGetErrorString(e)));
+        *ms = tot;
+        return WMB_OK;
+    };
     for (int stage = 0; stage < 2; stage++) {
-        // a whole step captured and replayed as a graph, as wmb_run_steps
-        // runs it (the sweeps of a stage as branches), its results going
-        // nowhere the next step reads: the update writes the other state
-        // copy, floors, protected faces and the signal-speed maximum go to
-        // the sinks, and the current copy and the flags are restored
-        auto time_stage = [&](float* ms) -> int {
-            unsigned long long *smax0 = c->d_smax, *nfl0 = c->d_nfloor;
-            const int cur0 = c->cur, ss0 = c->smax_state;
-            const bool xg0 = c->xg_valid, ek0 = c->edges_kept;
-            c->d_smax = smax0 + 2;
-            c->d_nfloor = nfl0 + 2;
-            hipGraph_t gr = nullptr;
-            hipGraphExec_t ge = nullptr;
-            int rc4 = WMB_OK;
-            hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
-            if (e == hipSuccess) {
-                e = hipEventRecord(c->ev_join, c->stream);  // the exchange is done
-                if (e == hipSuccess) rc4 = run_step<R>(c, true);
-                hipError_t e2 = hipStreamEndCapture(c->stream, &gr);
-                if (e == hipSuccess) e = e2;
-            }
-            c->d_smax = smax0;
-            c->d_nfloor = nfl0;
-            c->cur = cur0;
-            c->smax_state = ss0;
-            c->xg_valid = xg0;
-            c->edges_kept = ek0;
-            if (!rc4 && e == hipSuccess) e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
-            float tot = 1e30f;
-            for (int r = 0; r <= reps && !rc4 && e == hipSuccess; r++) {
-                e = hipEventRecord(e0, c->stream);
-                if (e == hipSuccess) e = hipGraphLaunch(ge, c->stream);
-                if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-                if (e == hipSuccess) e = hipEventSynchronize(e1);
-                float t = 0.f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-                if (r > 0) tot = std::min(tot, t);
-            }
-            // a graph executable is destroyed only on an idle device (ROCm 7
-            // otherwise keeps the memory its kernels used from being freed)
-            (void)hipDeviceSynchronize();
-            if (ge) (void)hipGraphExecDestroy(ge);
-            if (gr) (void)hipGraphDestroy(gr);
-            if (rc4) return cleanup(rc4);
-            if (e != hipSuccess) return cleanup(fail(c, WMB_EHIP, std::string("autotune: ") + hipGetErrorString(e)));
-            *ms = tot;
-            return WMB_OK;
-        };
         float best = 0.f;
         int rc2 = time_stage(&best);
         if (rc2) return rc2;
@@ -1416,6 +1532,22 @@ int autotune_t(wmb_ctx* c, int reps) {
                 for (auto& G : c->sweeps[d][stage])
                     if (!rc2) rc2 = set_group_W(c, d, stage, G, choice == 1 ? G.Wp : G.Wm);
         if (rc2) return cleanup(rc2);
+    }
+    // The fused x/y corrector: bands of 6, 9, 12 or 18 rows against the
+    // separate x and y sweeps, whole steps replayed as a graph.
+    {
+        float best = 0.f;
+        int rc2 = time_stage(&best);
+        if (rc2) return rc2;
+        int best_rb = 0;
+        for (int rb : {6, 9, 12, 18}) {
+            if (!xy_ok(c, rb)) continue;
+            if ((rc2 = set_xy(c, rb))) return cleanup(rc2);
+            float t = 0.f;
+            if ((rc2 = time_stage(&t))) return rc2;
+            if (t < best) best = t, best_rb = rb;
+        }
+        if ((rc2 = set_xy(c, best_rb))) return cleanup(rc2);
     }
     // The tiles of Steps 3-4 (widest tile along x) and of Steps 8-11 (zones
     // a tile plane): time each candidate's whole launch.  The intermediates
@@ -1518,6 +1650,7 @@ std::vector<int32_t> tuning_quads(const wmb_ctx* c) {
     q.insert(q.end(), {3, 0, 0, c->cth_tx});
     q.insert(q.end(), {4, 0, 0, c->upd_zones});
     q.insert(q.end(), {5, 0, 0, c->upd_queue});
+    q.insert(q.end(), {6, 0, 0, c->xy_rows});
     return q;
 }
 
@@ -1610,6 +1743,10 @@ int apply_groups(wmb_ctx* c, int groups) {
                 int rc = set_group_W(c, d, stage, SG, SG.W);
                 if (rc) return rc;
             }
+    if (c->xy_rows > 0) {
+        int rc = set_xy(c, c->xy_rows);
+        if (rc) return rc;
+    }
     return build_ct_update_lists(c);
 }
 
@@ -1903,6 +2040,12 @@ int wmb_set_tuning(wmb_ctx* c, const int32_t* quads, int32_t n) {
                 return fail(c, WMB_EINVAL, "tuning entry: (5, 0, 0, 0 or 1) picks the Steps 8-11 launch");
             continue;
         }
+        if (stage == 6) {
+            if (d != 0 || edge != 0 || W < 0 || (W > 0 && !xy_ok(c, W)))
+                return fail(c, WMB_EINVAL, "tuning entry: (6, 0, 0, r) fuses the x and y correctors with bands of at "
+                                           "most r rows (0: separate), each block within 1024 threads and 64 KiB of LDS");
+            continue;
+        }
         if (stage == 3 || stage == 4) {
             if (d != 0 || edge != 0) return fail(c, WMB_EINVAL, "tuning entry: tile entries have axis 0 and edge 0");
             if (stage == 3 && (W < 4 || W > 40))
@@ -1922,6 +2065,13 @@ int wmb_set_tuning(wmb_ctx* c, const int32_t* quads, int32_t n) {
         const int stage = quads[k], d = quads[k + 1], edge = quads[k + 2], W = quads[k + 3];
         if (stage == 5) {
             c->upd_queue = W;
+            continue;
+        }
+        if (stage == 6) {
+            if (W != c->xy_rows) {
+                int rc = set_xy(c, W);
+                if (rc) return rc;
+            }
             continue;
         }
         if (stage == 3 || stage == 4) {

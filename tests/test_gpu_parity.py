@@ -519,7 +519,7 @@ def test_autotune_does_not_change_results(wmb):
     N = G.shape
     dx = (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
     for prec in (1, 0):
-        tiles = [None, "auto", {(3, 0, 0): 13, (4, 0, 0): 256}, {(3, 0, 0): 20, (5, 0, 0): 1}]
+        tiles = [None, "auto", {(3, 0, 0): 13, (4, 0, 0): 256}, {(3, 0, 0): 20, (5, 0, 0): 1, (6, 0, 0): 12}]
         if prec == 1:
             tiles += [{(3, 0, 0): 40, (4, 0, 0): 512}, {(4, 0, 0): 512, (5, 0, 0): 1}]
         outs, chosen = [], None
@@ -528,7 +528,7 @@ def test_autotune_does_not_change_results(wmb):
             if t == "auto":
                 chosen = sim.autotune(reps=1)
                 assert chosen, "autotune returned no groups"
-                assert (3, 0, 0) in chosen and (4, 0, 0) in chosen and (5, 0, 0) in chosen, chosen
+                assert all((e, 0, 0) in chosen for e in (3, 4, 5, 6)), chosen
                 assert sim.autotune(reps=1) == chosen  # the cached choice
             elif t:
                 sim.set_tuning(t)
@@ -541,10 +541,12 @@ def test_autotune_does_not_change_results(wmb):
 
 
 def test_tile_tuning_entries_are_checked(wmb):
-    """wmb_set_tuning rejects tile entries outside what the kernels take."""
+    """wmb_set_tuning rejects tile and fused-corrector entries outside what
+    the kernels take."""
     G, (q, b) = CASES["uneven"]()
     for prec, bad in ((1, {(3, 0, 0): 41}), (1, {(3, 0, 0): 3}), (1, {(4, 0, 0): 384}), (0, {(4, 0, 0): 512}),
-                      (1, {(3, 0, 5): 20}), (1, {(5, 0, 0): 2})):
+                      (1, {(3, 0, 5): 20}), (1, {(5, 0, 0): 2}), (1, {(6, 0, 0): -1}), (0, {(6, 0, 0): 65}),
+                      (1, {(6, 0, 1): 9})):
         sim = gpu_sim(wmb, G, q, b, prec, dx=(1 / 64,) * 3)
         with pytest.raises(RuntimeError):
             sim.set_tuning(bad)
@@ -674,6 +676,63 @@ def test_sweep_forms_bitwise_equal(wmb, form):
         assert np.array_equal(outs[0][0][0], outs[k][0][0]) and np.array_equal(outs[0][0][1], outs[k][0][1]), k
         for i, (a, c) in enumerate(zip(outs[0][1], outs[k][1])):
             assert np.array_equal(a, c), (k, i, float(np.abs(a - c).max()))
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_fused_xy_corrector_bitwise_equal(wmb, form):
+    """The fused x/y corrector (one launch builds both predictor states from
+    one load of each zone and forms the x and y faces of a z-plane band)
+    gives bitwise the state of the separate x and y corrector sweeps after 3
+    eager steps, and the same Step-6/7 x and y fluxes on the faces and rows
+    the update reads, for bands of 6 and 9 rows (and 18 where the block
+    fits); the uneven tiling also through 3 graph-replayed steps, alone and
+    with two patch groups on their own streams."""
+    prec, kw, grid = FORMS[form]
+    if grid == "cube64":
+        G = I.uniform_grid(64, 64)
+        q, b = I.turbulence(64, seed=9)
+    else:
+        G, (q, b) = CASES[grid]()
+    N = G.shape
+    dx = (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
+    bands = [0, 6, 9] + ([18] if grid == "uneven" else [])
+    outs = []
+    for rb in bands:
+        sim = gpu_sim(wmb, G, q, b, prec, dx=dx, **kw)
+        sim.set_tuning({(6, 0, 0): rb})
+        for _ in range(3):
+            sim.fill_ghosts()
+            sim.compute_dt(fetch=False)
+            sim.advance(0.0)
+        st = I.gather(G, [sim.get_state(i) for i in range(G.npatch)])
+        g = int(sim.params.ghost)
+        fl = []
+        for ip in range(G.npatch):
+            n = G.descs[ip][0]
+            f = sim.debug_stage(ip, 5)
+            for d in (0, 1):
+                sl = [None] * 3
+                for a in range(3):
+                    lo, hi = (-1, 1) if a == d else (-1, 0)
+                    sl[2 - a] = slice(g + lo, g + n[a] + hi + 1)
+                fl.append(f[d][(slice(None),) + tuple(sl)])
+        graph = []
+        if grid == "uneven":
+            for groups in (1, 2):
+                sim2 = gpu_sim(wmb, G, q, b, prec, dx=dx, **kw)
+                sim2.set_tuning({(6, 0, 0): rb})
+                sim2.set_schedule(groups)
+                sim2.run_steps(3)
+                graph.append(I.gather(G, [sim2.get_state(i) for i in range(G.npatch)]))
+                sim2.close()
+        outs.append((st, fl, graph))
+        sim.close()
+    for k in range(1, len(bands)):
+        assert np.array_equal(outs[0][0][0], outs[k][0][0]) and np.array_equal(outs[0][0][1], outs[k][0][1]), k
+        for i, (a, c) in enumerate(zip(outs[0][1], outs[k][1])):
+            assert np.array_equal(a, c), (bands[k], i, float(np.abs(a - c).max()))
+        for a, c in zip(outs[0][2], outs[k][2]):
+            assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1]), bands[k]
 
 
 def test_c1_linear_fast_wave_32_fp64_10_steps(wmb):
