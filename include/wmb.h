@@ -231,7 +231,8 @@ int wmb_debug_stage(wmb_ctx *c, int32_t patch, int32_t stage, double *out);
    changes results (both forms compute every face with the same
    arithmetic).  It then times whole graph-replayed steps with the x and y
    correctors fused into one launch (bands of 6, 9, 12 or 18 rows, where
-   the blocks fit) against the separate sweeps, and the tiles of Steps 3-4
+   the blocks fit, each with three shapes of the z corrector that reads the
+   records it stores) against the separate sweeps, and the tiles of Steps 3-4
    (the widest tile along x: 40, 20 or 13 zones, 256 zones a plane) and of
    Steps 8-11 (256 or, in FP32, 512 zones a plane) with either Steps 8-11
    launch; none of these changes results either.  The
@@ -265,14 +266,17 @@ int wmb_autotune(wmb_ctx *c, int32_t reps, int32_t *chosen, int32_t nchosen);
    the default is the one that leaves fewer threads idle); (5, 0, 0, m) the
    Steps 8-11 launch: m = 0 one block a tile (the default), m = 1 a
    persistent grid whose blocks take the tiles of their XCD's queue from an
-   atomic counter; (6, 0, 0, r) the corrector (Steps 5-7) along x and y:
-   r = 0 two separate sweeps (the default), r > 0 one fused launch whose
+   atomic counter; (6, 0, 0, r) the corrector (Steps 5-7): r = 0 three
+   separate sweeps (the default), r > 0 one fused launch for x and y whose
    blocks each take one z-plane of a patch and a band of at most r rows
-   along y, load each zone's data once and build both predictor states from
-   it (bitwise the same fluxes; the y sweep groups' shapes are then unused).
-   WMB_EINVAL if a block of (n_x + 6) x (r + 3) threads, for any x edge,
-   exceeds 1024 threads or 64 KiB of LDS (16 words a thread).  Every entry
-   is checked before any is applied. */
+   along y, build the x, y and z predictor states of their zones from one
+   block's loads, form the x and y faces and store the z predictor records
+   in the z flux rows, which the z corrector sweep then reads instead of
+   q^n and the Step-1 fluxes (bitwise the same fluxes; the y corrector
+   groups' shapes are then unused, the z ones shape that sweep).  WMB_EINVAL
+   if a block of (n_x + 6) x (r + 3) threads, for any x edge, exceeds 1024
+   threads or 64 KiB of LDS (16 words a thread).  Every entry is checked
+   before any is applied. */
 int wmb_set_tuning(wmb_ctx *c, const int32_t *quads, int32_t n);
 
 /* Schedule of the captured step (wmb_run_steps).  groups = 1 (the default):

@@ -997,13 +997,22 @@ struct ZoneRaw {
     R fa[STAGE == 2 ? 7 : 1][2], fb[STAGE == 2 ? 7 : 1][2], b[STAGE == 2 ? 3 : 1][2];
 };
 
-// rs: the patch's state, rw: its step intermediates (the Step-1 fluxes)
+// rs: the patch's state, rw: its step intermediates (the Step-1 fluxes).
+// STAGE 3: the corrector along D from the predictor records that the fused
+// x/y corrector stored in the rows of D's corrector flux (q[0..6]: rho,
+// v_D, v_A1, v_A2, B_A1, B_A2, P), each read once before its slot is
+// overwritten by the flux of the same pencil.
 template <typename R, int D, int STAGE>
 __device__ __forceinline__ void zone_fetch(__amdgpu_buffer_rsrc_t rs, __amdgpu_buffer_rsrc_t rw, unsigned xo,
                                            const unsigned st[3], unsigned qs, unsigned VB, ZoneRaw<R, STAGE>& z) {
     constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
     constexpr unsigned ES = sizeof(R);
     const R z0 = R(0);
+    if (STAGE == 3) {
+#pragma unroll
+        for (int r = 0; r < 7; r++) z.q[r] = bload(z0, rw, xo, (unsigned)(F_FL2 + 7 * D + r) * VB);
+        return;
+    }
 #pragma unroll
     for (int c = 0; c < 8; c++) z.q[c] = bload(z0, rs, xo, qs + c * VB);
     if (STAGE == 2) {
@@ -1032,6 +1041,13 @@ __device__ __forceinline__ Rec8<R> zone_record(const ZoneRaw<R, STAGE>& z, const
                                                const StepConst& sc) {
 #pragma clang fp contract(on)
     constexpr int A1 = (D + 1) % 3, A2 = (D + 2) % 3;
+    if (STAGE == 3) {
+        Rec8<R> rec;
+#pragma unroll
+        for (int r = 0; r < 7; r++) rec.v[r] = z.q[r];
+        rec.v[7] = frsq(z.q[0]);
+        return rec;
+    }
     R u[8];
 #pragma unroll
     for (int c = 0; c < 8; c++) u[c] = z.q[c];
@@ -1497,10 +1513,12 @@ __global__ void __launch_bounds__(256) march_kernel(R* __restrict__ pool, const 
 
     // Zone s's loads and face field requested one iteration ahead, so that
     // their latency overlaps the previous face's arithmetic: always in FP32
-    // Step 1 (9 loads a zone); in the FP32 corrector (43 loads a zone) as
-    // the variant PF2, which takes 2 waves a SIMD instead of 4; never in
-    // FP64, whose marching kernels already use 256 VGPRs.
-    constexpr bool PF = sizeof(R) == 4 && (STAGE == 1 || PF2);
+    // Step 1 (9 loads a zone) and in the FP32 corrector from stored records
+    // (STAGE 3, 8 loads); in the FP32 corrector from q^n and the Step-1
+    // fluxes (43 loads a zone) as the variant PF2, which takes 2 waves a
+    // SIMD instead of 4; never in FP64, whose marching kernels already use
+    // 256 VGPRs.
+    constexpr bool PF = sizeof(R) == 4 && (STAGE != 2 || PF2);
     MarchFace<R> pv;  // zone s-1 and face s-1
     pv.rec = zone_phase<R, D, STAGE>(rs, rw, xo, st, qs, VB, cf, prm, scv);
     ZoneRaw<R, STAGE> nx;
@@ -1569,7 +1587,13 @@ __global__ void __launch_bounds__(256) march_kernel(R* __restrict__ pool, const 
 //   limiter stencil); item a = k + XY_BIAS, b = (y0 + XY_BIAS) | (y1 +
 //   XY_BIAS) << 16.
 // x faces are formed on the band's rows within [-1, n_y], y faces on the
-// band's rows at x in [-1, n_x]: the ranges of the separate sweeps.
+// band's rows at x in [-1, n_x]: the ranges of the separate sweeps.  The
+// same loads also give the z predictor state of the band's rows at x in
+// [-1, n_x]; its record (7 words) is stored in the zone's z corrector flux
+// rows, where the z sweep then reads it (STAGE 3) instead of 43 loads of
+// q^n and the Step-1 fluxes.  The z pencils need records on the planes
+// [-3, n_z + 3): the items of the four planes beyond [-1, n_z] form only
+// these records.
 // ---------------------------------------------------------------------------
 
 // rows of a transverse Step-1 flux in ZoneRaw's order (rows 0-4, then the
@@ -1622,8 +1646,11 @@ __global__ void __launch_bounds__(sizeof(R) == 4 ? 1024 : 512) corr_xy_kernel(R*
     const int rows = y1 - y0 + 3;  // the band's rows, [y0 - 2, y1]
     const int x = tx - 3, y = y0 - 2 + ty;
     const bool live = ty < rows;
-    const bool needX = live && y >= y0 && y < y1 && y <= Pt.n[1];  // x faces of this row
-    const bool needY = live && x >= -1 && x <= Pt.n[0];            // y faces of this column
+    const bool faces = k >= -1 && k <= Pt.n[2];  // planes of x and y faces (others: z records only)
+    const bool own = live && y >= y0 && y < y1 && y <= Pt.n[1];     // the band's rows within [-1, n_y]
+    const bool needX = faces && own;                                // x faces of this row
+    const bool needY = faces && live && x >= -1 && x <= Pt.n[0];    // y faces of this column
+    const bool needZ = own && x >= -1 && x <= Pt.n[0];              // the z predictor record
     const int g = prm.ghost;
     const unsigned st[3] = {1u, (unsigned)Pt.N[0], (unsigned)(Pt.N[0] * Pt.N[1])};
     const unsigned xo = live ? ((unsigned)(x + g) + st[1] * (unsigned)(y + g) + st[2] * (unsigned)(k + g)) * ES : 0u;
@@ -1665,9 +1692,32 @@ __global__ void __launch_bounds__(sizeof(R) == 4 ? 1024 : 512) corr_xy_kernel(R*
                 zy.fa[r][s] = F[2][row_a1(r)][s];
                 zy.fb[r][s] = F[0][row_a2(r)][s];
             }
+        if (needZ) {
+            // z predictor: transverse axes x (A1) and y (A2); its record goes
+            // to the z corrector flux rows, which the z sweep (STAGE 3) reads
+            ZoneRaw<R, 2> zz;
+#pragma unroll
+            for (int c = 0; c < 8; c++) zz.q[c] = zx.q[c];
+#pragma unroll
+            for (int a = 0; a < 3; a++) zz.b[a][0] = zx.b[a][0], zz.b[a][1] = zx.b[a][1];
+#pragma unroll
+            for (int r = 0; r < 7; r++)
+#pragma unroll
+                for (int s2 = 0; s2 < 2; s2++) {
+                    zz.fa[r][s2] = F[0][row_a1(r)][s2];
+                    zz.fb[r][s2] = F[1][row_a2(r)][s2];
+                }
+            const Rec8<R> rz = zone_record<R, 2, 2>(zz, cf, prm, scv);
+#pragma unroll
+            for (int r = 0; r < 7; r++) bstore(rz.v[r], rw, xo, (unsigned)(F_FL2 + 14 + r) * VB);
+        }
+        // the z record first (stored at once), so that its temporaries are
+        // dead before the x and y records are formed
+        __builtin_amdgcn_sched_barrier(0);
         if (needX) shp[tid] = zone_record<R, 0, 2>(zx, cf, prm, scv);
         if (needY) ry = zone_record<R, 1, 2>(zy, cf, prm, scv);
     }
+    if (!faces) return;  // a z-record plane: no barrier follows for the whole block
     __syncthreads();
 
     // ---------------- x faces: tx - 3 between zones tx - 4 and tx - 3 ----------------
@@ -1956,7 +2006,10 @@ hipError_t launch_sweep(int d, int stage, void* pool, const PatchDev* pt, const 
         else if (!pr) WMB_SW1(DD, SS, false, false);                                                                  \
         else WMB_SW1(DD, SS, false, true);                                                                            \
     } while (0)
-    if (stage == 1) {
+    if (stage == 3) {
+        if (d != 2) return hipErrorInvalidValue;  // the z corrector from stored records
+        WMB_SW(2, 3);
+    } else if (stage == 1) {
         if (d == 0) WMB_SW(0, 1);
         else if (d == 1) WMB_SW(1, 1);
         else WMB_SW(2, 1);
@@ -1978,6 +2031,7 @@ hipError_t launch_march(int d, int stage, void* pool, const PatchDev* pt, const 
                         unsigned long long* nprot, hipStream_t st) {
     if (nblk <= 0) return hipSuccess;
     // W > 512: the corrector with the one-zone-ahead loads (FP32), W - 512 pencils a block
+    // (stage 3, the corrector from stored records, issues them ahead always in FP32)
     const bool pf = W > 512 && sizeof(R) == 4 && stage == 2;
     if (W > 512) W -= 512;
     if (d < 1 || d > 2 || W < 1 || W > 256) return hipErrorInvalidValue;
@@ -1992,6 +2046,9 @@ hipError_t launch_march(int d, int stage, void* pool, const PatchDev* pt, const 
             hipLaunchKernelGGL((march_kernel<R, DD, SS, MM, PR, false>), dim3(nblk), dim3(W), 0, st, (R*)pool, pt,    \
                                wk, prm, cf, cur, sc, P, zlo, nprot);                                                \
     } while (0)
+#define WMB_MA3(MM, PR)                                                                                             \
+    hipLaunchKernelGGL((march_kernel<R, 2, 3, MM, PR, false>), dim3(nblk), dim3(W), 0, st, (R*)pool, pt, wk, prm,   \
+                       cf, cur, sc, P, zlo, nprot)
 #define WMB_MA(DD, SS)                                                                                              \
     do {                                                                                                            \
         if (mm && !pr) WMB_MA1(DD, SS, true, false);                                                                \
@@ -1999,7 +2056,14 @@ hipError_t launch_march(int d, int stage, void* pool, const PatchDev* pt, const 
         else if (!pr) WMB_MA1(DD, SS, false, false);                                                                \
         else WMB_MA1(DD, SS, false, true);                                                                          \
     } while (0)
-    if (stage == 1) {
+    if (stage == 3) {
+        // the z corrector from stored records (its loads always one zone ahead in FP32)
+        if (d != 2) return hipErrorInvalidValue;
+        if (mm && !pr) WMB_MA3(true, false);
+        else if (mm) WMB_MA3(true, true);
+        else if (!pr) WMB_MA3(false, false);
+        else WMB_MA3(false, true);
+    } else if (stage == 1) {
         if (d == 1) WMB_MA(1, 1);
         else WMB_MA(2, 1);
     } else {
@@ -2007,6 +2071,7 @@ hipError_t launch_march(int d, int stage, void* pool, const PatchDev* pt, const 
         else WMB_MA(2, 2);
     }
 #undef WMB_MA1
+#undef WMB_MA3
 #undef WMB_MA
     return hipGetLastError();
 }

@@ -440,6 +440,21 @@ hipError_t launch_group(wmb_ctx* c, int d, int stage, const SweepGroup& G, const
                            nprot, st);
 }
 
+// with the fused x/y corrector on, the z predictor records it stores are
+// what the z corrector reads (stage 3), so the z sweep follows it
+bool zrec(const wmb_ctx* c) { return c->xy_rows > 0; }
+
+// the z corrector sweeps of one group's list: from the stored records after
+// the fused x/y corrector, else from q^n and the Step-1 fluxes
+template <typename R>
+hipError_t launch_corr_z(wmb_ctx* c, int g, int cur, unsigned long long* nprot, hipStream_t st) {
+    for (auto& G : c->sweeps[2][1]) {
+        hipError_t r = launch_group<R>(c, 2, zrec(c) ? 3 : 2, G, g < 0 ? G.wl : G.wlg[g], cur, nprot, st);
+        if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+}
+
 // the corrector's x sweeps of one group's list (wl: all patches; g >= 0: step
 // group g), as the fused x/y kernel when xy_rows > 0
 template <typename R>
@@ -560,23 +575,31 @@ int run_step(wmb_ctx* c, bool split = false) {
         CKH(hipEventRecord(c->ev_br[2], c->stream));
         CKH(hipStreamWaitEvent(c->side, c->ev_br[2], 0));
         CKH(hipStreamWaitEvent(c->side2, c->ev_br[2], 0));
-        // with the fused x/y corrector the y branch is empty
+        // with the fused x/y corrector the y branch is empty; when it stores
+        // the z records, the z corrector follows it on the main stream
         if (!c->xy_rows) {
             e = sweeps(1, 2, &SweepGroup::wl, c->side);
             STEPCK("sweep2");
         }
-        e = sweeps(2, 2, &SweepGroup::wl, c->side2);
-        STEPCK("sweep2");
+        if (!zrec(c)) {
+            e = launch_corr_z<R>(c, -1, cur, c->d_nfloor + 1, c->side2);
+            STEPCK("sweep2");
+        }
         CKH(hipEventRecord(c->ev_br[3], c->side));
         CKH(hipEventRecord(c->ev_br[4], c->side2));
         e = launch_corr_x<R>(c, -1, cur, c->d_nfloor + 1, c->stream);
         STEPCK("sweep2");
+        if (zrec(c)) {
+            e = launch_corr_z<R>(c, -1, cur, c->d_nfloor + 1, c->stream);
+            STEPCK("sweep2");
+        }
         CKH(hipStreamWaitEvent(c->stream, c->ev_br[3], 0));
         CKH(hipStreamWaitEvent(c->stream, c->ev_br[4], 0));
     } else {
         for (int d = 0; d < 3; d++) {
             if (d == 0) e = launch_corr_x<R>(c, -1, cur, c->d_nfloor + 1, c->stream);
-            else if (d == 2 || !c->xy_rows) e = sweeps(d, 2, &SweepGroup::wl, c->stream);
+            else if (d == 2) e = launch_corr_z<R>(c, -1, cur, c->d_nfloor + 1, c->stream);
+            else if (!c->xy_rows) e = sweeps(d, 2, &SweepGroup::wl, c->stream);
             STEPCK("sweep2");
             mark(c);
         }
@@ -619,6 +642,8 @@ int run_step_grouped(wmb_ctx* c) {
             for (int d = 0; d < 3 && e == hipSuccess; d++) {
                 if (stage == 2 && d == 0) {
                     e = launch_corr_x<R>(c, g, cur, c->d_nfloor + 1, st);
+                } else if (stage == 2 && d == 2) {
+                    e = launch_corr_z<R>(c, g, cur, c->d_nfloor + 1, st);
                 } else if (!(stage == 2 && d == 1 && c->xy_rows)) {
                     for (auto& SG : c->sweeps[d][stage - 1])
                         if (e == hipSuccess) e = launch_group<R>(c, d, stage, SG, SG.wlg[g], cur, c->d_nfloor + 1, st);
@@ -948,9 +973,10 @@ int set_group_W(wmb_ctx* c, int d, int stage, SweepGroup& G, int W) {
 }
 
 // The fused x/y corrector (xy_rows > 0): for the patches whose x edge is n,
-// one item a z-plane k in [-1, n_z] and band of y-face rows, the rows [-1,
-// n_y + 2) cut into near-equal bands of at most rb rows.  Planes outermost,
-// so that consecutive blocks of a patch share the z-flux plane between them.
+// one item a z-plane k in [-3, n_z + 2] (beyond [-1, n_z] the z predictor
+// records only) and band of y-face rows, the rows [-1, n_y + 2) cut into
+// near-equal bands of at most rb rows.  Planes outermost, so that
+// consecutive blocks of a patch share the z-flux plane between them.
 std::vector<WorkItem> xy_items(const wmb_ctx* c, int n, int rb, int group = -1) {
     std::vector<WorkItem> items;
     for (int p = 0; p < c->npatch; p++) {
@@ -958,7 +984,7 @@ std::vector<WorkItem> xy_items(const wmb_ctx* c, int n, int rb, int group = -1) 
         if (group >= 0 && c->pgroup[p] != group) continue;
         const int* e = c->desc[p].n;
         const int E = e[1] + 3, nb = (E + rb - 1) / rb;
-        for (int k = -1; k <= e[2]; k++)
+        for (int k = -3; k <= e[2] + 2; k++)
             for (int b = 0; b < nb; b++) {
                 const int y0 = -1 + E * b / nb, y1 = -1 + E * (b + 1) / nb;
                 items.push_back(WorkItem{p, k + XY_BIAS, (y0 + XY_BIAS) | ((y1 + XY_BIAS) << 16), 0});
@@ -1533,21 +1559,39 @@ int autotune_t(wmb_ctx* c, int reps) {
                     if (!rc2) rc2 = set_group_W(c, d, stage, G, choice == 1 ? G.Wp : G.Wm);
         if (rc2) return cleanup(rc2);
     }
-    // The fused x/y corrector: bands of 6, 9, 12 or 18 rows against the
-    // separate x and y sweeps, whole steps replayed as a graph.
+    // The fused x/y corrector: bands of 6, 9, 12 or 18 rows, each with the z
+    // corrector (then reading the stored records) as marching sweeps of 256
+    // or 64 pencils a block or pencil sweeps of 16, against the separate
+    // sweeps as chosen above; whole steps replayed as a graph.
     {
         float best = 0.f;
         int rc2 = time_stage(&best);
         if (rc2) return rc2;
         int best_rb = 0;
+        std::vector<int> zw, best_zw;
+        for (auto& G : c->sweeps[2][1]) zw.push_back(G.W);
+        best_zw = zw;
         for (int rb : {6, 9, 12, 18}) {
             if (!xy_ok(c, rb)) continue;
             if ((rc2 = set_xy(c, rb))) return cleanup(rc2);
-            float t = 0.f;
-            if ((rc2 = time_stage(&t))) return rc2;
-            if (t < best) best = t, best_rb = rb;
+            for (int W : {-256, -64, 16}) {
+                std::vector<int> cur_zw;
+                for (auto& G : c->sweeps[2][1]) {
+                    const int w = shape_ok(2, G.P, es, W, 2) ? W : G.W;
+                    if (w != G.W && (rc2 = set_group_W(c, 2, 1, G, w))) return cleanup(rc2);
+                    cur_zw.push_back(w);
+                }
+                float t = 0.f;
+                if ((rc2 = time_stage(&t))) return rc2;
+                if (t < best) best = t, best_rb = rb, best_zw = cur_zw;
+            }
         }
         if ((rc2 = set_xy(c, best_rb))) return cleanup(rc2);
+        size_t i = 0;
+        for (auto& G : c->sweeps[2][1]) {
+            const int w = best_zw[i++];
+            if (w != G.W && (rc2 = set_group_W(c, 2, 1, G, w))) return cleanup(rc2);
+        }
     }
     // The tiles of Steps 3-4 (widest tile along x) and of Steps 8-11 (zones
     // a tile plane): time each candidate's whole launch.  The intermediates

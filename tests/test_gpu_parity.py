@@ -680,13 +680,15 @@ def test_sweep_forms_bitwise_equal(wmb, form):
 
 @pytest.mark.parametrize("form", sorted(FORMS))
 def test_fused_xy_corrector_bitwise_equal(wmb, form):
-    """The fused x/y corrector (one launch builds both predictor states from
-    one load of each zone and forms the x and y faces of a z-plane band)
-    gives bitwise the state of the separate x and y corrector sweeps after 3
-    eager steps, and the same Step-6/7 x and y fluxes on the faces and rows
-    the update reads, for bands of 6 and 9 rows (and 18 where the block
-    fits); the uneven tiling also through 3 graph-replayed steps, alone and
-    with two patch groups on their own streams."""
+    """The fused x/y corrector (one launch builds the x and y predictor
+    states of a z-plane band from one block's loads, forms its x and y
+    faces, and stores the z predictor records that the z corrector then
+    reads) gives bitwise the state of the separate corrector sweeps after 3
+    eager steps, and the same Step-6/7 fluxes on the faces and rows the
+    update reads, for bands of 6, 9 and 18 rows with the z corrector in the
+    pencil and marching forms; the uneven tiling also through 3
+    graph-replayed steps, alone and with two patch groups on their own
+    streams."""
     prec, kw, grid = FORMS[form]
     if grid == "cube64":
         G = I.uniform_grid(64, 64)
@@ -695,11 +697,13 @@ def test_fused_xy_corrector_bitwise_equal(wmb, form):
         G, (q, b) = CASES[grid]()
     N = G.shape
     dx = (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
-    bands = [0, 6, 9] + ([18] if grid == "uneven" else [])
+    # (band rows, z corrector shape): 0 rows for the separate sweeps
+    bands = [(0, None), (6, None), (9, -64)] + ([(18, -256)] if grid == "uneven" else [(9, 4)])
+    zedges = {int(n[2]) for n, _ in G.descs}
     outs = []
-    for rb in bands:
+    for rb, zw in bands:
         sim = gpu_sim(wmb, G, q, b, prec, dx=dx, **kw)
-        sim.set_tuning({(6, 0, 0): rb})
+        sim.set_tuning({(6, 0, 0): rb, **({(2, 2, e): zw for e in zedges} if zw else {})})
         for _ in range(3):
             sim.fill_ghosts()
             sim.compute_dt(fetch=False)
@@ -710,7 +714,7 @@ def test_fused_xy_corrector_bitwise_equal(wmb, form):
         for ip in range(G.npatch):
             n = G.descs[ip][0]
             f = sim.debug_stage(ip, 5)
-            for d in (0, 1):
+            for d in (0, 1, 2):
                 sl = [None] * 3
                 for a in range(3):
                     lo, hi = (-1, 1) if a == d else (-1, 0)
@@ -720,7 +724,7 @@ def test_fused_xy_corrector_bitwise_equal(wmb, form):
         if grid == "uneven":
             for groups in (1, 2):
                 sim2 = gpu_sim(wmb, G, q, b, prec, dx=dx, **kw)
-                sim2.set_tuning({(6, 0, 0): rb})
+                sim2.set_tuning({(6, 0, 0): rb, **({(2, 2, e): zw for e in zedges} if zw else {})})
                 sim2.set_schedule(groups)
                 sim2.run_steps(3)
                 graph.append(I.gather(G, [sim2.get_state(i) for i in range(G.npatch)]))
