@@ -126,8 +126,8 @@ def roofline(descs, g, es, zones, ms_step, kern_ms, prof=None):
 # rocprofv3 counter summary (written into profiles/, read back by roofline())
 # ---------------------------------------------------------------------------
 
-TUNING32_PROF = "1x32=12,1y32=16,1z32=16,2x32=2,2y32=16,2z32=16"
-TUNING64_PROF = "1x32=6,1y32=-256,1z32=-256,2x32=3,2y32=-64,2z32=-64"
+TUNING32_PROF = "1x32=12,1y32=16,1z32=16,2x32=2,2y32=16,2z32=-256,6x0=9"
+TUNING64_PROF = "1x32=6,1y32=-256,1z32=-256,2x32=3,2y32=-64,2z32=-64,6x0=0"
 COUNTER_ARGS = ("--steps 2 --warmup 1 --prof-steps 0 --no-fp64 --no-cpu-baseline --schedule 1 --calib-copy "
                 "--tuning32 " + TUNING32_PROF)
 SQ_COUNTERS = "SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES GRBM_GUI_ACTIVE"
@@ -142,7 +142,8 @@ def kernel_class(name):
 
     m = re.search(r"(?:sweep|march)_kernel<(?:float|double), (\d), (\d)", name)
     if m:
-        return "sweep%s_%s" % (m.group(2), "xyz"[int(m.group(1))])
+        # stage 3: the z corrector from the records the fused corrector stored
+        return "sweep%s_%s" % ("2" if m.group(2) == "3" else m.group(2), "xyz"[int(m.group(1))])
     if "corr_xy_kernel" in name:  # the fused x/y corrector: counted in the x class
         return "sweep2_x"
     for key, cls in (("fill_pass_kernel", "fill"), ("ct_half_kernel", "ct_half"), ("update_kernel", "update"),

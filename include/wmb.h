@@ -267,7 +267,8 @@ int wmb_autotune(wmb_ctx *c, int32_t reps, int32_t *chosen, int32_t nchosen);
    Steps 8-11 launch: m = 0 one block a tile (the default), m = 1 a
    persistent grid whose blocks take the tiles of their XCD's queue from an
    atomic counter; (6, 0, 0, r) the corrector (Steps 5-7): r = 0 three
-   separate sweeps (the default), r > 0 one fused launch for x and y whose
+   separate sweeps (the FP64 default), r > 0 (the FP32 default: 9, or 6
+   where those blocks do not fit) one fused launch for x and y whose
    blocks each take one z-plane of a patch and a band of at most r rows
    along y, build the x, y and z predictor states of their zones from one
    block's loads, form the x and y faces and store the z predictor records

@@ -582,7 +582,7 @@ def test_scratch_groups_bitwise(wmb, prec):
                     sim.set_schedule(1)
             sim.run_steps(3)
             ms = sim.profile_step()
-            assert ms["update"] > 0 and ms["sweep2_y"] > 0, ms
+            assert ms["update"] > 0 and ms["sweep2_z"] > 0, ms
             outs.append(I.gather(G, [sim.get_state(i) for i in range(G.npatch)]))
             sim.close()
         for k in range(1, len(outs)):
@@ -617,6 +617,36 @@ def test_scratch_groups_with_frozen_and_removed_patches(wmb):
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
+def test_fused_corrector_with_frozen_and_removed_patches(wmb):
+    """The fused corrector (the FP32 default) with the pool's other verbs:
+    the sequence of the scratch-group test above (a patch frozen and an
+    x-column removed after a graph-replayed step, 3 more steps, both undone,
+    2 more), FP32, bitwise equal with the corrector fused and as three
+    separate sweeps, and fused with 3 scratch groups."""
+    G = I.patch_grid([12] * 4, [12, 12], [12, 12], periodic=(False, True, True))
+    q, b = I.random_smooth(G.shape, 49)
+    dx = (1.0 / 48, 1.0 / 24, 1.0 / 24)
+    last = [(k * 2 + j) * 4 + 3 for k in range(2) for j in range(2)]
+    outs = []
+    for sg, rb in ((0, None), (0, 0), (3, None)):
+        sim = gpu_sim(wmb, G, q, b, 1, dx=dx, scratch_groups=sg)
+        if rb is not None:
+            sim.set_tuning({(6, 0, 0): rb})
+        sim.run_steps(1)
+        sim.set_active(5, False)
+        for p in last:
+            sim.set_present(p, False)
+        sim.run_steps(3)
+        for p in last:
+            sim.set_present(p, True)
+        sim.set_active(5, True)
+        sim.run_steps(2)
+        outs.append(I.gather(G, [sim.get_state(i) for i in range(G.npatch)]))
+        sim.close()
+    for k in (1, 2):
+        assert np.array_equal(outs[0][0], outs[k][0]) and np.array_equal(outs[0][1], outs[k][1]), k
+
+
 FORMS = {
     # (precision, extra params, grid): the minmod, general-limiter and
     # protected instantiations of both sweep forms, and one 64^3 patch
@@ -649,8 +679,12 @@ def test_sweep_forms_bitwise_equal(wmb, form):
     for shape in shapes:
         sim = gpu_sim(wmb, G, q, b, prec, dx=dx, **kw)
         edges = {(st, ax, int(n[ax])) for st in (1, 2) for ax in (1, 2) for n, _ in G.descs}
-        # the loads-ahead variant is a corrector (stage 2) shape
-        sim.set_tuning({k: (shape if shape > -512 or k[0] == 2 else -64) for k in edges})
+        # the loads-ahead variant is a corrector (stage 2) shape; the
+        # corrector as three separate sweeps (not fused), whose y and z forms
+        # are compared here
+        tun = {k: (shape if shape > -512 or k[0] == 2 else -64) for k in edges}
+        tun[(6, 0, 0)] = 0
+        sim.set_tuning(tun)
         for _ in range(3):
             sim.fill_ghosts()
             sim.compute_dt(fetch=False)
