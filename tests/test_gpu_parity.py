@@ -200,6 +200,28 @@ def test_minimum_patch_edges_fp64(wmb, case):
         assert rel_max(bg[c], bo[c]) < 1e-11
 
 
+@pytest.mark.parametrize("case", sorted(EDGE_CASES))
+def test_minimum_patch_edges_fused_corrector_bitwise(wmb, case):
+    """On the smallest patches (edges down to the ghost width, ghost widths
+    4, 5 and 7, self-neighbours along z), the fused corrector gives bitwise
+    the state of the three separate corrector sweeps after 4 graph-replayed
+    steps, in FP32 (where it is the default) and in FP64."""
+    g, grid = EDGE_CASES[case]
+    G = grid()
+    N = G.shape
+    q, b = I.random_smooth(N, 18)
+    dx = (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
+    for prec in (1, 0):
+        outs = []
+        for rb in (0, 9):
+            sim = gpu_sim(wmb, G, q, b, prec, dx=dx, ghost=g)
+            sim.set_tuning({(6, 0, 0): rb})
+            sim.run_steps(4)
+            outs.append(I.gather(G, [sim.get_state(i) for i in range(G.npatch)]))
+            sim.close()
+        assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1]), prec
+
+
 def _rel_l1(a, ref):
     return float(np.abs(a - ref).sum() / np.abs(ref).sum())
 
