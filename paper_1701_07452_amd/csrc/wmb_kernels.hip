@@ -1571,17 +1571,17 @@ __global__ void __launch_bounds__(256) march_kernel(R* __restrict__ pool, const 
 }
 
 // ---------------------------------------------------------------------------
-// Fused x and y correctors (Steps 5-7 along x and y in one launch).  A block
-// covers one z-plane k of a patch and a band of rows along y; every thread
-// owns one zone (x fastest, so loads cover consecutive x), loads the zone's
-// data once (q^n, b^n at the zone's lower and upper faces, the three Step-1
-// flux arrays at the zone and one zone up along their own axes) and builds
-// from it both predictor states q^{n+1/2}_x and q^{n+1/2}_y (Step 5), which
-// the separate sweeps each load and build on their own.  The x faces of the
-// band's rows, then the y faces of the band, are formed as in the pencil
-// kernel through the same LDS (zone records, then face g-tilde), with the
-// same phase functions, so the fluxes are bitwise those of the separate
-// sweeps.
+// Fused corrector (Steps 5-7 along x and y in one launch, and the z
+// predictor records).  A block covers one z-plane k of a patch and a band of
+// rows along y; every thread owns one zone (x fastest, so loads cover
+// consecutive x), loads the zone's data once (q^n, b^n at the zone's lower
+// and upper faces, the three Step-1 flux arrays at the zone and one zone up
+// along their own axes) and builds from it the predictor states
+// q^{n+1/2}_x, q^{n+1/2}_y and q^{n+1/2}_z (Step 5), which the separate
+// sweeps each load and build on their own.  The x faces of the band's rows,
+// then the y faces of the band, are formed as in the pencil kernel through
+// the same LDS (zone records, then face g-tilde), with the same phase
+// functions, so the fluxes are bitwise those of the separate sweeps.
 //   block (P, RT): P = n_x + 6 zones [-3, n_x + 3) along x; RT rows along y,
 //   the band's y-face rows [y0, y1) with two rows below and one above (the
 //   limiter stencil); item a = k + XY_BIAS, b = (y0 + XY_BIAS) | (y1 +
@@ -1625,11 +1625,13 @@ __device__ __forceinline__ void xy_flux(const Rec8<R>* shp, const Rec8<R>* shg, 
     store_flux<R, D>(out, rw, xo, (unsigned)(F_FL2 + 7 * D) * VB, VB);
 }
 
+// FP64 blocks stay within 512 threads (the LDS bound of the launch implies
+// it), which leaves the FP64 kernel its 142 VGPRs without spilling.
 template <typename R, bool MM, bool PROT>
-__global__ void __launch_bounds__(sizeof(R) == 4 ? 1024 : 512) corr_xy_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches,
-                                                       const WorkItem* __restrict__ work, DevParams prm, Coef<R> cf,
-                                                       int cur, const StepConst* __restrict__ sc,
-                                                       unsigned long long* __restrict__ nprot) {
+__global__ void __launch_bounds__(sizeof(R) == 4 ? 1024 : 512)
+    corr_xy_kernel(R* __restrict__ pool, const PatchDev* __restrict__ patches, const WorkItem* __restrict__ work,
+                   DevParams prm, Coef<R> cf, int cur, const StepConst* __restrict__ sc,
+                   unsigned long long* __restrict__ nprot) {
     extern __shared__ unsigned char smem_raw[];
     const int P = (int)blockDim.x, RT = (int)blockDim.y;
     Rec8<R>* shp = reinterpret_cast<Rec8<R>*>(smem_raw);  // zone records: x, then y
@@ -1661,7 +1663,7 @@ __global__ void __launch_bounds__(sizeof(R) == 4 ? 1024 : 512) corr_xy_kernel(R*
     const unsigned qs = (unsigned)(cur ? F_ST1 : F_ST0) * VB;
     const R z0 = R(0);
 
-    // ---------------- phase A: one load of the zone, two predictor records ----------------
+    // ---------------- phase A: one load of the zone, three predictor records ----------------
     Rec8<R> ry;
     if (live) {
         ZoneRaw<R, 2> zx, zy;
