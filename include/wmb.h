@@ -178,7 +178,9 @@ int wmb_advance(wmb_ctx *c, double dt);
    the x-ghosts), on a branch of its own beside the part of the Step-1 x sweep
    whose pencils have interior transverse coordinates (the overlap of
    exchange and interior work of Sect. 4); the three sweeps of each stage
-   run as concurrent branches (library-owned streams, default priority); the
+   run as concurrent branches (library-owned streams, default priority),
+   except that the fused corrector is followed by the z sweep that reads its
+   records; the
    x pass is enqueued first when the state was set since.  Results are
    bitwise those of the eager calls.  Enqueue only; this is the timed call. */
 int wmb_run_steps(wmb_ctx *c, int32_t nsteps);
@@ -281,7 +283,7 @@ int wmb_autotune(wmb_ctx *c, int32_t reps, int32_t *chosen, int32_t nchosen);
 int wmb_set_tuning(wmb_ctx *c, const int32_t *quads, int32_t n);
 
 /* Schedule of the captured step (wmb_run_steps).  groups = 1 (the default):
-   the three sweeps of each stage run as concurrent branches and the y/z
+   the three sweeps of each stage (the separate ones) run as concurrent branches and the y/z
    ghost exchange beside the interior part of the Step-1 x sweep.  groups =
    2..4: the patches are dealt, whole x-rows at a time, to that many groups,
    and each group runs its whole step (Steps 1-11) on a stream of its own

@@ -522,7 +522,9 @@ hipError_t launch_group(wmb_ctx* c, int d, int stage, const SweepGroup& G, const
 // onto the side stream (ev_join marks its end).  The three sweeps of a stage
 // are independent (each writes its own flux array), so they run as three
 // branches: x on the main stream, y on the side stream, z on the second side
-// stream, joined before Steps 3-4 and before Steps 8-11.  The Step-1 x sweep
+// stream, joined before Steps 3-4 and before Steps 8-11 (with the fused
+// corrector, Steps 5-7 are its launch and then the z sweep from its records,
+// both on the main stream).  The Step-1 x sweep
 // first covers the pencils whose transverse coords are interior, which read
 // only the x-ghosts the previous update wrote, then waits for the exchange
 // and covers the frame.
