@@ -283,8 +283,9 @@ int wmb_autotune(wmb_ctx *c, int32_t reps, int32_t *chosen, int32_t nchosen);
 int wmb_set_tuning(wmb_ctx *c, const int32_t *quads, int32_t n);
 
 /* Schedule of the captured step (wmb_run_steps).  groups = 1 (the default):
-   the three sweeps of each stage (the separate ones) run as concurrent branches and the y/z
-   ghost exchange beside the interior part of the Step-1 x sweep.  groups =
+   the three sweeps of each stage (the separate ones) run as concurrent
+   branches and the y/z ghost exchange beside the interior part of the
+   Step-1 x sweep.  groups =
    2..4: the patches are dealt, whole x-rows at a time, to that many groups,
    and each group runs its whole step (Steps 1-11) on a stream of its own
    after the exchange and dt, so that the memory-bound stages of one group
@@ -352,7 +353,9 @@ int wmb_keep_stages(wmb_ctx *c, int32_t on);
    order: fill (3 passes), dt (finalize of the reduction that the previous
    update folded in), sweep x, y, z (Step 1, the x sweep also forming the
    Step-2 reference EMF), CT half (Steps 3-4 fused: edge EMFs and
-   b^{n+1/2}), sweep x, y, z (Steps 5-7), update (Steps 8-11 fused:
+   b^{n+1/2}), sweep x, y, z (Steps 5-7; with the fused corrector its launch
+   counts as x, y is empty and z is the sweep from its records), update
+   (Steps 8-11 fused:
    half-step EMF, edge EMFs, conservative and CT update, and the
    signal-speed maximum of the new state).  Advances the state by one step.
    Synchronous. */
