@@ -72,10 +72,13 @@ __device__ __forceinline__ R qvisc(R chi, R eps, R q4e) {
 
 // g_i = SIGN(gp) * SWEBY(gp, gm) (Appendix A), Sweby family with parameter
 // beta; MM: beta = 1 (minmod), where both arguments of the outer max agree
-// exactly and one branch is dropped (bitwise the same result)
+// exactly and one branch is dropped.  Minmod is the median of gp, gm and 0,
+// one v_med3_f32 in FP32 (the same value; a zero result may differ in sign,
+// which no sum or product of the flux carries into a nonzero value).
 template <bool MM, typename R>
 __device__ __forceinline__ R sweby(R gp, R gm, R beta) {
 #pragma clang fp contract(on)
+    if constexpr (MM && sizeof(R) == 4) return __builtin_amdgcn_fmed3f(gp, gm, 0.0f);
     R s = sgn1(gp);
     if (MM) return s * fmax(R(0), fmin(fabs(gp), s * gm));
     R t1 = fmin(beta * fabs(gp), s * gm);
