@@ -579,6 +579,8 @@ def main():
                     help="skip the FP32 batch with the step intermediates shared by 4 patch groups (reported beside)")
     ap.add_argument("--planar", action="store_true",
                     help="also time the planar Orszag-Tang vortex (192^2 and 2048^2) run as one-patch-thin 3D boxes")
+    ap.add_argument("--patch-sweep", action="store_true",
+                    help="also time the FP32 turbulence box cut into patches of 16, 24, 32, 48 and 64 zones an edge")
     ap.add_argument("--schedule", type=int, default=0,
                     help="captured-step schedule: 1 (concurrent sweep branches), 2 or 3 patch groups; 0 picks by timing")
     ap.add_argument("--calib-copy", action="store_true",
@@ -766,6 +768,25 @@ def main():
             log("bench: planar %d^2: %.3f ms/step, %.3e planar zone-updates/s" %
                 (N2, ms2 / args.steps, planar[str(N2)]["planar_zone_updates_per_s"]))
 
+    sweep = None
+    if args.patch_sweep:
+        # the same turbulence recipe cut into cubic patches of each edge: 256^3
+        # where the edge divides it, else 240^3
+        sweep = {"workload": "turbulence box (256^3, or 240^3 for edges 24 and 48) as periodic cubic patches, "
+                             "ghost %d, FP32, autotuned" % g}
+        for e in (16, 24, 32, 48, 64):
+            Ne = 256 if 256 % e == 0 else 240
+            Ge = I.uniform_grid(Ne, e)
+            qe, be = I.turbulence(Ne)
+            log("bench: patch sweep %d^3 as %d patches of %d^3" % (Ne, Ge.npatch, e))
+            mse, _, kerne, diage = run_batch(W, Ge, qe, be, (1.0 / Ne,) * 3, W.WMB_FP32, g, args.steps, args.warmup, 1)
+            del qe, be
+            sweep[str(e)] = {"box": Ne, "patches": Ge.npatch, "ms_per_step": mse / args.steps,
+                             "value": Ge.zones() * args.steps / (mse / 1e3), "kernels_ms": kerne,
+                             "tuning": diage["tuning"], "schedule_groups": diage["schedule_groups"]}
+            log("bench: patch sweep edge %d: %.3f ms/step, %.3e zone-updates/s" %
+                (e, mse / args.steps, sweep[str(e)]["value"]))
+
     if not kern32:  # counter-collection runs skip the per-kernel pass
         print(json.dumps({"metric": METRIC, "value": value, "unit": "zone-updates/s", "partial": True}), flush=True)
         return
@@ -809,6 +830,7 @@ def main():
         "frozen_half_fp32": frozen,
         "outflow_fp32": outflow,
         "planar_fp32": planar,
+        "patch_sweep_fp32": sweep,
         "roofline": roof,
         "cpu_baseline": cpu,
         "bench_wall_s": round(time.perf_counter() - t_start, 1),
