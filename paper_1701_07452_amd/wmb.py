@@ -271,9 +271,11 @@ class Sim:
         return out.reshape((3, 8) + sh) if nw == 24 else out
 
     def autotune(self, reps=3):
-        """Pick the sweep block shapes and the Steps 3-4 / 8-11 tiles by timing (or from the
-        per-process cache; reps < 0 forces timing); returns {(stage, axis, edge): shape}, with
-        (3, 0, 0) the Steps 3-4 tile width and (4, 0, 0) the Steps 8-11 tile zones."""
+        """Pick the sweep block shapes, the fused corrector's band rows and the Steps 3-4 / 8-11
+        tiles by timing (or from the per-process cache; reps < 0 forces timing); returns
+        {(stage, axis, edge): shape}, with (3, 0, 0) the Steps 3-4 tile width, (4, 0, 0) the
+        Steps 8-11 tile zones, (5, 0, 0) their launch form and (6, 0, 0) the fused corrector's
+        band rows (0: three separate corrector sweeps)."""
         buf = (C.c_int32 * 256)()
         self._check(self.lib.wmb_autotune(self.h, int(reps), buf, 256))
         out, k = {}, 0
