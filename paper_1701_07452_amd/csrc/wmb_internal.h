@@ -104,6 +104,13 @@ constexpr int DIAG_REC = 20;
 // 512-thread block would run alone.
 constexpr int upd_tile_zones_max(int esize) { return esize == 4 ? 512 : 256; }
 
+// The Steps 8-11 kernel's LDS planes, sized for its largest block: E^r over
+// the tile and a one-zone ring, (tx + 2)(ty + 2) <= upd_er_plane, and the
+// edges, (tx + 1)(ty + 1) <= upd_ed_plane.  The tile planner keeps every tile
+// within both (and tx ty within the block).
+constexpr int upd_er_plane(int esize) { return upd_tile_zones_max(esize) + 68 + upd_tile_zones_max(esize) / 16; }
+constexpr int upd_ed_plane(int esize) { return upd_tile_zones_max(esize) + 33 + upd_tile_zones_max(esize) / 32; }
+
 // Box kernels: interior-relative inclusive ranges [lo, n + hi] per axis.
 struct Box {
     int lo, hi;

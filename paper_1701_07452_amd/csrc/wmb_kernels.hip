@@ -416,16 +416,17 @@ __device__ __forceinline__ R edge_combine(R Ea_0, R Ea_b, R Eb_0, R Eb_a, R ma_0
 
 // Column tiles of the marching kernels, ty <= 32.  Steps 3-4: tx <= 40 and
 // tx ty <= 256 zones per plane, LDS edge planes (tx+1)(ty+1) <= 297 long.
-// Steps 8-11: tx <= 32 and tx ty <= Z <= upd_tile_zones_max (the block size:
-// 256 or 512), so tx + ty <= 32 + Z/32: edge planes (tx+1)(ty+1) <= Z + 33 +
-// Z/32 long, E^r planes (tx+2)(ty+2) <= Z + 68 + Z/16.
+// Steps 8-11: tx ty <= Z <= upd_tile_zones_max (the block size: 256 or 512),
+// tx <= 48, the E^r planes (tx+2)(ty+2) <= upd_er_plane and the edge planes
+// (tx+1)(ty+1) <= upd_ed_plane long (the tile planner caps ty for these),
+// and the ring 2 (tx+2) + 2 ty <= Z.
 constexpr int TILE_THREADS = 256;
 constexpr int CTH_EDMAX = 297;
 template <typename R>
 struct UpdTile {
     static constexpr int threads = upd_tile_zones_max((int)sizeof(R));
-    static constexpr int er = threads + 68 + threads / 16;
-    static constexpr int ed = threads + 33 + threads / 32;
+    static constexpr int er = upd_er_plane((int)sizeof(R));
+    static constexpr int ed = upd_ed_plane((int)sizeof(R));
 };
 constexpr int TILE_BIAS = 16;  // tile origins are stored biased (they may be negative)
 

@@ -752,7 +752,7 @@ std::vector<int> x_rows(const wmb_ctx* c) { return rows_of(c->npatch, c->desc.da
 bool in_plan(const wmb_ctx* c, int p) { return c->hpatch[p].present && c->hpatch[p].active; }
 
 std::vector<WorkItem> tile_items(const wmb_ctx* c, int lo, int hi, int zlo, int zhi, int txmax_allowed, int maxz,
-                                 const std::vector<int>* group, int sgroup = -1) {
+                                 const std::vector<int>* group, int sgroup = -1, int ermax = 0, int edmax = 0) {
     std::vector<WorkItem> items;
     for (int p = 0; p < c->npatch; p++) {
         if (!in_plan(c, p) || (sgroup >= 0 && c->pgroup[p] != sgroup)) continue;
@@ -762,6 +762,9 @@ std::vector<WorkItem> tile_items(const wmb_ctx* c, int lo, int hi, int zlo, int 
         const int txmax = (ex + mx - 1) / mx;
         int tymax = maxz / txmax;
         if (tymax > 32) tymax = 32;
+        // LDS planes of the Steps 8-11 kernel: E^r with its ring, the edges
+        if (ermax > 0) tymax = std::min(tymax, ermax / (txmax + 2) - 2);
+        if (edmax > 0) tymax = std::min(tymax, edmax / (txmax + 1) - 1);
         const int my = (ey + tymax - 1) / tymax;
         const int k0 = zlo + TILE_BIAS, k1 = n[2] + zhi + 1 + TILE_BIAS;
         for (int by = 0; by < my; by++) {
@@ -777,8 +780,23 @@ std::vector<WorkItem> tile_items(const wmb_ctx* c, int lo, int hi, int zlo, int 
 }
 
 int build_tile_list(wmb_ctx* c, int lo, int hi, int zlo, int zhi, int txmax_allowed, int maxz,
-                    const std::vector<int>* group, DevList& out, int sgroup = -1) {
-    std::vector<WorkItem> items = tile_items(c, lo, hi, zlo, zhi, txmax_allowed, maxz, group, sgroup);
+                    const std::vector<int>* group, DevList& out, int sgroup = -1, int ermax = 0, int edmax = 0) {
+    std::vector<WorkItem> items = tile_items(c, lo, hi, zlo, zhi, txmax_allowed, maxz, group, sgroup, ermax, edmax);
+    out.n = (int)items.size();
+    return upload(c, &out.d, items);
+}
+
+// The Steps 8-11 tiles for tile planes of Z zones: whole rows of up to 48
+// zones in the 512-zone FP32 blocks (a 48^3 patch's rows stay whole: 48 x 10
+// tiles instead of 24 x 16), up to 32 otherwise, with ty capped so that the
+// E^r and edge planes fit the kernel's LDS.
+int upd_txmax(int Z) { return Z > 256 ? 48 : 32; }
+std::vector<WorkItem> upd_items(const wmb_ctx* c, int Z, const std::vector<int>* rows, int sgroup = -1) {
+    const int es = (int)c->esize;
+    return tile_items(c, 0, -1, 0, -1, upd_txmax(Z), Z, rows, sgroup, upd_er_plane(es), upd_ed_plane(es));
+}
+int build_upd_list(wmb_ctx* c, int Z, const std::vector<int>* rows, DevList& out, int sgroup = -1) {
+    std::vector<WorkItem> items = upd_items(c, Z, rows, sgroup);
     out.n = (int)items.size();
     return upload(c, &out.d, items);
 }
@@ -794,11 +812,14 @@ int choose_upd_zones(const wmb_ctx* c) {
     double fill[2];
     for (int v = 0; v < 2; v++) {
         long long zones = 0, slots = 0;
+        const int es = (int)c->esize, txa = upd_txmax(Z[v]);
         for (int p = 0; p < c->npatch; p++) {
-            // the column-tile cut of build_tile_list for the interior x-y plane
+            // the column-tile cut of upd_items for the interior x-y plane
             const int ex = c->desc[p].n[0], ey = c->desc[p].n[1];
-            const int mx = (ex + 31) / 32, txmax = (ex + mx - 1) / mx;
-            const int tymax = std::min(32, Z[v] / txmax), my = (ey + tymax - 1) / tymax;
+            const int mx = (ex + txa - 1) / txa, txmax = (ex + mx - 1) / mx;
+            const int tymax = std::min({32, Z[v] / txmax, upd_er_plane(es) / (txmax + 2) - 2,
+                                        upd_ed_plane(es) / (txmax + 1) - 1});
+            const int my = (ey + tymax - 1) / tymax;
             zones += (long long)ex * ey;
             slots += (long long)mx * my * Z[v];
         }
@@ -809,9 +830,8 @@ int choose_upd_zones(const wmb_ctx* c) {
 
 // The tile lists of Steps 3-4 and 8-11 for the current cth_tx and
 // upd_zones: Steps 3-4 tiles up to cth_tx zones wide and 256 a plane
-// ((tx+1)(ty+1) <= 297 edges for any tx <= 40); Steps 8-11 tiles up to 32
-// wide and upd_zones a plane (the LDS planes of the kernel are sized for
-// the largest).  The update
+// ((tx+1)(ty+1) <= 297 edges for any tx <= 40); Steps 8-11 tiles of
+// upd_zones a plane as upd_items cuts them.  The update
 // and the ghost exchange place whole x-rows of patches on an XCD, so that
 // the update's x-ghost pushes go to a patch on the same XCD: 256^3 FP32
 // update 1.14 against 1.24 ms, the uneven batch 1.80 against 2.04 ms, at the
@@ -826,7 +846,7 @@ int build_ct_update_lists(wmb_ctx* c) {
     }
     const std::vector<int> rows = x_rows(c);
     int rc = build_tile_list(c, -2, 2, -2, 2, c->cth_tx, 256, nullptr, c->wl_cth);
-    if (!rc) rc = build_tile_list(c, 0, -1, 0, -1, 32, c->upd_zones, &rows, c->wl_upd);
+    if (!rc) rc = build_upd_list(c, c->upd_zones, &rows, c->wl_upd);
     if (c->ngroups > 1 && c->wl_cth_g.size() < (size_t)c->ngroups) {
         c->wl_cth_g.resize(c->ngroups);
         c->wl_upd_g.resize(c->ngroups);
@@ -837,7 +857,7 @@ int build_ct_update_lists(wmb_ctx* c) {
             *L = DevList{};
         }
         rc = build_tile_list(c, -2, 2, -2, 2, c->cth_tx, 256, nullptr, c->wl_cth_g[g], g);
-        if (!rc) rc = build_tile_list(c, 0, -1, 0, -1, 32, c->upd_zones, &rows, c->wl_upd_g[g], g);
+        if (!rc) rc = build_upd_list(c, c->upd_zones, &rows, c->wl_upd_g[g], g);
     }
     return rc;
 }
@@ -1138,10 +1158,10 @@ int replan(wmb_ctx* c) {
     }
     const std::vector<int> rows = x_rows(c);
     if (!rc) rc = put(c->wl_cth, tile_items(c, -2, 2, -2, 2, c->cth_tx, 256, nullptr));
-    if (!rc) rc = put(c->wl_upd, tile_items(c, 0, -1, 0, -1, 32, c->upd_zones, &rows));
+    if (!rc) rc = put(c->wl_upd, upd_items(c, c->upd_zones, &rows));
     for (int g = 0; g < c->ngroups && c->ngroups > 1 && !rc; g++) {
         rc = put(c->wl_cth_g[g], tile_items(c, -2, 2, -2, 2, c->cth_tx, 256, nullptr, g));
-        if (!rc) rc = put(c->wl_upd_g[g], tile_items(c, 0, -1, 0, -1, 32, c->upd_zones, &rows, g));
+        if (!rc) rc = put(c->wl_upd_g[g], upd_items(c, c->upd_zones, &rows, g));
     }
     if (regrid) free_graphs(c);
     return rc;
@@ -1607,7 +1627,7 @@ int autotune_t(wmb_ctx* c, int reps) {
             DevList L;
             // kind 0: Steps 3-4; 1: Steps 8-11, one block a tile; 2: the same on the queues
             int rc3 = kind == 0 ? build_tile_list(c, -2, 2, -2, 2, v, 256, nullptr, L)
-                                : build_tile_list(c, 0, -1, 0, -1, 32, v, &rows, L);
+                                : build_upd_list(c, v, &rows, L);
             if (rc3) return cleanup(rc3);
             tl = L.d;  // released by cleanup on an error exit
             hipError_t e = hipSuccess;
