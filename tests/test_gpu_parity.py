@@ -562,6 +562,25 @@ def test_autotune_does_not_change_results(wmb):
             assert np.array_equal(outs[0][0], o[0]) and np.array_equal(outs[0][1], o[1])
 
 
+def test_wide_update_tiles_bitwise(wmb):
+    """Steps 8-11 tiles of whole rows up to 48 zones (512-zone FP32 blocks:
+    48 x 10 and 40 x 12 tiles, rows capped by the kernel's LDS planes) give
+    bitwise the state of 256-zone tiles (24 x 10, 20 x 12) after 3
+    graph-replayed steps, on periodic patches of 48 x 40 x 36 and 40^3."""
+    G = I.patch_grid([48, 40], [40, 40], [36, 40])
+    q, b = I.random_smooth(G.shape, 51)
+    N = G.shape
+    dx = (1.0 / N[2], 1.0 / N[1], 1.0 / N[0])
+    outs = []
+    for z in (256, 512):
+        sim = gpu_sim(wmb, G, q, b, 1, dx=dx)
+        sim.set_tuning({(4, 0, 0): z})
+        sim.run_steps(3)
+        outs.append(I.gather(G, [sim.get_state(i) for i in range(G.npatch)]))
+        sim.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_tile_tuning_entries_are_checked(wmb):
     """wmb_set_tuning rejects tile and fused-corrector entries outside what
     the kernels take."""
